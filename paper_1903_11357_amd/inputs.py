@@ -1,0 +1,338 @@
+"""Seeded synthetic inputs for the two-level Schwarz PCG path.
+
+This module produces problem data only: polygon meshes of the unit square,
+subdomain partitions, coarse partitions (nested agglomerates or an
+independent coarse polygon mesh), piecewise-constant coefficients and
+right-hand-side functions. It contains none of the discretisation or solver
+arithmetic; both the CPU oracle and the GPU library consume what it returns.
+
+Random numbers come from ``numpy.random.default_rng(seed)``. For a Voronoi
+mesh the N seed points are drawn first with ``rng.random((N, 2))``; any
+further draws (coarse seeds, coefficients, RHS coefficients) continue the
+same stream in that order.
+
+The named workloads mirror the problem classes of the paper's experiments
+(unit-square Poisson, Voronoi polygonal meshes, nested agglomerated and
+independent non-nested coarse meshes, piecewise-constant coefficient jumps;
+Sections 7.1-7.5) at sizes chosen for one GPU.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Conforming polygon mesh: shared vertex ids, counter-clockwise cells."""
+
+    xy: np.ndarray            # [n_vertices, 2] float64
+    cell_ptr: np.ndarray      # [n_cells + 1] int32 CSR offsets
+    cell_vertices: np.ndarray  # [cell_ptr[-1]] int32 vertex ids, CCW
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_ptr.shape[0] - 1)
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.xy.shape[0])
+
+    def cell(self, k: int) -> np.ndarray:
+        return self.cell_vertices[self.cell_ptr[k]:self.cell_ptr[k + 1]]
+
+    def vertex_mean(self) -> np.ndarray:
+        """Arithmetic mean of each cell's vertices (used only for binning)."""
+        counts = np.diff(self.cell_ptr).astype(np.float64)
+        owner = np.repeat(np.arange(self.n_cells), np.diff(self.cell_ptr))
+        sx = np.bincount(owner, weights=self.xy[self.cell_vertices, 0], minlength=self.n_cells)
+        sy = np.bincount(owner, weights=self.xy[self.cell_vertices, 1], minlength=self.n_cells)
+        return np.stack([sx / counts, sy / counts], axis=1)
+
+
+def square_mesh(nx: int, ny: Optional[int] = None) -> Mesh:
+    """nx-by-ny uniform squares on (0,1)^2, cells ordered x-fastest."""
+    ny = nx if ny is None else ny
+    gx = np.linspace(0.0, 1.0, nx + 1)
+    gy = np.linspace(0.0, 1.0, ny + 1)
+    X, Y = np.meshgrid(gx, gy, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    cells = []
+    for j in range(ny):
+        for i in range(nx):
+            v0 = j * (nx + 1) + i
+            cells.append([v0, v0 + 1, v0 + nx + 2, v0 + nx + 1])
+    cv = np.asarray(cells, dtype=np.int32).ravel()
+    ptr = np.arange(0, 4 * nx * ny + 1, 4, dtype=np.int32)
+    return Mesh(xy=xy, cell_ptr=ptr, cell_vertices=cv)
+
+
+def _signed_area(xy: np.ndarray) -> float:
+    x, y = xy[:, 0], xy[:, 1]
+    return 0.5 * float(np.dot(x, np.roll(y, -1)) - np.dot(np.roll(x, -1), y))
+
+
+def voronoi_mesh(seeds: np.ndarray, tol: float = 1e-12) -> Mesh:
+    """Voronoi tessellation of the unit square from seed points.
+
+    The seeds are mirrored across the four sides so that the cells of the
+    original seeds are exactly the Voronoi cells clipped to the square.
+    Coordinates within ``tol`` of 0 or 1 are snapped onto the boundary and
+    vertices closer than ``tol`` are merged, so the result is conforming.
+    """
+    from scipy.spatial import Voronoi, cKDTree
+
+    seeds = np.asarray(seeds, dtype=np.float64)
+    n = seeds.shape[0]
+    # Only seeds near a side need a mirror image. If every vertex of every
+    # original cell then lies in the closed square, the cells equal those of
+    # the fully mirrored set (inside the square a mirror image is never
+    # closer than its original); otherwise fall back to mirroring all seeds.
+    for margin in (min(1.0, 8.0 / math.sqrt(max(n, 1))), 1.0):
+        parts = [seeds]
+        for d, side in ((0, 0.0), (0, 1.0), (1, 0.0), (1, 1.0)):
+            near = np.abs(seeds[:, d] - side) <= margin
+            m = seeds[near].copy()
+            m[:, d] = 2.0 * side - m[:, d]
+            parts.append(m)
+        vor = Voronoi(np.concatenate(parts))
+        regions = [vor.regions[vor.point_region[i]] for i in range(n)]
+        used = np.unique(np.concatenate([np.asarray(r, dtype=np.int64) for r in regions]))
+        if used.size and used.min() < 0:
+            continue
+        v = vor.vertices[used]
+        if v.min() >= -tol and v.max() <= 1.0 + tol:
+            break
+    else:
+        raise RuntimeError("Voronoi clipping failed")
+    xy = vor.vertices[used].copy()
+    for d in range(2):
+        xy[np.abs(xy[:, d]) < tol, d] = 0.0
+        xy[np.abs(xy[:, d] - 1.0) < tol, d] = 1.0
+    # merge near-coincident vertices (union-find over close pairs)
+    parent = np.arange(xy.shape[0])
+    pairs = cKDTree(xy).query_pairs(r=tol, output_type="ndarray")
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b in pairs:
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[max(ra, rb)] = min(ra, rb)
+    root = parent.copy()
+    while True:
+        nxt = root[root]
+        if np.array_equal(nxt, root):
+            break
+        root = nxt
+    keep, new_id = np.unique(root, return_inverse=True)
+    xy = xy[keep]
+    remap = np.full(vor.vertices.shape[0], -1, dtype=np.int64)
+    remap[used] = new_id
+
+    ptr = [0]
+    verts = []
+    for r in regions:
+        ids = remap[np.asarray(r, dtype=np.int64)]
+        # drop consecutive duplicates produced by merging
+        out = [int(ids[0])]
+        for v in ids[1:]:
+            if v != out[-1]:
+                out.append(int(v))
+        while len(out) > 1 and out[-1] == out[0]:
+            out.pop()
+        if len(out) < 3:
+            raise RuntimeError("degenerate Voronoi cell")
+        if _signed_area(xy[out]) < 0.0:
+            out.reverse()
+        verts.extend(out)
+        ptr.append(len(verts))
+    return Mesh(xy=xy, cell_ptr=np.asarray(ptr, dtype=np.int32),
+                cell_vertices=np.asarray(verts, dtype=np.int32))
+
+
+def bins_partition(points: np.ndarray, bx: int, by: int) -> np.ndarray:
+    """Cell -> bin id for a bx-by-by grid of bins over (0,1)^2 (x-fastest)."""
+    ix = np.minimum(np.floor(points[:, 0] * bx).astype(np.int64), bx - 1)
+    iy = np.minimum(np.floor(points[:, 1] * by).astype(np.int64), by - 1)
+    return (iy * bx + ix).astype(np.int32)
+
+
+def warped_bins_256(points: np.ndarray) -> np.ndarray:
+    """256 uneven subdomains: 16x16 bins of (x^2, y), with the first column
+    split at x = 1/8 and the last two columns merged (16 columns remain)."""
+    w = points[:, 0] ** 2
+    col = np.minimum(np.floor(w * 16).astype(np.int64), 15)
+    # first column split in two halves in x, shift the others right by one
+    col = np.where(col == 0, np.where(points[:, 0] < 0.125, 0, 1), col + 1)
+    col = np.minimum(col, 15)  # columns 15 and 16 (old 14, 15) merge
+    row = np.minimum(np.floor(points[:, 1] * 16).astype(np.int64), 15)
+    return (row * 16 + col).astype(np.int32)
+
+
+def block_partition_squares(nx: int, block: int) -> np.ndarray:
+    """Partition of an nx-by-nx square mesh into block-by-block agglomerates."""
+    nb = nx // block
+    ids = np.empty(nx * nx, dtype=np.int32)
+    for j in range(nx):
+        for i in range(nx):
+            ids[j * nx + i] = (j // block) * nb + (i // block)
+    return ids
+
+
+def compact_labels(labels: np.ndarray) -> np.ndarray:
+    """Relabel to 0..k-1 (drops empty bins), preserving label order."""
+    _, inv = np.unique(labels, return_inverse=True)
+    return inv.astype(np.int32)
+
+
+# ---------------------------------------------------------------- RHS data
+def f_sinsin(xy: np.ndarray) -> np.ndarray:
+    """f = 2 pi^2 sin(pi x) sin(pi y), the load of u = sin(pi x) sin(pi y)."""
+    return 2.0 * math.pi ** 2 * np.sin(math.pi * xy[:, 0]) * np.sin(math.pi * xy[:, 1])
+
+
+def u_sinsin(xy: np.ndarray) -> np.ndarray:
+    return np.sin(math.pi * xy[:, 0]) * np.sin(math.pi * xy[:, 1])
+
+
+def grad_u_sinsin(xy: np.ndarray) -> np.ndarray:
+    x, y = xy[:, 0], xy[:, 1]
+    return math.pi * np.stack([np.cos(math.pi * x) * np.sin(math.pi * y),
+                               np.sin(math.pi * x) * np.cos(math.pi * y)], axis=1)
+
+
+def f_one(xy: np.ndarray) -> np.ndarray:
+    return np.ones(xy.shape[0])
+
+
+def make_f_series(coef: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+    """f = sum_{k,l=1..K} c_kl sin(k pi x) sin(l pi y)."""
+    coef = np.asarray(coef, dtype=np.float64)
+
+    def f(xy: np.ndarray) -> np.ndarray:
+        out = np.zeros(xy.shape[0])
+        for k in range(coef.shape[0]):
+            sk = np.sin((k + 1) * math.pi * xy[:, 0])
+            for l in range(coef.shape[1]):
+                out += coef[k, l] * sk * np.sin((l + 1) * math.pi * xy[:, 1])
+        return out
+
+    return f
+
+
+# ------------------------------------------------------------- workloads
+@dataclasses.dataclass
+class Problem:
+    """Everything the method takes as input."""
+
+    name: str
+    mesh: Mesh
+    p: int
+    c_sigma: float
+    rho: np.ndarray                 # [n_cells] float64, piecewise constant
+    subdomain: np.ndarray           # [n_cells] int32 in 0..n_sub-1
+    q: int
+    coarse_of_cell: Optional[np.ndarray]   # nested: [n_cells] int32
+    coarse_mesh: Optional[Mesh]            # non-nested: independent mesh
+    f: Callable[[np.ndarray], np.ndarray]
+    rtol: float = 1e-8
+    max_iter: int = 20000
+
+    @property
+    def n_sub(self) -> int:
+        return int(self.subdomain.max()) + 1
+
+    @property
+    def n_p(self) -> int:
+        return (self.p + 1) * (self.p + 2) // 2
+
+    @property
+    def n_dofs(self) -> int:
+        return self.mesh.n_cells * self.n_p
+
+
+def squares_problem(nx: int, p: int, sub_block: int, coarse_block: Optional[int],
+                    q: Optional[int] = None, c_sigma: float = 10.0,
+                    f=f_sinsin, name: str = "squares") -> Problem:
+    """nx-by-nx squares; subdomains of sub_block^2 cells; nested coarse of
+    coarse_block^2 cells (None: one coarse cell per subdomain)."""
+    mesh = square_mesh(nx)
+    sub = block_partition_squares(nx, sub_block)
+    coarse = block_partition_squares(nx, coarse_block if coarse_block else sub_block)
+    return Problem(name=name, mesh=mesh, p=p, c_sigma=c_sigma,
+                   rho=np.ones(mesh.n_cells), subdomain=sub,
+                   q=p if q is None else q, coarse_of_cell=coarse, coarse_mesh=None, f=f)
+
+
+def voronoi_problem(n_cells: int, seed: int, p: int, bx: int, by: int, q: int,
+                    nonnested_coarse: int = 0, log10_rho_range: float = 0.0,
+                    f=f_sinsin, warped: bool = False, name: str = "voronoi") -> Problem:
+    rng = np.random.default_rng(seed)
+    mesh = voronoi_mesh(rng.random((n_cells, 2)))
+    coarse_mesh = None
+    if nonnested_coarse:
+        coarse_mesh = voronoi_mesh(rng.random((nonnested_coarse, 2)))
+    pts = mesh.vertex_mean()
+    sub = warped_bins_256(pts) if warped else bins_partition(pts, bx, by)
+    sub = compact_labels(sub)
+    n_sub = int(sub.max()) + 1
+    if log10_rho_range > 0.0:
+        rho_sub = 10.0 ** rng.uniform(-log10_rho_range, log10_rho_range, size=n_sub)
+        rho = rho_sub[sub]
+    else:
+        rho = np.ones(mesh.n_cells)
+    return Problem(name=name, mesh=mesh, p=p, c_sigma=10.0, rho=rho, subdomain=sub,
+                   q=q, coarse_of_cell=None if coarse_mesh is not None else sub.copy(),
+                   coarse_mesh=coarse_mesh, f=f)
+
+
+def make_config(name: str) -> Problem:
+    """The five named workloads (C1-C5 sample) plus small test variants."""
+    if name == "C1":
+        # 16x16 squares, p=1, 2x2 subdomains of 8x8, coarse = subdomains, q=1
+        return squares_problem(16, 1, 8, None, q=1, name="C1")
+    if name == "C2":
+        return voronoi_problem(16384, 1, p=2, bx=8, by=8, q=1, name="C2")
+    if name == "C3":
+        return voronoi_problem(65536, 2, p=3, bx=16, by=16, q=2, warped=True, name="C3")
+    if name == "C4":
+        return voronoi_problem(131072, 3, p=2, bx=32, by=16, q=1, nonnested_coarse=64,
+                               log10_rho_range=4.0, f=f_one, name="C4")
+    raise KeyError(name)
+
+
+def serving_requests(n_requests: int = 2000, seed: int = 5, n_min: int = 4096,
+                     n_max: int = 65536):
+    """Request descriptors for the serving workload: log-uniform cell count,
+    p in {1,2,3}, about 64 cells per subdomain, log10 rho ~ U[-2,2] per
+    subdomain, random sine-series RHS. Meshes are generated lazily from the
+    per-request seed so the stream itself stays small."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n_requests):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        p = int(rng.integers(1, 4))
+        reqs.append({"id": k, "n_cells": n, "p": p, "seed": int(rng.integers(1 << 31))})
+    return reqs
+
+
+def serving_problem(req: dict) -> Problem:
+    rng = np.random.default_rng(req["seed"])
+    n = req["n_cells"]
+    mesh = voronoi_mesh(rng.random((n, 2)))
+    b = max(1, int(round(math.sqrt(n) / 8)))
+    sub = compact_labels(bins_partition(mesh.vertex_mean(), b, b))
+    n_sub = int(sub.max()) + 1
+    rho = (10.0 ** rng.uniform(-2.0, 2.0, size=n_sub))[sub]
+    coef = rng.standard_normal((4, 4))
+    return Problem(name=f"req{req['id']}", mesh=mesh, p=req["p"], c_sigma=10.0, rho=rho,
+                   subdomain=sub, q=1, coarse_of_cell=sub.copy(), coarse_mesh=None,
+                   f=make_f_series(coef))

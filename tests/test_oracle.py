@@ -1,0 +1,382 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics (closed forms, invariants, printed values). CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as la
+import scipy.sparse.linalg as spla
+
+from paper_1903_11357_amd import inputs as I
+from oracle.basis import eval_basis, index_pairs, n_basis
+from oracle.clip import clip_convex
+from oracle.geometry import cell_geometry, mesh_faces, polygon_area_centroid
+from oracle.pcg import pcg
+from oracle.quadrature import gauss_legendre_01, segments_rule, triangles_rule
+from oracle.schwarz import (TwoLevelSchwarz, preconditioned_spectrum, prolongation_nested,
+                            prolongation_nonnested, subdomain_colouring, subdomain_dofs)
+from oracle.sipg import assemble, l2_and_broken_h1_error, mass_blocks
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ quadrature
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 7])
+def test_gauss_legendre_exact_to_2m_minus_1(m):
+    x, w = gauss_legendre_01(m)
+    for k in range(2 * m):
+        assert abs((w * x ** k).sum() - 1.0 / (k + 1)) < 1e-14
+    assert abs((w * x ** (2 * m)).sum() - 1.0 / (2 * m + 1)) > 1e-12
+
+
+def _green_moment(P, a, b):
+    """int_P x^a y^b dA = closed line integral of x^{a+1} y^b / (a+1) dy,
+    evaluated exactly with a high-order rule from numpy directly."""
+    t, wt = np.polynomial.legendre.leggauss(a + b + 4)
+    t = 0.5 * (t + 1.0)
+    wt = 0.5 * wt
+    s = 0.0
+    for i in range(len(P)):
+        p0, p1 = P[i], P[(i + 1) % len(P)]
+        x = p0[0] + t * (p1[0] - p0[0])
+        y = p0[1] + t * (p1[1] - p0[1])
+        s += (wt * x ** (a + 1) * y ** b / (a + 1)).sum() * (p1[1] - p0[1])
+    return s
+
+
+@pytest.mark.parametrize("m", [2, 3, 4, 5])
+def test_collapsed_triangle_rule_exact_to_2m_minus_2(m):
+    rng = np.random.default_rng(m)
+    T = rng.random((3, 2))
+    if (T[1, 0] - T[0, 0]) * (T[2, 1] - T[0, 1]) - (T[1, 1] - T[0, 1]) * (T[2, 0] - T[0, 0]) < 0:
+        T = T[[0, 2, 1]]
+    pts, w = triangles_rule(T[0:1], T[1:2], T[2:3], m)
+    pts, w = pts[0], w[0]
+    worst_fail = 0.0
+    for deg in range(2 * m):
+        for a in range(deg + 1):
+            b = deg - a
+            q = (w * pts[:, 0] ** a * pts[:, 1] ** b).sum()
+            ex = _green_moment(T, a, b)
+            if deg <= 2 * m - 2:
+                assert abs(q - ex) <= 1e-13 * max(1.0, abs(ex)), (deg, a, b)
+            else:
+                worst_fail = max(worst_fail, abs(q - ex))
+    assert worst_fail > 1e-12  # not exact one degree higher
+
+
+def test_segment_rule_length_and_moments():
+    p0 = np.array([[0.2, 0.1]])
+    p1 = np.array([[0.7, 0.5]])
+    pts, w = segments_rule(p0, p1, 3)
+    assert abs(w.sum() - math.hypot(0.5, 0.4)) < 1e-15
+
+
+# ------------------------------------------------------------ geometry
+def test_polygon_area_centroid_closed_forms():
+    R = np.array([[0.1, 0.2], [0.6, 0.2], [0.6, 0.5], [0.1, 0.5]])
+    a, c = polygon_area_centroid(R)
+    assert abs(a - 0.15) < 1e-15 and np.allclose(c, [0.35, 0.35], atol=1e-15)
+    T = np.array([[0.0, 0.0], [1.0, 0.2], [0.3, 0.9]])
+    a, c = polygon_area_centroid(T)
+    assert abs(a - 0.5 * (1.0 * 0.9 - 0.2 * 0.3)) < 1e-15
+    assert np.allclose(c, T.mean(0), atol=1e-15)
+
+
+def test_voronoi_mesh_conforming_and_covers_square():
+    rng = np.random.default_rng(11)
+    mesh = I.voronoi_mesh(rng.random((500, 2)))
+    geo = cell_geometry(mesh)
+    assert (geo.area > 0).all()
+    assert abs(geo.area.sum() - 1.0) < 1e-12
+    faces = mesh_faces(mesh)  # raises on non-conforming edges
+    bd = faces.minus < 0
+    L = np.linalg.norm(mesh.xy[faces.v1[bd]] - mesh.xy[faces.v0[bd]], axis=1)
+    assert abs(L.sum() - 4.0) < 1e-12
+    # Euler characteristic of a disc: V - E + F = 1
+    assert mesh.n_vertices - len(faces.plus) + mesh.n_cells == 1
+
+
+# ------------------------------------------------------------ basis
+def test_basis_orthonormal_on_rectangle():
+    p = 4
+    box = np.array([0.2, 0.5, 0.1, 0.3])
+    R = np.array([[0.2, 0.1], [0.5, 0.1], [0.5, 0.3], [0.2, 0.3]])
+    c = R.mean(0)
+    a = np.repeat(c[None], 4, 0)
+    pts, w = triangles_rule(a, R, np.roll(R, -1, 0), p + 2)
+    val, _ = eval_basis(p, box, pts.reshape(-1, 2))
+    M = np.einsum("q,qa,qb->ab", w.ravel(), val, val)
+    assert np.allclose(M, np.eye(n_basis(p)), atol=1e-13)
+
+
+def test_basis_gradient_matches_finite_difference():
+    p = 3
+    box = np.array([0.1, 0.4, 0.3, 0.9])
+    x = np.array([[0.23, 0.51]])
+    v, g = eval_basis(p, box, x)
+    eps = 1e-6
+    for d in range(2):
+        e = np.zeros(2)
+        e[d] = eps
+        vp, _ = eval_basis(p, box, x + e)
+        vm, _ = eval_basis(p, box, x - e)
+        assert np.allclose((vp - vm) / (2 * eps), g[..., d], rtol=1e-6, atol=1e-6)
+
+
+def test_basis_spans_total_degree_polynomials():
+    p = 3
+    rng = np.random.default_rng(3)
+    mesh = I.voronoi_mesh(rng.random((30, 2)))
+    geo = cell_geometry(mesh)
+    k = 7
+    P = mesh.xy[mesh.cell(k)]
+    a = np.repeat(geo.centroid[k][None], len(P), 0)
+    pts, w = triangles_rule(a, P, np.roll(P, -1, 0), p + 2)
+    pts, w = pts.reshape(-1, 2), w.ravel()
+    val, _ = eval_basis(p, geo.box[k], pts)
+    M = np.einsum("q,qa,qb->ab", w, val, val)
+    test_pts = geo.centroid[k] + 0.01 * rng.standard_normal((5, 2))
+    tv, _ = eval_basis(p, geo.box[k], test_pts)
+    for (i, j) in index_pairs(p):
+        g = pts[:, 0] ** i * pts[:, 1] ** j
+        coef = np.linalg.solve(M, val.T @ (w * g))
+        assert np.allclose(tv @ coef, test_pts[:, 0] ** i * test_pts[:, 1] ** j, atol=1e-11)
+
+
+# ------------------------------------------------------------ SIPG matrix
+def _small_voronoi_problem(n=120, p=2, jumps=True, seed=5):
+    rng = np.random.default_rng(seed)
+    mesh = I.voronoi_mesh(rng.random((n, 2)))
+    rho = 10.0 ** rng.uniform(-3, 3, n) if jumps else np.ones(n)
+    return mesh, rho
+
+
+def test_sipg_symmetric_positive_definite():
+    mesh, rho = _small_voronoi_problem()
+    A, b, geo, faces = assemble(mesh, 2, rho, 10.0, I.f_one)
+    Ad = A.toarray()
+    assert np.abs(Ad - Ad.T).max() <= 1e-13 * np.abs(Ad).max()
+    la.cholesky(Ad, lower=True)  # raises if not SPD
+    assert la.eigvalsh(Ad).min() > 0.0
+
+
+def test_sipg_constant_in_kernel_of_interior_rows():
+    mesh, rho = _small_voronoi_problem(p=2)
+    p = 2
+    npb = n_basis(p)
+    A, _, geo, faces = assemble(mesh, p, rho, 10.0)
+    # coefficients of the global constant 1: phi_0 = 1/sqrt(dx dy)
+    one = np.zeros(mesh.n_cells * npb)
+    dx = geo.box[:, 1] - geo.box[:, 0]
+    dy = geo.box[:, 3] - geo.box[:, 2]
+    one[::npb] = np.sqrt(dx * dy)
+    r = (A @ one).reshape(-1, npb)
+    touches = np.zeros(mesh.n_cells, dtype=bool)
+    touches[faces.plus[faces.minus < 0]] = True
+    row_scale = abs(A).max(axis=1).toarray().reshape(-1, npb).max(axis=1)
+    assert (np.abs(r[~touches]).max(axis=1) / row_scale[~touches]).max() < 1e-12
+    assert (np.abs(r[touches]).max(axis=1) / row_scale[touches]).min() > 1e-4
+
+
+def test_sipg_penalty_is_harmonic_in_rho():
+    """Scaling rho by c scales A by c (every term is linear in rho)."""
+    mesh, rho = _small_voronoi_problem(p=1)
+    A1, *_ = assemble(mesh, 1, rho, 10.0)
+    A2, *_ = assemble(mesh, 1, 7.0 * rho, 10.0)
+    assert abs(A2 - 7.0 * A1).max() < 1e-12 * abs(A2).max()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_manufactured_solution_rates_on_squares(p):
+    errs = []
+    hs = []
+    for nx in (4, 8, 16):
+        P = I.squares_problem(nx, p, nx, None, q=1)
+        A, b, geo, _ = assemble(P.mesh, p, P.rho, 10.0, I.f_sinsin)
+        x = spla.spsolve(A.tocsc(), b)
+        e0, e1 = l2_and_broken_h1_error(P.mesh, p, geo, x, I.u_sinsin, I.grad_u_sinsin)
+        errs.append((e0, e1))
+        hs.append(1.0 / nx)
+    r0 = [math.log(errs[i][0] / errs[i + 1][0]) / math.log(2) for i in range(2)]
+    r1 = [math.log(errs[i][1] / errs[i + 1][1]) / math.log(2) for i in range(2)]
+    assert r0[-1] > p + 1 - 0.25, r0
+    assert r1[-1] > p - 0.25, r1
+
+
+def test_manufactured_solution_rate_on_voronoi():
+    p = 1
+    errs, hs = [], []
+    for n in (64, 256, 1024):
+        rng = np.random.default_rng(100 + n)
+        mesh = I.voronoi_mesh(rng.random((n, 2)))
+        A, b, geo, _ = assemble(mesh, p, np.ones(n), 10.0, I.f_sinsin)
+        x = spla.spsolve(A.tocsc(), b)
+        e0, _ = l2_and_broken_h1_error(mesh, p, geo, x, I.u_sinsin, I.grad_u_sinsin)
+        errs.append(e0)
+        hs.append(n ** -0.5)
+    rate = math.log(errs[1] / errs[2]) / math.log(hs[1] / hs[2])
+    assert rate > 1.7, rate
+
+
+# ------------------------------------------------------------ Schwarz
+def _schwarz_problem(nloc=4, coarse=True, q=1):
+    rng = np.random.default_rng(21)
+    mesh = I.voronoi_mesh(rng.random((144, 2)))
+    sub = I.compact_labels(I.bins_partition(mesh.vertex_mean(), nloc, nloc))
+    rho = np.ones(mesh.n_cells)
+    A, b, geo, faces = assemble(mesh, 1, rho, 10.0, I.f_sinsin)
+    M = TwoLevelSchwarz(A, mesh, 1, geo, sub, q=q, coarse_of_cell=sub, coarse=coarse)
+    return mesh, sub, A, b, geo, M
+
+
+def test_local_matrices_are_principal_submatrices_and_decouple():
+    mesh, sub, A, b, geo, M = _schwarz_problem()
+    Ad = A.toarray()
+    dofs = subdomain_dofs(sub, 3)
+    for d, (c, low) in zip(dofs, M.factors):
+        L = np.tril(c)
+        assert np.allclose(L @ L.T, Ad[np.ix_(d, d)], rtol=0, atol=1e-12 * np.abs(Ad).max())
+    colour, adj = subdomain_colouring(A, sub, 3)
+    for i in range(len(dofs)):
+        for j in range(len(dofs)):
+            if i != j and j not in adj[i]:
+                assert np.all(Ad[np.ix_(dofs[i], dofs[j])] == 0.0)
+
+
+def test_preconditioned_spectrum_within_colour_bound():
+    mesh, sub, A, b, geo, M = _schwarz_problem()
+    ev = preconditioned_spectrum(A, M.dense_inverse())
+    colour, _ = subdomain_colouring(A, sub, 3)
+    chi = colour.max() + 1
+    assert ev.min() > 0.0
+    assert ev.max() <= chi + 1 + 1e-9, (ev.max(), chi)
+
+
+def test_one_subdomain_plus_coarse_spectrum_is_one_and_two():
+    mesh, sub, A, b, geo, M = _schwarz_problem(nloc=1)
+    ev = preconditioned_spectrum(A, M.dense_inverse())
+    assert np.all((np.abs(ev - 1.0) < 1e-9) | (np.abs(ev - 2.0) < 1e-9))
+    x, info = pcg(A, b, M.apply, rtol=1e-8)
+    assert info.iterations <= 3
+    mesh, sub, A, b, geo, M = _schwarz_problem(nloc=1, coarse=False)
+    x, info = pcg(A, b, M.apply, rtol=1e-8)
+    assert info.iterations == 1
+
+
+def test_pcg_matches_direct_solve_and_lanczos_matches_dense():
+    mesh, sub, A, b, geo, M = _schwarz_problem()
+    x, info = pcg(A, b, M.apply, rtol=1e-12)
+    xd = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert info.true_rel_res < 1e-11
+    ev = preconditioned_spectrum(A, M.dense_inverse())
+    assert abs(info.condition_estimate() / (ev.max() / ev.min()) - 1.0) < 0.01
+
+
+def test_nested_prolongation_is_injection():
+    mesh, sub, A, b, geo, M = _schwarz_problem(q=1)
+    rng = np.random.default_rng(2)
+    v0 = rng.standard_normal(M.P0.shape[1])
+    vh = M.P0 @ v0
+    # compare pointwise inside every fine cell
+    pts = geo.centroid + 0.1 * (geo.box[:, [1, 3]] - geo.box[:, [0, 2]]) * 0.3
+    fv, _ = eval_basis(1, geo.box, pts)
+    cv, _ = eval_basis(1, M.cbox[sub], pts)
+    fine = (fv * vh.reshape(-1, 3)).sum(1)
+    coarse = (cv * v0.reshape(-1, 3)[sub]).sum(1)
+    assert np.allclose(fine, coarse, atol=1e-12)
+
+
+def _nonnested_setup(p=2, q=1):
+    rng = np.random.default_rng(8)
+    mesh = I.voronoi_mesh(rng.random((200, 2)))
+    cmesh = I.voronoi_mesh(rng.random((9, 2)))
+    geo = cell_geometry(mesh)
+    P0, cbox = prolongation_nonnested(mesh, p, q, geo, cmesh)
+    return mesh, cmesh, geo, P0, cbox
+
+
+def test_clipping_areas_partition_cells():
+    rng = np.random.default_rng(8)
+    mesh = I.voronoi_mesh(rng.random((200, 2)))
+    cmesh = I.voronoi_mesh(rng.random((9, 2)))
+    geo = cell_geometry(mesh)
+    cgeo = cell_geometry(cmesh)
+    tot_f = np.zeros(mesh.n_cells)
+    tot_c = np.zeros(cmesh.n_cells)
+    for k in range(mesh.n_cells):
+        for j in range(cmesh.n_cells):
+            Q = clip_convex(mesh.xy[mesh.cell(k)], cmesh.xy[cmesh.cell(j)])
+            if Q.shape[0] >= 3:
+                a, _ = polygon_area_centroid(Q)
+                tot_f[k] += a
+                tot_c[j] += a
+    assert np.allclose(tot_f, geo.area, rtol=1e-12, atol=1e-15)
+    assert np.allclose(tot_c, cgeo.area, rtol=1e-12, atol=1e-15)
+    S1 = np.array([[0, 0], [2, 0], [2, 1], [0, 1]], dtype=float)
+    S2 = np.array([[1, 0.5], [3, 0.5], [3, 2], [1, 2]], dtype=float)
+    a, _ = polygon_area_centroid(clip_convex(S1, S2))
+    assert abs(a - 0.5) < 1e-15
+
+
+def test_nonnested_prolongation_reproduces_global_polynomials_and_integrals():
+    p, q = 2, 1
+    mesh, cmesh, geo, P0, cbox = _nonnested_setup(p, q)
+    rng = np.random.default_rng(4)
+    # a global linear polynomial, written in every coarse cell's own basis
+    c = rng.standard_normal(3)
+    g = lambda X: c[0] + c[1] * X[:, 0] + c[2] * X[:, 1]
+    nq = n_basis(q)
+    v0 = np.zeros(cmesh.n_cells * nq)
+    for j in range(cmesh.n_cells):
+        pts = np.array([[cbox[j, 0], cbox[j, 2]], [cbox[j, 1], cbox[j, 2]], [cbox[j, 0], cbox[j, 3]]])
+        V, _ = eval_basis(q, cbox[j], pts)
+        v0[j * nq:(j + 1) * nq] = np.linalg.solve(V, g(pts))
+    vh = (P0 @ v0).reshape(-1, n_basis(p))
+    pts = geo.centroid + 0.2 * (mesh.xy[mesh.cell_vertices[mesh.cell_ptr[:-1]]] - geo.centroid)
+    fv, _ = eval_basis(p, geo.box, pts)
+    assert np.allclose((fv * vh).sum(1), g(pts), atol=1e-11)
+    # integrals are preserved for an arbitrary (discontinuous) coarse function
+    v0 = rng.standard_normal(cmesh.n_cells * nq)
+    vh = P0 @ v0
+    M = mass_blocks(mesh, p, geo)
+    one_f = np.zeros(mesh.n_cells * n_basis(p))
+    dx = geo.box[:, 1] - geo.box[:, 0]
+    dy = geo.box[:, 3] - geo.box[:, 2]
+    # int_Omega v_h = sum_k int_k v_h = sum_k coef_k . (M_k e_const) * sqrt(dx dy)
+    int_fine = sum((M[k] @ vh.reshape(-1, n_basis(p))[k])[0] * np.sqrt(dx[k] * dy[k]) for k in range(mesh.n_cells))
+    cgeo = cell_geometry(cmesh)
+    cdx = cbox[:, 1] - cbox[:, 0]
+    cdy = cbox[:, 3] - cbox[:, 2]
+    Mc = mass_blocks(cmesh, q, cgeo)
+    int_coarse = sum((Mc[j] @ v0.reshape(-1, nq)[j])[0] * np.sqrt(cdx[j] * cdy[j]) for j in range(cmesh.n_cells))
+    assert abs(int_fine - int_coarse) < 1e-12 * max(1.0, abs(int_coarse))
+
+
+# ------------------------------------------------------------ printed values
+def _read_fig6():
+    rows = []
+    with open(os.path.join(GOLDEN, "example5_fig6.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            nx, cb, p, K = line.split()
+            rows.append((int(nx), int(cb), int(p), float(K)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _read_fig6(), ids=lambda r: f"n{r[0]}_p{r[2]}")
+def test_example5_printed_condition_numbers(row):
+    """Massively parallel setting (subdomain = element), nested square
+    coarse mesh with H = 4h, q = p, f = 1: the Lanczos estimate from ASPCG
+    reproduces the printed K(P_ad) to 0.1%."""
+    nx, cb, p, K = row
+    P = I.squares_problem(nx, p, 1, cb, q=p, f=I.f_one)
+    P.subdomain = np.arange(nx * nx, dtype=np.int32)
+    A, b, geo, _ = assemble(P.mesh, p, P.rho, 10.0, P.f)
+    M = TwoLevelSchwarz(A, P.mesh, p, geo, P.subdomain, q=p, coarse_of_cell=P.coarse_of_cell)
+    x, info = pcg(A, b, M.apply, rtol=1e-8)
+    assert info.converged
+    assert abs(info.condition_estimate() / K - 1.0) < 1e-3, info.condition_estimate()
