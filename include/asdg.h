@@ -1,0 +1,198 @@
+/*
+ * asdg.h -- C ABI of the MI355X two-level additive Schwarz PCG library for
+ * symmetric interior penalty DG (SIPG) discretisations of
+ *     -div(rho grad u) = f in (0,1)^2,  u = 0 on the boundary,
+ * on conforming polygonal meshes.
+ *
+ * Method (Antonietti, Houston, Pennesi, Suli, arXiv:1903.11357):
+ *   - SIPG bilinear form, Sec. 2 eq. (Ah) with the weighted-average lifting
+ *     of eq. (lifting), omega = rho^-/(rho^+ + rho^-), penalty eq. (Sigma)
+ *     sigma_F = C_sigma <rho>_F p^2 / <h>_F (harmonic averages, h = cell
+ *     diameter), space V_h of eq. (Vh) (total degree p >= 1);
+ *   - additive Schwarz operator P_ad = sum_{i=0}^{N} P_i of Sec. 3 with exact
+ *     local solvers on non-overlapping subdomains (unions of fine cells) and
+ *     a coarse space V_0 of degree q (1 <= q <= p) on a coarse mesh that is
+ *     either nested (agglomerates) or independent (non-nested), coupled by the
+ *     L2 prolongation R_0^T of eq. (R0T) and the Galerkin operator of
+ *     eq. (A0);
+ *   - conjugate gradients preconditioned by P_ad from a zero initial guess,
+ *     stopped on the Euclidean norm of the relative residual (Sec. 7).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every call returns ASDG_OK (0) or a negative asdg_status; a
+ *     message is then available from asdg_last_error(). No exception or
+ *     signal crosses the ABI.
+ *   - Host pointers are read only during the call; the library copies what
+ *     it keeps. Device pointers are hipMalloc'd (or torch) device memory on
+ *     the current HIP device and must stay valid until the stream work that
+ *     uses them has finished.
+ *   - Device memory is owned by the caller: asdg_plan() reports four byte
+ *     counts, the caller allocates them and hands them over with asdg_bind().
+ *     The library never allocates device memory itself.
+ *   - Streams are passed as void* holding a hipStream_t (NULL = default
+ *     stream). All device work of a call is enqueued on that stream.
+ *   - Vector layout: x[c * n_p + k] for cell c in the caller's cell order and
+ *     basis index k; the basis on a cell with bounding box [x0,x1]x[y0,y1] is
+ *     sqrt((2i+1)(2j+1)/(dx dy)) L_i(2(x-xc)/dx) L_j(2(y-yc)/dy), i+j <= p,
+ *     ordered by degree d = i+j, then by j = 0..d (Legendre L_k).
+ *   - A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef ASDG_H
+#define ASDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ASDG_OK = 0,
+  ASDG_EINVAL = -1,      /* invalid argument, mesh or partition            */
+  ASDG_ENOMEM = -2,      /* bound buffer smaller than asdg_plan() reported */
+  ASDG_ENOTSPD = -3,     /* Cholesky pivot <= 0 or NaN (failed_subdomain)  */
+  ASDG_ENOCONV = -4,     /* max_iter reached; x and stats still written    */
+  ASDG_EBREAKDOWN = -5,  /* p.Ap <= 0 or NaN inside PCG                    */
+  ASDG_EHIP = -6,        /* a HIP runtime call failed                      */
+  ASDG_ESTATE = -7       /* call out of order (e.g. solve before factor)   */
+} asdg_status;
+
+typedef enum {
+  ASDG_FP64 = 0,        /* local factors and sweeps in FP64                 */
+  ASDG_FP32_LOCAL = 1   /* local factors/sweeps in FP32 (MFMA FP32 accumulate);
+                           outer PCG, dot products, coarse solve in FP64     */
+} asdg_precision;
+
+typedef struct asdg_problem asdg_problem;
+
+/* Conforming polygon mesh of the unit square: cell c has the vertices
+ * cell_vertices[cell_ptr[c] .. cell_ptr[c+1]-1] in counter-clockwise order;
+ * neighbouring cells share vertex ids (no hanging nodes). Cells must be
+ * convex when used as a non-nested coarse mesh. */
+typedef struct {
+  int32_t n_vertices;
+  const double* xy;              /* [n_vertices][2]                         */
+  int32_t n_cells;
+  const int32_t* cell_ptr;       /* [n_cells + 1]                           */
+  const int32_t* cell_vertices;  /* [cell_ptr[n_cells]]                     */
+} asdg_mesh;
+
+/* Vectorised right-hand side: out[k] = f(xy[2k], xy[2k+1]) for k < n. */
+typedef void (*asdg_field_fn)(int64_t n, const double* xy, double* out, void* user);
+
+typedef struct {
+  double rtol;          /* stop when ||r_k||_2 <= rtol * ||b||_2 (Sec. 7: 1e-8) */
+  int32_t max_iter;     /* >= 1                                            */
+  int32_t check_every;  /* iterations per captured graph replay (>= 1)     */
+  int32_t use_graph;    /* 1: replay a captured hipGraph, 0: eager launches */
+  int32_t time_kernels; /* 1: time the local-solve kernel with HIP events  */
+} asdg_pcg_opts;
+
+typedef struct {
+  int32_t iterations;      /* CG iterations taken                          */
+  int32_t converged;       /* 1 if ||r|| <= rtol ||b||                     */
+  double rel_res;          /* recursive ||r_k|| / ||b||                    */
+  double lambda_min;       /* Lanczos extreme eigenvalue estimates of      */
+  double lambda_max;       /*   P^{-1} A from the CG coefficients          */
+  double t_solve_ms;       /* wall time of the solve on the stream         */
+  double t_local_ms;       /* summed local-solve kernel time (time_kernels) */
+  int32_t n_local;         /* number of timed local-solve launches         */
+  int32_t failed_subdomain;/* ENOTSPD: subdomain index, -1 = coarse        */
+} asdg_pcg_stats;
+
+/* Handle lifetime. asdg_destroy(NULL) is a no-op. */
+asdg_status asdg_create(asdg_problem** out);
+void asdg_destroy(asdg_problem* pb);
+const char* asdg_last_error(const asdg_problem* pb);
+
+/* Host-side SIPG assembly (Sec. 2, eqs. (Ah), (lifting), (Sigma)).
+ * fine:      the fine mesh T_h.
+ * p:         polynomial degree, 1 <= p <= 4.
+ * c_sigma:   penalty constant C_sigma > 0 (the paper's experiments use 10).
+ * rho:       [n_cells] cell-wise constant coefficient, > 0 (Remark 2.1).
+ * subdomain: [n_cells] subdomain id of each cell in 0..n_sub-1, every id used
+ *            (the partition T_Hcal of Sec. 3 into unions of fine cells).
+ * f, f_user: right-hand side, integrated with the cell quadrature.
+ * Errors: EINVAL for p or c_sigma out of range, non-positive rho, a
+ * clockwise or degenerate cell, an edge shared by more than two cells or an
+ * unmatched edge inside the square, or an unused subdomain id. */
+asdg_status asdg_assemble(asdg_problem* pb, const asdg_mesh* fine, int32_t p, double c_sigma,
+                          const double* rho, const int32_t* subdomain, asdg_field_fn f,
+                          void* f_user);
+
+/* Coarse space choice and device footprint (Sec. 3, V_0, eqs. (R0T), (A0)).
+ * precision:      local factor precision.
+ * q:              coarse degree, 1 <= q <= p; q = 0 disables the coarse level
+ *                 (one-level method).
+ * coarse_of_cell: [n_cells] nested coarse partition (coarse cell id of each
+ *                 fine cell), or NULL when coarse_mesh is given.
+ * coarse_mesh:    independent convex coarse mesh (non-nested case), or NULL.
+ * bytes[4]:       out: sizes of the operator, factor, coarse and scratch
+ *                 buffers the caller must allocate for asdg_bind().
+ * The coarse transfer (L2 projection, exact convex clipping when non-nested)
+ * and the Galerkin A_0 = P_0^T A P_0 are formed here on the host. */
+asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q,
+                      const int32_t* coarse_of_cell, const asdg_mesh* coarse_mesh,
+                      size_t bytes[4]);
+
+/* Hands over caller-owned device buffers (sizes >= bytes[] from asdg_plan,
+ * 256-byte aligned) and uploads the operator and coarse data on stream.
+ * Errors: ENOMEM if a size is too small, EHIP on copy failure. */
+asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes[4],
+                      void* stream);
+
+/* Forms every A_i = R_i A R_i^T (principal submatrix, Sec. 3 local solvers)
+ * in tile-packed form and Cholesky-factorises all of them in one persistent
+ * launch (MFMA). Synchronises the stream to read the status word.
+ * Errors: ENOTSPD with failed_subdomain() = index. */
+asdg_status asdg_factor(asdg_problem* pb, void* stream);
+
+/* Uploads A_0 and factorises it in FP64 on the device (eq. (A0)).
+ * Errors: ENOTSPD (coarse), ESTATE before asdg_bind(). */
+asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream);
+
+/* Preconditioned CG (Sec. 7 protocol, x_0 = 0).
+ * d_b:  [n] device right-hand side in caller layout, or NULL for the
+ *       assembled load vector.
+ * d_x:  [n] device output, caller layout.
+ * opts: NULL = {1e-8, 20000, 16, 1, 0}.
+ * stats: optional output.
+ * Errors: ENOCONV (x written), EBREAKDOWN, ESTATE if not factored. */
+asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x,
+                           const asdg_pcg_opts* opts, asdg_pcg_stats* stats, void* stream);
+
+/* Single applications of hot-path steps on device vectors in caller layout,
+ * for verification and benchmarking (what = ASDG_APPLY_*):
+ *   OPERATOR: out = A in                       (SIPG operator, eq. (Ah))
+ *   LOCAL:    out = sum_i R_i^T A_i^{-1} R_i in (local solvers, Sec. 3)
+ *   COARSE:   out = P_0 A_0^{-1} P_0^T in       (coarse correction, Sec. 3)
+ *   PRECOND:  out = LOCAL + COARSE              (the preconditioner)  */
+enum { ASDG_APPLY_OPERATOR = 0, ASDG_APPLY_LOCAL = 1, ASDG_APPLY_COARSE = 2,
+       ASDG_APPLY_PRECOND = 3 };
+asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, double* d_out,
+                       void* stream);
+
+/* Problem sizes: info[0] = n_cells, [1] = n_p, [2] = n (DoFs), [3] = n_sub,
+ * [4] = n0 (coarse DoFs), [5] = nnz blocks of A, [6] = max subdomain DoFs,
+ * [7] = tile size of the local factors. */
+asdg_status asdg_info(const asdg_problem* pb, int64_t info[8]);
+
+/* Host copies for verification, caller layout:
+ *   asdg_export_rhs:      b [n]
+ *   asdg_export_operator: A as COO triplets of its blocks; rows/cols/vals
+ *                         have room for nnzb * n_p^2 entries (info[5]).
+ *   asdg_export_coarse:   A_0 dense row-major [n0 * n0] (host-formed). */
+asdg_status asdg_export_rhs(const asdg_problem* pb, double* b);
+asdg_status asdg_export_operator(const asdg_problem* pb, int64_t* rows, int64_t* cols,
+                                 double* vals);
+asdg_status asdg_export_coarse(const asdg_problem* pb, double* a0);
+
+/* Subdomain index of the last ENOTSPD failure (-1 = coarse, -2 = none). */
+int32_t asdg_failed_subdomain(const asdg_problem* pb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASDG_H */

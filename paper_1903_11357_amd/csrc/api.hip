@@ -1,0 +1,760 @@
+// C ABI of libasdg: problem handle, device-buffer planning, factorisation,
+// coarse setup and the preconditioned CG driver (Sec. 7 protocol).
+//
+// Device memory is caller-owned (four buffers, sizes from asdg_plan). The
+// CG loop runs entirely on the device: every kernel reads the iteration
+// state (iteration count, done flag, CG scalars) from device memory, so a
+// chunk of `check_every` iterations can be captured once as a hipGraph and
+// replayed; the host reads the state back only between replays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "asdg.h"
+#include "discretize.h"
+#include "kernels.h"
+
+using namespace asdg;
+
+namespace {
+
+struct Layout {
+  size_t size = 0;
+  size_t add(size_t bytes) {
+    size_t o = (size + 255) & ~(size_t)255;
+    size = o + std::max<size_t>(bytes, 1);
+    return o;
+  }
+};
+
+// Extreme eigenvalues of the symmetric tridiagonal matrix (d, e) by Sturm
+// bisection (count of eigenvalues below x from the LDL^T pivots).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < d.size(); ++i) {
+    double off = i ? e[i - 1] * e[i - 1] : 0.0;
+    q = d[i] - x - (i ? off / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double& lmin, double& lmax) {
+  size_t k = d.size();
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < k; ++i) {
+    double r = (i ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto kth = [&](int target) {  // smallest x with count(x) >= target
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      double m = 0.5 * (a + b);
+      if (sturm_count(d, e, m) >= target) b = m; else a = m;
+      if (b - a <= 1e-15 * std::max(std::fabs(a), std::fabs(b))) break;
+    }
+    return 0.5 * (a + b);
+  };
+  lmin = kth(1);
+  lmax = kth((int)k);
+}
+
+// Copy of a caller mesh (the fine mesh is needed again by asdg_plan).
+struct MeshCopy {
+  std::vector<double> xy;
+  std::vector<int32_t> ptr, verts;
+  void assign(const asdg_mesh& m) {
+    xy.assign(m.xy, m.xy + 2 * (size_t)m.n_vertices);
+    ptr.assign(m.cell_ptr, m.cell_ptr + m.n_cells + 1);
+    verts.assign(m.cell_vertices, m.cell_vertices + m.cell_ptr[m.n_cells]);
+  }
+  MeshView view() const {
+    return MeshView{(int32_t)(xy.size() / 2), xy.data(), (int32_t)ptr.size() - 1, ptr.data(), verts.data()};
+  }
+};
+
+}  // namespace
+
+struct asdg_problem {
+  std::string err;
+  MeshCopy fine;
+  int stage = 0;  // 1 assembled, 2 planned, 3 bound, 4 factored
+  bool coarse_ready = false;
+  Assembled A;
+  Coarse C;
+  bool has_coarse = false;
+  int f32 = 0;
+  int32_t n0 = 0;
+  std::vector<double> rhs_caller;
+  // local factor planning
+  std::vector<SubDesc> subs;
+  std::vector<int4> tile_meta, chol_tasks, trsv_tasks;
+  int64_t n_tiles = 0;
+  int32_t max_n = 0;
+  // coarse factor planning
+  SubDesc csub{0, 0, 0, 0};
+  std::vector<int4> cchol_tasks, ctrsv_tasks;
+  std::vector<double> ctiles_host;
+  int64_t n_ctiles = 0;
+  // buffer layout
+  struct { size_t row_ptr, col, blocks, rhs, perm; } o0{};
+  struct { size_t tiles, subs, chol, trsv, meta; } o1{};
+  struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv; } o2{};
+  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, ppq, prr, prz, pbb, st, rz2, ah, bh, flags; } o3{};
+  size_t bytes[4] = {0, 0, 0, 0};
+  char* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t failed_sub = -2;
+  int n_cu = 256;
+  // captured iteration chunk
+  hipGraphExec_t gexec = nullptr;
+  int g_k = 0, g_timed = 0;
+  hipStream_t own_stream = nullptr;
+  std::vector<hipEvent_t> ev;  // 2 per captured iteration (local solve start/end)
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+
+  template <class T>
+  T* ptr(int b, size_t off) const { return reinterpret_cast<T*>(buf[b] + off); }
+  int64_t n() const { return (int64_t)A.n_cells * A.np; }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    g_k = 0;
+  }
+  ~asdg_problem() {
+    drop_graph();
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
+};
+
+#define FAIL(pb, code, msg) \
+  do {                      \
+    (pb)->err = (msg);      \
+    return (code);          \
+  } while (0)
+#define HIPCHK(pb, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) FAIL(pb, ASDG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+asdg_status asdg_create(asdg_problem** out) {
+  if (!out) return ASDG_EINVAL;
+  *out = new (std::nothrow) asdg_problem();
+  return *out ? ASDG_OK : ASDG_ENOMEM;
+}
+
+void asdg_destroy(asdg_problem* pb) { delete pb; }
+
+const char* asdg_last_error(const asdg_problem* pb) { return pb ? pb->err.c_str() : "null handle"; }
+
+asdg_status asdg_assemble(asdg_problem* pb, const asdg_mesh* fine, int32_t p, double c_sigma, const double* rho,
+                          const int32_t* subdomain, asdg_field_fn f, void* f_user) {
+  if (!pb) return ASDG_EINVAL;
+  if (!fine || !fine->xy || !fine->cell_ptr || !fine->cell_vertices || !rho || !subdomain || fine->n_cells < 1)
+    FAIL(pb, ASDG_EINVAL, "null or empty input");
+  pb->drop_graph();
+  pb->stage = 0;
+  pb->coarse_ready = false;
+  MeshView mv{fine->n_vertices, fine->xy, fine->n_cells, fine->cell_ptr, fine->cell_vertices};
+  std::string e = assemble_sipg(mv, p, c_sigma, rho, subdomain, f, f_user, pb->A);
+  if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
+  const int np = pb->A.np;
+  pb->rhs_caller.assign(pb->A.rhs.size(), 0.0);
+  for (int32_t r = 0; r < pb->A.n_cells; ++r)
+    for (int a = 0; a < np; ++a) pb->rhs_caller[(size_t)pb->A.perm[r] * np + a] = pb->A.rhs[(size_t)r * np + a];
+  pb->fine.assign(*fine);  // kept for the coarse transfer
+  pb->stage = 1;
+  return ASDG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void plan_local(asdg_problem* pb) {
+  const Assembled& A = pb->A;
+  const int np = A.np;
+  const int32_t ns = A.n_sub;
+  pb->subs.resize(ns);
+  int64_t tiles = 0;
+  int nbmax = 0;
+  pb->max_n = 0;
+  for (int32_t i = 0; i < ns; ++i) {
+    SubDesc& s = pb->subs[i];
+    s.dof0 = A.sub_ptr[i] * np;
+    s.n = (A.sub_ptr[i + 1] - A.sub_ptr[i]) * np;
+    s.nb = (s.n + TILE - 1) / TILE;
+    s.tile0 = (int32_t)tiles;
+    tiles += (int64_t)s.nb * (s.nb + 1) / 2;
+    nbmax = std::max(nbmax, s.nb);
+    pb->max_n = std::max(pb->max_n, s.n);
+  }
+  pb->n_tiles = tiles;
+  pb->tile_meta.clear();
+  pb->tile_meta.reserve(tiles);
+  for (int32_t i = 0; i < ns; ++i)
+    for (int b = 0; b < pb->subs[i].nb; ++b)
+      for (int j = 0; j <= b; ++j) pb->tile_meta.push_back(make_int4(i, b, j, 0));
+  // factorisation tasks: (i, j, b) ordered by (nbmax - nb_i + j, i, b); every
+  // dependency (same i, smaller column, or same column and b' = j < b) comes first
+  struct K { int64_t key; int4 t; };
+  std::vector<K> ks;
+  ks.reserve(tiles);
+  for (int32_t i = 0; i < ns; ++i) {
+    int nb = pb->subs[i].nb;
+    for (int j = 0; j < nb; ++j)
+      for (int b = j; b < nb; ++b)
+        ks.push_back({(((int64_t)(nbmax - nb + j) * ns + i) << 20) | b, make_int4(i, j, b, 0)});
+  }
+  std::stable_sort(ks.begin(), ks.end(), [](const K& a, const K& b) { return a.key < b.key; });
+  pb->chol_tasks.resize(ks.size());
+  for (size_t k = 0; k < ks.size(); ++k) pb->chol_tasks[k] = ks[k].t;
+  // sweep tasks: forward b at step off+b, backward b at step off+2nb-1-b
+  ks.clear();
+  for (int32_t i = 0; i < ns; ++i) {
+    int nb = pb->subs[i].nb;
+    int64_t off = 2 * (int64_t)(nbmax - nb);
+    for (int b = 0; b < nb; ++b) {
+      ks.push_back({((off + b) * ns + i), make_int4(i, 0, b, 0)});
+      ks.push_back({((off + 2 * nb - 1 - b) * ns + i), make_int4(i, 1, b, 0)});
+    }
+  }
+  std::stable_sort(ks.begin(), ks.end(), [](const K& a, const K& b) { return a.key < b.key; });
+  pb->trsv_tasks.resize(ks.size());
+  for (size_t k = 0; k < ks.size(); ++k) pb->trsv_tasks[k] = ks[k].t;
+}
+
+void plan_coarse_factor(asdg_problem* pb) {
+  const int32_t n0 = pb->n0;
+  const int nb = (n0 + TILE - 1) / TILE;
+  pb->csub = SubDesc{0, n0, nb, 0};
+  pb->n_ctiles = (int64_t)nb * (nb + 1) / 2;
+  pb->ctiles_host.assign((size_t)pb->n_ctiles * TILE * TILE, 0.0);
+  for (int b = 0; b < nb; ++b)
+    for (int j = 0; j <= b; ++j) {
+      double* T = &pb->ctiles_host[(size_t)(b * (b + 1) / 2 + j) * TILE * TILE];
+      for (int r = 0; r < TILE; ++r)
+        for (int c = 0; c < TILE; ++c) {
+          int gr = b * TILE + r, gc = j * TILE + c;
+          T[r * TILE + c] = (gr < n0 && gc < n0) ? pb->C.a0[(size_t)gr * n0 + gc] : (gr == gc ? 1.0 : 0.0);
+        }
+    }
+  pb->cchol_tasks.clear();
+  for (int j = 0; j < nb; ++j)
+    for (int b = j; b < nb; ++b) pb->cchol_tasks.push_back(make_int4(0, j, b, 0));
+  pb->ctrsv_tasks.clear();
+  for (int b = 0; b < nb; ++b) pb->ctrsv_tasks.push_back(make_int4(0, 0, b, 0));
+  for (int b = nb - 1; b >= 0; --b) pb->ctrsv_tasks.push_back(make_int4(0, 1, b, 0));
+}
+
+asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_done, double* part_rz,
+                            hipEvent_t ev0, hipEvent_t ev1) {
+  const int np = pb->A.np;
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  const double* r = pb->ptr<double>(3, pb->o3.r);
+  if (pb->has_coarse) {
+    HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->ptr<int32_t>(2, pb->o2.tptr),
+                               pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
+                               pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
+                               pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), st_done, s));
+  }
+  if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
+  const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(), (int64_t)pb->n_cu * 4);
+  HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
+                         pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
+                         pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid, s));
+  if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
+  if (pb->has_coarse) {
+    const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
+    HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
+                           pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
+                           pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0),
+                           pb->ptr<void>(3, pb->o3.z0), st, &st->q_coarse, cgrid, s));
+  }
+  HIPCHK(pb, launch_prolong(np, pb->has_coarse ? pb->C.nq : 3, pb->A.n_cells,
+                            pb->has_coarse ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
+                            pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
+                            pb->ptr<double>(3, pb->o3.z0), pb->ptr<void>(3, pb->o3.zl), pb->f32, r,
+                            pb->ptr<double>(3, pb->o3.z), part_rz, st_done, s));
+  return ASDG_OK;
+}
+
+asdg_status enqueue_iteration(asdg_problem* pb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  const int np = pb->A.np;
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  double* x = pb->ptr<double>(3, pb->o3.x);
+  double* r = pb->ptr<double>(3, pb->o3.r);
+  double* p = pb->ptr<double>(3, pb->o3.p);
+  double* q = pb->ptr<double>(3, pb->o3.q);
+  double* z = pb->ptr<double>(3, pb->o3.z);
+  double* ppq = pb->ptr<double>(3, pb->o3.ppq);
+  double* prr = pb->ptr<double>(3, pb->o3.prr);
+  double* prz = pb->ptr<double>(3, pb->o3.prz);
+  double* rz2 = pb->ptr<double>(3, pb->o3.rz2);
+  HIPCHK(pb, launch_spmv(np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
+                         pb->ptr<double>(0, pb->o0.blocks), p, q, ppq, st, s));
+  HIPCHK(pb, launch_update_xr(pb->n(), st, ppq, rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x, r,
+                              pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), pb->f32, prr, s));
+  HIPCHK(pb, launch_check(st, prr, ppq, s));
+  asdg_status e = enqueue_precond(pb, s, st, prz, ev0, ev1);
+  if (e != ASDG_OK) return e;
+  HIPCHK(pb, launch_update_p(pb->n(), st, prz, rz2, pb->ptr<double>(3, pb->o3.bh), z, p, 0, s));
+  return ASDG_OK;
+}
+
+asdg_status read_state(asdg_problem* pb, hipStream_t s, DevState& h) {
+  HIPCHK(pb, hipMemcpyAsync(&h, pb->ptr<DevState>(3, pb->o3.st), sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(pb, hipStreamSynchronize(s));
+  return ASDG_OK;
+}
+
+}  // namespace
+
+
+extern "C" {
+
+asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, const int32_t* coarse_of_cell,
+                      const asdg_mesh* coarse_mesh, size_t bytes[4]) {
+  if (!pb) return ASDG_EINVAL;
+  if (pb->stage < 1) FAIL(pb, ASDG_ESTATE, "asdg_plan before asdg_assemble");
+  if (precision != ASDG_FP64 && precision != ASDG_FP32_LOCAL) FAIL(pb, ASDG_EINVAL, "unknown precision");
+  if (!bytes) FAIL(pb, ASDG_EINVAL, "bytes is null");
+  if (q < 0 || q > pb->A.p) FAIL(pb, ASDG_EINVAL, "coarse degree q must satisfy 1 <= q <= p (or 0: no coarse level)");
+  pb->drop_graph();
+  pb->stage = 1;
+  pb->coarse_ready = false;
+  pb->f32 = precision == ASDG_FP32_LOCAL;
+  pb->has_coarse = q > 0;
+  pb->n0 = 0;
+  pb->C = Coarse();
+  if (pb->has_coarse) {
+    if (!coarse_of_cell && !coarse_mesh) FAIL(pb, ASDG_EINVAL, "coarse level needs coarse_of_cell or coarse_mesh");
+    MeshView cm{};
+    if (coarse_mesh) {
+      if (!coarse_mesh->xy || !coarse_mesh->cell_ptr || !coarse_mesh->cell_vertices || coarse_mesh->n_cells < 1)
+        FAIL(pb, ASDG_EINVAL, "invalid coarse mesh");
+      cm = MeshView{coarse_mesh->n_vertices, coarse_mesh->xy, coarse_mesh->n_cells, coarse_mesh->cell_ptr,
+                    coarse_mesh->cell_vertices};
+    }
+    std::string e = build_coarse(pb->fine.view(), pb->A, q, coarse_of_cell, coarse_mesh ? &cm : nullptr, pb->C);
+    if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
+    pb->n0 = pb->C.n_coarse * pb->C.nq;
+    plan_coarse_factor(pb);
+  }
+  plan_local(pb);
+
+  const Assembled& A = pb->A;
+  const int64_t N = A.n_cells, n = pb->n(), nnzb = A.row_ptr[N];
+  const size_t w = pb->f32 ? 4 : 8;
+  Layout L0, L1, L2, L3;
+  pb->o0.row_ptr = L0.add(4 * (N + 1));
+  pb->o0.col = L0.add(4 * nnzb);
+  pb->o0.blocks = L0.add(8 * nnzb * A.np * A.np);
+  pb->o0.rhs = L0.add(8 * n);
+  pb->o0.perm = L0.add(4 * N);
+  pb->o1.tiles = L1.add((size_t)pb->n_tiles * TILE * TILE * w);
+  pb->o1.subs = L1.add(sizeof(SubDesc) * pb->subs.size());
+  pb->o1.chol = L1.add(sizeof(int4) * pb->chol_tasks.size());
+  pb->o1.trsv = L1.add(sizeof(int4) * pb->trsv_tasks.size());
+  pb->o1.meta = L1.add(sizeof(int4) * pb->tile_meta.size());
+  if (pb->has_coarse) {
+    const Coarse& C = pb->C;
+    pb->o2.pptr = L2.add(4 * (N + 1));
+    pb->o2.pcol = L2.add(4 * C.col.size());
+    pb->o2.pval = L2.add(8 * C.val.size());
+    pb->o2.tptr = L2.add(4 * C.tptr.size());
+    pb->o2.tcell = L2.add(4 * C.tcell.size());
+    pb->o2.tblk = L2.add(4 * C.tblk.size());
+    pb->o2.ctiles = L2.add(8 * pb->ctiles_host.size());
+    pb->o2.csub = L2.add(sizeof(SubDesc));
+    pb->o2.cchol = L2.add(sizeof(int4) * pb->cchol_tasks.size());
+    pb->o2.ctrsv = L2.add(sizeof(int4) * pb->ctrsv_tasks.size());
+  } else {
+    L2.add(256);
+  }
+  const int64_t n0 = std::max<int32_t>(pb->n0, 1);
+  pb->o3.x = L3.add(8 * n);
+  pb->o3.r = L3.add(8 * n);
+  pb->o3.p = L3.add(8 * n);
+  pb->o3.q = L3.add(8 * n);
+  pb->o3.z = L3.add(8 * n);
+  pb->o3.yl = L3.add(w * n);
+  pb->o3.zl = L3.add(w * n);
+  pb->o3.r0 = L3.add(8 * n0);
+  pb->o3.y0 = L3.add(8 * n0);
+  pb->o3.z0 = L3.add(8 * n0);
+  pb->o3.ppq = L3.add(8 * NPART);
+  pb->o3.prr = L3.add(8 * NPART);
+  pb->o3.prz = L3.add(8 * NPART);
+  pb->o3.pbb = L3.add(8 * NPART);
+  pb->o3.st = L3.add(sizeof(DevState));
+  pb->o3.rz2 = L3.add(16);
+  pb->o3.ah = L3.add(8 * (size_t)HIST);
+  pb->o3.bh = L3.add(8 * (size_t)HIST);
+  pb->o3.flags = L3.add(4 * (size_t)std::max<int64_t>(pb->n_tiles, pb->n_ctiles));
+  pb->bytes[0] = L0.size;
+  pb->bytes[1] = L1.size;
+  pb->bytes[2] = L2.size;
+  pb->bytes[3] = L3.size;
+  for (int i = 0; i < 4; ++i) bytes[i] = pb->bytes[i];
+  pb->stage = 2;
+  return ASDG_OK;
+}
+
+asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes[4], void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (pb->stage < 2) FAIL(pb, ASDG_ESTATE, "asdg_bind before asdg_plan");
+  if (!d_buf || !sizes) FAIL(pb, ASDG_EINVAL, "null buffer list");
+  for (int i = 0; i < 4; ++i) {
+    if (!d_buf[i]) FAIL(pb, ASDG_EINVAL, "null device buffer");
+    if (sizes[i] < pb->bytes[i]) FAIL(pb, ASDG_ENOMEM, "device buffer " + std::to_string(i) + " too small");
+    if (((uintptr_t)d_buf[i]) & 255) FAIL(pb, ASDG_EINVAL, "device buffer not 256-byte aligned");
+  }
+  pb->drop_graph();
+  for (int i = 0; i < 4; ++i) pb->buf[i] = (char*)d_buf[i];
+  int dev = 0;
+  HIPCHK(pb, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(pb, hipGetDeviceProperties(&prop, dev));
+  pb->n_cu = std::max(1, prop.multiProcessorCount);
+  hipStream_t s = (hipStream_t)stream;
+  const Assembled& A = pb->A;
+  auto up = [&](int b, size_t off, const void* src, size_t nbytes) {
+    return nbytes ? hipMemcpyAsync(pb->buf[b] + off, src, nbytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  HIPCHK(pb, up(0, pb->o0.row_ptr, A.row_ptr.data(), 4 * A.row_ptr.size()));
+  HIPCHK(pb, up(0, pb->o0.col, A.col_idx.data(), 4 * A.col_idx.size()));
+  HIPCHK(pb, up(0, pb->o0.blocks, A.blocks.data(), 8 * A.blocks.size()));
+  HIPCHK(pb, up(0, pb->o0.rhs, pb->rhs_caller.data(), 8 * pb->rhs_caller.size()));
+  HIPCHK(pb, up(0, pb->o0.perm, A.perm.data(), 4 * A.perm.size()));
+  HIPCHK(pb, up(1, pb->o1.subs, pb->subs.data(), sizeof(SubDesc) * pb->subs.size()));
+  HIPCHK(pb, up(1, pb->o1.chol, pb->chol_tasks.data(), sizeof(int4) * pb->chol_tasks.size()));
+  HIPCHK(pb, up(1, pb->o1.trsv, pb->trsv_tasks.data(), sizeof(int4) * pb->trsv_tasks.size()));
+  HIPCHK(pb, up(1, pb->o1.meta, pb->tile_meta.data(), sizeof(int4) * pb->tile_meta.size()));
+  if (pb->has_coarse) {
+    const Coarse& C = pb->C;
+    HIPCHK(pb, up(2, pb->o2.pptr, C.ptr.data(), 4 * C.ptr.size()));
+    HIPCHK(pb, up(2, pb->o2.pcol, C.col.data(), 4 * C.col.size()));
+    HIPCHK(pb, up(2, pb->o2.pval, C.val.data(), 8 * C.val.size()));
+    HIPCHK(pb, up(2, pb->o2.tptr, C.tptr.data(), 4 * C.tptr.size()));
+    HIPCHK(pb, up(2, pb->o2.tcell, C.tcell.data(), 4 * C.tcell.size()));
+    HIPCHK(pb, up(2, pb->o2.tblk, C.tblk.data(), 4 * C.tblk.size()));
+    HIPCHK(pb, up(2, pb->o2.csub, &pb->csub, sizeof(SubDesc)));
+    HIPCHK(pb, up(2, pb->o2.cchol, pb->cchol_tasks.data(), sizeof(int4) * pb->cchol_tasks.size()));
+    HIPCHK(pb, up(2, pb->o2.ctrsv, pb->ctrsv_tasks.data(), sizeof(int4) * pb->ctrsv_tasks.size()));
+  }
+  HIPCHK(pb, hipStreamSynchronize(s));
+  pb->stage = 3;
+  pb->coarse_ready = false;
+  return ASDG_OK;
+}
+
+static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int32_t n_tasks, const int4* tasks,
+                                const SubDesc* subs, void* tiles, int64_t n_tiles, int coarse) {
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  int32_t* flags = pb->ptr<int32_t>(3, pb->o3.flags);
+  HIPCHK(pb, launch_fill_i32(flags, n_tiles, 0, s));
+  HIPCHK(pb, launch_reset_queues(st, s));
+  const int per_cu = f32 ? 4 : 2;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tasks, (int64_t)pb->n_cu * per_cu));
+  HIPCHK(pb, launch_cholesky(f32, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
+  DevState h;
+  asdg_status e = read_state(pb, s, h);
+  if (e != ASDG_OK) return e;
+  if (h.abort) FAIL(pb, ASDG_EHIP, "factorisation wait budget exhausted");
+  if (h.chol_fail != 0x7fffffff) {
+    pb->failed_sub = coarse ? -1 : h.chol_fail;
+    FAIL(pb, ASDG_ENOTSPD, coarse ? "coarse matrix A_0 is not positive definite"
+                                  : "local matrix of subdomain " + std::to_string(h.chol_fail) +
+                                        " is not positive definite");
+  }
+  return ASDG_OK;
+}
+
+asdg_status asdg_factor(asdg_problem* pb, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "asdg_factor before asdg_bind");
+  hipStream_t s = (hipStream_t)stream;
+  pb->failed_sub = -2;
+  pb->stage = 3;
+  HIPCHK(pb, launch_gather_tiles(pb->A.np, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+                                 pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.row_ptr),
+                                 pb->ptr<int32_t>(0, pb->o0.col), pb->ptr<double>(0, pb->o0.blocks),
+                                 pb->ptr<void>(1, pb->o1.tiles), pb->f32, s));
+  asdg_status e = run_cholesky(pb, s, pb->f32, (int32_t)pb->chol_tasks.size(), pb->ptr<int4>(1, pb->o1.chol),
+                               pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0);
+  if (e != ASDG_OK) return e;
+  pb->stage = 4;
+  return ASDG_OK;
+}
+
+asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "asdg_setup_coarse before asdg_bind");
+  pb->coarse_ready = false;
+  if (!pb->has_coarse) {
+    pb->coarse_ready = true;
+    return ASDG_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(pb, hipMemcpyAsync(pb->buf[2] + pb->o2.ctiles, pb->ctiles_host.data(), 8 * pb->ctiles_host.size(),
+                            hipMemcpyHostToDevice, s));
+  asdg_status e = run_cholesky(pb, s, 0, (int32_t)pb->cchol_tasks.size(), pb->ptr<int4>(2, pb->o2.cchol),
+                               pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles), pb->n_ctiles, 1);
+  if (e != ASDG_OK) return e;
+  pb->coarse_ready = true;
+  return ASDG_OK;
+}
+
+asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, const asdg_pcg_opts* opts,
+                           asdg_pcg_stats* stats, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (pb->stage < 4 || !pb->coarse_ready) FAIL(pb, ASDG_ESTATE, "asdg_pcg_solve before asdg_factor/asdg_setup_coarse");
+  if (!d_x) FAIL(pb, ASDG_EINVAL, "d_x is null");
+  asdg_pcg_opts o{1e-8, 20000, 16, 1, 0};
+  if (opts) o = *opts;
+  if (!(o.rtol >= 0.0) || o.max_iter < 1 || o.check_every < 1) FAIL(pb, ASDG_EINVAL, "invalid PCG options");
+  hipStream_t s = (hipStream_t)stream;
+  const int np = pb->A.np;
+  const int32_t N = pb->A.n_cells;
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  if (!pb->t0) {
+    HIPCHK(pb, hipEventCreate(&pb->t0));
+    HIPCHK(pb, hipEventCreate(&pb->t1));
+  }
+  const int k = o.check_every;
+  if ((int)pb->ev.size() < 2 * k) {
+    while ((int)pb->ev.size() < 2 * k) {
+      hipEvent_t e;
+      HIPCHK(pb, hipEventCreate(&e));
+      pb->ev.push_back(e);
+    }
+  }
+  HIPCHK(pb, hipEventRecord(pb->t0, s));
+  // x = 0, r = b (internal order), ||b||^2, z = P^{-1} r, p = z
+  const double* src = d_b ? d_b : pb->ptr<double>(0, pb->o0.rhs);
+  HIPCHK(pb, launch_permute_in(np, N, pb->ptr<int32_t>(0, pb->o0.perm), src, pb->ptr<double>(3, pb->o3.r),
+                               pb->ptr<double>(3, pb->o3.x), pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
+                               pb->f32, pb->ptr<double>(3, pb->o3.pbb), s));
+  HIPCHK(pb, launch_init_check(st, pb->ptr<double>(3, pb->o3.pbb), o.rtol, o.max_iter, s));
+  asdg_status e = enqueue_precond(pb, s, st, pb->ptr<double>(3, pb->o3.prz), nullptr, nullptr);
+  if (e != ASDG_OK) return e;
+  HIPCHK(pb, launch_update_p(pb->n(), st, pb->ptr<double>(3, pb->o3.prz), pb->ptr<double>(3, pb->o3.rz2),
+                             pb->ptr<double>(3, pb->o3.bh), pb->ptr<double>(3, pb->o3.z), pb->ptr<double>(3, pb->o3.p),
+                             1, s));
+  double t_local = 0.0;
+  int n_local = 0;
+  DevState h;
+  e = read_state(pb, s, h);
+  if (e != ASDG_OK) return e;
+  if (o.use_graph) {
+    if (!pb->own_stream) HIPCHK(pb, hipStreamCreateWithFlags(&pb->own_stream, hipStreamNonBlocking));
+    hipStream_t gs = pb->own_stream;
+    if (!pb->gexec || pb->g_k != k || pb->g_timed != o.time_kernels) {
+      pb->drop_graph();
+      hipGraph_t g;
+      HIPCHK(pb, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      asdg_status ce = ASDG_OK;
+      for (int i = 0; i < k && ce == ASDG_OK; ++i)
+        ce = enqueue_iteration(pb, gs, o.time_kernels ? pb->ev[2 * i] : nullptr,
+                               o.time_kernels ? pb->ev[2 * i + 1] : nullptr);
+      hipError_t he = hipStreamEndCapture(gs, &g);
+      if (ce != ASDG_OK) return ce;
+      if (he != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("graph capture: ") + hipGetErrorString(he));
+      he = hipGraphInstantiate(&pb->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (he != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(he));
+      pb->g_k = k;
+      pb->g_timed = o.time_kernels;
+    }
+    while (!h.done) {
+      const int it0 = h.it;
+      HIPCHK(pb, hipGraphLaunch(pb->gexec, gs));
+      HIPCHK(pb, hipStreamSynchronize(gs));
+      e = read_state(pb, s, h);
+      if (e != ASDG_OK) return e;
+      if (o.time_kernels) {
+        const int ran = h.it - it0 - (h.done ? 1 : 0);
+        for (int i = 0; i < ran && i < k; ++i) {
+          float ms = 0.f;
+          HIPCHK(pb, hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]));
+          t_local += ms;
+          ++n_local;
+        }
+      }
+    }
+  } else {
+    while (!h.done) {
+      const int it0 = h.it;
+      for (int i = 0; i < k; ++i) {
+        e = enqueue_iteration(pb, s, o.time_kernels ? pb->ev[2 * i] : nullptr,
+                              o.time_kernels ? pb->ev[2 * i + 1] : nullptr);
+        if (e != ASDG_OK) return e;
+      }
+      e = read_state(pb, s, h);
+      if (e != ASDG_OK) return e;
+      if (o.time_kernels) {
+        const int ran = h.it - it0 - (h.done ? 1 : 0);
+        for (int i = 0; i < ran && i < k; ++i) {
+          float ms = 0.f;
+          HIPCHK(pb, hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]));
+          t_local += ms;
+          ++n_local;
+        }
+      }
+    }
+  }
+  HIPCHK(pb, launch_unpermute_out(np, N, pb->ptr<int32_t>(0, pb->o0.perm), pb->ptr<double>(3, pb->o3.x), d_x, s));
+  HIPCHK(pb, hipEventRecord(pb->t1, s));
+  HIPCHK(pb, hipEventSynchronize(pb->t1));
+  float solve_ms = 0.f;
+  HIPCHK(pb, hipEventElapsedTime(&solve_ms, pb->t0, pb->t1));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iterations = h.it;
+    stats->converged = h.status == 1;
+    stats->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    stats->t_solve_ms = solve_ms;
+    stats->t_local_ms = t_local;
+    stats->n_local = n_local;
+    stats->failed_subdomain = -2;
+    const int ka = std::min(h.it, HIST);
+    if (ka >= 1) {
+      std::vector<double> al(ka), be(std::max(ka - 1, 0));
+      HIPCHK(pb, hipMemcpy(al.data(), pb->ptr<double>(3, pb->o3.ah), 8 * ka, hipMemcpyDeviceToHost));
+      if (ka > 1) HIPCHK(pb, hipMemcpy(be.data(), pb->ptr<double>(3, pb->o3.bh), 8 * (ka - 1), hipMemcpyDeviceToHost));
+      std::vector<double> d(ka), off(std::max(ka - 1, 0));
+      d[0] = 1.0 / al[0];
+      for (int j = 1; j < ka; ++j) d[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
+      for (int j = 0; j + 1 < ka; ++j) off[j] = std::sqrt(std::max(be[j], 0.0)) / al[j];
+      tridiag_extremes(d, off, stats->lambda_min, stats->lambda_max);
+    }
+  }
+  if (h.status == 4) FAIL(pb, ASDG_EHIP, "local-solve wait budget exhausted");
+  if (h.status == 3) FAIL(pb, ASDG_EBREAKDOWN, "PCG breakdown (p.Ap <= 0 or NaN)");
+  if (h.status == 2) FAIL(pb, ASDG_ENOCONV, "maximum number of iterations reached");
+  return ASDG_OK;
+}
+
+asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, double* d_out, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (!d_in || !d_out) FAIL(pb, ASDG_EINVAL, "null vector");
+  if (what < 0 || what > 3) FAIL(pb, ASDG_EINVAL, "unknown operator");
+  if (what == ASDG_APPLY_OPERATOR && pb->stage < 3) FAIL(pb, ASDG_ESTATE, "apply before asdg_bind");
+  if ((what == ASDG_APPLY_LOCAL || what == ASDG_APPLY_PRECOND) && pb->stage < 4)
+    FAIL(pb, ASDG_ESTATE, "apply before asdg_factor");
+  if ((what == ASDG_APPLY_COARSE || what == ASDG_APPLY_PRECOND) && !pb->coarse_ready)
+    FAIL(pb, ASDG_ESTATE, "apply before asdg_setup_coarse");
+  hipStream_t s = (hipStream_t)stream;
+  const int np = pb->A.np;
+  const int32_t N = pb->A.n_cells;
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  double* r = pb->ptr<double>(3, pb->o3.r);
+  double* q = pb->ptr<double>(3, pb->o3.q);
+  double* z = pb->ptr<double>(3, pb->o3.z);
+  int32_t* perm = pb->ptr<int32_t>(0, pb->o0.perm);
+  HIPCHK(pb, launch_permute_in(np, N, perm, d_in, r, nullptr, pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
+                               pb->f32, nullptr, s));
+  HIPCHK(pb, launch_reset_queues(st, s));
+  if (what == ASDG_APPLY_OPERATOR) {
+    HIPCHK(pb, launch_spmv(np, N, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
+                           pb->ptr<double>(0, pb->o0.blocks), r, q, nullptr, nullptr, s));
+    HIPCHK(pb, launch_unpermute_out(np, N, perm, q, d_out, s));
+  } else {
+    const bool loc = what != ASDG_APPLY_COARSE, crs = what != ASDG_APPLY_LOCAL && pb->has_coarse;
+    if (crs)
+      HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->ptr<int32_t>(2, pb->o2.tptr),
+                                 pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
+                                 pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
+                                 pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), nullptr, s));
+    if (loc) {
+      const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(), (int64_t)pb->n_cu * 4);
+      HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
+                             pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
+                             pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid, s));
+    }
+    if (crs) {
+      const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
+      HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
+                             pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
+                             pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0), pb->ptr<void>(3, pb->o3.z0),
+                             st, &st->q_coarse, cgrid, s));
+    }
+    HIPCHK(pb, launch_prolong(np, crs ? pb->C.nq : 3, N, crs ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
+                              pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
+                              pb->ptr<double>(3, pb->o3.z0), loc ? pb->ptr<void>(3, pb->o3.zl) : nullptr, pb->f32, r, z,
+                              nullptr, nullptr, s));
+    HIPCHK(pb, launch_unpermute_out(np, N, perm, z, d_out, s));
+  }
+  DevState h;
+  asdg_status e = read_state(pb, s, h);
+  if (e != ASDG_OK) return e;
+  if (h.abort) FAIL(pb, ASDG_EHIP, "wait budget exhausted");
+  return ASDG_OK;
+}
+
+asdg_status asdg_info(const asdg_problem* pb, int64_t info[8]) {
+  if (!pb || !info) return ASDG_EINVAL;
+  if (pb->stage < 1) return ASDG_ESTATE;
+  info[0] = pb->A.n_cells;
+  info[1] = pb->A.np;
+  info[2] = (int64_t)pb->A.n_cells * pb->A.np;
+  info[3] = pb->A.n_sub;
+  info[4] = pb->n0;
+  info[5] = pb->A.row_ptr.empty() ? 0 : pb->A.row_ptr.back();
+  info[6] = pb->max_n;
+  info[7] = TILE;
+  return ASDG_OK;
+}
+
+asdg_status asdg_export_rhs(const asdg_problem* pb, double* b) {
+  if (!pb || !b) return ASDG_EINVAL;
+  if (pb->stage < 1) return ASDG_ESTATE;
+  std::memcpy(b, pb->rhs_caller.data(), 8 * pb->rhs_caller.size());
+  return ASDG_OK;
+}
+
+asdg_status asdg_export_operator(const asdg_problem* pb, int64_t* rows, int64_t* cols, double* vals) {
+  if (!pb || !rows || !cols || !vals) return ASDG_EINVAL;
+  if (pb->stage < 1) return ASDG_ESTATE;
+  const Assembled& A = pb->A;
+  const int np = A.np;
+  int64_t o = 0;
+  for (int32_t r = 0; r < A.n_cells; ++r)
+    for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
+      const int64_t cr = A.perm[r], cc = A.perm[A.col_idx[k]];
+      const double* B = &A.blocks[(size_t)k * np * np];
+      for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b, ++o) {
+          rows[o] = cr * np + a;
+          cols[o] = cc * np + b;
+          vals[o] = B[b * np + a];
+        }
+    }
+  return ASDG_OK;
+}
+
+asdg_status asdg_export_coarse(const asdg_problem* pb, double* a0) {
+  if (!pb || !a0) return ASDG_EINVAL;
+  if (pb->stage < 2 || !pb->has_coarse) return ASDG_ESTATE;
+  std::memcpy(a0, pb->C.a0.data(), 8 * pb->C.a0.size());
+  return ASDG_OK;
+}
+
+int32_t asdg_failed_subdomain(const asdg_problem* pb) { return pb ? pb->failed_sub : -2; }
+
+}  // extern "C"

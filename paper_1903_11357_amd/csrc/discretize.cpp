@@ -1,0 +1,792 @@
+// Host-side SIPG assembly and coarse transfer for libasdg.
+//
+// SIPG form (Sec. 2, eqs. (Ah), (lifting), (Sigma)): with rho constant per
+// cell the lifting terms become face integrals of the weighted average
+// {rho grad u}_w, w = rho^-/(rho^+ + rho^-), which equals
+// (<rho>/2)(grad u^+ + grad u^-) with <rho> the harmonic average. Per face F
+// with unit normal n (outward from the plus cell) and sides t, s in {+,-}
+// (eps_+ = 1, eps_- = -1) the block coupling test side t and trial side s is
+//   int_F -(g/2) eps_t phi^t_a (grad phi^s_b . n) - (g/2) eps_s (grad phi^t_a . n) phi^s_b
+//         + sigma eps_t eps_s phi^t_a phi^s_b,
+// g = <rho>_F, sigma = C_sigma g p^2 / <h>_F (harmonic mean of diameters);
+// on a boundary face g = rho_K, <h> = h_K and the 1/2 factors are absent.
+//
+// Quadrature: every cell is split into triangles (area centroid, v_k, v_k+1),
+// each integrated by a collapsed tensor Gauss-Legendre rule with m = p + 2
+// points per direction (exact to total degree 2m - 2); faces use m-point
+// Gauss-Legendre. All bilinear forms are therefore integrated exactly.
+//
+// Coarse transfer (Sec. 3, eq. (R0T)): block of fine cell K and coarse cell D
+// is M_K^{-1} int_{K cap D} phi^K psi^D; nested coarse cells contain whole
+// fine cells (Remark 3.2: the result is the injection), non-nested convex
+// coarse cells are intersected with each fine cell by polygon clipping.
+// A_0 = P_0^T A P_0 (eq. (A0)).
+#include "discretize.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <unordered_map>
+
+namespace asdg {
+
+namespace {
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 16));
+  if (n < 2048 || nt == 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int64_t t = 0; t < nt; ++t) {
+    int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([&fn, a, b] { fn(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
+
+struct QuadPoint {
+  double x, y, w;
+};
+
+// Collapsed rule on triangle (a, b, c): x = (1-s)a + s((1-t)b + t c),
+// weight 2|T| s ws wt.
+void triangle_points(const double* a, const double* b, const double* c, const std::vector<double>& g,
+                     const std::vector<double>& wg, std::vector<QuadPoint>& out) {
+  double e1x = b[0] - a[0], e1y = b[1] - a[1];
+  double e2x = c[0] - a[0], e2y = c[1] - a[1];
+  double area = 0.5 * std::fabs(e1x * e2y - e1y * e2x);
+  int m = (int)g.size();
+  for (int i = 0; i < m; ++i) {
+    double s = g[i];
+    for (int j = 0; j < m; ++j) {
+      double t = g[j];
+      double px = (1.0 - s) * a[0] + s * ((1.0 - t) * b[0] + t * c[0]);
+      double py = (1.0 - s) * a[1] + s * ((1.0 - t) * b[1] + t * c[1]);
+      out.push_back({px, py, 2.0 * area * s * wg[i] * wg[j]});
+    }
+  }
+}
+
+double polygon_area_centroid(const std::vector<double>& P, double& cx, double& cy) {
+  size_t k = P.size() / 2;
+  double a = 0.0, sx = 0.0, sy = 0.0;
+  for (size_t i = 0; i < k; ++i) {
+    size_t j = (i + 1) % k;
+    double cr = P[2 * i] * P[2 * j + 1] - P[2 * j] * P[2 * i + 1];
+    a += cr;
+    sx += (P[2 * i] + P[2 * j]) * cr;
+    sy += (P[2 * i + 1] + P[2 * j + 1]) * cr;
+  }
+  a *= 0.5;
+  cx = sx / (6.0 * a);
+  cy = sy / (6.0 * a);
+  return a;
+}
+
+// Centroid-fan rule over a polygon given as flat xy list.
+void polygon_points(const std::vector<double>& P, const std::vector<double>& g,
+                    const std::vector<double>& wg, std::vector<QuadPoint>& out) {
+  double cx, cy;
+  polygon_area_centroid(P, cx, cy);
+  double c[2] = {cx, cy};
+  size_t k = P.size() / 2;
+  for (size_t i = 0; i < k; ++i) {
+    size_t j = (i + 1) % k;
+    triangle_points(c, &P[2 * i], &P[2 * j], g, wg, out);
+  }
+}
+
+// Sutherland-Hodgman: subject polygon clipped by convex CCW clipper.
+std::vector<double> clip_polygon(const std::vector<double>& subject, const std::vector<double>& clipper) {
+  std::vector<double> out = subject, in;
+  size_t k = clipper.size() / 2;
+  for (size_t i = 0; i < k && !out.empty(); ++i) {
+    double ax = clipper[2 * i], ay = clipper[2 * i + 1];
+    size_t i1 = (i + 1) % k;
+    double ex = clipper[2 * i1] - ax, ey = clipper[2 * i1 + 1] - ay;
+    in.swap(out);
+    out.clear();
+    size_t n = in.size() / 2;
+    for (size_t j = 0; j < n; ++j) {
+      size_t j1 = (j + 1) % n;
+      double Px = in[2 * j], Py = in[2 * j + 1], Qx = in[2 * j1], Qy = in[2 * j1 + 1];
+      double sP = ex * (Py - ay) - ey * (Px - ax);
+      double sQ = ex * (Qy - ay) - ey * (Qx - ax);
+      if (sP >= 0.0) {
+        out.push_back(Px);
+        out.push_back(Py);
+        if (sQ < 0.0) {
+          double t = sP / (sP - sQ);
+          out.push_back(Px + (Qx - Px) * t);
+          out.push_back(Py + (Qy - Py) * t);
+        }
+      } else if (sQ >= 0.0) {
+        double t = sP / (sP - sQ);
+        out.push_back(Px + (Qx - Px) * t);
+        out.push_back(Py + (Qy - Py) * t);
+      }
+    }
+  }
+  if (out.size() < 6) out.clear();
+  return out;
+}
+
+// Small dense SPD solve (Cholesky), matrix n x n row-major, rhs n x k.
+bool spd_solve(int n, std::vector<double> M, double* B, int k) {
+  for (int j = 0; j < n; ++j) {
+    double d = M[j * n + j];
+    for (int l = 0; l < j; ++l) d -= M[j * n + l] * M[j * n + l];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    M[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = M[i * n + j];
+      for (int l = 0; l < j; ++l) s -= M[i * n + l] * M[j * n + l];
+      M[i * n + j] = s / d;
+    }
+  }
+  for (int c = 0; c < k; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = B[i * k + c];
+      for (int l = 0; l < i; ++l) s -= M[i * n + l] * B[l * k + c];
+      B[i * k + c] = s / M[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = B[i * k + c];
+      for (int l = i + 1; l < n; ++l) s -= M[l * n + i] * B[l * k + c];
+      B[i * k + c] = s / M[i * n + i];
+    }
+  }
+  return true;
+}
+
+bool on_boundary_side(double ax, double ay, double bx, double by) {
+  const double tol = 1e-12;
+  for (double s : {0.0, 1.0}) {
+    if (std::fabs(ax - s) < tol && std::fabs(bx - s) < tol) return true;
+    if (std::fabs(ay - s) < tol && std::fabs(by - s) < tol) return true;
+  }
+  return false;
+}
+
+std::string geometry(const MeshView& m, CellGeom& g, bool require_ccw) {
+  int32_t N = m.n_cells;
+  g.area.assign(N, 0.0);
+  g.cx.assign(N, 0.0);
+  g.cy.assign(N, 0.0);
+  g.diam.assign(N, 0.0);
+  g.box.assign(N, Box{0, 0, 0, 0});
+  for (int32_t c = 0; c < N; ++c) {
+    int32_t a = m.ptr[c], b = m.ptr[c + 1];
+    if (b - a < 3) return "cell " + std::to_string(c) + " has fewer than 3 vertices";
+    for (int32_t k = a; k < b; ++k)
+      if (m.verts[k] < 0 || m.verts[k] >= m.n_vertices) return "vertex id out of range";
+  }
+  std::vector<int> bad(N, 0);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    std::vector<double> P;
+    for (int64_t c = lo; c < hi; ++c) {
+      int32_t a = m.ptr[c], b = m.ptr[c + 1];
+      P.clear();
+      for (int32_t k = a; k < b; ++k) {
+        P.push_back(m.xy[2 * m.verts[k]]);
+        P.push_back(m.xy[2 * m.verts[k] + 1]);
+      }
+      double cx, cy;
+      double ar = polygon_area_centroid(P, cx, cy);
+      if (!(ar > 0.0) && require_ccw) {
+        bad[c] = 1;
+        continue;
+      }
+      g.area[c] = ar;
+      g.cx[c] = cx;
+      g.cy[c] = cy;
+      size_t k = P.size() / 2;
+      double d2 = 0.0;
+      Box B{P[0], P[0], P[1], P[1]};
+      for (size_t i = 0; i < k; ++i) {
+        B.x0 = std::min(B.x0, P[2 * i]);
+        B.x1 = std::max(B.x1, P[2 * i]);
+        B.y0 = std::min(B.y0, P[2 * i + 1]);
+        B.y1 = std::max(B.y1, P[2 * i + 1]);
+        for (size_t j = i + 1; j < k; ++j) {
+          double dx = P[2 * i] - P[2 * j], dy = P[2 * i + 1] - P[2 * j + 1];
+          d2 = std::max(d2, dx * dx + dy * dy);
+        }
+      }
+      g.diam[c] = std::sqrt(d2);
+      g.box[c] = B;
+    }
+  });
+  for (int32_t c = 0; c < N; ++c)
+    if (bad[c]) return "cell " + std::to_string(c) + " is clockwise or degenerate";
+  return "";
+}
+
+void cell_polygon(const MeshView& m, int32_t c, std::vector<double>& P) {
+  P.clear();
+  for (int32_t k = m.ptr[c]; k < m.ptr[c + 1]; ++k) {
+    P.push_back(m.xy[2 * m.verts[k]]);
+    P.push_back(m.xy[2 * m.verts[k] + 1]);
+  }
+}
+
+// Quadrature points of a cell's centroid fan (order fixed by vertex order).
+void cell_points(const MeshView& m, const CellGeom& g, int32_t c, const std::vector<double>& gq,
+                 const std::vector<double>& wq, std::vector<QuadPoint>& out) {
+  out.clear();
+  double C[2] = {g.cx[c], g.cy[c]};
+  int32_t a = m.ptr[c], b = m.ptr[c + 1];
+  for (int32_t k = a; k < b; ++k) {
+    int32_t k1 = (k + 1 < b) ? k + 1 : a;
+    triangle_points(C, &m.xy[2 * m.verts[k]], &m.xy[2 * m.verts[k1]], gq, wq, out);
+  }
+}
+
+}  // namespace
+
+void gauss_legendre01(int m, std::vector<double>& x, std::vector<double>& w) {
+  // Newton iteration on P_m using the three-term recurrence; nodes are the
+  // roots of P_m on [-1, 1], weights 2 / ((1 - t^2) P_m'(t)^2), then mapped.
+  x.assign(m, 0.0);
+  w.assign(m, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < m; ++i) {
+    double t = std::cos(pi * (i + 0.75) / (m + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 1; k < m; ++k) {
+        double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      if (m == 1) {
+        p1 = t;
+        p0 = 1.0;
+      }
+      dp = m * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    // recompute derivative at the converged node
+    double p0 = 1.0, p1 = t;
+    for (int k = 1; k < m; ++k) {
+      double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+      p0 = p1;
+      p1 = p2;
+    }
+    if (m == 1) p0 = 1.0;
+    dp = m * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = 0.5 * (t + 1.0);
+    w[i] = 0.5 * 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+  // ascending order
+  std::vector<int> idx(m);
+  for (int i = 0; i < m; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+  std::vector<double> xs(m), ws(m);
+  for (int i = 0; i < m; ++i) {
+    xs[i] = x[idx[i]];
+    ws[i] = w[idx[i]];
+  }
+  x.swap(xs);
+  w.swap(ws);
+}
+
+int n_basis(int p) { return (p + 1) * (p + 2) / 2; }
+
+void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx, double* gy) {
+  double dx = B.x1 - B.x0, dy = B.y1 - B.y0;
+  double xi = 2.0 * (x - 0.5 * (B.x0 + B.x1)) / dx;
+  double eta = 2.0 * (y - 0.5 * (B.y0 + B.y1)) / dy;
+  double Lx[16], dLx[16], Ly[16], dLy[16];
+  Lx[0] = 1.0;
+  dLx[0] = 0.0;
+  Ly[0] = 1.0;
+  dLy[0] = 0.0;
+  if (p >= 1) {
+    Lx[1] = xi;
+    dLx[1] = 1.0;
+    Ly[1] = eta;
+    dLy[1] = 1.0;
+  }
+  for (int k = 1; k < p; ++k) {
+    Lx[k + 1] = ((2 * k + 1) * xi * Lx[k] - k * Lx[k - 1]) / (k + 1);
+    Ly[k + 1] = ((2 * k + 1) * eta * Ly[k] - k * Ly[k - 1]) / (k + 1);
+    dLx[k + 1] = dLx[k - 1] + (2 * k + 1) * Lx[k];
+    dLy[k + 1] = dLy[k - 1] + (2 * k + 1) * Ly[k];
+  }
+  int a = 0;
+  for (int d = 0; d <= p; ++d) {
+    for (int j = 0; j <= d; ++j, ++a) {
+      int i = d - j;
+      double s = std::sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (dx * dy));
+      val[a] = s * Lx[i] * Ly[j];
+      if (gx) gx[a] = s * dLx[i] * (2.0 / dx) * Ly[j];
+      if (gy) gy[a] = s * Lx[i] * dLy[j] * (2.0 / dy);
+    }
+  }
+}
+
+std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const double* rho,
+                          const int32_t* subdomain,
+                          void (*f)(int64_t, const double*, double*, void*), void* f_user,
+                          Assembled& A) {
+  if (p < 1 || p > 4) return "p must be in 1..4";
+  if (!(c_sigma > 0.0)) return "c_sigma must be positive";
+  const int32_t N = mesh.n_cells;
+  if (N < 1) return "empty mesh";
+  for (int32_t c = 0; c < N; ++c)
+    if (!(rho[c] > 0.0) || !std::isfinite(rho[c])) return "rho must be positive and finite";
+  A.p = p;
+  A.np = n_basis(p);
+  A.c_sigma = c_sigma;
+  A.n_cells = N;
+  const int np = A.np;
+  std::string err = geometry(mesh, A.geom, true);
+  if (!err.empty()) return err;
+  const CellGeom& G = A.geom;
+
+  // faces by edge matching
+  A.faces.clear();
+  std::unordered_map<uint64_t, int32_t> open;
+  open.reserve((size_t)N * 4);
+  for (int32_t c = 0; c < N; ++c) {
+    int32_t a = mesh.ptr[c], b = mesh.ptr[c + 1];
+    for (int32_t k = a; k < b; ++k) {
+      int32_t v0 = mesh.verts[k], v1 = mesh.verts[(k + 1 < b) ? k + 1 : a];
+      if (v0 == v1) return "repeated vertex in cell " + std::to_string(c);
+      uint64_t key = ((uint64_t)std::min(v0, v1) << 32) | (uint32_t)std::max(v0, v1);
+      auto it = open.find(key);
+      if (it == open.end()) {
+        open.emplace(key, (int32_t)A.faces.size());
+        A.faces.push_back({c, -1, v0, v1});
+      } else {
+        Face& F = A.faces[it->second];
+        if (F.minus >= 0) return "edge shared by more than two cells";
+        if (!(F.v0 == v1 && F.v1 == v0)) return "inconsistent orientation across an edge";
+        F.minus = c;
+        open.erase(it);
+      }
+    }
+  }
+  for (const Face& F : A.faces) {
+    if (F.minus < 0 &&
+        !on_boundary_side(mesh.xy[2 * F.v0], mesh.xy[2 * F.v0 + 1], mesh.xy[2 * F.v1], mesh.xy[2 * F.v1 + 1]))
+      return "non-conforming mesh: unmatched edge inside the domain";
+  }
+
+  // subdomains and subdomain-major permutation (stable)
+  int32_t nsub = 0;
+  for (int32_t c = 0; c < N; ++c) {
+    if (subdomain[c] < 0) return "negative subdomain id";
+    nsub = std::max(nsub, subdomain[c] + 1);
+  }
+  A.n_sub = nsub;
+  A.sub_ptr.assign(nsub + 1, 0);
+  for (int32_t c = 0; c < N; ++c) A.sub_ptr[subdomain[c] + 1]++;
+  for (int32_t i = 0; i < nsub; ++i) {
+    if (A.sub_ptr[i + 1] == 0) return "subdomain id " + std::to_string(i) + " is unused";
+    A.sub_ptr[i + 1] += A.sub_ptr[i];
+  }
+  A.perm.assign(N, 0);
+  A.iperm.assign(N, 0);
+  {
+    std::vector<int32_t> fill(A.sub_ptr.begin(), A.sub_ptr.end() - 1);
+    for (int32_t c = 0; c < N; ++c) {
+      int32_t r = fill[subdomain[c]]++;
+      A.perm[r] = c;
+      A.iperm[c] = r;
+    }
+  }
+
+  // per-cell face lists (caller order), in face-index order
+  std::vector<int32_t> cf_ptr(N + 1, 0);
+  for (const Face& F : A.faces) {
+    cf_ptr[F.plus + 1]++;
+    if (F.minus >= 0) cf_ptr[F.minus + 1]++;
+  }
+  for (int32_t c = 0; c < N; ++c) cf_ptr[c + 1] += cf_ptr[c];
+  std::vector<int32_t> cf(cf_ptr[N]);
+  {
+    std::vector<int32_t> fill(cf_ptr.begin(), cf_ptr.end() - 1);
+    for (int32_t fidx = 0; fidx < (int32_t)A.faces.size(); ++fidx) {
+      const Face& F = A.faces[fidx];
+      cf[fill[F.plus]++] = 2 * fidx;  // side +
+      if (F.minus >= 0) cf[fill[F.minus]++] = 2 * fidx + 1;  // side -
+    }
+  }
+
+  // BSR structure, internal order
+  A.row_ptr.assign(N + 1, 0);
+  std::vector<std::vector<int32_t>> cols(N);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      int32_t c = A.perm[r];
+      auto& cl = cols[r];
+      cl.push_back((int32_t)r);
+      for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
+        const Face& F = A.faces[cf[k] >> 1];
+        if (F.minus < 0) continue;
+        int32_t other = (cf[k] & 1) ? F.plus : F.minus;
+        cl.push_back(A.iperm[other]);
+      }
+      std::sort(cl.begin(), cl.end());
+      cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+    }
+  });
+  for (int32_t r = 0; r < N; ++r) A.row_ptr[r + 1] = A.row_ptr[r] + (int32_t)cols[r].size();
+  A.col_idx.resize(A.row_ptr[N]);
+  for (int32_t r = 0; r < N; ++r) std::copy(cols[r].begin(), cols[r].end(), A.col_idx.begin() + A.row_ptr[r]);
+  cols.clear();
+  cols.shrink_to_fit();
+
+  const int m = p + 2;
+  std::vector<double> gq, wq;
+  gauss_legendre01(m, gq, wq);
+  const double pp = (double)p * (double)p;
+
+  // volume blocks and load vector, caller order
+  std::vector<double> vol((size_t)N * np * np, 0.0);
+  std::vector<double> rhs_c((size_t)N * np, 0.0);
+  {
+    const int64_t chunk = 8192;
+    for (int64_t c0 = 0; c0 < N; c0 += chunk) {
+      int64_t c1 = std::min<int64_t>(N, c0 + chunk);
+      // points of this chunk, in cell order
+      std::vector<int64_t> pptr(c1 - c0 + 1, 0);
+      for (int64_t c = c0; c < c1; ++c)
+        pptr[c - c0 + 1] = pptr[c - c0] + (int64_t)(mesh.ptr[c + 1] - mesh.ptr[c]) * m * m;
+      std::vector<double> pts(2 * pptr.back()), wts(pptr.back()), fv(pptr.back(), 0.0);
+      parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
+        std::vector<QuadPoint> qp;
+        for (int64_t cc = lo; cc < hi; ++cc) {
+          cell_points(mesh, G, (int32_t)(c0 + cc), gq, wq, qp);
+          int64_t o = pptr[cc];
+          for (size_t k = 0; k < qp.size(); ++k) {
+            pts[2 * (o + k)] = qp[k].x;
+            pts[2 * (o + k) + 1] = qp[k].y;
+            wts[o + k] = qp[k].w;
+          }
+        }
+      });
+      if (f) f(pptr.back(), pts.data(), fv.data(), f_user);
+      parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
+        double v[16], gx[16], gy[16];
+        for (int64_t cc = lo; cc < hi; ++cc) {
+          int64_t c = c0 + cc;
+          double* K = &vol[(size_t)c * np * np];
+          double* bl = &rhs_c[(size_t)c * np];
+          for (int64_t k = pptr[cc]; k < pptr[cc + 1]; ++k) {
+            basis_eval(p, G.box[c], pts[2 * k], pts[2 * k + 1], v, gx, gy);
+            double w = wts[k];
+            double wr = w * rho[c];
+            for (int b = 0; b < np; ++b)
+              for (int a = 0; a < np; ++a) K[b * np + a] += wr * (gx[a] * gx[b] + gy[a] * gy[b]);
+            double wf = w * fv[k];
+            for (int a = 0; a < np; ++a) bl[a] += wf * v[a];
+          }
+        }
+      });
+    }
+  }
+
+  // face blocks: interior faces 4 blocks (++, +-, -+, --), boundary 1 block;
+  // block (t, s) element (a, b) stored at b*np + a (a: test on t, b: trial on s)
+  const int64_t NF = (int64_t)A.faces.size();
+  std::vector<double> fblk((size_t)NF * 4 * np * np, 0.0);
+  parallel_for(NF, [&](int64_t lo, int64_t hi) {
+    double vp[16], gxp[16], gyp[16], vm[16], gxm[16], gym[16], gnp[16], gnm[16];
+    for (int64_t fi = lo; fi < hi; ++fi) {
+      const Face& F = A.faces[fi];
+      double ax = mesh.xy[2 * F.v0], ay = mesh.xy[2 * F.v0 + 1];
+      double bx = mesh.xy[2 * F.v1], by = mesh.xy[2 * F.v1 + 1];
+      double dx = bx - ax, dy = by - ay;
+      double L = std::sqrt(dx * dx + dy * dy);
+      double nx = dy / L, ny = -dx / L;
+      double* Bk = &fblk[(size_t)fi * 4 * np * np];
+      if (F.minus >= 0) {
+        double rp = rho[F.plus], rm = rho[F.minus];
+        double g = 2.0 * rp * rm / (rp + rm);
+        double hp = G.diam[F.plus], hm = G.diam[F.minus];
+        double hF = 2.0 * hp * hm / (hp + hm);
+        double sigma = c_sigma * g * pp / hF;
+        for (int q = 0; q < m; ++q) {
+          double x = ax + gq[q] * dx, y = ay + gq[q] * dy, w = L * wq[q];
+          basis_eval(p, G.box[F.plus], x, y, vp, gxp, gyp);
+          basis_eval(p, G.box[F.minus], x, y, vm, gxm, gym);
+          for (int a = 0; a < np; ++a) {
+            gnp[a] = gxp[a] * nx + gyp[a] * ny;
+            gnm[a] = gxm[a] * nx + gym[a] * ny;
+          }
+          const double* V[2] = {vp, vm};
+          const double* GN[2] = {gnp, gnm};
+          const double eps[2] = {1.0, -1.0};
+          for (int t = 0; t < 2; ++t)
+            for (int s = 0; s < 2; ++s) {
+              double* blk = Bk + (t * 2 + s) * np * np;
+              double c1 = -0.5 * g * eps[t] * w, c2 = -0.5 * g * eps[s] * w;
+              double c3 = sigma * eps[t] * eps[s] * w;
+              for (int b = 0; b < np; ++b)
+                for (int a = 0; a < np; ++a)
+                  blk[b * np + a] += c1 * V[t][a] * GN[s][b] + c2 * GN[t][a] * V[s][b] + c3 * V[t][a] * V[s][b];
+            }
+        }
+      } else {
+        double r = rho[F.plus];
+        double sigma = c_sigma * r * pp / G.diam[F.plus];
+        for (int q = 0; q < m; ++q) {
+          double x = ax + gq[q] * dx, y = ay + gq[q] * dy, w = L * wq[q];
+          basis_eval(p, G.box[F.plus], x, y, vp, gxp, gyp);
+          for (int a = 0; a < np; ++a) gnp[a] = gxp[a] * nx + gyp[a] * ny;
+          for (int b = 0; b < np; ++b)
+            for (int a = 0; a < np; ++a)
+              Bk[b * np + a] += w * (-r * vp[a] * gnp[b] - r * gnp[a] * vp[b] + sigma * vp[a] * vp[b]);
+        }
+      }
+    }
+  });
+
+  // accumulate rows (internal order), deterministic order: volume, then the
+  // cell's faces in face-index order
+  A.blocks.assign((size_t)A.row_ptr[N] * np * np, 0.0);
+  A.rhs.assign((size_t)N * np, 0.0);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      int32_t c = A.perm[r];
+      int32_t rs = A.row_ptr[r], re = A.row_ptr[r + 1];
+      auto slot = [&](int32_t col) {
+        int32_t k = (int32_t)(std::lower_bound(A.col_idx.begin() + rs, A.col_idx.begin() + re, col) -
+                              A.col_idx.begin());
+        return &A.blocks[(size_t)k * np * np];
+      };
+      double* D = slot((int32_t)r);
+      const double* Vb = &vol[(size_t)c * np * np];
+      for (int e = 0; e < np * np; ++e) D[e] += Vb[e];
+      for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
+        int32_t fi = cf[k] >> 1;
+        int t = cf[k] & 1;
+        const Face& F = A.faces[fi];
+        const double* Bk = &fblk[(size_t)fi * 4 * np * np];
+        if (F.minus < 0) {
+          for (int e = 0; e < np * np; ++e) D[e] += Bk[e];
+          continue;
+        }
+        const double* Btt = Bk + (t * 2 + t) * np * np;
+        for (int e = 0; e < np * np; ++e) D[e] += Btt[e];
+        int32_t other = t ? F.plus : F.minus;
+        double* O = slot(A.iperm[other]);
+        const double* Bts = Bk + (t * 2 + (1 - t)) * np * np;
+        for (int e = 0; e < np * np; ++e) O[e] += Bts[e];
+      }
+      for (int a = 0; a < np; ++a) A.rhs[(size_t)r * np + a] = rhs_c[(size_t)c * np + a];
+    }
+  });
+  return "";
+}
+
+std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const int32_t* coarse_of_cell,
+                         const MeshView* cmesh, Coarse& C) {
+  if (q < 1 || q > A.p) return "coarse degree q must satisfy 1 <= q <= p";
+  const int np = A.np, nq = n_basis(q);
+  const int32_t N = A.n_cells;
+  C.q = q;
+  C.nq = nq;
+  const int m = A.p + 2;
+  std::vector<double> gq, wq;
+  gauss_legendre01(m, gq, wq);
+  std::vector<std::vector<int32_t>> bcol(N);
+  std::vector<std::vector<double>> bval(N);
+  std::vector<Box> cbox;
+  const CellGeom& G = A.geom;
+
+  // mass matrix of a fine cell (caller index c)
+  auto mass = [&](int32_t c, std::vector<QuadPoint>& qp, std::vector<double>& M) {
+    double v[16];
+    cell_points(fine, G, c, gq, wq, qp);
+    M.assign(np * np, 0.0);
+    for (auto& P : qp) {
+      basis_eval(A.p, G.box[c], P.x, P.y, v, nullptr, nullptr);
+      for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) M[a * np + b] += P.w * v[a] * v[b];
+    }
+  };
+
+  if (cmesh == nullptr) {
+    if (!coarse_of_cell) return "need coarse_of_cell or coarse_mesh";
+    int32_t nc = 0;
+    for (int32_t c = 0; c < N; ++c) {
+      if (coarse_of_cell[c] < 0) return "negative coarse id";
+      nc = std::max(nc, coarse_of_cell[c] + 1);
+    }
+    std::vector<int> used(nc, 0);
+    cbox.assign(nc, Box{1e300, -1e300, 1e300, -1e300});
+    for (int32_t c = 0; c < N; ++c) {
+      int32_t j = coarse_of_cell[c];
+      used[j] = 1;
+      Box& B = cbox[j];
+      B.x0 = std::min(B.x0, G.box[c].x0);
+      B.x1 = std::max(B.x1, G.box[c].x1);
+      B.y0 = std::min(B.y0, G.box[c].y0);
+      B.y1 = std::max(B.y1, G.box[c].y1);
+    }
+    for (int32_t j = 0; j < nc; ++j)
+      if (!used[j]) return "coarse id " + std::to_string(j) + " is unused";
+    C.n_coarse = nc;
+    bool fail = false;
+    parallel_for(N, [&](int64_t lo, int64_t hi) {
+      std::vector<QuadPoint> qp;
+      std::vector<double> M, B(np * nq);
+      double v[16], psi[16];
+      for (int64_t c = lo; c < hi; ++c) {
+        mass((int32_t)c, qp, M);
+        int32_t j = coarse_of_cell[c];
+        std::fill(B.begin(), B.end(), 0.0);
+        for (auto& P : qp) {
+          basis_eval(A.p, G.box[c], P.x, P.y, v, nullptr, nullptr);
+          basis_eval(q, cbox[j], P.x, P.y, psi, nullptr, nullptr);
+          for (int a = 0; a < np; ++a)
+            for (int b = 0; b < nq; ++b) B[a * nq + b] += P.w * v[a] * psi[b];
+        }
+        if (!spd_solve(np, M, B.data(), nq)) fail = true;
+        bcol[c] = {j};
+        bval[c] = B;
+      }
+    });
+    if (fail) return "singular fine-cell mass matrix";
+  } else {
+    CellGeom CG;
+    std::string err = geometry(*cmesh, CG, true);
+    if (!err.empty()) return "coarse mesh: " + err;
+    int32_t nc = cmesh->n_cells;
+    C.n_coarse = nc;
+    cbox = CG.box;
+    std::vector<std::vector<double>> cpoly(nc);
+    for (int32_t j = 0; j < nc; ++j) cell_polygon(*cmesh, j, cpoly[j]);
+    bool fail = false;
+    parallel_for(N, [&](int64_t lo, int64_t hi) {
+      std::vector<QuadPoint> qp, cq;
+      std::vector<double> M, B(np * nq), P;
+      double v[16], psi[16];
+      for (int64_t c = lo; c < hi; ++c) {
+        mass((int32_t)c, qp, M);
+        cell_polygon(fine, (int32_t)c, P);
+        const Box& fb = G.box[c];
+        for (int32_t j = 0; j < nc; ++j) {
+          const Box& cb = cbox[j];
+          if (cb.x0 > fb.x1 || cb.x1 < fb.x0 || cb.y0 > fb.y1 || cb.y1 < fb.y0) continue;
+          std::vector<double> Q = clip_polygon(P, cpoly[j]);
+          if (Q.empty()) continue;
+          double qx, qy;
+          double ar = polygon_area_centroid(Q, qx, qy);
+          if (!(ar > 0.0)) continue;
+          cq.clear();
+          polygon_points(Q, gq, wq, cq);
+          std::fill(B.begin(), B.end(), 0.0);
+          for (auto& X : cq) {
+            basis_eval(A.p, fb, X.x, X.y, v, nullptr, nullptr);
+            basis_eval(q, cb, X.x, X.y, psi, nullptr, nullptr);
+            for (int a = 0; a < np; ++a)
+              for (int b = 0; b < nq; ++b) B[a * nq + b] += X.w * v[a] * psi[b];
+          }
+          if (!spd_solve(np, M, B.data(), nq)) fail = true;
+          bcol[c].push_back(j);
+          bval[c].insert(bval[c].end(), B.begin(), B.end());
+        }
+      }
+    });
+    if (fail) return "singular fine-cell mass matrix";
+    for (int32_t c = 0; c < N; ++c)
+      if (bcol[c].empty()) return "fine cell " + std::to_string(c) + " not covered by the coarse mesh";
+  }
+
+  // CSR by internal fine cell
+  C.ptr.assign(N + 1, 0);
+  for (int32_t r = 0; r < N; ++r) C.ptr[r + 1] = C.ptr[r] + (int32_t)bcol[A.perm[r]].size();
+  C.col.resize(C.ptr[N]);
+  C.val.resize((size_t)C.ptr[N] * np * nq);
+  for (int32_t r = 0; r < N; ++r) {
+    int32_t c = A.perm[r];
+    std::copy(bcol[c].begin(), bcol[c].end(), C.col.begin() + C.ptr[r]);
+    std::copy(bval[c].begin(), bval[c].end(), C.val.begin() + (size_t)C.ptr[r] * np * nq);
+  }
+  // transposed lists (coarse cell -> entries in increasing fine order)
+  const int32_t nc = C.n_coarse;
+  C.tptr.assign(nc + 1, 0);
+  for (int32_t e = 0; e < C.ptr[N]; ++e) C.tptr[C.col[e] + 1]++;
+  for (int32_t j = 0; j < nc; ++j) C.tptr[j + 1] += C.tptr[j];
+  C.tcell.resize(C.ptr[N]);
+  C.tblk.resize(C.ptr[N]);
+  {
+    std::vector<int32_t> fill(C.tptr.begin(), C.tptr.end() - 1);
+    for (int32_t r = 0; r < N; ++r)
+      for (int32_t e = C.ptr[r]; e < C.ptr[r + 1]; ++e) {
+        int32_t k = fill[C.col[e]]++;
+        C.tcell[k] = r;
+        C.tblk[k] = e;
+      }
+  }
+
+  // Galerkin A_0 = P_0^T A P_0. W_r = sum over row blocks A[r, s] P_0[s, :]
+  // (per fine row, sparse over coarse cells), then rows of A_0 per coarse cell.
+  std::vector<std::vector<int32_t>> wcol(N);
+  std::vector<std::vector<double>> wval(N);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      auto& wc = wcol[r];
+      auto& wv = wval[r];
+      for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
+        int32_t s = A.col_idx[k];
+        const double* Ab = &A.blocks[(size_t)k * np * np];
+        for (int32_t e = C.ptr[s]; e < C.ptr[s + 1]; ++e) {
+          int32_t J = C.col[e];
+          size_t pos = std::find(wc.begin(), wc.end(), J) - wc.begin();
+          if (pos == wc.size()) {
+            wc.push_back(J);
+            wv.resize(wv.size() + (size_t)np * nq, 0.0);
+          }
+          double* W = &wv[pos * np * nq];
+          const double* Pb = &C.val[(size_t)e * np * nq];
+          for (int a = 0; a < np; ++a)
+            for (int d = 0; d < nq; ++d) {
+              double acc = 0.0;
+              for (int b = 0; b < np; ++b) acc += Ab[b * np + a] * Pb[b * nq + d];
+              W[a * nq + d] += acc;
+            }
+        }
+      }
+    }
+  });
+  const int64_t n0 = (int64_t)nc * nq;
+  C.a0.assign((size_t)(n0 * n0), 0.0);
+  parallel_for(nc, [&](int64_t lo, int64_t hi) {
+    for (int64_t J = lo; J < hi; ++J) {
+      for (int32_t k = C.tptr[J]; k < C.tptr[J + 1]; ++k) {
+        int32_t r = C.tcell[k];
+        const double* Pb = &C.val[(size_t)C.tblk[k] * np * nq];
+        for (size_t t = 0; t < wcol[r].size(); ++t) {
+          int32_t K = wcol[r][t];
+          const double* W = &wval[r][t * np * nq];
+          for (int c = 0; c < nq; ++c)
+            for (int d = 0; d < nq; ++d) {
+              double acc = 0.0;
+              for (int a = 0; a < np; ++a) acc += Pb[a * nq + c] * W[a * nq + d];
+              C.a0[(size_t)(J * nq + c) * n0 + (size_t)K * nq + d] += acc;
+            }
+        }
+      }
+    }
+  });
+  return "";
+}
+
+}  // namespace asdg

@@ -1,0 +1,80 @@
+// Host-side discretisation of the SIPG problem and of the Schwarz coarse
+// transfer (internal to libasdg). Plain C++17, no HIP dependency.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace asdg {
+
+struct Box {
+  double x0, x1, y0, y1;
+};
+
+// Polygon mesh view (caller's arrays).
+struct MeshView {
+  int32_t n_vertices;
+  const double* xy;
+  int32_t n_cells;
+  const int32_t* ptr;
+  const int32_t* verts;
+};
+
+// Gauss-Legendre rule with m points on [0, 1] (weights sum to one).
+void gauss_legendre01(int m, std::vector<double>& x, std::vector<double>& w);
+
+// Scaled Legendre basis of total degree p on box B: n_p values and gradients.
+int n_basis(int p);
+void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx, double* gy);
+
+struct CellGeom {
+  std::vector<double> area, cx, cy, diam;
+  std::vector<Box> box;
+};
+
+struct Face {
+  int32_t plus, minus;  // minus < 0: boundary face
+  int32_t v0, v1;       // endpoints in the plus cell's CCW order
+};
+
+// SIPG system in the internal (subdomain-major) cell order.
+struct Assembled {
+  int p = 0, np = 0;
+  double c_sigma = 0.0;
+  int32_t n_cells = 0, n_sub = 0;
+  std::vector<int32_t> perm;     // internal cell -> caller cell
+  std::vector<int32_t> iperm;    // caller cell -> internal cell
+  std::vector<int32_t> sub_ptr;  // [n_sub + 1] internal cell offsets
+  std::vector<int32_t> row_ptr;  // BSR, internal order
+  std::vector<int32_t> col_idx;
+  std::vector<double> blocks;    // per block np*np, element (a,b) at b*np + a
+  std::vector<double> rhs;       // internal order
+  CellGeom geom;                 // caller order
+  std::vector<Face> faces;       // caller cell ids
+};
+
+// Returns empty string on success, otherwise an error message.
+std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const double* rho,
+                          const int32_t* subdomain,
+                          void (*f)(int64_t, const double*, double*, void*), void* f_user,
+                          Assembled& out);
+
+// Coarse transfer P_0 (internal fine order), CSR by fine cell with np x nq
+// blocks (row-major, element (a,c) at a*nq + c), and the Galerkin A_0.
+struct Coarse {
+  int q = 0, nq = 0;
+  int32_t n_coarse = 0;
+  std::vector<int32_t> ptr;     // [n_cells + 1]
+  std::vector<int32_t> col;     // coarse cell of each block
+  std::vector<double> val;      // blocks
+  std::vector<int32_t> tptr;    // [n_coarse + 1] transposed lists
+  std::vector<int32_t> tcell;   // fine (internal) cell of each entry
+  std::vector<int32_t> tblk;    // block index into col/val
+  std::vector<double> a0;       // dense n0 x n0 row-major
+};
+
+std::string build_coarse(const MeshView& fine, const Assembled& A, int q,
+                         const int32_t* coarse_of_cell, const MeshView* coarse_mesh, Coarse& out);
+
+}  // namespace asdg

@@ -1,0 +1,284 @@
+// Local matrices A_i = R_i A R_i^T (principal submatrices, Sec. 3) in
+// tile-packed form and their batched Cholesky factorisation in one
+// persistent launch.
+//
+// Left-looking tile algorithm. Task (i, j, b), b >= j, owns tile (b, j) of
+// subdomain i:
+//   S = A_bj - sum_{k<j} L_bk L_jk^T                      (MFMA)
+//   b == j: L_jj = chol(S) in LDS, store inv(L_jj) in the diagonal slot
+//   b >  j: L_bj = S inv(L_jj)^T                           (MFMA)
+// and raises the tile's flag. Tasks are dequeued from an atomic counter in
+// a host order where every dependency precedes its consumer; a task waits
+// (bounded) only on flags of tasks already dequeued by running work-groups.
+// Producers write tiles with device-coherent stores and release them with
+// an agent-scope fence before the flag; consumers read tiles produced in the
+// same launch with device-coherent loads.
+//
+// MFMA tiles: TILE = 64, four waves per work-group, each wave owns a 32x32
+// quadrant. FP32: v_mfma_f32_32x32x2f32; FP64: 2x2 v_mfma_f64_16x16x4f64.
+#include "kern_common.h"
+
+namespace asdg {
+
+namespace {
+
+constexpr int LDA = TILE + 1;  // padded LDS row (bank spread for column reads)
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Per-lane accumulator of a wave's 32x32 quadrant, 16 values per lane.
+template <typename T>
+struct Quad;
+
+template <>
+struct Quad<float> {
+  f32x16 c;
+  __device__ void zero() {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) c[e] = 0.0f;
+  }
+  __device__ static int row(int e, int lane) { return 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3); }
+  __device__ static int col(int e, int lane) { return lane & 31; }
+  __device__ float get(int e) const { return c[e]; }
+  __device__ void set(int e, float v) { c[e] = v; }
+  // c += sign * A[R0.., :] * B[C0.., :]^T with A, B in LDS (row-major, LDA)
+  __device__ void mma(const float* A, const float* B, int R0, int C0, int lane, float sign) {
+    const float* a = A + (R0 + (lane & 31)) * LDA + (lane >> 5);
+    const float* b = B + (C0 + (lane & 31)) * LDA + (lane >> 5);
+#pragma unroll 8
+    for (int k0 = 0; k0 < TILE; k0 += 2) c = __builtin_amdgcn_mfma_f32_32x32x2f32(sign * a[k0], b[k0], c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Quad<double> {
+  f64x4 c[4];
+  __device__ void zero() {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[s][v] = 0.0;
+  }
+  __device__ static int row(int e, int lane) { return 16 * ((e >> 2) >> 1) + 4 * (lane >> 4) + (e & 3); }
+  __device__ static int col(int e, int lane) { return 16 * ((e >> 2) & 1) + (lane & 15); }
+  __device__ double get(int e) const { return c[e >> 2][e & 3]; }
+  __device__ void set(int e, double v) { c[e >> 2][e & 3] = v; }
+  __device__ void mma(const double* A, const double* B, int R0, int C0, int lane, double sign) {
+    const double* a0 = A + (R0 + (lane & 15)) * LDA + (lane >> 4);
+    const double* a1 = a0 + 16 * LDA;
+    const double* b0 = B + (C0 + (lane & 15)) * LDA + (lane >> 4);
+    const double* b1 = b0 + 16 * LDA;
+#pragma unroll 4
+    for (int k0 = 0; k0 < TILE; k0 += 4) {
+      const double x0 = sign * a0[k0], x1 = sign * a1[k0];
+      const double y0 = b0[k0], y1 = b1[k0];
+      c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, c[1], 0, 0, 0);
+      c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, c[2], 0, 0, 0);
+      c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c[3], 0, 0, 0);
+    }
+  }
+};
+
+__device__ __forceinline__ void wait_flag(const int32_t* f, DevState* st) {
+  if (threadIdx.x == 0) {
+    int ok = load_agent(f) != 0;
+    for (int64_t budget = WAIT_BUDGET; !ok && budget > 0; --budget) {
+      __builtin_amdgcn_s_sleep(2);
+      ok = load_agent(f) != 0;
+      if (!ok && (budget & 255) == 0 && load_agent(&st->abort)) break;
+    }
+    if (!ok) store_agent(&st->abort, 1);
+    __threadfence();
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// Cooperative copy of a tile (global, row-major TILE x TILE) into LDS.
+template <typename T>
+__device__ __forceinline__ void tile_to_lds(const T* g, T* s, bool coherent) {
+  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
+    const T v = coherent ? load_agent(g + e) : g[e];
+    s[(e / TILE) * LDA + (e % TILE)] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* __restrict__ tasks,
+                                                  const SubDesc* __restrict__ subs, T* tiles, int32_t* flags,
+                                                  DevState* st, int32_t* queue) {
+  extern __shared__ unsigned char smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  T* Bs = As + TILE * LDA;
+  __shared__ int s_task;
+  __shared__ int s_fail;
+  constexpr size_t TT = (size_t)TILE * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R0 = 32 * (wave >> 1), C0 = 32 * (wave & 1);
+
+  for (;;) {
+    // after a failed wait every work-group stops taking tasks
+    if (tid == 0) s_task = load_agent(&st->abort) ? n_tasks : atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= n_tasks) break;
+    const int4 td = tasks[t];  // x: subdomain, y: column j, z: row b
+    const SubDesc sd = subs[td.x];
+    const int j = td.y, b = td.z;
+    T* base = tiles + (size_t)sd.tile0 * TT;
+    int32_t* fl = flags + sd.tile0;
+    T* Cg = base + (size_t)(b * (b + 1) / 2 + j) * TT;
+
+    Quad<T> acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      acc.set(e, Cg[(R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane)]);
+
+    for (int k = 0; k < j; ++k) {
+      wait_flag(fl + b * (b + 1) / 2 + k, st);
+      wait_flag(fl + j * (j + 1) / 2 + k, st);
+      tile_to_lds(base + (size_t)(b * (b + 1) / 2 + k) * TT, As, true);
+      tile_to_lds(base + (size_t)(j * (j + 1) / 2 + k) * TT, Bs, true);
+      __syncthreads();
+      acc.mma(As, Bs, R0, C0, lane, T(-1));
+      __syncthreads();
+    }
+
+    if (b == j) {
+      // S -> LDS, unblocked Cholesky of the lower triangle
+#pragma unroll
+      for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
+      if (tid == 0) s_fail = 0;
+      __syncthreads();
+      for (int kk = 0; kk < TILE; ++kk) {
+        if (tid == 0) {
+          T d = As[kk * LDA + kk];
+          if (!(d > T(0))) {
+            s_fail = 1;
+            d = T(1);
+          }
+          As[kk * LDA + kk] = sqrt(d);
+        }
+        __syncthreads();
+        if (tid > kk && tid < TILE) As[tid * LDA + kk] /= As[kk * LDA + kk];
+        __syncthreads();
+        const int m = TILE - kk - 1;
+        for (int e = tid; e < m * m; e += blockDim.x) {
+          const int ii = kk + 1 + e / m, jj = kk + 1 + e % m;
+          if (jj <= ii) As[ii * LDA + jj] -= As[ii * LDA + kk] * As[jj * LDA + kk];
+        }
+        __syncthreads();
+      }
+      if (s_fail && tid == 0) atomicMin(&st->chol_fail, td.x);
+      // inverse of the lower-triangular L_jj, one column per thread
+      if (tid < TILE) {
+        const int c = tid;
+        for (int ii = 0; ii < TILE; ++ii) {
+          T v;
+          if (ii < c) {
+            v = T(0);
+          } else if (ii == c) {
+            v = T(1) / As[c * LDA + c];
+          } else {
+            T s = T(0);
+            for (int m2 = c; m2 < ii; ++m2) s += As[ii * LDA + m2] * Bs[m2 * LDA + c];
+            v = -s / As[ii * LDA + ii];
+          }
+          Bs[ii * LDA + c] = v;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < TILE * TILE; e += blockDim.x) store_agent(Cg + e, Bs[(e / TILE) * LDA + (e % TILE)]);
+    } else {
+      // L_bj = S inv(L_jj)^T
+      wait_flag(fl + j * (j + 1) / 2 + j, st);
+      tile_to_lds(base + (size_t)(j * (j + 1) / 2 + j) * TT, Bs, true);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
+      __syncthreads();
+      acc.zero();
+      acc.mma(As, Bs, R0, C0, lane, T(1));
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        store_agent(Cg + (R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane), acc.get(e));
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) store_agent(fl + b * (b + 1) / 2 + j, 1);
+    __syncthreads();
+  }
+}
+
+// Tile-packed A_i from the BSR operator (identity on the padding).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(int np, int64_t n_elems, const int4* __restrict__ meta,
+                                                const SubDesc* __restrict__ subs, const int32_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ col, const double* __restrict__ blocks,
+                                                T* __restrict__ tiles) {
+  constexpr int64_t TT = (int64_t)TILE * TILE;
+  for (int64_t E = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; E < n_elems; E += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = E / TT;
+    const int e = (int)(E - t * TT);
+    const int4 m = meta[t];  // x: subdomain, y: b, z: j
+    const SubDesc sd = subs[m.x];
+    const int gr = m.y * TILE + e / TILE, gc = m.z * TILE + e % TILE;
+    double v;
+    if (gr >= sd.n || gc >= sd.n) {
+      v = (gr == gc) ? 1.0 : 0.0;
+    } else {
+      const int R = sd.dof0 + gr, C = sd.dof0 + gc;
+      const int cr = R / np, a = R - cr * np, cc = C / np, bb = C - cc * np;
+      v = 0.0;
+      for (int k = row_ptr[cr]; k < row_ptr[cr + 1]; ++k) {
+        if (col[k] == cc) {
+          v = blocks[(size_t)k * np * np + bb * np + a];
+          break;
+        }
+      }
+    }
+    tiles[E] = (T)v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* meta, const SubDesc* subs, const int32_t* row_ptr,
+                               const int32_t* col, const double* blocks, void* tiles, int f32, hipStream_t s) {
+  const int64_t n = (int64_t)n_tiles * TILE * TILE;
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
+  if (f32)
+    hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, np, n, meta, subs, row_ptr, col, blocks,
+                       (float*)tiles);
+  else
+    hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(256), 0, s, np, n, meta, subs, row_ptr, col, blocks,
+                       (double*)tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
+                           int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  if (f32) {
+    const size_t sh = 2 * TILE * LDA * sizeof(float);
+    hipLaunchKernelGGL(k_cholesky<float>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (float*)tiles, flags,
+                       st, queue);
+  } else {
+    const size_t sh = 2 * TILE * LDA * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_cholesky<double>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_cholesky<double>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (double*)tiles, flags,
+                       st, queue);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace asdg

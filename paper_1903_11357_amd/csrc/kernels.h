@@ -1,0 +1,79 @@
+// Launchers of the gfx950 kernels (internal to libasdg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace asdg {
+
+constexpr int TILE = 64;            // tile edge of the packed local/coarse factors
+constexpr int NPART = 1024;         // work-groups (and partial sums) of vector kernels
+constexpr int HIST = 65536;         // recorded CG coefficients (Lanczos estimate)
+
+// Device-resident PCG state (lives in the scratch buffer).
+struct DevState {
+  double bb;        // ||b||^2
+  double tol2;      // rtol^2 ||b||^2
+  double rr;        // last ||r||^2
+  int32_t it;       // completed iterations
+  int32_t done;     // 1 once the loop must stop
+  int32_t status;   // 0 running, 1 converged, 2 max_iter, 3 breakdown, 4 spin timeout
+  int32_t max_iter;
+  int32_t q_local;  // work queue counter of the local triangular solves
+  int32_t q_coarse; // work queue counter of the coarse triangular solves
+  int32_t q_chol;   // work queue counter of the factorisation
+  int32_t chol_fail;// smallest failing subdomain (0x7fffffff = none)
+  int32_t abort;    // set when a bounded wait expired
+  int32_t pad;
+};
+
+// Per-subdomain descriptor of a tile-packed lower-triangular factor.
+struct SubDesc {
+  int32_t dof0;   // first (internal) DoF of the subdomain
+  int32_t n;      // DoFs
+  int32_t nb;     // tile rows = ceil(n / TILE)
+  int32_t tile0;  // index of tile (0,0); tile (b,j) is tile0 + b(b+1)/2 + j
+};
+
+// Vector / operator kernels (kern_vec.hip).
+hipError_t launch_spmv(int np, int32_t n_cells, const int32_t* row_ptr, const int32_t* col,
+                       const double* blocks, const double* p, double* q, double* part_pq,
+                       const DevState* st, hipStream_t s);
+hipError_t launch_permute_in(int np, int32_t n_cells, const int32_t* perm, const double* src,
+                             double* r, double* x, void* yl, void* zl, int local_f32,
+                             double* part_bb, hipStream_t s);
+hipError_t launch_unpermute_out(int np, int32_t n_cells, const int32_t* perm, const double* x,
+                                double* dst, hipStream_t s);
+hipError_t launch_init_check(DevState* st, const double* part_bb, double rtol, int max_iter,
+                             hipStream_t s);
+hipError_t launch_update_xr(int64_t n, DevState* st, const double* part_pq, const double* rz_hist,
+                            double* alpha_hist, const double* p, const double* q, double* x,
+                            double* r, void* yl, void* zl, int local_f32, double* part_rr,
+                            hipStream_t s);
+hipError_t launch_check(DevState* st, const double* part_rr, const double* part_pq, hipStream_t s);
+hipError_t launch_restrict(int np, int nq, int32_t n_coarse, const int32_t* tptr, const int32_t* tcell,
+                           const int32_t* tblk, const double* P, const double* r, double* r0,
+                           double* y0, double* z0, const DevState* st, hipStream_t s);
+hipError_t launch_prolong(int np, int nq, int32_t n_cells, const int32_t* pptr, const int32_t* pcol,
+                          const double* P, const double* z0, const void* zl, int local_f32,
+                          const double* r, double* z, double* part_rz, const DevState* st,
+                          hipStream_t s);
+hipError_t launch_update_p(int64_t n, DevState* st, const double* part_rz, double* rz_hist,
+                           double* beta_hist, const double* z, double* p, int init, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_reset_queues(DevState* st, hipStream_t s);
+
+// Local-factor formation and batched Cholesky (kern_chol.hip).
+hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* tile_meta, const SubDesc* subs,
+                               const int32_t* row_ptr, const int32_t* col, const double* blocks,
+                               void* tiles, int f32, hipStream_t s);
+hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
+                           int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
+
+// Batched forward/backward triangular sweeps (kern_trsv.hip).
+hipError_t launch_trsv(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs,
+                       const void* tiles, const double* r, void* y, void* z, DevState* st,
+                       int32_t* queue, int grid, hipStream_t s);
+
+}  // namespace asdg

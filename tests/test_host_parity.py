@@ -1,0 +1,104 @@
+"""Host side of the C ABI (no GPU needed): symbols, SIPG assembly, load
+vector and Galerkin coarse operator against the oracle, input validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1903_11357_amd import asdg
+from paper_1903_11357_amd import inputs as I
+from oracle.schwarz import TwoLevelSchwarz
+from oracle.sipg import assemble
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "asdg.h")).read()
+    names = set(re.findall(r"\b(asdg_[a-z_0-9]+)\s*\(", hdr))
+    names -= {"asdg_field_fn"}
+    assert len(names) >= 14
+    lib = ctypes.CDLL(asdg.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def _rel(a, b):
+    return abs(a - b).max() / abs(b).max()
+
+
+CASES = {
+    "C1": lambda: I.make_config("C1"),
+    "voronoi_p2_jumps": lambda: I.voronoi_problem(400, 7, p=2, bx=3, by=3, q=1, log10_rho_range=3.0),
+    "voronoi_p3_nonnested": lambda: I.voronoi_problem(400, 8, p=3, bx=4, by=4, q=2, nonnested_coarse=9,
+                                                      log10_rho_range=1.0),
+    "voronoi_p4_q3": lambda: I.voronoi_problem(150, 9, p=4, bx=2, by=2, q=3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_host_assembly_matches_oracle(name):
+    P = CASES[name]()
+    pr = asdg.Problem()
+    pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    pr.plan(asdg.FP64, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
+            coarse_mesh=P.coarse_mesh)
+    A, b, geo, _ = assemble(P.mesh, P.p, P.rho, P.c_sigma, P.f)
+    M = TwoLevelSchwarz(A, P.mesh, P.p, geo, P.subdomain, q=P.q, coarse_of_cell=P.coarse_of_cell,
+                        coarse_mesh=P.coarse_mesh, local=False)
+    assert _rel(pr.export_operator().toarray(), A.toarray()) < 1e-13
+    assert _rel(pr.export_rhs(), b) < 1e-13
+    assert _rel(pr.export_coarse(), M.A0) < 1e-12
+    info = pr.info()
+    assert info[0] == P.mesh.n_cells and info[1] == P.n_p and info[3] == P.n_sub
+
+
+def test_plan_reports_buffer_sizes():
+    P = I.make_config("C1")
+    pr = asdg.Problem()
+    pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    b64 = pr.plan(asdg.FP64, 1, coarse_of_cell=P.coarse_of_cell)
+    b32 = pr.plan(asdg.FP32_LOCAL, 1, coarse_of_cell=P.coarse_of_cell)
+    assert all(v > 0 for v in b64)
+    # factor storage halves in FP32-local mode: 4 subdomains of 192 DoFs = 3x3 tile rows -> 6 tiles each
+    assert b64[1] >= 4 * 6 * 64 * 64 * 8 and b32[1] < b64[1]
+
+
+def test_validation_errors():
+    P = I.make_config("C1")
+    pr = asdg.Problem()
+    with pytest.raises(asdg.AsdgError) as e:
+        pr.assemble(P.mesh, 0, 10.0, P.rho, P.subdomain, P.f)
+    assert e.value.status == asdg.EINVAL
+    with pytest.raises(asdg.AsdgError):
+        pr.assemble(P.mesh, 1, -1.0, P.rho, P.subdomain, P.f)
+    with pytest.raises(asdg.AsdgError):
+        pr.assemble(P.mesh, 1, 10.0, -P.rho, P.subdomain, P.f)
+    bad = P.subdomain.copy()
+    bad[bad == 2] = 3
+    bad[bad == 1] = 3  # ids 1, 2 unused
+    with pytest.raises(asdg.AsdgError):
+        pr.assemble(P.mesh, 1, 10.0, P.rho, bad, P.f)
+    cw = I.Mesh(P.mesh.xy, P.mesh.cell_ptr, P.mesh.cell_vertices.copy())
+    cw.cell_vertices[0:4] = cw.cell_vertices[0:4][::-1]
+    with pytest.raises(asdg.AsdgError):
+        pr.assemble(cw, 1, 10.0, P.rho, P.subdomain, P.f)
+    # hole in the mesh: drop one interior cell
+    keep = np.arange(P.mesh.n_cells) != 17
+    cells = [P.mesh.cell(k) for k in range(P.mesh.n_cells) if keep[k]]
+    holed = I.Mesh(P.mesh.xy, np.arange(0, 4 * len(cells) + 1, 4, dtype=np.int32),
+                   np.concatenate(cells).astype(np.int32))
+    with pytest.raises(asdg.AsdgError):
+        pr.assemble(holed, 1, 10.0, P.rho[keep], P.subdomain[keep], P.f)
+    pr.assemble(P.mesh, 1, 10.0, P.rho, P.subdomain, P.f)
+    with pytest.raises(asdg.AsdgError):
+        pr.plan(asdg.FP64, 2, coarse_of_cell=P.coarse_of_cell)  # q > p
+    with pytest.raises(asdg.AsdgError) as e:
+        pr.factor(stream=_NullStream())
+    assert e.value.status == asdg.ESTATE
+
+
+class _NullStream:
+    cuda_stream = 0
