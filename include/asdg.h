@@ -86,7 +86,8 @@ typedef struct {
   int32_t max_iter;     /* >= 1                                            */
   int32_t check_every;  /* iterations per captured graph replay (>= 1)     */
   int32_t use_graph;    /* 1: replay a captured hipGraph, 0: eager launches */
-  int32_t time_kernels; /* 1: time the local-solve kernel with HIP events  */
+  int32_t time_kernels; /* 1: time every local-solve launch with HIP events
+                           on the launch stream (forces eager launches)    */
 } asdg_pcg_opts;
 
 typedef struct {
@@ -187,6 +188,31 @@ asdg_status asdg_export_rhs(const asdg_problem* pb, double* b);
 asdg_status asdg_export_operator(const asdg_problem* pb, int64_t* rows, int64_t* cols,
                                  double* vals);
 asdg_status asdg_export_coarse(const asdg_problem* pb, double* a0);
+
+/* Raw copy of the factor tiles of local subdomain `sub` (or the coarse
+ * factor for sub = -1) into host memory `out`: nb(nb+1)/2 row-major
+ * TILE x TILE tiles in packed lower order, diagonal tiles holding
+ * inv(L_bb), elements of the factor precision (8 bytes in FP64 mode, 4 in
+ * FP32-local mode; always 8 for the coarse factor). `out_bytes` must cover
+ * them. For verification of asdg_factor/asdg_setup_coarse. */
+asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, size_t out_bytes);
+
+/* Launch-shape tuning (autotuner hook): what = ASDG_TUNE_*; value 0 restores
+ * the default. CHOL_WG_PER_CU / TRSV_WG_PER_CU: persistent work-groups per
+ * compute unit of the factorisation and triangular-sweep launches;
+ * CHOL_GRID: total work-groups of the factorisation launch. */
+enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
+       ASDG_TUNE_TRACE = 3 };
+asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
+
+/* Task trace of the last batched local solve launched while
+ * ASDG_TUNE_TRACE = 1 (profiling aid). tasks: [n][4] int32 (subdomain,
+ * direction 0 = forward / 1 = backward, tile row, 0) in queue order; times:
+ * [n][3] wall-clock ticks per task (dequeued, waits done, finished);
+ * clock_mhz: tick rate. With tasks/times NULL only n_tasks (and the clock)
+ * are returned. */
+asdg_status asdg_export_trace(asdg_problem* pb, int32_t* tasks, uint64_t* times, int64_t max_tasks,
+                              int64_t* n_tasks, double* clock_mhz);
 
 /* Subdomain index of the last ENOTSPD failure (-1 = coarse, -2 = none). */
 int32_t asdg_failed_subdomain(const asdg_problem* pb);

@@ -70,7 +70,12 @@ _SIGS = {
                                        C.POINTER(C.c_double)]),
     "asdg_export_coarse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "asdg_failed_subdomain": (C.c_int32, [C.c_void_p]),
+    "asdg_export_factor_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
+    "asdg_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "asdg_export_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double)]),
 }
+TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE = 0, 1, 2, 3
 
 
 def lib():
@@ -139,6 +144,7 @@ class Problem:
         self._cb = FIELD_FN(cb)
         self._check(self._L.asdg_assemble(self.h, C.byref(m), p, c_sigma, _dptr(rho, C.c_double),
                                           _dptr(sub, C.c_int32), self._cb, None))
+        self._subsizes = np.bincount(sub) * ((p + 1) * (p + 2) // 2)
         del keep
         info = self.info()
         self.n_cells, self.n_p, self.n = int(info[0]), int(info[1]), int(info[2])
@@ -157,6 +163,7 @@ class Problem:
             cm = C.byref(m)
         self._check(self._L.asdg_plan(self.h, precision, q, coc, cm, b))
         del keep
+        self.precision = precision
         self.bytes = [int(v) for v in b]
         return self.bytes
 
@@ -178,6 +185,47 @@ class Problem:
 
     def factor(self, stream=None):
         self._check(self._L.asdg_factor(self.h, self._stream(stream)))
+
+    def set_tuning(self, what: int, value: int):
+        self._check(self._L.asdg_set_tuning(self.h, what, value))
+
+    def factor_dense(self, sub: int) -> np.ndarray:
+        """Dense lower-triangular factor of subdomain ``sub`` (-1: coarse),
+        rebuilt from the exported tiles (diagonal tiles hold inverses)."""
+        info = self.info()
+        T = info[7]
+        if sub < 0:
+            n, dt = info[4], np.float64
+        else:
+            n, dt = self._sub_sizes()[sub], (np.float32 if self.precision == FP32_LOCAL else np.float64)
+        nb = (n + T - 1) // T
+        buf = np.empty(nb * (nb + 1) // 2 * T * T, dtype=dt)
+        self._check(self._L.asdg_export_factor_tiles(self.h, sub, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+        tiles = buf.reshape(-1, T, T).astype(np.float64)
+        L = np.zeros((nb * T, nb * T))
+        for b in range(nb):
+            for j in range(b + 1):
+                t = tiles[b * (b + 1) // 2 + j]
+                if j == b:
+                    t = np.linalg.inv(np.tril(t))
+                L[b * T:(b + 1) * T, j * T:(j + 1) * T] = t
+        return np.tril(L)[:n, :n]
+
+    def _sub_sizes(self):
+        return self._subsizes
+
+    def export_trace(self):
+        """(tasks [n,4] int32, times [n,3] uint64, clock MHz) of the last
+        traced batched local solve."""
+        n = C.c_int64()
+        mhz = C.c_double()
+        self._check(self._L.asdg_export_trace(self.h, None, None, 0, C.byref(n), C.byref(mhz)))
+        tasks = np.empty((n.value, 4), dtype=np.int32)
+        times = np.empty((n.value, 3), dtype=np.uint64)
+        self._check(self._L.asdg_export_trace(self.h, tasks.ctypes.data_as(C.c_void_p),
+                                              times.ctypes.data_as(C.c_void_p), n.value, C.byref(n),
+                                              C.byref(mhz)))
+        return tasks, times, mhz.value
 
     def failed_subdomain(self) -> int:
         return int(self._L.asdg_failed_subdomain(self.h))

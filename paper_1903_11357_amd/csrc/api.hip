@@ -109,11 +109,12 @@ struct asdg_problem {
   struct { size_t row_ptr, col, blocks, rhs, perm; } o0{};
   struct { size_t tiles, subs, chol, trsv, meta; } o1{};
   struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv; } o2{};
-  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, ppq, prr, prz, pbb, st, rz2, ah, bh, flags; } o3{};
+  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace; } o3{};
   size_t bytes[4] = {0, 0, 0, 0};
   char* buf[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t failed_sub = -2;
   int n_cu = 256;
+  int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
   // captured iteration chunk
   hipGraphExec_t gexec = nullptr;
   int g_k = 0, g_timed = 0;
@@ -223,11 +224,12 @@ void plan_local(asdg_problem* pb) {
   std::stable_sort(ks.begin(), ks.end(), [](const K& a, const K& b) { return a.key < b.key; });
   pb->chol_tasks.resize(ks.size());
   for (size_t k = 0; k < ks.size(); ++k) pb->chol_tasks[k] = ks[k].t;
-  // sweep tasks: forward b at step off+b, backward b at step off+2nb-1-b
+  // sweep tasks: forward b at step b, backward b at step 2nb-1-b; all
+  // subdomains start together, tasks of one step are contiguous in the queue
   ks.clear();
   for (int32_t i = 0; i < ns; ++i) {
     int nb = pb->subs[i].nb;
-    int64_t off = 2 * (int64_t)(nbmax - nb);
+    int64_t off = 0;
     for (int b = 0; b < nb; ++b) {
       ks.push_back({((off + b) * ns + i), make_int4(i, 0, b, 0)});
       ks.push_back({((off + 2 * nb - 1 - b) * ns + i), make_int4(i, 1, b, 0)});
@@ -261,7 +263,7 @@ void plan_coarse_factor(asdg_problem* pb) {
   for (int b = nb - 1; b >= 0; --b) pb->ctrsv_tasks.push_back(make_int4(0, 1, b, 0));
 }
 
-asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_done, double* part_rz,
+asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_done, Reduction* red,
                             hipEvent_t ev0, hipEvent_t ev1) {
   const int np = pb->A.np;
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
@@ -273,46 +275,45 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_
                                pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), st_done, s));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
-  const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(), (int64_t)pb->n_cu * 4);
+  const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
+                                                 (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
   HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
                          pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
-                         pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid, s));
+                         pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
+                         pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
   if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
   if (pb->has_coarse) {
     const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
     HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
                            pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
                            pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0),
-                           pb->ptr<void>(3, pb->o3.z0), st, &st->q_coarse, cgrid, s));
+                           pb->ptr<void>(3, pb->o3.z0), st, &st->q_coarse, cgrid, nullptr, s));
   }
   HIPCHK(pb, launch_prolong(np, pb->has_coarse ? pb->C.nq : 3, pb->A.n_cells,
                             pb->has_coarse ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                             pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
                             pb->ptr<double>(3, pb->o3.z0), pb->ptr<void>(3, pb->o3.zl), pb->f32, r,
-                            pb->ptr<double>(3, pb->o3.z), part_rz, st_done, s));
+                            pb->ptr<double>(3, pb->o3.z), red, st_done, s));
   return ASDG_OK;
 }
 
 asdg_status enqueue_iteration(asdg_problem* pb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int np = pb->A.np;
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  Reduction* red = pb->ptr<Reduction>(3, pb->o3.red);
   double* x = pb->ptr<double>(3, pb->o3.x);
   double* r = pb->ptr<double>(3, pb->o3.r);
   double* p = pb->ptr<double>(3, pb->o3.p);
   double* q = pb->ptr<double>(3, pb->o3.q);
   double* z = pb->ptr<double>(3, pb->o3.z);
-  double* ppq = pb->ptr<double>(3, pb->o3.ppq);
-  double* prr = pb->ptr<double>(3, pb->o3.prr);
-  double* prz = pb->ptr<double>(3, pb->o3.prz);
   double* rz2 = pb->ptr<double>(3, pb->o3.rz2);
   HIPCHK(pb, launch_spmv(np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
-                         pb->ptr<double>(0, pb->o0.blocks), p, q, ppq, st, s));
-  HIPCHK(pb, launch_update_xr(pb->n(), st, ppq, rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x, r,
-                              pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), pb->f32, prr, s));
-  HIPCHK(pb, launch_check(st, prr, ppq, s));
-  asdg_status e = enqueue_precond(pb, s, st, prz, ev0, ev1);
+                         pb->ptr<double>(0, pb->o0.blocks), p, q, red, st, s));
+  HIPCHK(pb, launch_update_xr(pb->n(), st, red, rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x, r,
+                              pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), pb->f32, s));
+  asdg_status e = enqueue_precond(pb, s, st, red, ev0, ev1);
   if (e != ASDG_OK) return e;
-  HIPCHK(pb, launch_update_p(pb->n(), st, prz, rz2, pb->ptr<double>(3, pb->o3.bh), z, p, 0, s));
+  HIPCHK(pb, launch_update_p(pb->n(), st, red, rz2, pb->ptr<double>(3, pb->o3.bh), z, p, 0, s));
   return ASDG_OK;
 }
 
@@ -397,15 +398,13 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o3.r0 = L3.add(8 * n0);
   pb->o3.y0 = L3.add(8 * n0);
   pb->o3.z0 = L3.add(8 * n0);
-  pb->o3.ppq = L3.add(8 * NPART);
-  pb->o3.prr = L3.add(8 * NPART);
-  pb->o3.prz = L3.add(8 * NPART);
-  pb->o3.pbb = L3.add(8 * NPART);
+  pb->o3.red = L3.add(sizeof(Reduction) * N_RED);
   pb->o3.st = L3.add(sizeof(DevState));
   pb->o3.rz2 = L3.add(16);
   pb->o3.ah = L3.add(8 * (size_t)HIST);
   pb->o3.bh = L3.add(8 * (size_t)HIST);
   pb->o3.flags = L3.add(4 * (size_t)std::max<int64_t>(pb->n_tiles, pb->n_ctiles));
+  pb->o3.trace = L3.add(3 * 8 * pb->trsv_tasks.size());
   pb->bytes[0] = L0.size;
   pb->bytes[1] = L1.size;
   pb->bytes[2] = L2.size;
@@ -438,7 +437,16 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   };
   HIPCHK(pb, up(0, pb->o0.row_ptr, A.row_ptr.data(), 4 * A.row_ptr.size()));
   HIPCHK(pb, up(0, pb->o0.col, A.col_idx.data(), 4 * A.col_idx.size()));
-  HIPCHK(pb, up(0, pb->o0.blocks, A.blocks.data(), 8 * A.blocks.size()));
+  {
+    // device blocks are row-major (host assembly keeps them column-major)
+    const int np = A.np;
+    std::vector<double> rm(A.blocks.size());
+    for (size_t k = 0; k < A.blocks.size() / (np * np); ++k)
+      for (int r = 0; r < np; ++r)
+        for (int c = 0; c < np; ++c) rm[k * np * np + r * np + c] = A.blocks[k * np * np + c * np + r];
+    HIPCHK(pb, up(0, pb->o0.blocks, rm.data(), 8 * rm.size()));
+    HIPCHK(pb, hipStreamSynchronize(s));  // rm is released at the end of this scope
+  }
   HIPCHK(pb, up(0, pb->o0.rhs, pb->rhs_caller.data(), 8 * pb->rhs_caller.size()));
   HIPCHK(pb, up(0, pb->o0.perm, A.perm.data(), 4 * A.perm.size()));
   HIPCHK(pb, up(1, pb->o1.subs, pb->subs.data(), sizeof(SubDesc) * pb->subs.size()));
@@ -457,6 +465,7 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
     HIPCHK(pb, up(2, pb->o2.cchol, pb->cchol_tasks.data(), sizeof(int4) * pb->cchol_tasks.size()));
     HIPCHK(pb, up(2, pb->o2.ctrsv, pb->ctrsv_tasks.data(), sizeof(int4) * pb->ctrsv_tasks.size()));
   }
+  HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.red), (int64_t)(sizeof(Reduction) * N_RED / 4), 0, s));
   HIPCHK(pb, hipStreamSynchronize(s));
   pb->stage = 3;
   pb->coarse_ready = false;
@@ -469,8 +478,9 @@ static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int32_
   int32_t* flags = pb->ptr<int32_t>(3, pb->o3.flags);
   HIPCHK(pb, launch_fill_i32(flags, n_tiles, 0, s));
   HIPCHK(pb, launch_reset_queues(st, s));
-  const int per_cu = f32 ? 4 : 2;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tasks, (int64_t)pb->n_cu * per_cu));
+  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : (f32 ? 4 : 2);
+  int64_t gmax = pb->chol_grid > 0 ? pb->chol_grid : (int64_t)pb->n_cu * per_cu;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tasks, gmax));
   HIPCHK(pb, launch_cholesky(f32, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
   DevState h;
   asdg_status e = read_state(pb, s, h);
@@ -528,6 +538,9 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
   asdg_pcg_opts o{1e-8, 20000, 16, 1, 0};
   if (opts) o = *opts;
   if (!(o.rtol >= 0.0) || o.max_iter < 1 || o.check_every < 1) FAIL(pb, ASDG_EINVAL, "invalid PCG options");
+  // HIP events recorded inside a captured graph do not bracket the kernel
+  // between them, so kernel timing always uses eager launches
+  if (o.time_kernels) o.use_graph = 0;
   hipStream_t s = (hipStream_t)stream;
   const int np = pb->A.np;
   const int32_t N = pb->A.n_cells;
@@ -547,13 +560,13 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
   HIPCHK(pb, hipEventRecord(pb->t0, s));
   // x = 0, r = b (internal order), ||b||^2, z = P^{-1} r, p = z
   const double* src = d_b ? d_b : pb->ptr<double>(0, pb->o0.rhs);
+  Reduction* red = pb->ptr<Reduction>(3, pb->o3.red);
   HIPCHK(pb, launch_permute_in(np, N, pb->ptr<int32_t>(0, pb->o0.perm), src, pb->ptr<double>(3, pb->o3.r),
                                pb->ptr<double>(3, pb->o3.x), pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
-                               pb->f32, pb->ptr<double>(3, pb->o3.pbb), s));
-  HIPCHK(pb, launch_init_check(st, pb->ptr<double>(3, pb->o3.pbb), o.rtol, o.max_iter, s));
-  asdg_status e = enqueue_precond(pb, s, st, pb->ptr<double>(3, pb->o3.prz), nullptr, nullptr);
+                               pb->f32, red, st, o.rtol, o.max_iter, s));
+  asdg_status e = enqueue_precond(pb, s, st, red, nullptr, nullptr);
   if (e != ASDG_OK) return e;
-  HIPCHK(pb, launch_update_p(pb->n(), st, pb->ptr<double>(3, pb->o3.prz), pb->ptr<double>(3, pb->o3.rz2),
+  HIPCHK(pb, launch_update_p(pb->n(), st, red, pb->ptr<double>(3, pb->o3.rz2),
                              pb->ptr<double>(3, pb->o3.bh), pb->ptr<double>(3, pb->o3.z), pb->ptr<double>(3, pb->o3.p),
                              1, s));
   double t_local = 0.0;
@@ -587,11 +600,16 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
       HIPCHK(pb, hipStreamSynchronize(gs));
       e = read_state(pb, s, h);
       if (e != ASDG_OK) return e;
-      if (o.time_kernels) {
+      if (o.time_kernels && n_local >= 0) {
         const int ran = h.it - it0 - (h.done ? 1 : 0);
         for (int i = 0; i < ran && i < k; ++i) {
           float ms = 0.f;
-          HIPCHK(pb, hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]));
+          if (hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]) != hipSuccess) {
+            (void)hipGetLastError();
+            n_local = -1;  // event timing inside graphs unavailable
+            t_local = 0.0;
+            break;
+          }
           t_local += ms;
           ++n_local;
         }
@@ -668,7 +686,7 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
   double* z = pb->ptr<double>(3, pb->o3.z);
   int32_t* perm = pb->ptr<int32_t>(0, pb->o0.perm);
   HIPCHK(pb, launch_permute_in(np, N, perm, d_in, r, nullptr, pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
-                               pb->f32, nullptr, s));
+                               pb->f32, nullptr, nullptr, 0.0, 0, s));
   HIPCHK(pb, launch_reset_queues(st, s));
   if (what == ASDG_APPLY_OPERATOR) {
     HIPCHK(pb, launch_spmv(np, N, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
@@ -682,17 +700,19 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                                  pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
                                  pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), nullptr, s));
     if (loc) {
-      const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(), (int64_t)pb->n_cu * 4);
+      const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
+                                                 (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
       HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
                              pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
-                             pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid, s));
+                             pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
+                         pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
     }
     if (crs) {
       const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
       HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
                              pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
                              pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0), pb->ptr<void>(3, pb->o3.z0),
-                             st, &st->q_coarse, cgrid, s));
+                             st, &st->q_coarse, cgrid, nullptr, s));
     }
     HIPCHK(pb, launch_prolong(np, crs ? pb->C.nq : 3, N, crs ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                               pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
@@ -756,5 +776,59 @@ asdg_status asdg_export_coarse(const asdg_problem* pb, double* a0) {
 }
 
 int32_t asdg_failed_subdomain(const asdg_problem* pb) { return pb ? pb->failed_sub : -2; }
+
+asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, size_t out_bytes) {
+  if (!pb || !out) return ASDG_EINVAL;
+  if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "no bound factor storage");
+  const char* src;
+  size_t nbytes;
+  if (sub < 0) {
+    if (!pb->has_coarse) FAIL(pb, ASDG_ESTATE, "no coarse level");
+    src = pb->buf[2] + pb->o2.ctiles;
+    nbytes = (size_t)pb->n_ctiles * TILE * TILE * 8;
+  } else {
+    if (sub >= pb->A.n_sub) FAIL(pb, ASDG_EINVAL, "subdomain out of range");
+    const SubDesc& d = pb->subs[sub];
+    const size_t w = pb->f32 ? 4 : 8;
+    src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * TILE * TILE * w;
+    nbytes = (size_t)d.nb * (d.nb + 1) / 2 * TILE * TILE * w;
+  }
+  if (out_bytes < nbytes) FAIL(pb, ASDG_ENOMEM, "output too small");
+  HIPCHK(pb, hipDeviceSynchronize());
+  HIPCHK(pb, hipMemcpy(out, src, nbytes, hipMemcpyDeviceToHost));
+  return ASDG_OK;
+}
+
+asdg_status asdg_export_trace(asdg_problem* pb, int32_t* tasks, uint64_t* times, int64_t max_tasks,
+                              int64_t* n_tasks, double* clock_mhz) {
+  if (!pb || !n_tasks) return ASDG_EINVAL;
+  if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "nothing traced");
+  const int64_t nt = (int64_t)pb->trsv_tasks.size();
+  *n_tasks = nt;
+  if (clock_mhz) {
+    int dev = 0, khz = 0;
+    HIPCHK(pb, hipGetDevice(&dev));
+    HIPCHK(pb, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *clock_mhz = khz / 1000.0;
+  }
+  if (!tasks || !times) return ASDG_OK;
+  if (max_tasks < nt) FAIL(pb, ASDG_ENOMEM, "output too small");
+  std::memcpy(tasks, pb->trsv_tasks.data(), sizeof(int4) * nt);
+  HIPCHK(pb, hipDeviceSynchronize());
+  HIPCHK(pb, hipMemcpy(times, pb->buf[3] + pb->o3.trace, 3 * 8 * nt, hipMemcpyDeviceToHost));
+  return ASDG_OK;
+}
+
+asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
+  if (!pb) return ASDG_EINVAL;
+  if (value < 0 || value > 65536) FAIL(pb, ASDG_EINVAL, "tuning value out of range");
+  if (what == ASDG_TUNE_CHOL_WG_PER_CU) pb->chol_per_cu = value;
+  else if (what == ASDG_TUNE_TRSV_WG_PER_CU) pb->trsv_per_cu = value;
+  else if (what == ASDG_TUNE_CHOL_GRID) pb->chol_grid = value;
+  else if (what == ASDG_TUNE_TRACE) pb->trace = value;
+  else FAIL(pb, ASDG_EINVAL, "unknown tuning key");
+  pb->drop_graph();
+  return ASDG_OK;
+}
 
 }  // extern "C"

@@ -10,9 +10,10 @@
 // and raises the tile's flag. Tasks are dequeued from an atomic counter in
 // a host order where every dependency precedes its consumer; a task waits
 // (bounded) only on flags of tasks already dequeued by running work-groups.
-// Producers write tiles with device-coherent stores and release them with
-// an agent-scope fence before the flag; consumers read tiles produced in the
-// same launch with device-coherent loads.
+// Producers write tiles with device-coherent stores and raise the flag only
+// after those stores have completed; consumers read tiles produced in the
+// same launch with device-coherent loads, so no cache write-back or
+// invalidation is needed.
 //
 // MFMA tiles: TILE = 64, four waves per work-group, each wave owns a 32x32
 // quadrant. FP32: v_mfma_f32_32x32x2f32; FP64: 2x2 v_mfma_f64_16x16x4f64.
@@ -38,6 +39,7 @@ struct Quad<float> {
 #pragma unroll
     for (int e = 0; e < 16; ++e) c[e] = 0.0f;
   }
+  // v_mfma_f32_32x32x2f32 result: register e of lane l holds D[8(e/4) + 4(l/32) + e%4][l%32]
   __device__ static int row(int e, int lane) { return 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3); }
   __device__ static int col(int e, int lane) { return lane & 31; }
   __device__ float get(int e) const { return c[e]; }
@@ -60,7 +62,8 @@ struct Quad<double> {
 #pragma unroll
       for (int v = 0; v < 4; ++v) c[s][v] = 0.0;
   }
-  __device__ static int row(int e, int lane) { return 16 * ((e >> 2) >> 1) + 4 * (lane >> 4) + (e & 3); }
+  // v_mfma_f64_16x16x4f64 result: register v of lane l holds D[4v + l/16][l%16]
+  __device__ static int row(int e, int lane) { return 16 * ((e >> 2) >> 1) + 4 * (e & 3) + (lane >> 4); }
   __device__ static int col(int e, int lane) { return 16 * ((e >> 2) & 1) + (lane & 15); }
   __device__ double get(int e) const { return c[e >> 2][e & 3]; }
   __device__ void set(int e, double v) { c[e >> 2][e & 3] = v; }
@@ -90,10 +93,8 @@ __device__ __forceinline__ void wait_flag(const int32_t* f, DevState* st) {
       if (!ok && (budget & 255) == 0 && load_agent(&st->abort)) break;
     }
     if (!ok) store_agent(&st->abort, 1);
-    __threadfence();
   }
   __syncthreads();
-  __threadfence();
 }
 
 // Cooperative copy of a tile (global, row-major TILE x TILE) into LDS.
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* _
       for (int e = 0; e < 16; ++e)
         store_agent(Cg + (R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane), acc.get(e));
     }
-    __threadfence();
+    wait_own_stores();
     __syncthreads();
     if (tid == 0) store_agent(fl + b * (b + 1) / 2 + j, 1);
     __syncthreads();
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void k_gather(int np, int64_t n_elems, const i
       v = 0.0;
       for (int k = row_ptr[cr]; k < row_ptr[cr + 1]; ++k) {
         if (col[k] == cc) {
-          v = blocks[(size_t)k * np * np + bb * np + a];
+          v = blocks[(size_t)k * np * np + a * np + bb];  // row-major blocks
           break;
         }
       }

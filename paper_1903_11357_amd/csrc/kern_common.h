@@ -33,6 +33,11 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Waits until every earlier memory operation of this thread has completed.
+// Data written with store_agent() is then visible device-wide, so a flag or
+// counter updated afterwards publishes it without an L2 write-back.
+__device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
 // Bounded wait budget: every wait ends, either when its value arrives or
 // when the budget is spent (then the kernel raises DevState::abort and all
 // other waits end at once).
@@ -59,11 +64,47 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return s;
 }
 
-// Deterministic sum of NPART partials, computed redundantly by a work-group.
-__device__ __forceinline__ double reduce_partials(const double* part, double* scratch) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < NPART; i += blockDim.x) v += part[i];
-  return block_sum(v, scratch);
+// Deterministic grid-wide sum. Every work-group of the launch calls this
+// once with its thread values. Arrivals are counted in two levels (groups of
+// RGROUP consecutive work-groups, then the groups) so that no counter sees
+// more than RGROUP or MAXG/RGROUP atomic increments. The last work-group of
+// a group adds the group's partials in index order; the last group adds the
+// group sums in index order, stores the total in R->result and returns true
+// (all its threads receive the total). Counters re-arm themselves. Requires
+// gridDim.x <= MAXG.
+__device__ __forceinline__ bool grid_sum(double v, Reduction* R, double* scratch, double& total) {
+  __shared__ int s_flag;
+  v = block_sum(v, scratch);
+  const int g = blockIdx.x / RGROUP;
+  const int g0 = g * RGROUP;
+  const int gsize = min(RGROUP, (int)gridDim.x - g0);
+  const int ngroups = ((int)gridDim.x + RGROUP - 1) / RGROUP;
+  if (threadIdx.x == 0) {
+    store_agent(&R->partial[blockIdx.x], v);
+    wait_own_stores();
+    s_flag = atomicAdd(&R->gcounter[g], 1u) == (uint32_t)(gsize - 1);
+  }
+  __syncthreads();
+  if (!s_flag) return false;
+  // last of its group
+  double s = threadIdx.x < gsize ? load_agent(&R->partial[g0 + threadIdx.x]) : 0.0;
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) {
+    store_agent(&R->gcounter[g], 0u);
+    store_agent(&R->gpartial[g], s);
+    wait_own_stores();
+    s_flag = atomicAdd(&R->counter, 1u) == (uint32_t)(ngroups - 1);
+  }
+  __syncthreads();
+  if (!s_flag) return false;
+  // last group
+  double t = threadIdx.x < ngroups ? load_agent(&R->gpartial[threadIdx.x]) : 0.0;
+  total = block_sum(t, scratch);
+  if (threadIdx.x == 0) {
+    R->result = total;
+    store_agent(&R->counter, 0u);
+  }
+  return true;
 }
 
 }  // namespace asdg

@@ -15,7 +15,8 @@
 // assumption). The dependency "value written" is carried by the values
 // themselves: y and z are pre-filled with a NaN sentinel and written with
 // device-coherent stores; consumers poll the values they need with
-// device-coherent loads. Every wait is bounded (see kern_common.h).
+// device-coherent loads (one per thread per chunk of tiles, shared through
+// LDS). Every wait is bounded (see kern_common.h).
 #include "kern_common.h"
 
 namespace asdg {
@@ -51,13 +52,21 @@ __device__ __forceinline__ T wait_value(const T* p, DevState* st) {
   return T(0);
 }
 
-constexpr int UNROLL = 4;
-
+// One thread waits for `p` (the value a producer wrote last, or one of the
+// values it wrote together); the barrier then releases the work-group, whose
+// threads read their own values with wait_value (almost always at once).
+// Keeps the polling traffic of a waiting work-group to a single thread.
 template <typename T>
+__device__ __forceinline__ void wait_group(const T* p, DevState* st) {
+  if (threadIdx.x == 0 && p) (void)wait_value(p, st);
+  __syncthreads();
+}
+
+template <typename T, int UNROLL>
 __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __restrict__ tasks,
                                               const SubDesc* __restrict__ subs, const T* __restrict__ tiles,
                                               const double* __restrict__ r, T* y, T* z, DevState* st,
-                                              int32_t* queue) {
+                                              int32_t* queue, uint64_t* trace) {
   using VT = Vec16<T>;
   using V = typename VT::V;
   constexpr int VEC = VT::N;
@@ -68,6 +77,8 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
   __shared__ int s_task;
   __shared__ T s_vec[TILE];
   __shared__ T s_red[4][TILE];
+  __shared__ T s_x[2][UNROLL * TILE];  // staged y (forward) or z (backward) values, double-buffered
+  static_assert(UNROLL * TILE <= 256, "one staged value per thread");
   if (st->done) return;
   const int tid = threadIdx.x;
   const int lc = tid % LPR, r0 = tid / LPR;
@@ -79,12 +90,23 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
     const int t = s_task;
     __syncthreads();
     if (t >= n_tasks) break;
+    if (trace && tid == 0) trace[3 * (size_t)t] = wall_clock64();
     const int4 td = tasks[t];
     const SubDesc sd = subs[td.x];
     const int b = td.z;
     const int n = sd.n;
     const T* base = tiles + (size_t)sd.tile0 * TT;
     const T* D = base + (size_t)(b * (b + 1) / 2 + b) * TT;
+    // the diagonal inverse and the right-hand side are needed last: fetch them first
+    V dv[PASSES];
+#pragma unroll
+    for (int k = 0; k < PASSES; ++k) dv[k] = *(const V*)(D + (r0 + RPP * k) * TILE + lc * VEC);
+    T rhs[PASSES];  // forward: r rows of this tile row (lanes lc == 0)
+#pragma unroll
+    for (int k = 0; k < PASSES; ++k) {
+      const int gi = b * TILE + r0 + RPP * k;
+      rhs[k] = (td.y == 0 && lc == 0 && gi < n) ? (T)r[sd.dof0 + gi] : T(0);
+    }
 
     if (td.y == 0) {
       // ---------------- forward: row tiles (b, 0..b-1), then inv(L_bb)
@@ -92,40 +114,34 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
 #pragma unroll
       for (int k = 0; k < PASSES; ++k) acc[k] = T(0);
       const T* rowbase = base + (size_t)(b * (b + 1) / 2) * TT;
-      const T* yv = y + sd.dof0 + lc * VEC;
-      int j = 0;
-      for (; j + UNROLL <= b; j += UNROLL) {
+      const T* yv0 = y + sd.dof0;
+      int buf = 0;
+      for (int j = 0; j < b; j += UNROLL, buf ^= 1) {
         V tv[UNROLL][PASSES];
 #pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const bool ok = j + u < b;
+#pragma unroll
+          for (int k = 0; k < PASSES; ++k)
+            tv[u][k] = ok ? *(const V*)(rowbase + (size_t)(j + u) * TT + (r0 + RPP * k) * TILE + lc * VEC) : V{};
+        }
+        // the chunk's y values: one poller for the latest tile, then one
+        // device-coherent load per thread, shared via LDS
+        const int jl = min(j + UNROLL, b) - 1;
+        wait_group(yv0 + jl * TILE + TILE - 1, st);
+        if (tid < UNROLL * TILE) {
+          const int jt = j + tid / TILE;
+          s_x[buf][tid] = jt < b ? wait_value(yv0 + jt * TILE + (tid % TILE), st) : T(0);
+        }
+        __syncthreads();
+#pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
           for (int k = 0; k < PASSES; ++k)
-            tv[u][k] = *(const V*)(rowbase + (size_t)(j + u) * TT + (r0 + RPP * k) * TILE + lc * VEC);
-        T xv[UNROLL][VEC];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) xv[u][v] = wait_value(yv + (j + u) * TILE + v, st);
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-          for (int k = 0; k < PASSES; ++k)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[k] += VT::at(tv[u][k], v) * xv[u][v];
+            for (int v = 0; v < VEC; ++v) acc[k] += VT::at(tv[u][k], v) * s_x[buf][u * TILE + lc * VEC + v];
       }
-      for (; j < b; ++j) {
-        V tv[PASSES];
-#pragma unroll
-        for (int k = 0; k < PASSES; ++k)
-          tv[k] = *(const V*)(rowbase + (size_t)j * TT + (r0 + RPP * k) * TILE + lc * VEC);
-        T xv[VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) xv[v] = wait_value(yv + j * TILE + v, st);
-#pragma unroll
-        for (int k = 0; k < PASSES; ++k)
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[k] += VT::at(tv[k], v) * xv[v];
-      }
+      if (trace && tid == 0) trace[3 * (size_t)t + 1] = wall_clock64();
 #pragma unroll
       for (int k = 0; k < PASSES; ++k)
 #pragma unroll
@@ -133,10 +149,7 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
       if (lc == 0) {
 #pragma unroll
         for (int k = 0; k < PASSES; ++k) {
-          const int row = r0 + RPP * k;
-          const int gi = b * TILE + row;
-          const T rv = gi < n ? (T)r[sd.dof0 + gi] : T(0);
-          s_vec[row] = rv - acc[k];
+          s_vec[r0 + RPP * k] = rhs[k] - acc[k];
         }
       }
       __syncthreads();
@@ -145,10 +158,9 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
       for (int v = 0; v < VEC; ++v) sv[v] = s_vec[lc * VEC + v];
 #pragma unroll
       for (int k = 0; k < PASSES; ++k) {
-        const V dv = *(const V*)(D + (r0 + RPP * k) * TILE + lc * VEC);
         T a = T(0);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) a += VT::at(dv, v) * sv[v];
+        for (int v = 0; v < VEC; ++v) a += VT::at(dv[k], v) * sv[v];
         acc[k] = a;
       }
 #pragma unroll
@@ -162,6 +174,7 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
           if (gi < n) store_agent(y + sd.dof0 + gi, acc[k]);
         }
       }
+      if (trace && tid == 0) trace[3 * (size_t)t + 2] = wall_clock64();
       __syncthreads();
     } else {
       // ---------------- backward: column tiles (b+1..nb-1, b)^T, then inv(L_bb)^T
@@ -169,45 +182,34 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] = T(0);
       const int nb = sd.nb;
-      int j = b + 1;
-      for (; j + UNROLL <= nb; j += UNROLL) {
+      // oldest tiles first: z_{b+1} (produced last) is needed in the last chunk
+      int buf = 0;
+      for (int jhi = nb - 1; jhi > b; jhi -= UNROLL, buf ^= 1) {
+        const int jlo = max(jhi - UNROLL + 1, b + 1);  // chunk = tiles jlo..jhi
         V tv[UNROLL][PASSES];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const T* tile = base + (size_t)((j + u) * (j + u + 1) / 2 + b) * TT;
+          const int jj = jlo + u;
+          const bool ok = jj <= jhi;
+          const T* tile = base + (size_t)(jj * (jj + 1) / 2 + b) * TT;
 #pragma unroll
-          for (int k = 0; k < PASSES; ++k) tv[u][k] = *(const V*)(tile + (r0 + RPP * k) * TILE + lc * VEC);
+          for (int k = 0; k < PASSES; ++k) tv[u][k] = ok ? *(const V*)(tile + (r0 + RPP * k) * TILE + lc * VEC) : V{};
         }
-        T zv[UNROLL][PASSES];
+        // tile jlo was finished last among the chunk's tiles
+        wait_group(z + sd.dof0 + jlo * TILE, st);
+        if (tid < UNROLL * TILE) {
+          const int gi = jlo * TILE + tid;
+          s_x[buf][tid] = (gi < (jhi + 1) * TILE && gi < n) ? wait_value(z + sd.dof0 + gi, st) : T(0);
+        }
+        __syncthreads();
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
           for (int k = 0; k < PASSES; ++k) {
-            const int gi = (j + u) * TILE + r0 + RPP * k;
-            zv[u][k] = gi < n ? wait_value(z + sd.dof0 + gi, st) : T(0);
+            const T zk = s_x[buf][u * TILE + r0 + RPP * k];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += VT::at(tv[u][k], v) * zk;
           }
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-          for (int k = 0; k < PASSES; ++k)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] += VT::at(tv[u][k], v) * zv[u][k];
-      }
-      for (; j < nb; ++j) {
-        const T* tile = base + (size_t)(j * (j + 1) / 2 + b) * TT;
-        V tv[PASSES];
-#pragma unroll
-        for (int k = 0; k < PASSES; ++k) tv[k] = *(const V*)(tile + (r0 + RPP * k) * TILE + lc * VEC);
-        T zv[PASSES];
-#pragma unroll
-        for (int k = 0; k < PASSES; ++k) {
-          const int gi = j * TILE + r0 + RPP * k;
-          zv[k] = gi < n ? wait_value(z + sd.dof0 + gi, st) : T(0);
-        }
-#pragma unroll
-        for (int k = 0; k < PASSES; ++k)
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v] += VT::at(tv[k], v) * zv[k];
       }
       // combine the RPP row groups: in-wave, then across the 4 waves
 #pragma unroll
@@ -230,10 +232,9 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
       for (int v = 0; v < VEC; ++v) acc[v] = T(0);
 #pragma unroll
       for (int k = 0; k < PASSES; ++k) {
-        const V dv = *(const V*)(D + (r0 + RPP * k) * TILE + lc * VEC);
         const T s = s_vec[r0 + RPP * k];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] += VT::at(dv, v) * s;
+        for (int v = 0; v < VEC; ++v) acc[v] += VT::at(dv[k], v) * s;
       }
 #pragma unroll
       for (int v = 0; v < VEC; ++v)
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
         const int gi = b * TILE + tid;
         if (gi < n) store_agent(z + sd.dof0 + gi, u);
       }
+      if (trace && tid == 0) trace[3 * (size_t)t + 2] = wall_clock64();
       __syncthreads();
     }
   }
@@ -258,14 +260,14 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
 
 hipError_t launch_trsv(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, const void* tiles,
                        const double* r, void* y, void* z, DevState* st, int32_t* queue, int grid,
-                       hipStream_t s) {
+                       uint64_t* trace, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
   if (f32)
-    hipLaunchKernelGGL(k_trsv<float>, dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs, (const float*)tiles, r,
-                       (float*)y, (float*)z, st, queue);
+    hipLaunchKernelGGL((k_trsv<float, 4>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs, (const float*)tiles, r,
+                       (float*)y, (float*)z, st, queue, trace);
   else
-    hipLaunchKernelGGL(k_trsv<double>, dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs, (const double*)tiles, r,
-                       (double*)y, (double*)z, st, queue);
+    hipLaunchKernelGGL((k_trsv<double, 2>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs, (const double*)tiles,
+                       r, (double*)y, (double*)z, st, queue, trace);
   return hipGetLastError();
 }
 

@@ -1,63 +1,71 @@
 // Operator apply, PCG vector updates, coarse restriction/prolongation.
 //
-// Block-sparse SIPG operator (Sec. 2, eq. (Ah)): one wavefront per block row;
-// the row's blocks are read as one dense n_p x (nnz_row * n_p) panel stored
-// column-major, so a load instruction of the wave covers 64/n_p consecutive
-// columns = one contiguous run of memory. Partial sums of the 64/n_p column
-// groups are combined with cross-lane reads.
+// Block-sparse SIPG operator (Sec. 2, eq. (Ah)): one thread per output DoF
+// (cell, a); blocks are stored row-major, so the thread streams row a of
+// each block of its block row (n_p contiguous doubles) against the n_p
+// contiguous entries of the neighbour's p; the n_p threads of a cell read
+// one contiguous block together. Every DoF is independent, so the launch has
+// n threads of memory-level parallelism instead of one dependent chain per
+// block row.
 //
 // PCG (Sec. 7): every reduction is two-stage and deterministic (fixed
-// per-work-group order, then a fixed-order sum of the NPART partials that
-// each consumer work-group recomputes redundantly), so no floating-point
-// atomics are used and repeated solves are bitwise identical.
+// per-work-group order, then the last work-group to finish adds the
+// partials in index order), so no floating-point atomics are used and
+// repeated solves are bitwise identical. The last work-group of the
+// residual update also takes the stopping decision, so an iteration needs
+// no separate control kernel.
 #include "kern_common.h"
 
 namespace asdg {
 
 namespace {
 
+constexpr int VEC_GRID = 2048;  // work-groups of the grid-stride vector kernels
+
+int grid_for(int64_t n, int cap) {
+  int64_t g = (n + 255) / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
 template <int NP>
 __global__ __launch_bounds__(256) void k_spmv(int32_t N, const int32_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col,
                                               const double* __restrict__ blocks,
                                               const double* __restrict__ p, double* __restrict__ q,
-                                              double* __restrict__ part, const DevState* st) {
+                                              Reduction* red, const DevState* st) {
   __shared__ double scratch[4];
   if (st && st->done) return;
-  constexpr int G = 64 / NP;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int g = lane / NP, rr = lane - g * NP;
-  const bool active = g < G;
+  const int64_t n = (int64_t)N * NP;
   double dot = 0.0;
-  const int total_waves = gridDim.x * 4;
-  for (int row = blockIdx.x * 4 + w; row < N; row += total_waves) {
-    const int k0 = row_ptr[row], k1 = row_ptr[row + 1];
-    const int ncol = (k1 - k0) * NP;
-    const double* Bp = blocks + (size_t)k0 * NP * NP;
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+    const int cell = (int)(d / NP);
+    const int a = (int)(d - (int64_t)cell * NP);
+    const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
     double acc = 0.0;
-    if (active) {
-      for (int c = g; c < ncol; c += G) {
-        const int blk = c / NP, cc = c - blk * NP;
-        acc += Bp[(size_t)c * NP + rr] * p[(size_t)col[k0 + blk] * NP + cc];
-      }
-    }
-    double s = acc;
+#pragma unroll 2
+    for (int k = k0; k < k1; ++k) {
+      const double* B = blocks + ((size_t)k * NP + a) * NP;  // row a of block k
+      const double* pv = p + (size_t)col[k] * NP;
 #pragma unroll
-    for (int gg = 1; gg < G; ++gg) s += __shfl(acc, gg * NP + rr, 64);
-    if (g == 0) {
-      q[(size_t)row * NP + rr] = s;
-      dot += p[(size_t)row * NP + rr] * s;
+      for (int b = 0; b < NP; ++b) acc += B[b] * pv[b];
     }
+    q[d] = acc;
+    dot += p[d] * acc;
   }
-  dot = block_sum(dot, scratch);
-  if (part && threadIdx.x == 0) part[blockIdx.x] = dot;
+  if (red) {
+    double total;
+    grid_sum(dot, red + RED_PQ, scratch, total);
+  }
 }
 
+// r = permuted b, x = 0, triangular-sweep outputs = sentinel; with `st`,
+// ||b||^2 and the initial PCG state.
 template <typename T>
 __global__ __launch_bounds__(256) void k_permute_in(int np, int32_t N, const int32_t* __restrict__ perm,
                                                     const double* __restrict__ src, double* __restrict__ r,
                                                     double* __restrict__ x, T* __restrict__ yl,
-                                                    T* __restrict__ zl, double* __restrict__ part) {
+                                                    T* __restrict__ zl, Reduction* red, DevState* st,
+                                                    double rtol, int max_iter) {
   __shared__ double scratch[4];
   const int64_t n = (int64_t)N * np;
   double acc = 0.0;
@@ -71,25 +79,9 @@ __global__ __launch_bounds__(256) void k_permute_in(int np, int32_t N, const int
     zl[d] = sentinel<T>();
     acc += v * v;
   }
-  acc = block_sum(acc, scratch);
-  if (part && threadIdx.x == 0) part[blockIdx.x] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_unpermute(int np, int32_t N, const int32_t* __restrict__ perm,
-                                                   const double* __restrict__ x, double* __restrict__ dst) {
-  const int64_t n = (int64_t)N * np;
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cell = d / np;
-    const int a = (int)(d - cell * np);
-    dst[(int64_t)perm[cell] * np + a] = x[d];
-  }
-}
-
-__global__ __launch_bounds__(256) void k_init_check(DevState* st, const double* __restrict__ part_bb,
-                                                    double rtol, int max_iter) {
-  __shared__ double scratch[4];
-  const double bb = reduce_partials(part_bb, scratch);
-  if (threadIdx.x == 0) {
+  if (!st) return;
+  double bb;
+  if (grid_sum(acc, red + RED_BB, scratch, bb) && threadIdx.x == 0) {
     st->bb = bb;
     st->tol2 = rtol * rtol * bb;
     st->rr = bb;
@@ -111,16 +103,28 @@ __global__ __launch_bounds__(256) void k_init_check(DevState* st, const double* 
   }
 }
 
+__global__ __launch_bounds__(256) void k_unpermute(int np, int32_t N, const int32_t* __restrict__ perm,
+                                                   const double* __restrict__ x, double* __restrict__ dst) {
+  const int64_t n = (int64_t)N * np;
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cell = d / np;
+    const int a = (int)(d - cell * np);
+    dst[(int64_t)perm[cell] * np + a] = x[d];
+  }
+}
+
+// alpha = (r.z)/(p.Ap); x += alpha p; r -= alpha Ap; ||r||^2; the last
+// work-group decides convergence / breakdown / max_iter and counts the
+// iteration.
 template <typename T>
-__global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, const double* __restrict__ part_pq,
+__global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Reduction* red,
                                                    const double* __restrict__ rz2, double* __restrict__ alpha_hist,
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    double* __restrict__ x, double* __restrict__ r,
-                                                   T* __restrict__ yl, T* __restrict__ zl,
-                                                   double* __restrict__ part_rr) {
+                                                   T* __restrict__ yl, T* __restrict__ zl) {
   __shared__ double scratch[4];
   if (st->done) return;
-  const double pq = reduce_partials(part_pq, scratch);
+  const double pq = red[RED_PQ].result;
   const int it = st->it;
   const double alpha = rz2[it & 1] / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0 && it < HIST) alpha_hist[it] = alpha;
@@ -133,19 +137,10 @@ __global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, cons
     yl[d] = sentinel<T>();
     zl[d] = sentinel<T>();
   }
-  acc = block_sum(acc, scratch);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_check(DevState* st, const double* __restrict__ part_rr,
-                                               const double* __restrict__ part_pq) {
-  __shared__ double scratch[4];
-  if (st->done) return;
-  const double rr = reduce_partials(part_rr, scratch);
-  const double pq = reduce_partials(part_pq, scratch);
-  if (threadIdx.x == 0) {
-    const int it = st->it + 1;
-    st->it = it;
+  double rr;
+  if (grid_sum(acc, red + RED_RR, scratch, rr) && threadIdx.x == 0) {
+    const int it1 = it + 1;
+    st->it = it1;
     st->rr = rr;
     st->q_local = 0;
     st->q_coarse = 0;
@@ -158,7 +153,7 @@ __global__ __launch_bounds__(256) void k_check(DevState* st, const double* __res
     } else if (rr <= st->tol2) {
       st->status = 1;
       st->done = 1;
-    } else if (it >= st->max_iter) {
+    } else if (it1 >= st->max_iter) {
       st->status = 2;
       st->done = 1;
     }
@@ -200,13 +195,13 @@ __global__ __launch_bounds__(256) void k_restrict(const int32_t* __restrict__ tp
   }
 }
 
-// z = z_loc + P_0 z0 (coarse part optional), partial sums of r.z.
+// z = z_loc + P_0 z0 (either part optional), and r.z.
 template <int NP, int NQ, typename T>
 __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __restrict__ pptr,
                                                  const int32_t* __restrict__ pcol, const double* __restrict__ P,
                                                  const double* __restrict__ z0, const T* __restrict__ zl,
                                                  const double* __restrict__ r, double* __restrict__ z,
-                                                 double* __restrict__ part, const DevState* st) {
+                                                 Reduction* red, const DevState* st) {
   __shared__ double scratch[4];
   if (st && st->done) return;
   const int64_t n = (int64_t)N * NP;
@@ -224,20 +219,20 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
       }
     }
     z[d] = v;
-    if (part) acc += r[d] * v;
+    acc += r[d] * v;
   }
-  if (part) {
-    acc = block_sum(acc, scratch);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (red) {
+    double total;
+    grid_sum(acc, red + RED_RZ, scratch, total);
   }
 }
 
-__global__ __launch_bounds__(256) void k_update_p(int64_t n, DevState* st, const double* __restrict__ part_rz,
+// beta = (r.z)_new / (r.z)_old; p = z + beta p (init: p = z).
+__global__ __launch_bounds__(256) void k_update_p(int64_t n, DevState* st, const Reduction* red,
                                                   double* __restrict__ rz2, double* __restrict__ beta_hist,
                                                   const double* __restrict__ z, double* __restrict__ p, int init) {
-  __shared__ double scratch[4];
   if (st->done) return;
-  const double rz_new = reduce_partials(part_rz, scratch);
+  const double rz_new = red[RED_RZ].result;
   if (init) {
     if (blockIdx.x == 0 && threadIdx.x == 0) rz2[0] = rz_new;
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
@@ -271,62 +266,50 @@ __global__ void k_reset_queues(DevState* st) {
   }
 }
 
-int grid_for(int64_t n) {
-  int64_t g = (n + 255) / 256;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, NPART));
-}
-
 }  // namespace
 
 hipError_t launch_spmv(int np, int32_t N, const int32_t* row_ptr, const int32_t* col, const double* blocks,
-                       const double* p, double* q, double* part, const DevState* st, hipStream_t s) {
-  dim3 g(NPART), b(256);
+                       const double* p, double* q, Reduction* red, const DevState* st, hipStream_t s) {
+  dim3 g(grid_for((int64_t)N * np, MAXG)), b(256);
   switch (np) {
-    case 3: hipLaunchKernelGGL(k_spmv<3>, g, b, 0, s, N, row_ptr, col, blocks, p, q, part, st); break;
-    case 6: hipLaunchKernelGGL(k_spmv<6>, g, b, 0, s, N, row_ptr, col, blocks, p, q, part, st); break;
-    case 10: hipLaunchKernelGGL(k_spmv<10>, g, b, 0, s, N, row_ptr, col, blocks, p, q, part, st); break;
-    case 15: hipLaunchKernelGGL(k_spmv<15>, g, b, 0, s, N, row_ptr, col, blocks, p, q, part, st); break;
+    case 3: hipLaunchKernelGGL(k_spmv<3>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 6: hipLaunchKernelGGL(k_spmv<6>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 10: hipLaunchKernelGGL(k_spmv<10>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 15: hipLaunchKernelGGL(k_spmv<15>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_permute_in(int np, int32_t N, const int32_t* perm, const double* src, double* r, double* x,
-                             void* yl, void* zl, int local_f32, double* part_bb, hipStream_t s) {
-  dim3 g(NPART), b(256);
+                             void* yl, void* zl, int local_f32, Reduction* red, DevState* st, double rtol,
+                             int max_iter, hipStream_t s) {
+  dim3 g(grid_for((int64_t)N * np, VEC_GRID)), b(256);
   if (local_f32)
-    hipLaunchKernelGGL(k_permute_in<float>, g, b, 0, s, np, N, perm, src, r, x, (float*)yl, (float*)zl, part_bb);
+    hipLaunchKernelGGL(k_permute_in<float>, g, b, 0, s, np, N, perm, src, r, x, (float*)yl, (float*)zl, red, st,
+                       rtol, max_iter);
   else
-    hipLaunchKernelGGL(k_permute_in<double>, g, b, 0, s, np, N, perm, src, r, x, (double*)yl, (double*)zl, part_bb);
+    hipLaunchKernelGGL(k_permute_in<double>, g, b, 0, s, np, N, perm, src, r, x, (double*)yl, (double*)zl, red, st,
+                       rtol, max_iter);
   return hipGetLastError();
 }
 
 hipError_t launch_unpermute_out(int np, int32_t N, const int32_t* perm, const double* x, double* dst,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_unpermute, dim3(grid_for((int64_t)N * np)), dim3(256), 0, s, np, N, perm, x, dst);
+  hipLaunchKernelGGL(k_unpermute, dim3(grid_for((int64_t)N * np, VEC_GRID)), dim3(256), 0, s, np, N, perm, x, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_init_check(DevState* st, const double* part_bb, double rtol, int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_check, dim3(1), dim3(256), 0, s, st, part_bb, rtol, max_iter);
-  return hipGetLastError();
-}
-
-hipError_t launch_update_xr(int64_t n, DevState* st, const double* part_pq, const double* rz_hist,
-                            double* alpha_hist, const double* p, const double* q, double* x, double* r, void* yl,
-                            void* zl, int local_f32, double* part_rr, hipStream_t s) {
-  dim3 g(NPART), b(256);
+hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, const double* rz2, double* alpha_hist,
+                            const double* p, const double* q, double* x, double* r, void* yl, void* zl,
+                            int local_f32, hipStream_t s) {
+  dim3 g(grid_for(n, VEC_GRID)), b(256);
   if (local_f32)
-    hipLaunchKernelGGL(k_update_xr<float>, g, b, 0, s, n, st, part_pq, rz_hist, alpha_hist, p, q, x, r,
-                       (float*)yl, (float*)zl, part_rr);
+    hipLaunchKernelGGL(k_update_xr<float>, g, b, 0, s, n, st, red, rz2, alpha_hist, p, q, x, r, (float*)yl,
+                       (float*)zl);
   else
-    hipLaunchKernelGGL(k_update_xr<double>, g, b, 0, s, n, st, part_pq, rz_hist, alpha_hist, p, q, x, r,
-                       (double*)yl, (double*)zl, part_rr);
-  return hipGetLastError();
-}
-
-hipError_t launch_check(DevState* st, const double* part_rr, const double* part_pq, hipStream_t s) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, s, st, part_rr, part_pq);
+    hipLaunchKernelGGL(k_update_xr<double>, g, b, 0, s, n, st, red, rz2, alpha_hist, p, q, x, r, (double*)yl,
+                       (double*)zl);
   return hipGetLastError();
 }
 
@@ -353,35 +336,35 @@ hipError_t launch_restrict(int np, int nq, int32_t nc, const int32_t* tptr, cons
 
 template <int NP, int NQ>
 static void prolong_t(int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P, const double* z0,
-                      const void* zl, int f32, const double* r, double* z, double* part, const DevState* st,
+                      const void* zl, int f32, const double* r, double* z, Reduction* red, const DevState* st,
                       hipStream_t s) {
-  dim3 g(NPART), b(256);
+  dim3 g(grid_for((int64_t)N * NP, VEC_GRID)), b(256);
   if (f32)
-    hipLaunchKernelGGL((k_prolong<NP, NQ, float>), g, b, 0, s, N, pptr, pcol, P, z0, (const float*)zl, r, z, part, st);
+    hipLaunchKernelGGL((k_prolong<NP, NQ, float>), g, b, 0, s, N, pptr, pcol, P, z0, (const float*)zl, r, z, red, st);
   else
-    hipLaunchKernelGGL((k_prolong<NP, NQ, double>), g, b, 0, s, N, pptr, pcol, P, z0, (const double*)zl, r, z, part,
+    hipLaunchKernelGGL((k_prolong<NP, NQ, double>), g, b, 0, s, N, pptr, pcol, P, z0, (const double*)zl, r, z, red,
                        st);
 }
 
 hipError_t launch_prolong(int np, int nq, int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P,
-                          const double* z0, const void* zl, int f32, const double* r, double* z, double* part,
+                          const double* z0, const void* zl, int f32, const double* r, double* z, Reduction* red,
                           const DevState* st, hipStream_t s) {
   if (!pptr) nq = 3;  // no coarse level: any instantiation, the loop is skipped
-#define P_(A, B) ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, f32, r, z, part, st, s)))
+#define P_(A, B) ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, f32, r, z, red, st, s)))
   P_(3, 3) P_(6, 3) P_(6, 6) P_(10, 3) P_(10, 6) P_(10, 10) P_(15, 3) P_(15, 6) P_(15, 10) P_(15, 15)
 #undef P_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_update_p(int64_t n, DevState* st, const double* part_rz, double* rz2, double* beta_hist,
+hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, double* rz2, double* beta_hist,
                            const double* z, double* p, int init, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(NPART), dim3(256), 0, s, n, st, part_rz, rz2, beta_hist, z, p, init);
+  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n, VEC_GRID)), dim3(256), 0, s, n, st, red, rz2, beta_hist, z, p, init);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, dst, n, v);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 4096)), dim3(256), 0, s, dst, n, v);
   return hipGetLastError();
 }
 

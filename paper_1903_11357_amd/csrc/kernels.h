@@ -8,8 +8,21 @@
 namespace asdg {
 
 constexpr int TILE = 64;            // tile edge of the packed local/coarse factors
-constexpr int NPART = 1024;         // work-groups (and partial sums) of vector kernels
+constexpr int MAXG = 8192;          // max work-groups of a kernel that reduces over the grid
 constexpr int HIST = 65536;         // recorded CG coefficients (Lanczos estimate)
+
+// Deterministic grid-wide sum: per-work-group partials, then the last
+// work-group to finish adds them in index order (see grid_sum()).
+constexpr int RGROUP = 64;  // work-groups per first-level arrival counter
+struct Reduction {
+  double partial[MAXG];             // one per work-group
+  double gpartial[MAXG / RGROUP];   // one per group of RGROUP work-groups
+  uint32_t gcounter[MAXG / RGROUP]; // arrivals per group; re-armed by the group's last
+  uint32_t counter;                 // arrivals of group sums; re-armed by the last
+  uint32_t pad;
+  double result;
+};
+enum { RED_PQ = 0, RED_RR = 1, RED_RZ = 2, RED_BB = 3, N_RED = 4 };
 
 // Device-resident PCG state (lives in the scratch buffer).
 struct DevState {
@@ -36,30 +49,27 @@ struct SubDesc {
   int32_t tile0;  // index of tile (0,0); tile (b,j) is tile0 + b(b+1)/2 + j
 };
 
-// Vector / operator kernels (kern_vec.hip).
+// Vector / operator kernels (kern_vec.hip). `red` points at the N_RED
+// reduction slots; kernels that reduce write red[RED_*].result.
 hipError_t launch_spmv(int np, int32_t n_cells, const int32_t* row_ptr, const int32_t* col,
-                       const double* blocks, const double* p, double* q, double* part_pq,
+                       const double* blocks, const double* p, double* q, Reduction* red,
                        const DevState* st, hipStream_t s);
 hipError_t launch_permute_in(int np, int32_t n_cells, const int32_t* perm, const double* src,
                              double* r, double* x, void* yl, void* zl, int local_f32,
-                             double* part_bb, hipStream_t s);
+                             Reduction* red, DevState* st, double rtol, int max_iter, hipStream_t s);
 hipError_t launch_unpermute_out(int np, int32_t n_cells, const int32_t* perm, const double* x,
                                 double* dst, hipStream_t s);
-hipError_t launch_init_check(DevState* st, const double* part_bb, double rtol, int max_iter,
-                             hipStream_t s);
-hipError_t launch_update_xr(int64_t n, DevState* st, const double* part_pq, const double* rz_hist,
-                            double* alpha_hist, const double* p, const double* q, double* x,
-                            double* r, void* yl, void* zl, int local_f32, double* part_rr,
-                            hipStream_t s);
-hipError_t launch_check(DevState* st, const double* part_rr, const double* part_pq, hipStream_t s);
+hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, const double* rz2, double* alpha_hist,
+                            const double* p, const double* q, double* x, double* r, void* yl, void* zl,
+                            int local_f32, hipStream_t s);
 hipError_t launch_restrict(int np, int nq, int32_t n_coarse, const int32_t* tptr, const int32_t* tcell,
                            const int32_t* tblk, const double* P, const double* r, double* r0,
                            double* y0, double* z0, const DevState* st, hipStream_t s);
 hipError_t launch_prolong(int np, int nq, int32_t n_cells, const int32_t* pptr, const int32_t* pcol,
                           const double* P, const double* z0, const void* zl, int local_f32,
-                          const double* r, double* z, double* part_rz, const DevState* st,
+                          const double* r, double* z, Reduction* red, const DevState* st,
                           hipStream_t s);
-hipError_t launch_update_p(int64_t n, DevState* st, const double* part_rz, double* rz_hist,
+hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, double* rz2,
                            double* beta_hist, const double* z, double* p, int init, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_reset_queues(DevState* st, hipStream_t s);
@@ -72,8 +82,9 @@ hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const Su
                            int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
 
 // Batched forward/backward triangular sweeps (kern_trsv.hip).
+// trace (optional): per task, wall-clock at dequeue, end of waits, end.
 hipError_t launch_trsv(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs,
                        const void* tiles, const double* r, void* y, void* z, DevState* st,
-                       int32_t* queue, int grid, hipStream_t s);
+                       int32_t* queue, int grid, uint64_t* trace, hipStream_t s);
 
 }  // namespace asdg

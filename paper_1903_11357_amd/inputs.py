@@ -7,9 +7,9 @@ right-hand-side functions. It contains none of the discretisation or solver
 arithmetic; both the CPU oracle and the GPU library consume what it returns.
 
 Random numbers come from ``numpy.random.default_rng(seed)``. For a Voronoi
-mesh the N seed points are drawn first with ``rng.random((N, 2))``; any
-further draws (coarse seeds, coefficients, RHS coefficients) continue the
-same stream in that order.
+mesh the N seed points are drawn first with ``rng.random((N, 2))`` and then
+relaxed by two Lloyd steps; any further draws (coarse seeds, coefficients,
+RHS coefficients) continue the same stream in that order.
 
 The named workloads mirror the problem classes of the paper's experiments
 (unit-square Poisson, Voronoi polygonal meshes, nested agglomerated and
@@ -158,6 +158,36 @@ def voronoi_mesh(seeds: np.ndarray, tol: float = 1e-12) -> Mesh:
                 cell_vertices=np.asarray(verts, dtype=np.int32))
 
 
+LLOYD_STEPS = 2
+
+
+def _cell_centroids(mesh: Mesh) -> np.ndarray:
+    """Area centroids of all cells (shoelace), used by the Lloyd step."""
+    xy, cv, ptr = mesh.xy, mesh.cell_vertices, mesh.cell_ptr
+    N = mesh.n_cells
+    owner = np.repeat(np.arange(N), np.diff(ptr))
+    nxt = np.arange(cv.shape[0]) + 1
+    nxt[ptr[1:] - 1] = ptr[:-1]
+    a, b = xy[cv], xy[cv[nxt]]
+    cr = a[:, 0] * b[:, 1] - b[:, 0] * a[:, 1]
+    area = 0.5 * np.bincount(owner, cr, N)
+    cx = np.bincount(owner, (a[:, 0] + b[:, 0]) * cr, N) / (6.0 * area)
+    cy = np.bincount(owner, (a[:, 1] + b[:, 1]) * cr, N) / (6.0 * area)
+    return np.stack([cx, cy], axis=1)
+
+
+def relaxed_voronoi_mesh(seeds: np.ndarray, steps: int = LLOYD_STEPS) -> Mesh:
+    """Voronoi mesh after ``steps`` Lloyd iterations (seeds moved to the area
+    centroids of their cells). Uniform random seeds give occasional sliver
+    cells whose trace-inverse constant is far outside the shape-regularity
+    the method assumes; two Lloyd steps remove them while keeping the mesh
+    random."""
+    mesh = voronoi_mesh(seeds)
+    for _ in range(steps):
+        mesh = voronoi_mesh(_cell_centroids(mesh))
+    return mesh
+
+
 def bins_partition(points: np.ndarray, bx: int, by: int) -> np.ndarray:
     """Cell -> bin id for a bx-by-by grid of bins over (0,1)^2 (x-fastest)."""
     ix = np.minimum(np.floor(points[:, 0] * bx).astype(np.int64), bx - 1)
@@ -276,10 +306,10 @@ def voronoi_problem(n_cells: int, seed: int, p: int, bx: int, by: int, q: int,
                     nonnested_coarse: int = 0, log10_rho_range: float = 0.0,
                     f=f_sinsin, warped: bool = False, name: str = "voronoi") -> Problem:
     rng = np.random.default_rng(seed)
-    mesh = voronoi_mesh(rng.random((n_cells, 2)))
+    mesh = relaxed_voronoi_mesh(rng.random((n_cells, 2)))
     coarse_mesh = None
     if nonnested_coarse:
-        coarse_mesh = voronoi_mesh(rng.random((nonnested_coarse, 2)))
+        coarse_mesh = relaxed_voronoi_mesh(rng.random((nonnested_coarse, 2)))
     pts = mesh.vertex_mean()
     sub = warped_bins_256(pts) if warped else bins_partition(pts, bx, by)
     sub = compact_labels(sub)
@@ -327,7 +357,7 @@ def serving_requests(n_requests: int = 2000, seed: int = 5, n_min: int = 4096,
 def serving_problem(req: dict) -> Problem:
     rng = np.random.default_rng(req["seed"])
     n = req["n_cells"]
-    mesh = voronoi_mesh(rng.random((n, 2)))
+    mesh = relaxed_voronoi_mesh(rng.random((n, 2)))
     b = max(1, int(round(math.sqrt(n) / 8)))
     sub = compact_labels(bins_partition(mesh.vertex_mean(), b, b))
     n_sub = int(sub.max()) + 1
