@@ -39,6 +39,27 @@ WORKLOADS = {
 }
 
 
+def measured_traffic(workload, mode):
+    """HBM bytes per local-solve launch from the committed rocprofv3 counter
+    summary, if it was taken on this workload/mode with the current kernel
+    source; else None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_trsv_{workload}_{mode}_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1903_11357_amd", "csrc", "kern_trsv.hip")
+    if not os.path.exists(path):
+        return None
+    meta = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("source_sha256_16", "traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            meta[k] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if meta.get("source_sha256_16") != sha:
+        return None
+    return float(meta["traffic_bytes_per_launch"])
+
+
 def local_solve_bytes(pr, word_bytes):
     """Algorithmic bytes of one batched local solve (both sweeps): each sweep
     reads the packed lower triangle n_i(n_i+1)/2 of every factor once; the
@@ -77,8 +98,6 @@ def run_mode(P, precision, steps, warmup, check_every):
     # kernel-timing pass: the same solves launched eagerly with HIP events
     # around every local-solve launch, on the stream it is launched on
     use_graph = False
-    pr.solve(x=x, rtol=P.rtol, max_iter=P.max_iter, check_every=check_every, time_kernels=True,
-             raise_on_noconv=False)
     torch.cuda.synchronize()
     its, lat, tl, nl = [], [], 0.0, 0
     ta = time.perf_counter()
@@ -152,13 +171,17 @@ def cpu_baseline(P, n_iter):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--check-every", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--modes", default="fp32,fp64")
+    ap.add_argument("--max-iter", type=int, default=0,
+                    help="cap PCG iterations (profiling runs; 0 = the workload's own limit)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is a design "
@@ -170,7 +193,16 @@ def main():
     from paper_1903_11357_amd import asdg, inputs
 
     asdg.lib()  # fail loudly if the native library is missing
+    if a.calibrate_copy_mib:
+        n = a.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     P = inputs.make_config(a.workload)
+    if a.max_iter:
+        P.max_iter = a.max_iter
     print(f"[bench] workload {a.workload}: n={P.n_dofs} subdomains={P.n_sub}", file=sys.stderr, flush=True)
     modes = {}
     for m in a.modes.split(","):
@@ -197,8 +229,10 @@ def main():
                    "subdomains": P.n_sub, "rtol": P.rtol, "parallelism": "single GPU"},
         "modes": modes,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                     "kernel": "k_trsv (batched local forward+backward sweeps)"},
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": measured_traffic(a.workload, "fp32" if "fp32" in modes else "fp64"),
+                     "kernel": "k_trsv (batched local forward+backward sweeps)",
+                     "algorithmic_bytes": ls["algorithmic_bytes"], "avg_ms": ls["avg_ms"]},
     }
     if "fp32" in modes and "fp64" in modes:
         out["fp32_local_speedup_per_iteration"] = modes["fp64"]["ms_per_iteration"] / modes["fp32"]["ms_per_iteration"]
