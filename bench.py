@@ -168,6 +168,42 @@ def cpu_baseline(P, n_iter):
                       f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
 
 
+def serving_bench(n_requests, seed=5, workers=16):
+    """Continuous batching (C5 shape): requests with log-uniform 4096..65536
+    Voronoi cells, p in {1,2,3}, ~64 cells per subdomain, rho = 10^U[-2,2]
+    per subdomain, random sine-series RHS, nested coarse q=1, FP32-local.
+    First all requests at once (capacity), then a Poisson stream at 80% of
+    that capacity; latency = arrival to completion."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+
+    from paper_1903_11357_amd import asdg, inputs
+    from paper_1903_11357_amd.serve import Request, Server, latency_stats
+
+    descs = inputs.serving_requests(n_requests, seed=seed)
+    t = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        problems = list(ex.map(inputs.serving_problem, descs))
+    t_gen = time.perf_counter() - t
+    srv = Server(precision=asdg.FP32_LOCAL, max_active=16, check_every=16, setup_workers=8)
+    burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems)])
+    cap = latency_stats(burst)
+    rate = 0.8 * cap["solves_per_s"]
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    stream = srv.run([Request(i, P, float(a)) for i, (P, a) in enumerate(zip(problems, arrivals))])
+    st = latency_stats(stream)
+    dofs = [P.n_dofs for P in problems]
+    return {"requests": n_requests, "dofs_min": int(min(dofs)), "dofs_max": int(max(dofs)),
+            "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate_per_s": rate,
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "solves_per_s": st["solves_per_s"], "iterations_mean": st["iterations_mean"],
+            "all_converged": st["all_converged"] and cap["all_converged"], "peak_active": srv.peak_active,
+            "input_generation_s": t_gen, "precision": "fp32-local"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +216,9 @@ def main():
     ap.add_argument("--modes", default="fp32,fp64")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap PCG iterations (profiling runs; 0 = the workload's own limit)")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests of the continuous-batching run (0 = skip)")
+    ap.add_argument("--only-serving", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -200,6 +239,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.only_serving:
+        print(json.dumps({"serving": serving_bench(a.serving_requests)}), flush=True)
+        return
     P = inputs.make_config(a.workload)
     if a.max_iter:
         P.max_iter = a.max_iter
@@ -237,6 +279,9 @@ def main():
     if "fp32" in modes and "fp64" in modes:
         out["fp32_local_speedup_per_iteration"] = modes["fp64"]["ms_per_iteration"] / modes["fp32"]["ms_per_iteration"]
         out["fp32_local_speedup_per_solve"] = modes["fp64"]["ms_per_step"] / modes["fp32"]["ms_per_step"]
+    if a.serving_requests > 0:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = serving_bench(a.serving_requests)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, a.cpu_iters)

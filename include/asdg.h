@@ -163,6 +163,28 @@ asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream);
 asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x,
                            const asdg_pcg_opts* opts, asdg_pcg_stats* stats, void* stream);
 
+/* Non-blocking form of asdg_pcg_solve for request loops that keep several
+ * solves in flight on different streams (each handle is one solve).
+ *   asdg_pcg_begin:  enqueues x = 0, r = b, z = P^{-1} r, p = z on stream
+ *                    (d_b as in asdg_pcg_solve) and an asynchronous copy of
+ *                    the iteration state; returns at once.
+ *   asdg_pcg_step:   enqueues one chunk of opts->check_every iterations (a
+ *                    captured hipGraph) and the state copy; no-op once the
+ *                    solve is done. Call only after asdg_pcg_poll reported
+ *                    the previous chunk done (else ESTATE).
+ *   asdg_pcg_poll:   never blocks; chunk_done = 1 once the last enqueued
+ *                    chunk has finished, then solve_done = 1 if the solve
+ *                    stopped (converged, max_iter or breakdown) and
+ *                    iterations = iterations so far.
+ *   asdg_pcg_finish: after solve_done, writes x (caller layout) and the
+ *                    statistics; synchronises the stream; returns the
+ *                    solve's status (OK, ENOCONV, EBREAKDOWN).
+ * The state copy goes to a small pinned host buffer owned by the handle. */
+asdg_status asdg_pcg_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_opts* opts, void* stream);
+asdg_status asdg_pcg_step(asdg_problem* pb, void* stream);
+asdg_status asdg_pcg_poll(asdg_problem* pb, int32_t* chunk_done, int32_t* solve_done, int32_t* iterations);
+asdg_status asdg_pcg_finish(asdg_problem* pb, double* d_x, asdg_pcg_stats* stats, void* stream);
+
 /* Single applications of hot-path steps on device vectors in caller layout,
  * for verification and benchmarking (what = ASDG_APPLY_*):
  *   OPERATOR: out = A in                       (SIPG operator, eq. (Ah))

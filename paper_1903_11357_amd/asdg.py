@@ -74,6 +74,10 @@ _SIGS = {
     "asdg_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "asdg_export_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double)]),
+    "asdg_pcg_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgOpts), C.c_void_p]),
+    "asdg_pcg_step": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "asdg_pcg_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE = 0, 1, 2, 3
 
@@ -245,6 +249,34 @@ class Problem:
         s = PcgStats()
         st = self._L.asdg_pcg_solve(self.h, bp, C.c_void_p(x.data_ptr()), C.byref(o), C.byref(s),
                                     self._stream(stream))
+        stats = {k: getattr(s, k) for k, _ in PcgStats._fields_}
+        stats["status"] = STATUS_NAMES.get(st, st)
+        if st != OK and not (st == ENOCONV and not raise_on_noconv):
+            self._check(st)
+        return x, stats
+
+    # ------------------------------------------------------- non-blocking
+    def begin(self, b=None, rtol=1e-8, max_iter=20000, check_every=16, stream=None):
+        bp = C.c_void_p(b.data_ptr()) if b is not None else None
+        o = PcgOpts(rtol, max_iter, check_every, 1, 0)
+        self._check(self._L.asdg_pcg_begin(self.h, bp, C.byref(o), self._stream(stream)))
+
+    def step(self, stream=None):
+        self._check(self._L.asdg_pcg_step(self.h, self._stream(stream)))
+
+    def poll(self):
+        """(chunk_done, solve_done, iterations); never blocks."""
+        c, d, it = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self._L.asdg_pcg_poll(self.h, C.byref(c), C.byref(d), C.byref(it)))
+        return bool(c.value), bool(d.value), int(it.value)
+
+    def finish(self, x=None, stream=None, raise_on_noconv=True):
+        import torch
+
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        s = PcgStats()
+        st = self._L.asdg_pcg_finish(self.h, C.c_void_p(x.data_ptr()), C.byref(s), self._stream(stream))
         stats = {k: getattr(s, k) for k, _ in PcgStats._fields_}
         stats["status"] = STATUS_NAMES.get(st, st)
         if st != OK and not (st == ENOCONV and not raise_on_noconv):

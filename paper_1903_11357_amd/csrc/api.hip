@@ -121,6 +121,12 @@ struct asdg_problem {
   hipStream_t own_stream = nullptr;
   std::vector<hipEvent_t> ev;  // 2 per captured iteration (local solve start/end)
   hipEvent_t t0 = nullptr, t1 = nullptr;
+  // non-blocking solve state
+  DevState* h_state = nullptr;  // pinned host copy target
+  hipEvent_t chunk_ev = nullptr;
+  bool chunk_in_flight = false, solve_open = false;
+  DevState hs{};
+  asdg_pcg_opts aopts{1e-8, 20000, 16, 1, 0};
 
   template <class T>
   T* ptr(int b, size_t off) const { return reinterpret_cast<T*>(buf[b] + off); }
@@ -136,6 +142,8 @@ struct asdg_problem {
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     if (own_stream) (void)hipStreamDestroy(own_stream);
+    if (chunk_ev) (void)hipEventDestroy(chunk_ev);
+    if (h_state) (void)hipHostFree(h_state);
   }
 };
 
@@ -326,7 +334,165 @@ asdg_status read_state(asdg_problem* pb, hipStream_t s, DevState& h) {
 }  // namespace
 
 
+namespace {
+
+asdg_status ensure_graph(asdg_problem* pb, int k) {
+  if (pb->gexec && pb->g_k == k && !pb->g_timed) return ASDG_OK;
+  if (!pb->own_stream) HIPCHK(pb, hipStreamCreateWithFlags(&pb->own_stream, hipStreamNonBlocking));
+  pb->drop_graph();
+  hipGraph_t g;
+  HIPCHK(pb, hipStreamBeginCapture(pb->own_stream, hipStreamCaptureModeThreadLocal));
+  asdg_status ce = ASDG_OK;
+  for (int i = 0; i < k && ce == ASDG_OK; ++i) ce = enqueue_iteration(pb, pb->own_stream, nullptr, nullptr);
+  hipError_t he = hipStreamEndCapture(pb->own_stream, &g);
+  if (ce != ASDG_OK) return ce;
+  if (he != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("graph capture: ") + hipGetErrorString(he));
+  he = hipGraphInstantiate(&pb->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (he != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(he));
+  pb->g_k = k;
+  pb->g_timed = 0;
+  return ASDG_OK;
+}
+
+// x = 0, r = b, z = P^{-1} r, p = z on stream s.
+asdg_status enqueue_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_opts& o, hipStream_t s) {
+  const int np = pb->A.np;
+  const int32_t N = pb->A.n_cells;
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  Reduction* red = pb->ptr<Reduction>(3, pb->o3.red);
+  const double* src = d_b ? d_b : pb->ptr<double>(0, pb->o0.rhs);
+  HIPCHK(pb, launch_permute_in(np, N, pb->ptr<int32_t>(0, pb->o0.perm), src, pb->ptr<double>(3, pb->o3.r),
+                               pb->ptr<double>(3, pb->o3.x), pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
+                               pb->f32, red, st, o.rtol, o.max_iter, s));
+  asdg_status e = enqueue_precond(pb, s, st, red, nullptr, nullptr);
+  if (e != ASDG_OK) return e;
+  HIPCHK(pb, launch_update_p(pb->n(), st, red, pb->ptr<double>(3, pb->o3.rz2), pb->ptr<double>(3, pb->o3.bh),
+                             pb->ptr<double>(3, pb->o3.z), pb->ptr<double>(3, pb->o3.p), 1, s));
+  return ASDG_OK;
+}
+
+asdg_status fill_stats(asdg_problem* pb, const DevState& h, double solve_ms, double t_local, int n_local,
+                       asdg_pcg_stats* stats) {
+  if (!stats) return ASDG_OK;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->iterations = h.it;
+  stats->converged = h.status == 1;
+  stats->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  stats->t_solve_ms = solve_ms;
+  stats->t_local_ms = t_local;
+  stats->n_local = n_local;
+  stats->failed_subdomain = -2;
+  const int ka = std::min(h.it, HIST);
+  if (ka >= 1) {
+    std::vector<double> al(ka), be(std::max(ka - 1, 0));
+    HIPCHK(pb, hipMemcpy(al.data(), pb->ptr<double>(3, pb->o3.ah), 8 * ka, hipMemcpyDeviceToHost));
+    if (ka > 1) HIPCHK(pb, hipMemcpy(be.data(), pb->ptr<double>(3, pb->o3.bh), 8 * (ka - 1), hipMemcpyDeviceToHost));
+    std::vector<double> d(ka), off(std::max(ka - 1, 0));
+    d[0] = 1.0 / al[0];
+    for (int j = 1; j < ka; ++j) d[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
+    for (int j = 0; j + 1 < ka; ++j) off[j] = std::sqrt(std::max(be[j], 0.0)) / al[j];
+    tridiag_extremes(d, off, stats->lambda_min, stats->lambda_max);
+  }
+  return ASDG_OK;
+}
+
+asdg_status status_of(asdg_problem* pb, const DevState& h) {
+  if (h.status == 4) FAIL(pb, ASDG_EHIP, "local-solve wait budget exhausted");
+  if (h.status == 3) FAIL(pb, ASDG_EBREAKDOWN, "PCG breakdown (p.Ap <= 0 or NaN)");
+  if (h.status == 2) FAIL(pb, ASDG_ENOCONV, "maximum number of iterations reached");
+  return ASDG_OK;
+}
+
+asdg_status enqueue_state_copy(asdg_problem* pb, hipStream_t s) {
+  if (!pb->h_state) {
+    void* p = nullptr;
+    HIPCHK(pb, hipHostMalloc(&p, sizeof(DevState), hipHostMallocDefault));
+    pb->h_state = (DevState*)p;
+  }
+  if (!pb->chunk_ev) HIPCHK(pb, hipEventCreateWithFlags(&pb->chunk_ev, hipEventDisableTiming));
+  HIPCHK(pb, hipMemcpyAsync(pb->h_state, pb->ptr<DevState>(3, pb->o3.st), sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(pb, hipEventRecord(pb->chunk_ev, s));
+  pb->chunk_in_flight = true;
+  return ASDG_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+asdg_status asdg_pcg_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_opts* opts, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (pb->stage < 4 || !pb->coarse_ready) FAIL(pb, ASDG_ESTATE, "asdg_pcg_begin before asdg_factor/asdg_setup_coarse");
+  if (pb->chunk_in_flight) FAIL(pb, ASDG_ESTATE, "a chunk of the previous solve is still in flight");
+  asdg_pcg_opts o{1e-8, 20000, 16, 1, 0};
+  if (opts) o = *opts;
+  if (!(o.rtol >= 0.0) || o.max_iter < 1 || o.check_every < 1) FAIL(pb, ASDG_EINVAL, "invalid PCG options");
+  o.use_graph = 1;
+  o.time_kernels = 0;
+  asdg_status e = ensure_graph(pb, o.check_every);
+  if (e != ASDG_OK) return e;
+  hipStream_t s = (hipStream_t)stream;
+  if (!pb->t0) {
+    HIPCHK(pb, hipEventCreate(&pb->t0));
+    HIPCHK(pb, hipEventCreate(&pb->t1));
+  }
+  HIPCHK(pb, hipEventRecord(pb->t0, s));
+  e = enqueue_begin(pb, d_b, o, s);
+  if (e != ASDG_OK) return e;
+  pb->aopts = o;
+  pb->solve_open = true;
+  pb->hs = DevState{};
+  return enqueue_state_copy(pb, s);
+}
+
+asdg_status asdg_pcg_step(asdg_problem* pb, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (!pb->solve_open) FAIL(pb, ASDG_ESTATE, "no open solve");
+  if (pb->chunk_in_flight) FAIL(pb, ASDG_ESTATE, "previous chunk not yet observed by asdg_pcg_poll");
+  if (pb->hs.done) return ASDG_OK;
+  HIPCHK(pb, hipGraphLaunch(pb->gexec, (hipStream_t)stream));
+  return enqueue_state_copy(pb, (hipStream_t)stream);
+}
+
+asdg_status asdg_pcg_poll(asdg_problem* pb, int32_t* chunk_done, int32_t* solve_done, int32_t* iterations) {
+  if (!pb) return ASDG_EINVAL;
+  if (!pb->solve_open) FAIL(pb, ASDG_ESTATE, "no open solve");
+  if (pb->chunk_in_flight) {
+    hipError_t q = hipEventQuery(pb->chunk_ev);
+    if (q == hipErrorNotReady) {
+      if (chunk_done) *chunk_done = 0;
+      if (solve_done) *solve_done = 0;
+      if (iterations) *iterations = pb->hs.it;
+      return ASDG_OK;
+    }
+    if (q != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    pb->hs = *pb->h_state;
+    pb->chunk_in_flight = false;
+  }
+  if (chunk_done) *chunk_done = 1;
+  if (solve_done) *solve_done = pb->hs.done ? 1 : 0;
+  if (iterations) *iterations = pb->hs.it;
+  return ASDG_OK;
+}
+
+asdg_status asdg_pcg_finish(asdg_problem* pb, double* d_x, asdg_pcg_stats* stats, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (!pb->solve_open) FAIL(pb, ASDG_ESTATE, "no open solve");
+  if (pb->chunk_in_flight || !pb->hs.done) FAIL(pb, ASDG_ESTATE, "solve not finished (poll until solve_done)");
+  if (!d_x) FAIL(pb, ASDG_EINVAL, "d_x is null");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(pb, launch_unpermute_out(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm),
+                                  pb->ptr<double>(3, pb->o3.x), d_x, s));
+  HIPCHK(pb, hipEventRecord(pb->t1, s));
+  HIPCHK(pb, hipEventSynchronize(pb->t1));
+  float ms = 0.f;
+  HIPCHK(pb, hipEventElapsedTime(&ms, pb->t0, pb->t1));
+  pb->solve_open = false;
+  asdg_status e = fill_stats(pb, pb->hs, ms, 0.0, 0, stats);
+  if (e != ASDG_OK) return e;
+  return status_of(pb, pb->hs);
+}
 
 asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, const int32_t* coarse_of_cell,
                       const asdg_mesh* coarse_mesh, size_t bytes[4]) {
@@ -535,6 +701,7 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
   if (!pb) return ASDG_EINVAL;
   if (pb->stage < 4 || !pb->coarse_ready) FAIL(pb, ASDG_ESTATE, "asdg_pcg_solve before asdg_factor/asdg_setup_coarse");
   if (!d_x) FAIL(pb, ASDG_EINVAL, "d_x is null");
+  if (pb->chunk_in_flight) FAIL(pb, ASDG_ESTATE, "a non-blocking solve is in flight");
   asdg_pcg_opts o{1e-8, 20000, 16, 1, 0};
   if (opts) o = *opts;
   if (!(o.rtol >= 0.0) || o.max_iter < 1 || o.check_every < 1) FAIL(pb, ASDG_EINVAL, "invalid PCG options");
@@ -542,130 +709,61 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
   // between them, so kernel timing always uses eager launches
   if (o.time_kernels) o.use_graph = 0;
   hipStream_t s = (hipStream_t)stream;
-  const int np = pb->A.np;
-  const int32_t N = pb->A.n_cells;
-  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  const int k = o.check_every;
   if (!pb->t0) {
     HIPCHK(pb, hipEventCreate(&pb->t0));
     HIPCHK(pb, hipEventCreate(&pb->t1));
   }
-  const int k = o.check_every;
-  if ((int)pb->ev.size() < 2 * k) {
-    while ((int)pb->ev.size() < 2 * k) {
-      hipEvent_t e;
-      HIPCHK(pb, hipEventCreate(&e));
-      pb->ev.push_back(e);
-    }
+  while ((int)pb->ev.size() < 2 * k) {
+    hipEvent_t e;
+    HIPCHK(pb, hipEventCreate(&e));
+    pb->ev.push_back(e);
+  }
+  if (o.use_graph) {
+    asdg_status ge = ensure_graph(pb, k);
+    if (ge != ASDG_OK) return ge;
   }
   HIPCHK(pb, hipEventRecord(pb->t0, s));
-  // x = 0, r = b (internal order), ||b||^2, z = P^{-1} r, p = z
-  const double* src = d_b ? d_b : pb->ptr<double>(0, pb->o0.rhs);
-  Reduction* red = pb->ptr<Reduction>(3, pb->o3.red);
-  HIPCHK(pb, launch_permute_in(np, N, pb->ptr<int32_t>(0, pb->o0.perm), src, pb->ptr<double>(3, pb->o3.r),
-                               pb->ptr<double>(3, pb->o3.x), pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
-                               pb->f32, red, st, o.rtol, o.max_iter, s));
-  asdg_status e = enqueue_precond(pb, s, st, red, nullptr, nullptr);
+  asdg_status e = enqueue_begin(pb, d_b, o, s);
   if (e != ASDG_OK) return e;
-  HIPCHK(pb, launch_update_p(pb->n(), st, red, pb->ptr<double>(3, pb->o3.rz2),
-                             pb->ptr<double>(3, pb->o3.bh), pb->ptr<double>(3, pb->o3.z), pb->ptr<double>(3, pb->o3.p),
-                             1, s));
   double t_local = 0.0;
   int n_local = 0;
   DevState h;
   e = read_state(pb, s, h);
   if (e != ASDG_OK) return e;
-  if (o.use_graph) {
-    if (!pb->own_stream) HIPCHK(pb, hipStreamCreateWithFlags(&pb->own_stream, hipStreamNonBlocking));
-    hipStream_t gs = pb->own_stream;
-    if (!pb->gexec || pb->g_k != k || pb->g_timed != o.time_kernels) {
-      pb->drop_graph();
-      hipGraph_t g;
-      HIPCHK(pb, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-      asdg_status ce = ASDG_OK;
-      for (int i = 0; i < k && ce == ASDG_OK; ++i)
-        ce = enqueue_iteration(pb, gs, o.time_kernels ? pb->ev[2 * i] : nullptr,
-                               o.time_kernels ? pb->ev[2 * i + 1] : nullptr);
-      hipError_t he = hipStreamEndCapture(gs, &g);
-      if (ce != ASDG_OK) return ce;
-      if (he != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("graph capture: ") + hipGetErrorString(he));
-      he = hipGraphInstantiate(&pb->gexec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (he != hipSuccess) FAIL(pb, ASDG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(he));
-      pb->g_k = k;
-      pb->g_timed = o.time_kernels;
-    }
-    while (!h.done) {
-      const int it0 = h.it;
-      HIPCHK(pb, hipGraphLaunch(pb->gexec, gs));
-      HIPCHK(pb, hipStreamSynchronize(gs));
-      e = read_state(pb, s, h);
-      if (e != ASDG_OK) return e;
-      if (o.time_kernels && n_local >= 0) {
-        const int ran = h.it - it0 - (h.done ? 1 : 0);
-        for (int i = 0; i < ran && i < k; ++i) {
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]) != hipSuccess) {
-            (void)hipGetLastError();
-            n_local = -1;  // event timing inside graphs unavailable
-            t_local = 0.0;
-            break;
-          }
-          t_local += ms;
-          ++n_local;
-        }
-      }
-    }
-  } else {
-    while (!h.done) {
-      const int it0 = h.it;
+  while (!h.done) {
+    const int it0 = h.it;
+    if (o.use_graph) {
+      HIPCHK(pb, hipGraphLaunch(pb->gexec, s));
+    } else {
       for (int i = 0; i < k; ++i) {
         e = enqueue_iteration(pb, s, o.time_kernels ? pb->ev[2 * i] : nullptr,
                               o.time_kernels ? pb->ev[2 * i + 1] : nullptr);
         if (e != ASDG_OK) return e;
       }
-      e = read_state(pb, s, h);
-      if (e != ASDG_OK) return e;
-      if (o.time_kernels) {
-        const int ran = h.it - it0 - (h.done ? 1 : 0);
-        for (int i = 0; i < ran && i < k; ++i) {
-          float ms = 0.f;
-          HIPCHK(pb, hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]));
-          t_local += ms;
-          ++n_local;
-        }
+    }
+    e = read_state(pb, s, h);
+    if (e != ASDG_OK) return e;
+    if (o.time_kernels) {
+      // the local solve of the iteration that stops does not run
+      const int ran = h.it - it0 - (h.done ? 1 : 0);
+      for (int i = 0; i < ran && i < k; ++i) {
+        float ms = 0.f;
+        HIPCHK(pb, hipEventElapsedTime(&ms, pb->ev[2 * i], pb->ev[2 * i + 1]));
+        t_local += ms;
+        ++n_local;
       }
     }
   }
-  HIPCHK(pb, launch_unpermute_out(np, N, pb->ptr<int32_t>(0, pb->o0.perm), pb->ptr<double>(3, pb->o3.x), d_x, s));
+  HIPCHK(pb, launch_unpermute_out(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm),
+                                  pb->ptr<double>(3, pb->o3.x), d_x, s));
   HIPCHK(pb, hipEventRecord(pb->t1, s));
   HIPCHK(pb, hipEventSynchronize(pb->t1));
   float solve_ms = 0.f;
   HIPCHK(pb, hipEventElapsedTime(&solve_ms, pb->t0, pb->t1));
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->iterations = h.it;
-    stats->converged = h.status == 1;
-    stats->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-    stats->t_solve_ms = solve_ms;
-    stats->t_local_ms = t_local;
-    stats->n_local = n_local;
-    stats->failed_subdomain = -2;
-    const int ka = std::min(h.it, HIST);
-    if (ka >= 1) {
-      std::vector<double> al(ka), be(std::max(ka - 1, 0));
-      HIPCHK(pb, hipMemcpy(al.data(), pb->ptr<double>(3, pb->o3.ah), 8 * ka, hipMemcpyDeviceToHost));
-      if (ka > 1) HIPCHK(pb, hipMemcpy(be.data(), pb->ptr<double>(3, pb->o3.bh), 8 * (ka - 1), hipMemcpyDeviceToHost));
-      std::vector<double> d(ka), off(std::max(ka - 1, 0));
-      d[0] = 1.0 / al[0];
-      for (int j = 1; j < ka; ++j) d[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
-      for (int j = 0; j + 1 < ka; ++j) off[j] = std::sqrt(std::max(be[j], 0.0)) / al[j];
-      tridiag_extremes(d, off, stats->lambda_min, stats->lambda_max);
-    }
-  }
-  if (h.status == 4) FAIL(pb, ASDG_EHIP, "local-solve wait budget exhausted");
-  if (h.status == 3) FAIL(pb, ASDG_EBREAKDOWN, "PCG breakdown (p.Ap <= 0 or NaN)");
-  if (h.status == 2) FAIL(pb, ASDG_ENOCONV, "maximum number of iterations reached");
-  return ASDG_OK;
+  e = fill_stats(pb, h, solve_ms, t_local, n_local, stats);
+  if (e != ASDG_OK) return e;
+  return status_of(pb, h);
 }
 
 asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, double* d_out, void* stream) {

@@ -243,19 +243,23 @@ def f_one(xy: np.ndarray) -> np.ndarray:
     return np.ones(xy.shape[0])
 
 
-def make_f_series(coef: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
-    """f = sum_{k,l=1..K} c_kl sin(k pi x) sin(l pi y)."""
-    coef = np.asarray(coef, dtype=np.float64)
+class SineSeries:
+    """f = sum_{k,l=1..K} c_kl sin(k pi x) sin(l pi y) (picklable)."""
 
-    def f(xy: np.ndarray) -> np.ndarray:
+    def __init__(self, coef):
+        self.coef = np.asarray(coef, dtype=np.float64)
+
+    def __call__(self, xy: np.ndarray) -> np.ndarray:
         out = np.zeros(xy.shape[0])
-        for k in range(coef.shape[0]):
+        for k in range(self.coef.shape[0]):
             sk = np.sin((k + 1) * math.pi * xy[:, 0])
-            for l in range(coef.shape[1]):
-                out += coef[k, l] * sk * np.sin((l + 1) * math.pi * xy[:, 1])
+            for l in range(self.coef.shape[1]):
+                out += self.coef[k, l] * sk * np.sin((l + 1) * math.pi * xy[:, 1])
         return out
 
-    return f
+
+def make_f_series(coef: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+    return SineSeries(coef)
 
 
 # ------------------------------------------------------------- workloads

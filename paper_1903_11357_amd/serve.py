@@ -1,0 +1,167 @@
+"""Continuous-batching request loop for two-level Schwarz PCG solves.
+
+Requests (a mesh, coefficients and a right-hand side each) arrive over
+time. The server
+  * assembles arriving requests on host worker threads (the native assembly
+    runs without the Python lock),
+  * admits an assembled request when a slot is free and its exact device
+    footprint (the four buffer sizes reported by asdg_plan) fits the HBM
+    budget, then binds its buffers, factorises and sets up the coarse level,
+  * keeps every admitted request's factors resident and advances all active
+    solves in chunks of `check_every` PCG iterations, each on its own HIP
+    stream (captured graphs), so the iterations of different requests are
+    in flight on the device together; new requests join as slots and memory
+    free up, finished ones leave at once and release their buffers,
+  * records arrival-to-completion latency for every request.
+
+Each request's arithmetic is independent of the others' (own buffers,
+deterministic kernels), so a result is the same alone and in the mix.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import dataclasses
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import asdg
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    problem: object                 # inputs.Problem
+    arrival: float = 0.0            # seconds after the start of the run
+    # filled by the server
+    t_assembled: float = -1.0
+    t_admitted: float = -1.0
+    t_done: float = -1.0
+    iterations: int = 0
+    status: str = ""
+    bytes: int = 0
+    x: Optional[object] = None      # torch tensor when keep_solutions
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+class _Active:
+    def __init__(self, req, pr, stream):
+        self.req = req
+        self.pr = pr
+        self.stream = stream
+
+
+def _host_setup(req, precision):
+    P = req.problem
+    pr = asdg.Problem()
+    pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    b = pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
+                coarse_mesh=P.coarse_mesh)
+    return pr, int(sum(b))
+
+
+class Server:
+    def __init__(self, device="cuda:0", precision=asdg.FP32_LOCAL, hbm_budget: Optional[int] = None,
+                 max_active: int = 16, check_every: int = 16, setup_workers: int = 4,
+                 keep_solutions: bool = False, rtol: float = 1e-8, max_iter: int = 20000):
+        import torch
+
+        self.device = torch.device(device)
+        self.precision = precision
+        if hbm_budget is None:
+            free, total = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.5 * free)
+        self.hbm_budget = hbm_budget
+        self.max_active = max_active
+        self.check_every = check_every
+        self.setup_workers = setup_workers
+        self.keep_solutions = keep_solutions
+        self.rtol = rtol
+        self.max_iter = max_iter
+        self.peak_active = 0
+        self.peak_bytes = 0
+
+    def run(self, requests: List[Request]) -> List[Request]:
+        import torch
+
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        pool = cf.ThreadPoolExecutor(max_workers=self.setup_workers)
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        nxt = 0                      # next request not yet arrived
+        preparing = []               # (req, future) in arrival order
+        active: List[_Active] = []
+        used = 0
+        done: List[Request] = []
+        try:
+            while len(done) < len(reqs):
+                t = now()
+                # arrivals -> host assembly
+                while nxt < len(reqs) and reqs[nxt].arrival <= t:
+                    r = reqs[nxt]
+                    preparing.append((r, pool.submit(_host_setup, r, self.precision)))
+                    nxt += 1
+                # admission in arrival order (no overtaking)
+                while preparing and preparing[0][1].done() and len(active) < self.max_active:
+                    r, fut = preparing[0]
+                    pr, nbytes = fut.result()
+                    if r.t_assembled < 0:
+                        r.t_assembled = now()
+                    if nbytes > self.hbm_budget:
+                        raise RuntimeError(f"request {r.rid} needs {nbytes} B, more than the HBM budget")
+                    if used + nbytes > self.hbm_budget:
+                        break
+                    preparing.pop(0)
+                    stream = torch.cuda.Stream(self.device)
+                    with torch.cuda.stream(stream):  # buffers belong to the request's stream
+                        pr.bind(self.device, stream=stream)
+                    pr.factor(stream=stream)
+                    pr.setup_coarse(stream=stream)
+                    pr.begin(rtol=self.rtol, max_iter=self.max_iter, check_every=self.check_every,
+                             stream=stream)
+                    r.bytes = nbytes
+                    r.t_admitted = now()
+                    used += nbytes
+                    active.append(_Active(r, pr, stream))
+                    self.peak_active = max(self.peak_active, len(active))
+                    self.peak_bytes = max(self.peak_bytes, used)
+                # advance / retire active solves
+                progressed = False
+                for a in list(active):
+                    chunk_done, solve_done, its = a.pr.poll()
+                    if not chunk_done:
+                        continue
+                    progressed = True
+                    if solve_done:
+                        x, st = a.pr.finish(stream=a.stream, raise_on_noconv=False)
+                        r = a.req
+                        r.t_done = now()
+                        r.iterations = st["iterations"]
+                        r.status = st["status"]
+                        if self.keep_solutions:
+                            r.x = x.clone()
+                        used -= r.bytes
+                        active.remove(a)
+                        del a.pr
+                        done.append(r)
+                    else:
+                        a.pr.step(stream=a.stream)
+                if not progressed and not (preparing and preparing[0][1].done()):
+                    time.sleep(2e-5)
+        finally:
+            pool.shutdown(wait=True)
+        return done
+
+
+def latency_stats(done: List[Request]) -> dict:
+    lat = np.array([r.latency for r in done])
+    span = max(r.t_done for r in done) - min(r.arrival for r in done)
+    return {"n": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "solves_per_s": len(done) / span if span > 0 else None,
+            "iterations_mean": float(np.mean([r.iterations for r in done])),
+            "all_converged": all(r.status == "OK" for r in done)}
