@@ -39,14 +39,16 @@ WORKLOADS = {
 }
 
 
-def measured_traffic(workload, mode):
+def measured_traffic(workload, mode, local="sweeps"):
     """HBM bytes per local-solve launch from the committed rocprofv3 counter
     summary, if it was taken on this workload/mode with the current kernel
     source; else None."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"k_trsv_{workload}_{mode}_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_1903_11357_amd", "csrc", "kern_trsv.hip")
+    kern = "k_symv" if local == "inverse" else "k_trsv"
+    path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_{mode}_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1903_11357_amd", "csrc",
+                       "kern_inv.hip" if local == "inverse" else "kern_trsv.hip")
     if not os.path.exists(path):
         return None
     meta = {}
@@ -60,19 +62,23 @@ def measured_traffic(workload, mode):
     return float(meta["traffic_bytes_per_launch"])
 
 
-def local_solve_bytes(pr, word_bytes):
-    """Algorithmic bytes of one batched local solve (both sweeps): each sweep
-    reads the packed lower triangle n_i(n_i+1)/2 of every factor once; the
-    vectors add r (FP64 read), y (write + read) and z (write)."""
+def local_solve_bytes(pr, word_bytes, inverse=False):
+    """Algorithmic bytes of one batched local solve. Triangular sweeps: each
+    of the two sweeps reads the packed lower triangle n_i(n_i+1)/2 of every
+    factor once; vectors: r (FP64 read), y (write + read), z (write).
+    Explicit inverse: one read of the packed lower triangle of every
+    A_i^{-1}; vectors: r (FP64 read), z (write)."""
     import numpy as np
 
     n_i = pr._sub_sizes().astype(np.float64)
+    if inverse:
+        return float((n_i * (n_i + 1) / 2).sum()) * word_bytes + pr.n * (8 + word_bytes)
     factor = float((n_i * (n_i + 1)).sum()) * word_bytes
     vec = pr.n * (8 + 3 * word_bytes)
     return factor + vec
 
 
-def run_mode(P, precision, steps, warmup, check_every):
+def run_mode(P, precision, steps, warmup, check_every, inverse=False):
     import torch
 
     from paper_1903_11357_amd import asdg
@@ -80,6 +86,8 @@ def run_mode(P, precision, steps, warmup, check_every):
     t0 = time.perf_counter()
     pr = asdg.Problem()
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    if inverse:
+        pr.set_tuning(asdg.TUNE_LOCAL_INVERSE, 1)
     pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
             coarse_mesh=P.coarse_mesh)
     t1 = time.perf_counter()
@@ -135,7 +143,8 @@ def run_mode(P, precision, steps, warmup, check_every):
         "setup_s": {"assemble_plan_host": t1 - t0, "bind_upload": t2 - t1, "factor": t3 - t2,
                     "coarse": t4 - t3},
         "local_solve": {"avg_ms": tl / max(nl, 1), "launches": nl,
-                        "algorithmic_bytes": local_solve_bytes(pr, w)},
+                        "algorithmic_bytes": local_solve_bytes(pr, w, inverse),
+                        "representation": "explicit inverse" if inverse else "triangular sweeps"},
     }
     del pr
     torch.cuda.empty_cache()
@@ -214,6 +223,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--modes", default="fp32,fp64")
+    ap.add_argument("--local", default="inverse,sweeps",
+                    help="local-solve representations, the first is the headline: inverse (packed "
+                         "A_i^{-1}, one pass) and/or sweeps (Cholesky forward/backward sweeps)")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap PCG iterations (profiling runs; 0 = the workload's own limit)")
     ap.add_argument("--serving-requests", type=int, default=64,
@@ -247,11 +259,15 @@ def main():
         P.max_iter = a.max_iter
     print(f"[bench] workload {a.workload}: n={P.n_dofs} subdomains={P.n_sub}", file=sys.stderr, flush=True)
     modes = {}
-    for m in a.modes.split(","):
-        prec = asdg.FP32_LOCAL if m == "fp32" else asdg.FP64
-        modes[m] = run_mode(P, prec, a.steps, a.warmup, a.check_every)
-        print(f"[bench] {m}: {json.dumps(modes[m])}", file=sys.stderr, flush=True)
-    head = modes.get("fp32") or modes.get("fp64")
+    for loc in a.local.split(","):
+        for m in a.modes.split(","):
+            prec = asdg.FP32_LOCAL if m == "fp32" else asdg.FP64
+            key = m if loc == "inverse" else f"{m}-sweeps"
+            modes[key] = run_mode(P, prec, a.steps, a.warmup, a.check_every, inverse=(loc == "inverse"))
+            print(f"[bench] {key}: {json.dumps(modes[key])}", file=sys.stderr, flush=True)
+    first = a.local.split(",")[0]
+    hk = lambda m: m if first == "inverse" else f"{m}-sweeps"  # noqa: E731
+    head = modes.get(hk("fp32")) or modes.get(hk("fp64"))
     ls = head["local_solve"]
     achieved = ls["algorithmic_bytes"] / (ls["avg_ms"] * 1e-3) / 1e9 if ls["avg_ms"] > 0 else None
     out = {
@@ -265,20 +281,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-local+f64" if "fp32" in modes else "f64",
+        "dtype": "f32-local+f64" if hk("fp32") in modes else "f64",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}", "n_dofs": P.n_dofs,
                    "subdomains": P.n_sub, "rtol": P.rtol, "parallelism": "single GPU"},
         "modes": modes,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic(a.workload, "fp32" if "fp32" in modes else "fp64"),
-                     "kernel": "k_trsv (batched local forward+backward sweeps)",
+                     "traffic": measured_traffic(a.workload, "fp32" if hk("fp32") in modes else "fp64", first),
+                     "kernel": ("k_symv_tiles + k_symv_gather (packed local inverses)" if first == "inverse"
+                                else "k_trsv (batched local forward+backward sweeps)"),
                      "algorithmic_bytes": ls["algorithmic_bytes"], "avg_ms": ls["avg_ms"]},
     }
-    if "fp32" in modes and "fp64" in modes:
-        out["fp32_local_speedup_per_iteration"] = modes["fp64"]["ms_per_iteration"] / modes["fp32"]["ms_per_iteration"]
-        out["fp32_local_speedup_per_solve"] = modes["fp64"]["ms_per_step"] / modes["fp32"]["ms_per_step"]
+    if hk("fp32") in modes and hk("fp64") in modes:
+        f32, f64 = modes[hk("fp32")], modes[hk("fp64")]
+        out["fp32_local_speedup_per_iteration"] = f64["ms_per_iteration"] / f32["ms_per_iteration"]
+        out["fp32_local_speedup_per_solve"] = f64["ms_per_step"] / f32["ms_per_step"]
     if a.serving_requests > 0:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(a.serving_requests)

@@ -222,9 +222,14 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
 /* Launch-shape tuning (autotuner hook): what = ASDG_TUNE_*; value 0 restores
  * the default. CHOL_WG_PER_CU / TRSV_WG_PER_CU: persistent work-groups per
  * compute unit of the factorisation and triangular-sweep launches;
- * CHOL_GRID: total work-groups of the factorisation launch. */
+ * CHOL_GRID: total work-groups of the factorisation launch.
+ * LOCAL_INVERSE (set before asdg_plan): 1 = apply the exact local solvers
+ * through explicit inverses A_i^{-1} = L_i^{-T} L_i^{-1} formed after the
+ * Cholesky factorisation (one pass over a packed symmetric matrix per
+ * solve instead of two triangular sweeps; the factor buffer doubles); the
+ * factor tiles then hold the lower tiles of A_i^{-1}. 0 = triangular sweeps. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
-       ASDG_TUNE_TRACE = 3 };
+       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Task trace of the last batched local solve launched while

@@ -79,7 +79,7 @@ _SIGS = {
     "asdg_pcg_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
-TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE = 0, 1, 2, 3
+TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE = 0, 1, 2, 3, 4
 
 
 def lib():
@@ -322,11 +322,13 @@ class Problem:
         return a.reshape(n0, n0)
 
 
-def setup_problem(P, precision=FP64, device="cuda", factor=True):
+def setup_problem(P, precision=FP64, device="cuda", factor=True, local_inverse=False):
     """Assemble + plan (+ bind/factor/coarse if a device is given) for an
     ``inputs.Problem``."""
     pr = Problem()
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    if local_inverse:
+        pr.set_tuning(TUNE_LOCAL_INVERSE, 1)
     pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
             coarse_mesh=P.coarse_mesh)
     if device is not None:

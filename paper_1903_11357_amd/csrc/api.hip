@@ -106,15 +106,18 @@ struct asdg_problem {
   std::vector<double> ctiles_host;
   int64_t n_ctiles = 0;
   // buffer layout
-  struct { size_t row_ptr, col, blocks, rhs, perm; } o0{};
-  struct { size_t tiles, subs, chol, trsv, meta; } o1{};
+  struct { size_t row_ptr, col, blocks, rhs, perm, cell_sub; } o0{};
+  struct { size_t tiles, subs, chol, trsv, meta, xtiles, inv; } o1{};
   struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv; } o2{};
-  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace; } o3{};
+  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace, part; } o3{};
   size_t bytes[4] = {0, 0, 0, 0};
   char* buf[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t failed_sub = -2;
   int n_cu = 256;
   int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
+  int local_inverse = 0, inv_planned = 0;  // explicit local inverses (set before asdg_plan)
+  std::vector<int4> inv_tasks;
+  std::vector<int32_t> cell_sub;
   // captured iteration chunk
   hipGraphExec_t gexec = nullptr;
   int g_k = 0, g_timed = 0;
@@ -283,12 +286,19 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_
                                pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), st_done, s));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
+  if (pb->inv_planned) {
+    HIPCHK(pb, launch_symv(pb->f32, np, pb->A.n_cells, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+                           pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.cell_sub),
+                           pb->ptr<void>(1, pb->o1.tiles), r, pb->ptr<void>(3, pb->o3.part),
+                           pb->ptr<void>(3, pb->o3.zl), st, s));
+  } else {
   const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
                                                  (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
   HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
                          pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
                          pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
                          pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
+  }
   if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
   if (pb->has_coarse) {
     const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
@@ -523,6 +533,20 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
     plan_coarse_factor(pb);
   }
   plan_local(pb);
+  pb->inv_planned = pb->local_inverse;
+  pb->inv_tasks.clear();
+  if (pb->inv_planned) {
+    // X = L^{-1} tasks (i, j, b), j <= b, in row order: every X_kj with k < b comes first
+    int nbmax = 0;
+    for (const SubDesc& d : pb->subs) nbmax = std::max(nbmax, d.nb);
+    for (int b = 0; b < nbmax; ++b)
+      for (int32_t i = 0; i < pb->A.n_sub; ++i)
+        if (b < pb->subs[i].nb)
+          for (int j = 0; j <= b; ++j) pb->inv_tasks.push_back(make_int4(i, j, b, 0));
+  }
+  pb->cell_sub.assign(pb->A.n_cells, 0);
+  for (int32_t i = 0; i < pb->A.n_sub; ++i)
+    for (int32_t c = pb->A.sub_ptr[i]; c < pb->A.sub_ptr[i + 1]; ++c) pb->cell_sub[c] = i;
 
   const Assembled& A = pb->A;
   const int64_t N = A.n_cells, n = pb->n(), nnzb = A.row_ptr[N];
@@ -533,11 +557,16 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o0.blocks = L0.add(8 * nnzb * A.np * A.np);
   pb->o0.rhs = L0.add(8 * n);
   pb->o0.perm = L0.add(4 * N);
+  pb->o0.cell_sub = L0.add(4 * N);
   pb->o1.tiles = L1.add((size_t)pb->n_tiles * TILE * TILE * w);
   pb->o1.subs = L1.add(sizeof(SubDesc) * pb->subs.size());
   pb->o1.chol = L1.add(sizeof(int4) * pb->chol_tasks.size());
   pb->o1.trsv = L1.add(sizeof(int4) * pb->trsv_tasks.size());
   pb->o1.meta = L1.add(sizeof(int4) * pb->tile_meta.size());
+  if (pb->inv_planned) {
+    pb->o1.xtiles = L1.add((size_t)pb->n_tiles * TILE * TILE * w);
+    pb->o1.inv = L1.add(sizeof(int4) * pb->inv_tasks.size());
+  }
   if (pb->has_coarse) {
     const Coarse& C = pb->C;
     pb->o2.pptr = L2.add(4 * (N + 1));
@@ -571,6 +600,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o3.bh = L3.add(8 * (size_t)HIST);
   pb->o3.flags = L3.add(4 * (size_t)std::max<int64_t>(pb->n_tiles, pb->n_ctiles));
   pb->o3.trace = L3.add(3 * 8 * pb->trsv_tasks.size());
+  pb->o3.part = L3.add(pb->inv_planned ? (size_t)pb->n_tiles * 2 * TILE * w : 0);
   pb->bytes[0] = L0.size;
   pb->bytes[1] = L1.size;
   pb->bytes[2] = L2.size;
@@ -615,6 +645,8 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   }
   HIPCHK(pb, up(0, pb->o0.rhs, pb->rhs_caller.data(), 8 * pb->rhs_caller.size()));
   HIPCHK(pb, up(0, pb->o0.perm, A.perm.data(), 4 * A.perm.size()));
+  HIPCHK(pb, up(0, pb->o0.cell_sub, pb->cell_sub.data(), 4 * pb->cell_sub.size()));
+  if (pb->inv_planned) HIPCHK(pb, up(1, pb->o1.inv, pb->inv_tasks.data(), sizeof(int4) * pb->inv_tasks.size()));
   HIPCHK(pb, up(1, pb->o1.subs, pb->subs.data(), sizeof(SubDesc) * pb->subs.size()));
   HIPCHK(pb, up(1, pb->o1.chol, pb->chol_tasks.data(), sizeof(int4) * pb->chol_tasks.size()));
   HIPCHK(pb, up(1, pb->o1.trsv, pb->trsv_tasks.data(), sizeof(int4) * pb->trsv_tasks.size()));
@@ -674,6 +706,22 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
   asdg_status e = run_cholesky(pb, s, pb->f32, (int32_t)pb->chol_tasks.size(), pb->ptr<int4>(1, pb->o1.chol),
                                pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0);
   if (e != ASDG_OK) return e;
+  if (pb->inv_planned) {
+    DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+    HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_tiles, 0, s));
+    HIPCHK(pb, launch_reset_queues(st, s));
+    const int per_cu = pb->f32 ? 4 : 2;
+    const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)pb->inv_tasks.size(), (int64_t)pb->n_cu * per_cu));
+    const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>(pb->n_tiles, (int64_t)pb->n_cu * per_cu * 4));
+    HIPCHK(pb, launch_inverse(pb->f32, (int32_t)pb->inv_tasks.size(), pb->ptr<int4>(1, pb->o1.inv),
+                              (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta), pb->ptr<SubDesc>(1, pb->o1.subs),
+                              pb->ptr<void>(1, pb->o1.tiles), pb->ptr<void>(1, pb->o1.xtiles),
+                              pb->ptr<int32_t>(3, pb->o3.flags), st, &st->q_chol, g1, g2, s));
+    DevState h;
+    e = read_state(pb, s, h);
+    if (e != ASDG_OK) return e;
+    if (h.abort) FAIL(pb, ASDG_EHIP, "inverse formation wait budget exhausted");
+  }
   pb->stage = 4;
   return ASDG_OK;
 }
@@ -797,7 +845,12 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                                  pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
                                  pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
                                  pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), nullptr, s));
-    if (loc) {
+    if (loc && pb->inv_planned) {
+      HIPCHK(pb, launch_symv(pb->f32, np, N, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+                             pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.cell_sub),
+                             pb->ptr<void>(1, pb->o1.tiles), r, pb->ptr<void>(3, pb->o3.part),
+                             pb->ptr<void>(3, pb->o3.zl), nullptr, s));
+    } else if (loc) {
       const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
                                                  (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
       HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
@@ -924,6 +977,7 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_TRSV_WG_PER_CU) pb->trsv_per_cu = value;
   else if (what == ASDG_TUNE_CHOL_GRID) pb->chol_grid = value;
   else if (what == ASDG_TUNE_TRACE) pb->trace = value;
+  else if (what == ASDG_TUNE_LOCAL_INVERSE) pb->local_inverse = value ? 1 : 0;
   else FAIL(pb, ASDG_EINVAL, "unknown tuning key");
   pb->drop_graph();
   return ASDG_OK;

@@ -1,0 +1,104 @@
+// MFMA tile helpers shared by the factorisation kernels (gfx950, wave64).
+// A work-group of four waves owns a TILE x TILE tile; wave w owns the 32x32
+// quadrant at rows 32*(w/2), columns 32*(w%2).
+#pragma once
+
+#include "kern_common.h"
+
+namespace asdg {
+namespace mfma {
+
+constexpr int LDA = TILE + 1;  // padded LDS row (bank spread for column reads)
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Per-lane accumulator of a wave's 32x32 quadrant, 16 values per lane.
+template <typename T>
+struct Quad;
+
+template <>
+struct Quad<float> {
+  f32x16 c;
+  __device__ void zero() {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) c[e] = 0.0f;
+  }
+  // v_mfma_f32_32x32x2f32 result: register e of lane l holds D[8(e/4) + 4(l/32) + e%4][l%32]
+  __device__ static int row(int e, int lane) { return 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3); }
+  __device__ static int col(int e, int lane) { return lane & 31; }
+  __device__ float get(int e) const { return c[e]; }
+  __device__ void set(int e, float v) { c[e] = v; }
+  // c += sign * A[R0.., :] * B[C0.., :]^T with A, B in LDS (row-major, LDA)
+  __device__ void mma(const float* A, const float* B, int R0, int C0, int lane, float sign) {
+    const float* a = A + (R0 + (lane & 31)) * LDA + (lane >> 5);
+    const float* b = B + (C0 + (lane & 31)) * LDA + (lane >> 5);
+#pragma unroll 8
+    for (int k0 = 0; k0 < TILE; k0 += 2) c = __builtin_amdgcn_mfma_f32_32x32x2f32(sign * a[k0], b[k0], c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Quad<double> {
+  f64x4 c[4];
+  __device__ void zero() {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[s][v] = 0.0;
+  }
+  // v_mfma_f64_16x16x4f64 result: register v of lane l holds D[4v + l/16][l%16]
+  __device__ static int row(int e, int lane) { return 16 * ((e >> 2) >> 1) + 4 * (e & 3) + (lane >> 4); }
+  __device__ static int col(int e, int lane) { return 16 * ((e >> 2) & 1) + (lane & 15); }
+  __device__ double get(int e) const { return c[e >> 2][e & 3]; }
+  __device__ void set(int e, double v) { c[e >> 2][e & 3] = v; }
+  __device__ void mma(const double* A, const double* B, int R0, int C0, int lane, double sign) {
+    const double* a0 = A + (R0 + (lane & 15)) * LDA + (lane >> 4);
+    const double* a1 = a0 + 16 * LDA;
+    const double* b0 = B + (C0 + (lane & 15)) * LDA + (lane >> 4);
+    const double* b1 = b0 + 16 * LDA;
+#pragma unroll 4
+    for (int k0 = 0; k0 < TILE; k0 += 4) {
+      const double x0 = sign * a0[k0], x1 = sign * a1[k0];
+      const double y0 = b0[k0], y1 = b1[k0];
+      c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c[0], 0, 0, 0);
+      c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, c[1], 0, 0, 0);
+      c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, c[2], 0, 0, 0);
+      c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c[3], 0, 0, 0);
+    }
+  }
+};
+
+__device__ __forceinline__ void wait_flag(const int32_t* f, DevState* st) {
+  if (threadIdx.x == 0) {
+    int ok = load_agent(f) != 0;
+    for (int64_t budget = WAIT_BUDGET; !ok && budget > 0; --budget) {
+      __builtin_amdgcn_s_sleep(2);
+      ok = load_agent(f) != 0;
+      if (!ok && (budget & 255) == 0 && load_agent(&st->abort)) break;
+    }
+    if (!ok) store_agent(&st->abort, 1);
+  }
+  __syncthreads();
+}
+
+// Cooperative copy of a tile (global, row-major TILE x TILE) into LDS.
+template <typename T>
+__device__ __forceinline__ void tile_to_lds(const T* g, T* s, bool coherent) {
+  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
+    const T v = coherent ? load_agent(g + e) : g[e];
+    s[(e / TILE) * LDA + (e % TILE)] = v;
+  }
+}
+
+// Cooperative transposed copy: s[c][r] = g[r][c].
+template <typename T>
+__device__ __forceinline__ void tile_to_lds_t(const T* g, T* s, bool coherent) {
+  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
+    const T v = coherent ? load_agent(g + e) : g[e];
+    s[(e % TILE) * LDA + (e / TILE)] = v;
+  }
+}
+
+}  // namespace mfma
+}  // namespace asdg

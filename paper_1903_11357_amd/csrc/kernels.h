@@ -81,6 +81,14 @@ hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* tile_meta, c
 hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
                            int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
 
+// Explicit local inverses and their packed symmetric apply (kern_inv.hip).
+hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
+                          const SubDesc* subs, void* L, void* X, int32_t* flags, DevState* st, int32_t* queue,
+                          int grid_lower, int grid_gram, hipStream_t s);
+hipError_t launch_symv(int f32, int np, int32_t n_cells, int32_t n_tiles, const int4* meta, const SubDesc* subs,
+                       const int32_t* cell_sub, const void* S, const double* r, void* part, void* z,
+                       const DevState* st, hipStream_t s);
+
 // Batched forward/backward triangular sweeps (kern_trsv.hip).
 // trace (optional): per task, wall-clock at dequeue, end of waits, end.
 hipError_t launch_trsv(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs,

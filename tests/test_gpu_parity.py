@@ -24,20 +24,20 @@ CASES = {
 _cache = {}
 
 
-def _setup(name, precision):
+def _setup(name, precision, inverse=False):
     import torch
 
     from oracle import OracleSolver
     from paper_1903_11357_amd import asdg
 
-    key = (name, precision)
+    key = (name, precision, inverse)
     if key not in _cache:
         P = CASES[name]()
         if (name, "oracle") not in _cache:
             _cache[(name, "oracle")] = (P, OracleSolver(P))
         P, orc = _cache[(name, "oracle")]
-        print(f"[setup] {name} precision={precision} n={P.n_dofs}", flush=True)
-        pr = asdg.setup_problem(P, precision, device="cuda:0")
+        print(f"[setup] {name} precision={precision} inverse={inverse} n={P.n_dofs}", flush=True)
+        pr = asdg.setup_problem(P, precision, device="cuda:0", local_inverse=inverse)
         torch.cuda.synchronize()
         _cache[key] = (P, orc, pr)
     return _cache[key]
@@ -218,3 +218,53 @@ def test_example5_printed_condition_number_on_gpu():
     K = st["lambda_max"] / st["lambda_min"]
     print("K =", K, "iterations", st["iterations"])
     assert abs(K / 43.6818 - 1.0) < 1e-3
+
+
+# ---------------------------------------------------------------- explicit local inverses
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_local_inverse_apply_matches_oracle_and_is_symmetric(name, prec):
+    import torch
+
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, inverse=True)
+    u = _vec(pr.n, 7)
+    v = _vec(pr.n, 8)
+    lu = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(u).cuda()).cpu().numpy()
+    lv = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = orc.M.local_apply(u)
+    # an explicit inverse computed from the Cholesky factor carries relative
+    # error ~ n u kappa(A_i), like the triangular solves
+    tol = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * _kappa_local(name, orc)
+    assert _rel(lu, ref) <= tol, _rel(lu, ref)
+    # the packed symmetric apply is symmetric up to rounding of the dot products
+    eps = 1e-13 if prec == "fp64" else 1e-5
+    assert abs(u @ lv - v @ lu) <= eps * np.linalg.norm(u) * np.linalg.norm(lv)
+    pre = pr.apply(asdg.APPLY_PRECOND, torch.from_numpy(u).cuda()).cpu().numpy()
+    assert _rel(pre, ref + orc.M.coarse_apply(u)) <= tol
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_pcg_fp64_local_inverse_matches_oracle(name):
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup(name, asdg.FP64, inverse=True)
+    x, st = pr.solve(rtol=1e-8)
+    _check_pcg_parity(name + "/inverse", orc, st, x.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_pcg_fp32_local_inverse_solution_within_1e8(name):
+    import scipy.sparse.linalg as spla
+
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup(name, asdg.FP32_LOCAL, inverse=True)
+    x, st = pr.solve(rtol=1e-12, max_iter=5000)
+    xd = spla.spsolve(orc.A.tocsc(), orc.b)
+    xg = x.cpu().numpy()
+    e = xg - xd
+    erra = math.sqrt(e @ (orc.A @ e)) / math.sqrt(xd @ (orc.A @ xd))
+    print(f"{name}: fp32-local inverse iterations={st['iterations']} rel2={_rel(xg, xd):.2e} relA={erra:.2e}")
+    assert _rel(xg, xd) <= 1e-8 and erra <= 1e-8
