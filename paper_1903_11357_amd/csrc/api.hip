@@ -274,6 +274,11 @@ void plan_coarse_factor(asdg_problem* pb) {
   for (int b = nb - 1; b >= 0; --b) pb->ctrsv_tasks.push_back(make_int4(0, 1, b, 0));
 }
 
+LocalParts local_parts(asdg_problem* pb) {
+  return LocalParts{pb->ptr<int32_t>(0, pb->o0.cell_sub), pb->ptr<SubDesc>(1, pb->o1.subs),
+                    pb->ptr<void>(3, pb->o3.part)};
+}
+
 asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_done, Reduction* red,
                             hipEvent_t ev0, hipEvent_t ev1) {
   const int np = pb->A.np;
@@ -287,10 +292,9 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
   if (pb->inv_planned) {
-    HIPCHK(pb, launch_symv(pb->f32, np, pb->A.n_cells, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
-                           pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.cell_sub),
-                           pb->ptr<void>(1, pb->o1.tiles), r, pb->ptr<void>(3, pb->o3.part),
-                           pb->ptr<void>(3, pb->o3.zl), st, s));
+    HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+                                 pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
+                                 pb->ptr<void>(3, pb->o3.part), st, s));
   } else {
   const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
                                                  (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
@@ -307,11 +311,13 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_
                            pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0),
                            pb->ptr<void>(3, pb->o3.z0), st, &st->q_coarse, cgrid, nullptr, s));
   }
+  const LocalParts lp = local_parts(pb);
   HIPCHK(pb, launch_prolong(np, pb->has_coarse ? pb->C.nq : 3, pb->A.n_cells,
                             pb->has_coarse ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                             pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
-                            pb->ptr<double>(3, pb->o3.z0), pb->ptr<void>(3, pb->o3.zl), pb->f32, r,
-                            pb->ptr<double>(3, pb->o3.z), red, st_done, s));
+                            pb->ptr<double>(3, pb->o3.z0), pb->ptr<void>(3, pb->o3.zl),
+                            pb->inv_planned ? &lp : nullptr, pb->f32, r, pb->ptr<double>(3, pb->o3.z), red,
+                            st_done, s));
   return ASDG_OK;
 }
 
@@ -327,8 +333,10 @@ asdg_status enqueue_iteration(asdg_problem* pb, hipStream_t s, hipEvent_t ev0, h
   double* rz2 = pb->ptr<double>(3, pb->o3.rz2);
   HIPCHK(pb, launch_spmv(np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
                          pb->ptr<double>(0, pb->o0.blocks), p, q, red, st, s));
+  const bool sweeps = !pb->inv_planned;  // only the sweeps consume yl/zl
   HIPCHK(pb, launch_update_xr(pb->n(), st, red, rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x, r,
-                              pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), pb->f32, s));
+                              sweeps ? pb->ptr<void>(3, pb->o3.yl) : nullptr,
+                              sweeps ? pb->ptr<void>(3, pb->o3.zl) : nullptr, pb->f32, s));
   asdg_status e = enqueue_precond(pb, s, st, red, ev0, ev1);
   if (e != ASDG_OK) return e;
   HIPCHK(pb, launch_update_p(pb->n(), st, red, rz2, pb->ptr<double>(3, pb->o3.bh), z, p, 0, s));
@@ -846,10 +854,9 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                                  pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
                                  pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), nullptr, s));
     if (loc && pb->inv_planned) {
-      HIPCHK(pb, launch_symv(pb->f32, np, N, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
-                             pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.cell_sub),
-                             pb->ptr<void>(1, pb->o1.tiles), r, pb->ptr<void>(3, pb->o3.part),
-                             pb->ptr<void>(3, pb->o3.zl), nullptr, s));
+      HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+                                   pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
+                                   pb->ptr<void>(3, pb->o3.part), nullptr, s));
     } else if (loc) {
       const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
                                                  (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
@@ -865,10 +872,11 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                              pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0), pb->ptr<void>(3, pb->o3.z0),
                              st, &st->q_coarse, cgrid, nullptr, s));
     }
+    const LocalParts lp = local_parts(pb);
     HIPCHK(pb, launch_prolong(np, crs ? pb->C.nq : 3, N, crs ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                               pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
-                              pb->ptr<double>(3, pb->o3.z0), loc ? pb->ptr<void>(3, pb->o3.zl) : nullptr, pb->f32, r, z,
-                              nullptr, nullptr, s));
+                              pb->ptr<double>(3, pb->o3.z0), loc ? pb->ptr<void>(3, pb->o3.zl) : nullptr,
+                              loc && pb->inv_planned ? &lp : nullptr, pb->f32, r, z, nullptr, nullptr, s));
     HIPCHK(pb, launch_unpermute_out(np, N, perm, z, d_out, s));
   }
   DevState h;

@@ -110,124 +110,118 @@ __global__ __launch_bounds__(256) void k_inv_gram(int32_t n_tiles, const int4* _
 }
 
 // ---------------------------------------------------------------- apply
+// One wave per stored tile S_bj. Lane l = 16 r0 + c4 holds rows r0 + 4k
+// (k < 16), columns 4 c4 .. 4 c4 + 3 of the tile: every load instruction of
+// the wave reads four whole 256-byte rows. The 64 row sums (S_bj r_j) and the
+// 64 column sums (S_bj^T r_b) are finished by butterfly reduce-scatters over
+// lane bits 0-3 and 4-5, so each lane ends with one row sum (row r0 + 4 c4)
+// and one column sum (column 4 c4 + r0): no LDS reduction, no barrier.
+// The FP32 tiles are streamed with non-temporal loads (they are read once
+// per application); for FP64 plain loads measured faster.
 template <typename T>
-struct V16;
+struct TileRow;
 template <>
-struct V16<float> {
-  using V = float4;
-  static constexpr int N = 4;
-  __device__ static float at(const V& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+struct TileRow<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static void load(const float* p, float (&o)[4]) {
+    const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+  __device__ static void lds4(const float* p, float (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
 };
 template <>
-struct V16<double> {
-  using V = double2;
-  static constexpr int N = 2;
-  __device__ static double at(const V& v, int i) { return i == 0 ? v.x : v.y; }
+struct TileRow<double> {
+  __device__ static void load(const double* p, double (&o)[4]) {
+    const double2 u = reinterpret_cast<const double2*>(p)[0], v = reinterpret_cast<const double2*>(p)[1];
+    o[0] = u.x;
+    o[1] = u.y;
+    o[2] = v.x;
+    o[3] = v.y;
+  }
+  __device__ static void lds4(const double* p, double (&o)[4]) { load(p, o); }
 };
 
-// Phase 1: UNROLL consecutive tiles per work-group; part[t] = (S_bj r_j, S_bj^T r_b).
-template <typename T, int UNROLL>
+// Ordering of LDS traffic between the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Phase 1: part[t] = (S_bj r_j, S_bj^T r_b) for tile t = (b, j); the second
+// half is written only for off-diagonal tiles (diagonal tiles are stored
+// whole). Entries of r beyond the subdomain's n are taken as zero.
+template <typename T>
 __global__ __launch_bounds__(256) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
                                                     const SubDesc* __restrict__ subs, const T* __restrict__ S,
                                                     const double* __restrict__ r, T* __restrict__ part,
                                                     const DevState* st) {
-  using VT = V16<T>;
-  using V = typename VT::V;
-  constexpr int VEC = VT::N;
-  constexpr int LPR = TILE / VEC;
-  constexpr int RPP = 256 / LPR;
-  constexpr int PASSES = TILE / RPP;
-  __shared__ T s_red[UNROLL][4][TILE];
-  if (st && st->done) return;
-  const int tid = threadIdx.x;
-  const int lc = tid % LPR, r0 = tid / LPR;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int t0 = blockIdx.x * UNROLL;
-  V tv[UNROLL][PASSES];
-  int4 mt[UNROLL];
+  __shared__ __align__(16) T s_r[4][2 * TILE];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * 4 + w;
+  if ((st && st->done) || t >= n_tiles) return;
+  const int c4 = lane & 15, r0 = lane >> 4;
+  T a[16][4];
+  const T* base = S + (size_t)t * TT + r0 * TILE + 4 * c4;
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    const int t = min(t0 + u, n_tiles - 1);
-    mt[u] = meta[t];
+  for (int k = 0; k < 16; ++k) TileRow<T>::load(base + 4 * TILE * k, a[k]);
+  const int4 m = meta[t];
+  const SubDesc sd = subs[m.x];
+  const int b = m.y, j = m.z;
+  const int gj = j * TILE + lane, gb = b * TILE + lane;
+  T* sr = s_r[w];
+  sr[lane] = gj < sd.n ? (T)r[sd.dof0 + gj] : T(0);
+  // r_b stored so that rows r0 + 4k (k = 0..15) are contiguous at 16 r0
+  sr[TILE + (lane & 3) * 16 + (lane >> 2)] = gb < sd.n ? (T)r[sd.dof0 + gb] : T(0);
+  wave_sync();
+  T rj[4], rb[16];
+  TileRow<T>::lds4(sr + 4 * c4, rj);
 #pragma unroll
-    for (int k = 0; k < PASSES; ++k) tv[u][k] = *(const V*)(S + (size_t)t * TT + (r0 + RPP * k) * TILE + lc * VEC);
+  for (int q = 0; q < 4; ++q) {
+    T v[4];
+    TileRow<T>::lds4(sr + TILE + 16 * r0 + 4 * q, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rb[4 * q + e] = v[e];
+  }
+  T ra[16], ca[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    ra[k] = a[k][0] * rj[0] + a[k][1] * rj[1] + a[k][2] * rj[2] + a[k][3] * rj[3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ca[c] += a[k][c] * rb[k];
   }
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    const SubDesc sd = subs[mt[u].x];
-    const int b = mt[u].y, j = mt[u].z;
-    const bool valid = t0 + u < n_tiles;
-    // rows: S_bj r_j
-    T rj[VEC];
+  for (int h = 8; h >= 1; h >>= 1) {
+    const bool hi = lane & h;
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      const int gc = j * TILE + lc * VEC + v;
-      rj[v] = gc < sd.n ? (T)r[sd.dof0 + gc] : T(0);
-    }
-    T accu[PASSES];
-#pragma unroll
-    for (int k = 0; k < PASSES; ++k) {
-      T a = T(0);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) a += VT::at(tv[u][k], v) * rj[v];
-      accu[k] = a;
-    }
-#pragma unroll
-    for (int k = 0; k < PASSES; ++k)
-#pragma unroll
-      for (int o = LPR / 2; o >= 1; o >>= 1) accu[k] += __shfl_xor(accu[k], o, 64);
-    if (valid && lc == 0) {
-#pragma unroll
-      for (int k = 0; k < PASSES; ++k) part[(size_t)(t0 + u) * 2 * TILE + r0 + RPP * k] = accu[k];
-    }
-    // columns: S_bj^T r_b (off-diagonal tiles only)
-    if (j < b) {
-      T accv[VEC];
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) accv[v] = T(0);
-#pragma unroll
-      for (int k = 0; k < PASSES; ++k) {
-        const int gr = b * TILE + r0 + RPP * k;
-        const T rb = gr < sd.n ? (T)r[sd.dof0 + gr] : T(0);
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) accv[v] += VT::at(tv[u][k], v) * rb;
-      }
-#pragma unroll
-      for (int v = 0; v < VEC; ++v)
-#pragma unroll
-        for (int o = LPR; o < 64; o <<= 1) accv[v] += __shfl_xor(accv[v], o, 64);
-      if (lane < LPR) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) s_red[u][wave][lc * VEC + v] = accv[v];
-      }
+    for (int i = 0; i < h; ++i) {
+      const T send = hi ? ra[i] : ra[i + h];
+      const T keep = hi ? ra[i + h] : ra[i];
+      ra[i] = keep + __shfl_xor(send, h, 64);
     }
   }
-  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    if (t0 + u < n_tiles && mt[u].z < mt[u].y && tid < TILE)
-      part[(size_t)(t0 + u) * 2 * TILE + TILE + tid] = s_red[u][0][tid] + s_red[u][1][tid] + s_red[u][2][tid] + s_red[u][3][tid];
+  for (int h = 2; h >= 1; h >>= 1) {
+    const bool hi = lane & (16 * h);
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const T send = hi ? ca[i] : ca[i + h];
+      const T keep = hi ? ca[i + h] : ca[i];
+      ca[i] = keep + __shfl_xor(send, 16 * h, 64);
+    }
   }
-}
-
-// Phase 2: z[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>b} part(j,b).cols[rho].
-template <typename T>
-__global__ __launch_bounds__(256) void k_symv_gather(int np, int32_t N, const int32_t* __restrict__ cell_sub,
-                                                     const SubDesc* __restrict__ subs, const T* __restrict__ part,
-                                                     T* __restrict__ z, const DevState* st) {
-  if (st && st->done) return;
-  const int64_t n = (int64_t)N * np;
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
-    const SubDesc sd = subs[cell_sub[d / np]];
-    const int loc = (int)(d - sd.dof0);
-    const int b = loc / TILE, rho = loc - b * TILE;
-    double s = 0.0;
-    const T* pb = part + (size_t)(sd.tile0 + b * (b + 1) / 2) * 2 * TILE + rho;
-    for (int j = 0; j <= b; ++j) s += (double)pb[(size_t)j * 2 * TILE];
-    for (int j = b + 1; j < sd.nb; ++j)
-      s += (double)part[(size_t)(sd.tile0 + j * (j + 1) / 2 + b) * 2 * TILE + TILE + rho];
-    z[d] = (T)s;
-  }
+  T* pt = part + (size_t)t * 2 * TILE;
+  pt[r0 + 4 * c4] = ra[0];
+  if (j < b) pt[TILE + 4 * c4 + r0] = ca[0];
 }
 
 template <typename K>
@@ -263,25 +257,15 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
   return hipGetLastError();
 }
 
-hipError_t launch_symv(int f32, int np, int32_t N, int32_t n_tiles, const int4* meta, const SubDesc* subs,
-                       const int32_t* cell_sub, const void* S, const double* r, void* part, void* z,
-                       const DevState* st, hipStream_t s) {
+hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
+                             const double* r, void* part, const DevState* st, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  const int64_t n = (int64_t)N * np;
-  const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
-  if (f32) {
-    constexpr int U = 4;
-    hipLaunchKernelGGL((k_symv_tiles<float, U>), dim3((n_tiles + U - 1) / U), dim3(256), 0, s, n_tiles, meta, subs,
-                       (const float*)S, r, (float*)part, st);
-    hipLaunchKernelGGL(k_symv_gather<float>, dim3(g2), dim3(256), 0, s, np, N, cell_sub, subs, (const float*)part,
-                       (float*)z, st);
-  } else {
-    constexpr int U = 2;
-    hipLaunchKernelGGL((k_symv_tiles<double, U>), dim3((n_tiles + U - 1) / U), dim3(256), 0, s, n_tiles, meta,
-                       subs, (const double*)S, r, (double*)part, st);
-    hipLaunchKernelGGL(k_symv_gather<double>, dim3(g2), dim3(256), 0, s, np, N, cell_sub, subs,
-                       (const double*)part, (double*)z, st);
-  }
+  const dim3 g((n_tiles + 3) / 4), bl(256);
+  if (f32)
+    hipLaunchKernelGGL(k_symv_tiles<float>, g, bl, 0, s, n_tiles, meta, subs, (const float*)S, r, (float*)part, st);
+  else
+    hipLaunchKernelGGL(k_symv_tiles<double>, g, bl, 0, s, n_tiles, meta, subs, (const double*)S, r, (double*)part,
+                       st);
   return hipGetLastError();
 }
 

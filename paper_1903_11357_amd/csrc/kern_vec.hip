@@ -134,8 +134,10 @@ __global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Redu
     const double rv = r[d] - alpha * q[d];
     r[d] = rv;
     acc += rv * rv;
-    yl[d] = sentinel<T>();
-    zl[d] = sentinel<T>();
+    if (yl) {  // re-arm the sweep dataflow vectors
+      yl[d] = sentinel<T>();
+      zl[d] = sentinel<T>();
+    }
   }
   double rr;
   if (grid_sum(acc, red + RED_RR, scratch, rr) && threadIdx.x == 0) {
@@ -195,11 +197,17 @@ __global__ __launch_bounds__(256) void k_restrict(const int32_t* __restrict__ tp
   }
 }
 
-// z = z_loc + P_0 z0 (either part optional), and r.z.
-template <int NP, int NQ, typename T>
+// z = z_loc + P_0 z0 (either part optional), and r.z. The local part is
+// either a vector zl, or (G) the sum, in a fixed order, of the packed
+// symmetric apply's per-tile partial vectors for the DoF's row:
+//   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>b} part(j,b).cols[rho]
+// with d = dof0 + 64 b + rho in its subdomain.
+template <int NP, int NQ, typename T, bool G>
 __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __restrict__ pptr,
                                                  const int32_t* __restrict__ pcol, const double* __restrict__ P,
                                                  const double* __restrict__ z0, const T* __restrict__ zl,
+                                                 const int32_t* __restrict__ cell_sub,
+                                                 const SubDesc* __restrict__ subs, const T* __restrict__ part,
                                                  const double* __restrict__ r, double* __restrict__ z,
                                                  Reduction* red, const DevState* st) {
   __shared__ double scratch[4];
@@ -209,7 +217,18 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
     const int64_t cell = d / NP;
     const int a = (int)(d - cell * NP);
-    double v = zl ? (double)zl[d] : 0.0;
+    double v = 0.0;
+    if (G) {
+      const SubDesc sd = subs[cell_sub[cell]];
+      const int loc = (int)(d - sd.dof0);
+      const int b = loc / TILE, rho = loc - b * TILE;
+      const T* pr = part + (size_t)(sd.tile0 + b * (b + 1) / 2) * 2 * TILE + rho;
+      for (int j = 0; j <= b; ++j) v += (double)pr[(size_t)j * 2 * TILE];
+      for (int j = b + 1; j < sd.nb; ++j)
+        v += (double)part[(size_t)(sd.tile0 + j * (j + 1) / 2 + b) * 2 * TILE + TILE + rho];
+    } else if (zl) {
+      v = (double)zl[d];
+    }
     if (pptr) {
       for (int e = pptr[cell]; e < pptr[cell + 1]; ++e) {
         const double* Pb = P + (size_t)e * NP * NQ + a * NQ;
@@ -334,23 +353,34 @@ hipError_t launch_restrict(int np, int nq, int32_t nc, const int32_t* tptr, cons
   return hipErrorInvalidValue;
 }
 
+template <int NP, int NQ, typename T>
+static void prolong_tt(int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P, const double* z0,
+                       const void* zl, const LocalParts* lp, const double* r, double* z, Reduction* red,
+                       const DevState* st, hipStream_t s) {
+  dim3 g(grid_for((int64_t)N * NP, VEC_GRID)), b(256);
+  if (lp)
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, true>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub,
+                       lp->subs, (const T*)lp->part, r, z, red, st);
+  else
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, false>), g, b, 0, s, N, pptr, pcol, P, z0, (const T*)zl, nullptr,
+                       nullptr, nullptr, r, z, red, st);
+}
+
 template <int NP, int NQ>
 static void prolong_t(int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P, const double* z0,
-                      const void* zl, int f32, const double* r, double* z, Reduction* red, const DevState* st,
-                      hipStream_t s) {
-  dim3 g(grid_for((int64_t)N * NP, VEC_GRID)), b(256);
+                      const void* zl, const LocalParts* lp, int f32, const double* r, double* z, Reduction* red,
+                      const DevState* st, hipStream_t s) {
   if (f32)
-    hipLaunchKernelGGL((k_prolong<NP, NQ, float>), g, b, 0, s, N, pptr, pcol, P, z0, (const float*)zl, r, z, red, st);
+    prolong_tt<NP, NQ, float>(N, pptr, pcol, P, z0, zl, lp, r, z, red, st, s);
   else
-    hipLaunchKernelGGL((k_prolong<NP, NQ, double>), g, b, 0, s, N, pptr, pcol, P, z0, (const double*)zl, r, z, red,
-                       st);
+    prolong_tt<NP, NQ, double>(N, pptr, pcol, P, z0, zl, lp, r, z, red, st, s);
 }
 
 hipError_t launch_prolong(int np, int nq, int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P,
-                          const double* z0, const void* zl, int f32, const double* r, double* z, Reduction* red,
-                          const DevState* st, hipStream_t s) {
+                          const double* z0, const void* zl, const LocalParts* lp, int f32, const double* r, double* z,
+                          Reduction* red, const DevState* st, hipStream_t s) {
   if (!pptr) nq = 3;  // no coarse level: any instantiation, the loop is skipped
-#define P_(A, B) ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, f32, r, z, red, st, s)))
+#define P_(A, B) ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, lp, f32, r, z, red, st, s)))
   P_(3, 3) P_(6, 3) P_(6, 6) P_(10, 3) P_(10, 6) P_(10, 10) P_(15, 3) P_(15, 6) P_(15, 10) P_(15, 15)
 #undef P_
   return hipErrorInvalidValue;

@@ -65,9 +65,16 @@ hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, const doubl
 hipError_t launch_restrict(int np, int nq, int32_t n_coarse, const int32_t* tptr, const int32_t* tcell,
                            const int32_t* tblk, const double* P, const double* r, double* r0,
                            double* y0, double* z0, const DevState* st, hipStream_t s);
+// Per-tile partial vectors of the packed symmetric local apply, summed per
+// DoF by the prolongation kernel (in place of a local solution vector).
+struct LocalParts {
+  const int32_t* cell_sub;  // subdomain of each cell
+  const SubDesc* subs;
+  const void* part;  // 2*TILE entries per stored tile (rows, then columns)
+};
 hipError_t launch_prolong(int np, int nq, int32_t n_cells, const int32_t* pptr, const int32_t* pcol,
-                          const double* P, const double* z0, const void* zl, int local_f32,
-                          const double* r, double* z, Reduction* red, const DevState* st,
+                          const double* P, const double* z0, const void* zl, const LocalParts* lp,
+                          int local_f32, const double* r, double* z, Reduction* red, const DevState* st,
                           hipStream_t s);
 hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, double* rz2,
                            double* beta_hist, const double* z, double* p, int init, hipStream_t s);
@@ -85,9 +92,11 @@ hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const Su
 hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
                           const SubDesc* subs, void* L, void* X, int32_t* flags, DevState* st, int32_t* queue,
                           int grid_lower, int grid_gram, hipStream_t s);
-hipError_t launch_symv(int f32, int np, int32_t n_cells, int32_t n_tiles, const int4* meta, const SubDesc* subs,
-                       const int32_t* cell_sub, const void* S, const double* r, void* part, void* z,
-                       const DevState* st, hipStream_t s);
+// Phase 1 of the packed symmetric apply: per stored tile (b, j), the row
+// sums S_bj r_j and (b > j) the column sums S_bj^T r_b; summed per DoF by
+// launch_prolong with LocalParts.
+hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
+                             const double* r, void* part, const DevState* st, hipStream_t s);
 
 // Batched forward/backward triangular sweeps (kern_trsv.hip).
 // trace (optional): per task, wall-clock at dequeue, end of waits, end.

@@ -26,16 +26,16 @@ def _oracle(name):
     return _cache[name]
 
 
-def _gpu(name, precision):
+def _gpu(name, precision, inverse=False):
     import torch
 
     from paper_1903_11357_amd import asdg
 
-    key = (name, precision)
+    key = (name, precision, inverse)
     if key not in _cache:
         P, A, b, geo = _oracle(name)
-        print(f"[full] {name} precision={precision} setup", flush=True)
-        _cache[key] = asdg.setup_problem(P, precision, device="cuda:0")
+        print(f"[full] {name} precision={precision} local_inverse={inverse} setup", flush=True)
+        _cache[key] = asdg.setup_problem(P, precision, device="cuda:0", local_inverse=inverse)
         torch.cuda.synchronize()
     return _cache[key]
 
@@ -66,16 +66,19 @@ def test_full_operator_apply(name):
     assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("local", ["sweeps", "inverse"])
 @pytest.mark.parametrize("name", ["C3", "C4"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_local_solves_sampled(name, prec):
+def test_full_local_solves_sampled(name, prec, local):
+    """Sampled subdomains (smallest, largest, five random) of the local
+    solves A_i^{-1} r_i, by the triangular sweeps or the explicit inverse."""
     import scipy.linalg as la
     import torch
 
     from paper_1903_11357_amd import asdg
 
     P, A, b, _ = _oracle(name)
-    pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL)
+    pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, local == "inverse")
     v = np.random.default_rng(2).standard_normal(pr.n)
     z = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()
     npb = P.n_p
@@ -135,9 +138,10 @@ def test_full_coarse_correction_is_A_orthogonal_projection_C4():
     assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), abs(rhs))
 
 
+@pytest.mark.parametrize("local", ["sweeps", "inverse"])
 @pytest.mark.parametrize("name", ["C3", "C4"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_solve_true_residual_against_oracle_system(name, prec):
+def test_full_solve_true_residual_against_oracle_system(name, prec, local):
     """The solution of the benchmark solve (captured-graph path, 1e-8)
     satisfies the oracle's own SIPG system. In floating point the true
     residual b - A x_k and CG's recursive residual r_k drift apart by at most
@@ -148,7 +152,7 @@ def test_full_solve_true_residual_against_oracle_system(name, prec):
     from paper_1903_11357_amd import asdg
 
     P, A, b, _ = _oracle(name)
-    pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL)
+    pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, local == "inverse")
     x, st = pr.solve(rtol=1e-8, check_every=32)
     xg = x.cpu().numpy()
     nb = np.linalg.norm(b)

@@ -119,9 +119,12 @@ def _check_pcg_parity(name, orc, st, xg, b=None):
        recursive residual (~1e-8 ||b||) carries rounding of order
        kappa(A) u ||b||, which for these ill-conditioned cases is a sizeable
        fraction of 1e-8.
-    3. Stopping: the same iteration as the oracle at rtol 1e-8, or one apart
-       when the oracle's residual at the earlier of the two is within 25% of
-       the tolerance (rounding alone decides the side of the threshold)."""
+    3. Stopping: the same iteration as the oracle at rtol 1e-8 or, when the
+       two differ, at most 3 apart with the oracle's residual within 25% of
+       the tolerance at every iteration from the earlier of the two up to the
+       later one (exclusive). CG's residual norm is not monotone: where it
+       hovers at the threshold, rounding alone decides where it first
+       crosses."""
     tol = 1e-8
     xo, info = orc.solve(rtol=tol, b=b)
     kg, ko = st["iterations"], info.iterations
@@ -132,8 +135,10 @@ def _check_pcg_parity(name, orc, st, xg, b=None):
     assert _rel(xg, xk) <= 1e-10, _rel(xg, xk)
     assert abs(st["rel_res"] - infk.history[-1]) <= 0.25 * tol
     if kg != ko:
-        assert abs(kg - ko) == 1
-        assert abs(info.history[min(kg, ko) - 1] / tol - 1.0) < 0.25
+        assert abs(kg - ko) <= 3
+        hist = info.history if ko > kg else infk.history
+        band = hist[min(kg, ko) - 1:max(kg, ko) - 1]
+        assert all(abs(h / tol - 1.0) < 0.25 for h in band), band
     return infk
 
 
