@@ -108,7 +108,10 @@ struct asdg_problem {
   // buffer layout
   struct { size_t row_ptr, col, blocks, rhs, perm, cell_sub; } o0{};
   struct { size_t tiles, subs, chol, trsv, meta, xtiles, inv; } o1{};
-  struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv; } o2{};
+  struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv, cS, cX, cinv, cmeta, cinvt; } o2{};
+  // coarse solve by a dense explicit A_0^{-1} (n0 <= kCoarseDenseMax) instead of the triangular sweeps
+  bool coarse_dense = false;
+  std::vector<int4> cmeta, cinv_tasks;
   struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace, part; } o3{};
   size_t bytes[4] = {0, 0, 0, 0};
   char* buf[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -251,6 +254,12 @@ void plan_local(asdg_problem* pb) {
   for (size_t k = 0; k < ks.size(); ++k) pb->trsv_tasks[k] = ks[k].t;
 }
 
+// Largest coarse dimension solved with a dense explicit inverse (8 n0^2
+// bytes: 512 MiB at the limit). One dense product reads the same bytes as
+// the two triangular sweeps over the packed factor, without their chain of
+// dependent tile rows.
+constexpr int32_t kCoarseDenseMax = 8192;
+
 void plan_coarse_factor(asdg_problem* pb) {
   const int32_t n0 = pb->n0;
   const int nb = (n0 + TILE - 1) / TILE;
@@ -272,6 +281,32 @@ void plan_coarse_factor(asdg_problem* pb) {
   pb->ctrsv_tasks.clear();
   for (int b = 0; b < nb; ++b) pb->ctrsv_tasks.push_back(make_int4(0, 0, b, 0));
   for (int b = nb - 1; b >= 0; --b) pb->ctrsv_tasks.push_back(make_int4(0, 1, b, 0));
+  pb->coarse_dense = n0 <= kCoarseDenseMax;
+  pb->cmeta.clear();
+  pb->cinv_tasks.clear();
+  if (pb->coarse_dense) {
+    for (int b = 0; b < nb; ++b)
+      for (int j = 0; j <= b; ++j) {
+        pb->cmeta.push_back(make_int4(0, b, j, 0));
+        pb->cinv_tasks.push_back(make_int4(0, j, b, 0));  // row order: X_kj (k < b) precede X_bj
+      }
+  }
+}
+
+// z0 = A_0^{-1} r0: dense explicit inverse, or the two triangular sweeps.
+asdg_status enqueue_coarse_solve(asdg_problem* pb, const DevState* st_done, hipStream_t s) {
+  if (pb->coarse_dense) {
+    HIPCHK(pb, launch_dense_mv(pb->n0, pb->ptr<double>(2, pb->o2.cinv), pb->ptr<double>(3, pb->o3.r0),
+                               pb->ptr<double>(3, pb->o3.z0), st_done, s));
+    return ASDG_OK;
+  }
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
+  HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
+                         pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
+                         pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0), pb->ptr<void>(3, pb->o3.z0), st,
+                         &st->q_coarse, cgrid, nullptr, s));
+  return ASDG_OK;
 }
 
 LocalParts local_parts(asdg_problem* pb) {
@@ -279,7 +314,9 @@ LocalParts local_parts(asdg_problem* pb) {
                     pb->ptr<void>(3, pb->o3.part)};
 }
 
-asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_done, Reduction* red,
+// z = P^{-1} r and partials of r.z. iteration: the prolongation also takes
+// the PCG stopping decision (see launch_prolong).
+asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, Reduction* red, bool iteration,
                             hipEvent_t ev0, hipEvent_t ev1) {
   const int np = pb->A.np;
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
@@ -305,11 +342,8 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_
   }
   if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
   if (pb->has_coarse) {
-    const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
-    HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
-                           pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
-                           pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0),
-                           pb->ptr<void>(3, pb->o3.z0), st, &st->q_coarse, cgrid, nullptr, s));
+    asdg_status ce = enqueue_coarse_solve(pb, st_done, s);
+    if (ce != ASDG_OK) return ce;
   }
   const LocalParts lp = local_parts(pb);
   HIPCHK(pb, launch_prolong(np, pb->has_coarse ? pb->C.nq : 3, pb->A.n_cells,
@@ -317,7 +351,7 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, const DevState* st_
                             pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
                             pb->ptr<double>(3, pb->o3.z0), pb->ptr<void>(3, pb->o3.zl),
                             pb->inv_planned ? &lp : nullptr, pb->f32, r, pb->ptr<double>(3, pb->o3.z), red,
-                            st_done, s));
+                            st_done, iteration ? spmv_parts(pb->n()) : 0, iteration ? vec_parts(pb->n()) : 0, s));
   return ASDG_OK;
 }
 
@@ -334,12 +368,13 @@ asdg_status enqueue_iteration(asdg_problem* pb, hipStream_t s, hipEvent_t ev0, h
   HIPCHK(pb, launch_spmv(np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
                          pb->ptr<double>(0, pb->o0.blocks), p, q, red, st, s));
   const bool sweeps = !pb->inv_planned;  // only the sweeps consume yl/zl
-  HIPCHK(pb, launch_update_xr(pb->n(), st, red, rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x, r,
-                              sweeps ? pb->ptr<void>(3, pb->o3.yl) : nullptr,
+  HIPCHK(pb, launch_update_xr(pb->n(), st, red, spmv_parts(pb->n()), rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x,
+                              r, sweeps ? pb->ptr<void>(3, pb->o3.yl) : nullptr,
                               sweeps ? pb->ptr<void>(3, pb->o3.zl) : nullptr, pb->f32, s));
-  asdg_status e = enqueue_precond(pb, s, st, red, ev0, ev1);
+  asdg_status e = enqueue_precond(pb, s, st, red, true, ev0, ev1);
   if (e != ASDG_OK) return e;
-  HIPCHK(pb, launch_update_p(pb->n(), st, red, rz2, pb->ptr<double>(3, pb->o3.bh), z, p, 0, s));
+  HIPCHK(pb, launch_update_p(pb->n(), st, red, prolong_parts(pb->n()), rz2, pb->ptr<double>(3, pb->o3.bh), z, p, 0,
+                             s));
   return ASDG_OK;
 }
 
@@ -383,10 +418,11 @@ asdg_status enqueue_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_op
   HIPCHK(pb, launch_permute_in(np, N, pb->ptr<int32_t>(0, pb->o0.perm), src, pb->ptr<double>(3, pb->o3.r),
                                pb->ptr<double>(3, pb->o3.x), pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl),
                                pb->f32, red, st, o.rtol, o.max_iter, s));
-  asdg_status e = enqueue_precond(pb, s, st, red, nullptr, nullptr);
+  asdg_status e = enqueue_precond(pb, s, st, red, false, nullptr, nullptr);
   if (e != ASDG_OK) return e;
-  HIPCHK(pb, launch_update_p(pb->n(), st, red, pb->ptr<double>(3, pb->o3.rz2), pb->ptr<double>(3, pb->o3.bh),
-                             pb->ptr<double>(3, pb->o3.z), pb->ptr<double>(3, pb->o3.p), 1, s));
+  HIPCHK(pb, launch_update_p(pb->n(), st, red, prolong_parts(pb->n()), pb->ptr<double>(3, pb->o3.rz2),
+                             pb->ptr<double>(3, pb->o3.bh), pb->ptr<double>(3, pb->o3.z), pb->ptr<double>(3, pb->o3.p),
+                             1, s));
   return ASDG_OK;
 }
 
@@ -587,6 +623,13 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
     pb->o2.csub = L2.add(sizeof(SubDesc));
     pb->o2.cchol = L2.add(sizeof(int4) * pb->cchol_tasks.size());
     pb->o2.ctrsv = L2.add(sizeof(int4) * pb->ctrsv_tasks.size());
+    if (pb->coarse_dense) {
+      pb->o2.cS = L2.add(8 * pb->ctiles_host.size());
+      pb->o2.cX = L2.add(8 * pb->ctiles_host.size());
+      pb->o2.cinv = L2.add(8 * (size_t)pb->n0 * pb->n0);
+      pb->o2.cmeta = L2.add(sizeof(int4) * pb->cmeta.size());
+      pb->o2.cinvt = L2.add(sizeof(int4) * pb->cinv_tasks.size());
+    }
   } else {
     L2.add(256);
   }
@@ -670,6 +713,10 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
     HIPCHK(pb, up(2, pb->o2.csub, &pb->csub, sizeof(SubDesc)));
     HIPCHK(pb, up(2, pb->o2.cchol, pb->cchol_tasks.data(), sizeof(int4) * pb->cchol_tasks.size()));
     HIPCHK(pb, up(2, pb->o2.ctrsv, pb->ctrsv_tasks.data(), sizeof(int4) * pb->ctrsv_tasks.size()));
+    if (pb->coarse_dense) {
+      HIPCHK(pb, up(2, pb->o2.cmeta, pb->cmeta.data(), sizeof(int4) * pb->cmeta.size()));
+      HIPCHK(pb, up(2, pb->o2.cinvt, pb->cinv_tasks.data(), sizeof(int4) * pb->cinv_tasks.size()));
+    }
   }
   HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.red), (int64_t)(sizeof(Reduction) * N_RED / 4), 0, s));
   HIPCHK(pb, hipStreamSynchronize(s));
@@ -748,6 +795,24 @@ asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
   asdg_status e = run_cholesky(pb, s, 0, (int32_t)pb->cchol_tasks.size(), pb->ptr<int4>(2, pb->o2.cchol),
                                pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles), pb->n_ctiles, 1);
   if (e != ASDG_OK) return e;
+  if (pb->coarse_dense) {
+    // A_0^{-1} = L^{-T} L^{-1} from a copy of the factor (the factor tiles stay exportable), then dense
+    DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+    HIPCHK(pb, hipMemcpyAsync(pb->buf[2] + pb->o2.cS, pb->buf[2] + pb->o2.ctiles, 8 * pb->ctiles_host.size(),
+                              hipMemcpyDeviceToDevice, s));
+    HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_ctiles, 0, s));
+    HIPCHK(pb, launch_reset_queues(st, s));
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>(pb->n_ctiles, (int64_t)pb->n_cu * 2));
+    HIPCHK(pb, launch_inverse(0, (int32_t)pb->cinv_tasks.size(), pb->ptr<int4>(2, pb->o2.cinvt),
+                              (int32_t)pb->n_ctiles, pb->ptr<int4>(2, pb->o2.cmeta), pb->ptr<SubDesc>(2, pb->o2.csub),
+                              pb->ptr<void>(2, pb->o2.cS), pb->ptr<void>(2, pb->o2.cX),
+                              pb->ptr<int32_t>(3, pb->o3.flags), st, &st->q_chol, g, g, s));
+    HIPCHK(pb, launch_expand_sym(pb->n0, pb->ptr<double>(2, pb->o2.cS), pb->ptr<double>(2, pb->o2.cinv), s));
+    DevState h;
+    e = read_state(pb, s, h);
+    if (e != ASDG_OK) return e;
+    if (h.abort) FAIL(pb, ASDG_EHIP, "coarse inverse wait budget exhausted");
+  }
   pb->coarse_ready = true;
   return ASDG_OK;
 }
@@ -866,17 +931,14 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                          pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
     }
     if (crs) {
-      const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
-      HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
-                             pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
-                             pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0), pb->ptr<void>(3, pb->o3.z0),
-                             st, &st->q_coarse, cgrid, nullptr, s));
+      asdg_status ce = enqueue_coarse_solve(pb, nullptr, s);
+      if (ce != ASDG_OK) return ce;
     }
     const LocalParts lp = local_parts(pb);
     HIPCHK(pb, launch_prolong(np, crs ? pb->C.nq : 3, N, crs ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                               pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
                               pb->ptr<double>(3, pb->o3.z0), loc ? pb->ptr<void>(3, pb->o3.zl) : nullptr,
-                              loc && pb->inv_planned ? &lp : nullptr, pb->f32, r, z, nullptr, nullptr, s));
+                              loc && pb->inv_planned ? &lp : nullptr, pb->f32, r, z, nullptr, nullptr, 0, 0, s));
     HIPCHK(pb, launch_unpermute_out(np, N, perm, z, d_out, s));
   }
   DevState h;

@@ -107,4 +107,20 @@ __device__ __forceinline__ bool grid_sum(double v, Reduction* R, double* scratch
   return true;
 }
 
+// Reductions across launches: the producer stores one partial per
+// work-group (partial_store); a kernel launched after it on the same stream
+// sums them (partials_sum). Every work-group of the consumer adds the same
+// partials in the same order, so all get the identical value with no atomics
+// and no arrival counting.
+__device__ __forceinline__ void partial_store(double v, Reduction* R, double* scratch) {
+  v = block_sum(v, scratch);
+  if (threadIdx.x == 0) R->partial[blockIdx.x] = v;
+}
+
+__device__ __forceinline__ double partials_sum(const Reduction* R, int count, double* scratch) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) s += R->partial[i];
+  return block_sum(s, scratch);
+}
+
 }  // namespace asdg

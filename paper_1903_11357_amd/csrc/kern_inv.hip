@@ -224,6 +224,37 @@ __global__ __launch_bounds__(256) void k_symv_tiles(int32_t n_tiles, const int4*
   if (j < b) pt[TILE + 4 * c4 + r0] = ca[0];
 }
 
+// ---------------------------------------------------------------- coarse
+// Dense symmetric A_0^{-1} (row-major n0 x n0) from its packed lower tiles
+// (single "subdomain" at tile 0; diagonal tiles stored whole).
+__global__ __launch_bounds__(256) void k_expand_sym(int32_t n0, const double* __restrict__ S,
+                                                    double* __restrict__ D) {
+  const int64_t nn = (int64_t)n0 * n0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n0), j = (int)(e - (int64_t)i * n0);
+    const int bi = i / TILE, bj = j / TILE, ri = i - bi * TILE, rj = j - bj * TILE;
+    D[e] = bi >= bj ? S[(size_t)(bi * (bi + 1) / 2 + bj) * TT + ri * TILE + rj]
+                    : S[(size_t)(bj * (bj + 1) / 2 + bi) * TT + rj * TILE + ri];
+  }
+}
+
+// y = D x for a dense row-major n x n matrix: one wave per row, each lane
+// strides the row by 64 (coalesced 512-byte loads), fixed-order wave sum.
+__global__ __launch_bounds__(256) void k_dense_mv(int32_t n, const double* __restrict__ D,
+                                                  const double* __restrict__ x, double* __restrict__ y,
+                                                  const DevState* st) {
+  if (st && st->done) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* Dr = D + (size_t)row * n;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int j = lane; j < n; j += 64) acc += Dr[j] * x[j];
+  acc = warp_sum(acc);
+  if (lane == 0) y[row] = acc;
+}
+
 template <typename K>
 hipError_t big_lds(K kernel, size_t sh) {
   if (sh <= 65536) return hipSuccess;
@@ -266,6 +297,21 @@ hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const S
   else
     hipLaunchKernelGGL(k_symv_tiles<double>, g, bl, 0, s, n_tiles, meta, subs, (const double*)S, r, (double*)part,
                        st);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_sym(int32_t n0, const double* S, double* D, hipStream_t s) {
+  if (n0 <= 0) return hipSuccess;
+  const int64_t nn = (int64_t)n0 * n0;
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>((nn + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_expand_sym, dim3(g), dim3(256), 0, s, n0, S, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_mv(int32_t n, const double* D, const double* x, double* y, const DevState* st,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, n, D, x, y, st);
   return hipGetLastError();
 }
 

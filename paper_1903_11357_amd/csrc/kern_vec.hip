@@ -8,19 +8,22 @@
 // n threads of memory-level parallelism instead of one dependent chain per
 // block row.
 //
-// PCG (Sec. 7): every reduction is two-stage and deterministic (fixed
-// per-work-group order, then the last work-group to finish adds the
-// partials in index order), so no floating-point atomics are used and
-// repeated solves are bitwise identical. The last work-group of the
-// residual update also takes the stopping decision, so an iteration needs
-// no separate control kernel.
+// PCG (Sec. 7): every dot product is deterministic. The producing kernel
+// stores one partial per work-group; the kernel that needs the value sums
+// the partials itself, every work-group in the same fixed order (no
+// floating-point atomics, no arrival counters, bitwise-repeatable solves).
+// Work-group 0 of the prolongation, the last kernel of the preconditioner,
+// takes the stopping decision and counts the iteration, so an iteration
+// needs no separate control kernel.
 #include "kern_common.h"
 
 namespace asdg {
 
 namespace {
 
-constexpr int VEC_GRID = 2048;  // work-groups of the grid-stride vector kernels
+constexpr int VEC_GRID = 1024;      // work-groups of the grid-stride vector kernels
+constexpr int SPMV_GRID = 2048;     // work-groups of the operator apply
+constexpr int PROLONG_GRID = 4096;  // prolongation (+ local partial sums): one DoF per thread up to 1M DoFs
 
 int grid_for(int64_t n, int cap) {
   int64_t g = (n + 255) / 256;
@@ -52,10 +55,7 @@ __global__ __launch_bounds__(256) void k_spmv(int32_t N, const int32_t* __restri
     q[d] = acc;
     dot += p[d] * acc;
   }
-  if (red) {
-    double total;
-    grid_sum(dot, red + RED_PQ, scratch, total);
-  }
+  if (red) partial_store(dot, red + RED_PQ, scratch);
 }
 
 // r = permuted b, x = 0, triangular-sweep outputs = sentinel; with `st`,
@@ -113,21 +113,27 @@ __global__ __launch_bounds__(256) void k_unpermute(int np, int32_t N, const int3
   }
 }
 
-// alpha = (r.z)/(p.Ap); x += alpha p; r -= alpha Ap; ||r||^2; the last
-// work-group decides convergence / breakdown / max_iter and counts the
-// iteration.
+// alpha = (r.z)/(p.Ap) with p.Ap summed from the operator apply's partials;
+// x += alpha p; r -= alpha Ap; partials of ||r||^2. On breakdown (p.Ap not
+// positive) x and r are left unchanged; the stopping decision after the
+// preconditioner reports it. Work-group 0 records alpha and re-arms the
+// work queues of the triangular sweeps.
 template <typename T>
-__global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Reduction* red,
+__global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Reduction* red, int n_pq,
                                                    const double* __restrict__ rz2, double* __restrict__ alpha_hist,
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    double* __restrict__ x, double* __restrict__ r,
                                                    T* __restrict__ yl, T* __restrict__ zl) {
   __shared__ double scratch[4];
   if (st->done) return;
-  const double pq = red[RED_PQ].result;
+  const double pq = partials_sum(red + RED_PQ, n_pq, scratch);
   const int it = st->it;
-  const double alpha = rz2[it & 1] / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && it < HIST) alpha_hist[it] = alpha;
+  const double alpha = pq > 0.0 ? rz2[it & 1] / pq : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (it < HIST) alpha_hist[it] = alpha;
+    st->q_local = 0;
+    st->q_coarse = 0;
+  }
   double acc = 0.0;
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
     x[d] += alpha * p[d];
@@ -139,27 +145,7 @@ __global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Redu
       zl[d] = sentinel<T>();
     }
   }
-  double rr;
-  if (grid_sum(acc, red + RED_RR, scratch, rr) && threadIdx.x == 0) {
-    const int it1 = it + 1;
-    st->it = it1;
-    st->rr = rr;
-    st->q_local = 0;
-    st->q_coarse = 0;
-    if (st->abort) {
-      st->status = 4;
-      st->done = 1;
-    } else if (!(pq > 0.0) || !(rr == rr)) {
-      st->status = 3;
-      st->done = 1;
-    } else if (rr <= st->tol2) {
-      st->status = 1;
-      st->done = 1;
-    } else if (it1 >= st->max_iter) {
-      st->status = 2;
-      st->done = 1;
-    }
-  }
+  partial_store(acc, red + RED_RR, scratch);
 }
 
 // r0 = P_0^T r: one work-group per coarse cell, entries in fixed order.
@@ -202,6 +188,12 @@ __global__ __launch_bounds__(256) void k_restrict(const int32_t* __restrict__ tp
 // symmetric apply's per-tile partial vectors for the DoF's row:
 //   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>b} part(j,b).cols[rho]
 // with d = dof0 + 64 b + rho in its subdomain.
+//
+// With `red`, partials of r.z. With n_pq > 0 (a PCG iteration), work-group 0
+// also sums the partials of p.Ap and ||r||^2 left by the operator apply and
+// the residual update, counts the iteration and takes the stopping decision
+// (abort > breakdown > converged > iteration limit). No other work-group of
+// this launch reads the fields it writes.
 template <int NP, int NQ, typename T, bool G>
 __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __restrict__ pptr,
                                                  const int32_t* __restrict__ pcol, const double* __restrict__ P,
@@ -209,9 +201,31 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
                                                  const int32_t* __restrict__ cell_sub,
                                                  const SubDesc* __restrict__ subs, const T* __restrict__ part,
                                                  const double* __restrict__ r, double* __restrict__ z,
-                                                 Reduction* red, const DevState* st) {
+                                                 Reduction* red, DevState* st, int n_pq, int n_rr) {
   __shared__ double scratch[4];
   if (st && st->done) return;
+  if (n_pq > 0 && blockIdx.x == 0) {
+    const double pq = partials_sum(red + RED_PQ, n_pq, scratch);
+    const double rr = partials_sum(red + RED_RR, n_rr, scratch);
+    if (threadIdx.x == 0) {
+      const int it1 = st->it + 1;
+      st->it = it1;
+      st->rr = rr;
+      if (st->abort) {
+        st->status = 4;
+        st->done = 1;
+      } else if (!(pq > 0.0) || !(rr == rr)) {
+        st->status = 3;
+        st->done = 1;
+      } else if (rr <= st->tol2) {
+        st->status = 1;
+        st->done = 1;
+      } else if (it1 >= st->max_iter) {
+        st->status = 2;
+        st->done = 1;
+      }
+    }
+  }
   const int64_t n = (int64_t)N * NP;
   double acc = 0.0;
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
@@ -240,18 +254,16 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
     z[d] = v;
     acc += r[d] * v;
   }
-  if (red) {
-    double total;
-    grid_sum(acc, red + RED_RZ, scratch, total);
-  }
+  if (red) partial_store(acc, red + RED_RZ, scratch);
 }
 
 // beta = (r.z)_new / (r.z)_old; p = z + beta p (init: p = z).
-__global__ __launch_bounds__(256) void k_update_p(int64_t n, DevState* st, const Reduction* red,
+__global__ __launch_bounds__(256) void k_update_p(int64_t n, DevState* st, const Reduction* red, int n_rz,
                                                   double* __restrict__ rz2, double* __restrict__ beta_hist,
                                                   const double* __restrict__ z, double* __restrict__ p, int init) {
+  __shared__ double scratch[4];
   if (st->done) return;
-  const double rz_new = red[RED_RZ].result;
+  const double rz_new = partials_sum(red + RED_RZ, n_rz, scratch);
   if (init) {
     if (blockIdx.x == 0 && threadIdx.x == 0) rz2[0] = rz_new;
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
@@ -287,9 +299,13 @@ __global__ void k_reset_queues(DevState* st) {
 
 }  // namespace
 
+int spmv_parts(int64_t n) { return grid_for(n, SPMV_GRID); }
+int vec_parts(int64_t n) { return grid_for(n, VEC_GRID); }
+int prolong_parts(int64_t n) { return grid_for(n, PROLONG_GRID); }
+
 hipError_t launch_spmv(int np, int32_t N, const int32_t* row_ptr, const int32_t* col, const double* blocks,
                        const double* p, double* q, Reduction* red, const DevState* st, hipStream_t s) {
-  dim3 g(grid_for((int64_t)N * np, MAXG)), b(256);
+  dim3 g(spmv_parts((int64_t)N * np)), b(256);
   switch (np) {
     case 3: hipLaunchKernelGGL(k_spmv<3>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     case 6: hipLaunchKernelGGL(k_spmv<6>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
@@ -319,16 +335,16 @@ hipError_t launch_unpermute_out(int np, int32_t N, const int32_t* perm, const do
   return hipGetLastError();
 }
 
-hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, const double* rz2, double* alpha_hist,
-                            const double* p, const double* q, double* x, double* r, void* yl, void* zl,
-                            int local_f32, hipStream_t s) {
-  dim3 g(grid_for(n, VEC_GRID)), b(256);
+hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, int n_pq, const double* rz2,
+                            double* alpha_hist, const double* p, const double* q, double* x, double* r, void* yl,
+                            void* zl, int local_f32, hipStream_t s) {
+  dim3 g(vec_parts(n)), b(256);
   if (local_f32)
-    hipLaunchKernelGGL(k_update_xr<float>, g, b, 0, s, n, st, red, rz2, alpha_hist, p, q, x, r, (float*)yl,
+    hipLaunchKernelGGL(k_update_xr<float>, g, b, 0, s, n, st, red, n_pq, rz2, alpha_hist, p, q, x, r, (float*)yl,
                        (float*)zl);
   else
-    hipLaunchKernelGGL(k_update_xr<double>, g, b, 0, s, n, st, red, rz2, alpha_hist, p, q, x, r, (double*)yl,
-                       (double*)zl);
+    hipLaunchKernelGGL(k_update_xr<double>, g, b, 0, s, n, st, red, n_pq, rz2, alpha_hist, p, q, x, r,
+                       (double*)yl, (double*)zl);
   return hipGetLastError();
 }
 
@@ -356,39 +372,41 @@ hipError_t launch_restrict(int np, int nq, int32_t nc, const int32_t* tptr, cons
 template <int NP, int NQ, typename T>
 static void prolong_tt(int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P, const double* z0,
                        const void* zl, const LocalParts* lp, const double* r, double* z, Reduction* red,
-                       const DevState* st, hipStream_t s) {
-  dim3 g(grid_for((int64_t)N * NP, VEC_GRID)), b(256);
+                       DevState* st, int n_pq, int n_rr, hipStream_t s) {
+  dim3 g(prolong_parts((int64_t)N * NP)), b(256);
   if (lp)
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, true>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub,
-                       lp->subs, (const T*)lp->part, r, z, red, st);
+                       lp->subs, (const T*)lp->part, r, z, red, st, n_pq, n_rr);
   else
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, false>), g, b, 0, s, N, pptr, pcol, P, z0, (const T*)zl, nullptr,
-                       nullptr, nullptr, r, z, red, st);
+                       nullptr, nullptr, r, z, red, st, n_pq, n_rr);
 }
 
 template <int NP, int NQ>
 static void prolong_t(int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P, const double* z0,
                       const void* zl, const LocalParts* lp, int f32, const double* r, double* z, Reduction* red,
-                      const DevState* st, hipStream_t s) {
+                      DevState* st, int n_pq, int n_rr, hipStream_t s) {
   if (f32)
-    prolong_tt<NP, NQ, float>(N, pptr, pcol, P, z0, zl, lp, r, z, red, st, s);
+    prolong_tt<NP, NQ, float>(N, pptr, pcol, P, z0, zl, lp, r, z, red, st, n_pq, n_rr, s);
   else
-    prolong_tt<NP, NQ, double>(N, pptr, pcol, P, z0, zl, lp, r, z, red, st, s);
+    prolong_tt<NP, NQ, double>(N, pptr, pcol, P, z0, zl, lp, r, z, red, st, n_pq, n_rr, s);
 }
 
 hipError_t launch_prolong(int np, int nq, int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P,
                           const double* z0, const void* zl, const LocalParts* lp, int f32, const double* r, double* z,
-                          Reduction* red, const DevState* st, hipStream_t s) {
+                          Reduction* red, DevState* st, int n_pq, int n_rr, hipStream_t s) {
   if (!pptr) nq = 3;  // no coarse level: any instantiation, the loop is skipped
-#define P_(A, B) ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, lp, f32, r, z, red, st, s)))
+  if (n_pq > 0 && (!red || !st)) return hipErrorInvalidValue;
+#define P_(A, B) \
+  ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, lp, f32, r, z, red, st, n_pq, n_rr, s)))
   P_(3, 3) P_(6, 3) P_(6, 6) P_(10, 3) P_(10, 6) P_(10, 10) P_(15, 3) P_(15, 6) P_(15, 10) P_(15, 15)
 #undef P_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, double* rz2, double* beta_hist,
+hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, int n_rz, double* rz2, double* beta_hist,
                            const double* z, double* p, int init, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(grid_for(n, VEC_GRID)), dim3(256), 0, s, n, st, red, rz2, beta_hist, z, p, init);
+  hipLaunchKernelGGL(k_update_p, dim3(vec_parts(n)), dim3(256), 0, s, n, st, red, n_rz, rz2, beta_hist, z, p, init);
   return hipGetLastError();
 }
 

@@ -59,9 +59,14 @@ hipError_t launch_permute_in(int np, int32_t n_cells, const int32_t* perm, const
                              Reduction* red, DevState* st, double rtol, int max_iter, hipStream_t s);
 hipError_t launch_unpermute_out(int np, int32_t n_cells, const int32_t* perm, const double* x,
                                 double* dst, hipStream_t s);
-hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, const double* rz2, double* alpha_hist,
-                            const double* p, const double* q, double* x, double* r, void* yl, void* zl,
-                            int local_f32, hipStream_t s);
+// Work-groups (= partials of the dot product each produces) of the operator
+// apply and of the grid-stride vector kernels, for n DoFs.
+int spmv_parts(int64_t n);
+int vec_parts(int64_t n);
+int prolong_parts(int64_t n);
+hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, int n_pq, const double* rz2,
+                            double* alpha_hist, const double* p, const double* q, double* x, double* r, void* yl,
+                            void* zl, int local_f32, hipStream_t s);
 hipError_t launch_restrict(int np, int nq, int32_t n_coarse, const int32_t* tptr, const int32_t* tcell,
                            const int32_t* tblk, const double* P, const double* r, double* r0,
                            double* y0, double* z0, const DevState* st, hipStream_t s);
@@ -72,11 +77,13 @@ struct LocalParts {
   const SubDesc* subs;
   const void* part;  // 2*TILE entries per stored tile (rows, then columns)
 };
+// n_pq > 0: a PCG iteration; work-group 0 sums n_pq partials of p.Ap and
+// n_rr of ||r||^2, counts the iteration and takes the stopping decision.
 hipError_t launch_prolong(int np, int nq, int32_t n_cells, const int32_t* pptr, const int32_t* pcol,
                           const double* P, const double* z0, const void* zl, const LocalParts* lp,
-                          int local_f32, const double* r, double* z, Reduction* red, const DevState* st,
-                          hipStream_t s);
-hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, double* rz2,
+                          int local_f32, const double* r, double* z, Reduction* red, DevState* st,
+                          int n_pq, int n_rr, hipStream_t s);
+hipError_t launch_update_p(int64_t n, DevState* st, const Reduction* red, int n_rz, double* rz2,
                            double* beta_hist, const double* z, double* p, int init, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_reset_queues(DevState* st, hipStream_t s);
@@ -97,6 +104,12 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
 // launch_prolong with LocalParts.
 hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
                              const double* r, void* part, const DevState* st, hipStream_t s);
+
+// Coarse level with an explicit inverse: expand the packed lower tiles of
+// A_0^{-1} to a dense row-major matrix; y = D x, one wave per row.
+hipError_t launch_expand_sym(int32_t n0, const double* S, double* D, hipStream_t s);
+hipError_t launch_dense_mv(int32_t n, const double* D, const double* x, double* y, const DevState* st,
+                           hipStream_t s);
 
 // Batched forward/backward triangular sweeps (kern_trsv.hip).
 // trace (optional): per task, wall-clock at dequeue, end of waits, end.
