@@ -111,6 +111,7 @@ struct asdg_problem {
   struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv, cS, cX, cinv, cmeta, cinvt; } o2{};
   // coarse solve by a dense explicit A_0^{-1} (n0 <= kCoarseDenseMax) instead of the triangular sweeps
   bool coarse_dense = false;
+  int rsplits = 1;  // work-groups per coarse cell in the restriction (partials added by the dense coarse solve)
   std::vector<int4> cmeta, cinv_tasks;
   struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace, part; } o3{};
   size_t bytes[4] = {0, 0, 0, 0};
@@ -282,6 +283,14 @@ void plan_coarse_factor(asdg_problem* pb) {
   for (int b = 0; b < nb; ++b) pb->ctrsv_tasks.push_back(make_int4(0, 0, b, 0));
   for (int b = nb - 1; b >= 0; --b) pb->ctrsv_tasks.push_back(make_int4(0, 1, b, 0));
   pb->coarse_dense = n0 <= kCoarseDenseMax;
+  // restriction: about 512 (entry, row) pairs per work-group, at most 32 work-groups per coarse cell
+  if (pb->coarse_dense) {
+    const int64_t pairs = (int64_t)pb->C.tptr.back() * pb->A.np;
+    const int64_t per_cell = (pairs + pb->C.n_coarse - 1) / pb->C.n_coarse;
+    pb->rsplits = (int)std::max<int64_t>(1, std::min<int64_t>(32, (per_cell + 511) / 512));
+  } else {
+    pb->rsplits = 1;
+  }
   pb->cmeta.clear();
   pb->cinv_tasks.clear();
   if (pb->coarse_dense) {
@@ -296,7 +305,7 @@ void plan_coarse_factor(asdg_problem* pb) {
 // z0 = A_0^{-1} r0: dense explicit inverse, or the two triangular sweeps.
 asdg_status enqueue_coarse_solve(asdg_problem* pb, const DevState* st_done, hipStream_t s) {
   if (pb->coarse_dense) {
-    HIPCHK(pb, launch_dense_mv(pb->n0, pb->ptr<double>(2, pb->o2.cinv), pb->ptr<double>(3, pb->o3.r0),
+    HIPCHK(pb, launch_dense_mv(pb->n0, pb->rsplits, pb->ptr<double>(2, pb->o2.cinv), pb->ptr<double>(3, pb->o3.r0),
                                pb->ptr<double>(3, pb->o3.z0), st_done, s));
     return ASDG_OK;
   }
@@ -322,10 +331,11 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   const double* r = pb->ptr<double>(3, pb->o3.r);
   if (pb->has_coarse) {
-    HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->ptr<int32_t>(2, pb->o2.tptr),
+    HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->rsplits, pb->ptr<int32_t>(2, pb->o2.tptr),
                                pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
                                pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
-                               pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), st_done, s));
+                               pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.y0),
+                               pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), st_done, s));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
   if (pb->inv_planned) {
@@ -641,7 +651,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o3.z = L3.add(8 * n);
   pb->o3.yl = L3.add(w * n);
   pb->o3.zl = L3.add(w * n);
-  pb->o3.r0 = L3.add(8 * n0);
+  pb->o3.r0 = L3.add(8 * n0 * (pb->has_coarse ? pb->rsplits : 1));
   pb->o3.y0 = L3.add(8 * n0);
   pb->o3.z0 = L3.add(8 * n0);
   pb->o3.red = L3.add(sizeof(Reduction) * N_RED);
@@ -914,10 +924,11 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
   } else {
     const bool loc = what != ASDG_APPLY_COARSE, crs = what != ASDG_APPLY_LOCAL && pb->has_coarse;
     if (crs)
-      HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->ptr<int32_t>(2, pb->o2.tptr),
+      HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->rsplits, pb->ptr<int32_t>(2, pb->o2.tptr),
                                  pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
                                  pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
-                                 pb->ptr<double>(3, pb->o3.y0), pb->ptr<double>(3, pb->o3.z0), nullptr, s));
+                                 pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.y0),
+                                 pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), nullptr, s));
     if (loc && pb->inv_planned) {
       HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                    pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,

@@ -238,19 +238,28 @@ __global__ __launch_bounds__(256) void k_expand_sym(int32_t n0, const double* __
   }
 }
 
-// y = D x for a dense row-major n x n matrix: one wave per row, each lane
-// strides the row by 64 (coalesced 512-byte loads), fixed-order wave sum.
-__global__ __launch_bounds__(256) void k_dense_mv(int32_t n, const double* __restrict__ D,
-                                                  const double* __restrict__ x, double* __restrict__ y,
+// y = D x for a dense row-major n x n matrix, x given as `splits` partial
+// vectors (x = sum_s xp[s n + i], added in order of s into LDS by every
+// work-group). One wave per row; each lane strides the row by 64 (coalesced
+// 512-byte loads, eight in flight); fixed-order wave sum.
+__global__ __launch_bounds__(256) void k_dense_mv(int32_t n, int splits, const double* __restrict__ D,
+                                                  const double* __restrict__ xp, double* __restrict__ y,
                                                   const DevState* st) {
+  extern __shared__ double xs[];
   if (st && st->done) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    for (int sp = 0; sp < splits; ++sp) v += xp[(size_t)sp * n + i];
+    xs[i] = v;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const double* Dr = D + (size_t)row * n;
   double acc = 0.0;
-#pragma unroll 4
-  for (int j = lane; j < n; j += 64) acc += Dr[j] * x[j];
+#pragma unroll 8
+  for (int j = lane; j < n; j += 64) acc += Dr[j] * xs[j];
   acc = warp_sum(acc);
   if (lane == 0) y[row] = acc;
 }
@@ -308,10 +317,11 @@ hipError_t launch_expand_sym(int32_t n0, const double* S, double* D, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_dense_mv(int32_t n, const double* D, const double* x, double* y, const DevState* st,
+hipError_t launch_dense_mv(int32_t n, int splits, const double* D, const double* xp, double* y, const DevState* st,
                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), 0, s, n, D, x, y, st);
+  if (splits < 1 || (size_t)n * 8 > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dense_mv, dim3((n + 3) / 4), dim3(256), (size_t)n * 8, s, n, splits, D, xp, y, st);
   return hipGetLastError();
 }
 

@@ -148,37 +148,44 @@ __global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Redu
   partial_store(acc, red + RED_RR, scratch);
 }
 
-// r0 = P_0^T r: one work-group per coarse cell, entries in fixed order.
+// r0 = P_0^T r. The (entry, fine row a) pairs of coarse cell J's transposed
+// list are split over `splits` work-groups (blockIdx.x = J * splits + s,
+// threads stride the pairs: consecutive threads read consecutive rows of a
+// P block and consecutive entries of r); work-group (J, s) writes its NQ
+// fixed-order sums to out[(s n_coarse + J) NQ + c].
+// With one split that is r0 itself; otherwise the coarse solve adds the
+// splits (launch_dense_mv). y0/z0 (optional): re-armed sweep sentinels.
 template <int NP, int NQ>
-__global__ __launch_bounds__(256) void k_restrict(const int32_t* __restrict__ tptr, const int32_t* __restrict__ tcell,
+__global__ __launch_bounds__(256) void k_restrict(int32_t n_coarse, int splits, const int32_t* __restrict__ tptr,
+                                                  const int32_t* __restrict__ tcell,
                                                   const int32_t* __restrict__ tblk, const double* __restrict__ P,
-                                                  const double* __restrict__ r, double* __restrict__ r0,
+                                                  const double* __restrict__ r, double* __restrict__ out,
                                                   double* __restrict__ y0, double* __restrict__ z0,
                                                   const DevState* st) {
   __shared__ double scratch[4];
   if (st && st->done) return;
-  const int J = blockIdx.x;
+  const int J = blockIdx.x / splits, sp = blockIdx.x - J * splits;
   double acc[NQ];
 #pragma unroll
   for (int c = 0; c < NQ; ++c) acc[c] = 0.0;
-  for (int k = tptr[J] + threadIdx.x; k < tptr[J + 1]; k += blockDim.x) {
-    const int cell = tcell[k];
-    const double* Pb = P + (size_t)tblk[k] * NP * NQ;
-    const double* rv = r + (size_t)cell * NP;
+  const int k0 = tptr[J], pairs = (tptr[J + 1] - k0) * NP;
+  for (int i = sp * blockDim.x + threadIdx.x; i < pairs; i += splits * blockDim.x) {
+    const int kk = i / NP, a = i - kk * NP;
+    const int k = k0 + kk;
+    const double v = r[(size_t)tcell[k] * NP + a];
+    const double* Pr = P + ((size_t)tblk[k] * NP + a) * NQ;
 #pragma unroll
-    for (int a = 0; a < NP; ++a) {
-      const double v = rv[a];
-#pragma unroll
-      for (int c = 0; c < NQ; ++c) acc[c] += Pb[a * NQ + c] * v;
-    }
+    for (int c = 0; c < NQ; ++c) acc[c] += Pr[c] * v;
   }
 #pragma unroll
   for (int c = 0; c < NQ; ++c) {
-    const double s = block_sum(acc[c], scratch);
+    const double sum = block_sum(acc[c], scratch);
     if (threadIdx.x == 0) {
-      r0[J * NQ + c] = s;
-      y0[J * NQ + c] = sentinel_f64();
-      z0[J * NQ + c] = sentinel_f64();
+      out[((size_t)sp * n_coarse + J) * NQ + c] = sum;
+      if (y0) {
+        y0[J * NQ + c] = sentinel_f64();
+        z0[J * NQ + c] = sentinel_f64();
+      }
     }
   }
 }
@@ -349,9 +356,11 @@ hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, int n_pq, c
 }
 
 template <int NP, int NQ>
-static void restrict_t(int32_t nc, const int32_t* tptr, const int32_t* tcell, const int32_t* tblk, const double* P,
-                       const double* r, double* r0, double* y0, double* z0, const DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_restrict<NP, NQ>), dim3(nc), dim3(256), 0, s, tptr, tcell, tblk, P, r, r0, y0, z0, st);
+static void restrict_t(int32_t nc, int splits, const int32_t* tptr, const int32_t* tcell, const int32_t* tblk,
+                       const double* P, const double* r, double* out, double* y0, double* z0, const DevState* st,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_restrict<NP, NQ>), dim3(nc * splits), dim3(256), 0, s, nc, splits, tptr, tcell, tblk, P, r,
+                     out, y0, z0, st);
 }
 
 #define ASDG_PQ_SWITCH(NPV, NQV, CALL) \
@@ -360,10 +369,11 @@ static void restrict_t(int32_t nc, const int32_t* tptr, const int32_t* tcell, co
     return hipGetLastError();          \
   }
 
-hipError_t launch_restrict(int np, int nq, int32_t nc, const int32_t* tptr, const int32_t* tcell, const int32_t* tblk,
-                           const double* P, const double* r, double* r0, double* y0, double* z0, const DevState* st,
-                           hipStream_t s) {
-#define R_(A, B) ASDG_PQ_SWITCH(A, B, (restrict_t<A, B>(nc, tptr, tcell, tblk, P, r, r0, y0, z0, st, s)))
+hipError_t launch_restrict(int np, int nq, int32_t nc, int splits, const int32_t* tptr, const int32_t* tcell,
+                           const int32_t* tblk, const double* P, const double* r, double* out, double* y0, double* z0,
+                           const DevState* st, hipStream_t s) {
+  if (splits < 1 || (int64_t)nc * splits > 0x7fffffff) return hipErrorInvalidValue;
+#define R_(A, B) ASDG_PQ_SWITCH(A, B, (restrict_t<A, B>(nc, splits, tptr, tcell, tblk, P, r, out, y0, z0, st, s)))
   R_(3, 3) R_(6, 3) R_(6, 6) R_(10, 3) R_(10, 6) R_(10, 10) R_(15, 3) R_(15, 6) R_(15, 10) R_(15, 15)
 #undef R_
   return hipErrorInvalidValue;

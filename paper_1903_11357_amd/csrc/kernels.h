@@ -67,9 +67,11 @@ int prolong_parts(int64_t n);
 hipError_t launch_update_xr(int64_t n, DevState* st, Reduction* red, int n_pq, const double* rz2,
                             double* alpha_hist, const double* p, const double* q, double* x, double* r, void* yl,
                             void* zl, int local_f32, hipStream_t s);
-hipError_t launch_restrict(int np, int nq, int32_t n_coarse, const int32_t* tptr, const int32_t* tcell,
-                           const int32_t* tblk, const double* P, const double* r, double* r0,
-                           double* y0, double* z0, const DevState* st, hipStream_t s);
+// r0 = P_0^T r with each coarse cell's entries split over `splits` work-
+// groups: out holds `splits` partial vectors of n0 (splits = 1: r0).
+hipError_t launch_restrict(int np, int nq, int32_t n_coarse, int splits, const int32_t* tptr,
+                           const int32_t* tcell, const int32_t* tblk, const double* P, const double* r,
+                           double* out, double* y0, double* z0, const DevState* st, hipStream_t s);
 // Per-tile partial vectors of the packed symmetric local apply, summed per
 // DoF by the prolongation kernel (in place of a local solution vector).
 struct LocalParts {
@@ -108,7 +110,7 @@ hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const S
 // Coarse level with an explicit inverse: expand the packed lower tiles of
 // A_0^{-1} to a dense row-major matrix; y = D x, one wave per row.
 hipError_t launch_expand_sym(int32_t n0, const double* S, double* D, hipStream_t s);
-hipError_t launch_dense_mv(int32_t n, const double* D, const double* x, double* y, const DevState* st,
+hipError_t launch_dense_mv(int32_t n, int splits, const double* D, const double* xp, double* y, const DevState* st,
                            hipStream_t s);
 
 // Batched forward/backward triangular sweeps (kern_trsv.hip).
