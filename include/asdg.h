@@ -227,9 +227,15 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * through explicit inverses A_i^{-1} = L_i^{-T} L_i^{-1} formed after the
  * Cholesky factorisation (one pass over a packed symmetric matrix per
  * solve instead of two triangular sweeps; the factor buffer doubles); the
- * factor tiles then hold the lower tiles of A_i^{-1}. 0 = triangular sweeps. */
+ * factor tiles then hold the lower tiles of A_i^{-1}. 0 = triangular sweeps.
+ * SMALL_OFF (set before asdg_plan): by default, when every subdomain has at
+ * most 64 DoFs (e.g. one element per subdomain, the setting of Sec. 7's
+ * experiments), each A_i^{-1} is formed whole on the device (n_i x n_i,
+ * row-major, factor precision) and applied inside the prolongation kernel;
+ * asdg_export_factor_tiles then returns that n_i x n_i inverse. 1 = use the
+ * tile path for such subdomains too. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
-       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4 };
+       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Task trace of the last batched local solve launched while
@@ -240,6 +246,14 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
  * are returned. */
 asdg_status asdg_export_trace(asdg_problem* pb, int32_t* tasks, uint64_t* times, int64_t max_tasks,
                               int64_t* n_tasks, double* clock_mhz);
+
+/* Local-solver representation chosen by asdg_plan: ASDG_LOCAL_SWEEPS (tile
+ * Cholesky factors, two triangular sweeps), ASDG_LOCAL_INVERSE (packed tile
+ * inverses, one symmetric pass), ASDG_LOCAL_SMALL (whole inverses of
+ * subdomains of at most 64 DoFs, applied inside the prolongation);
+ * -1 before asdg_plan or for a NULL handle. */
+enum { ASDG_LOCAL_SWEEPS = 0, ASDG_LOCAL_INVERSE = 1, ASDG_LOCAL_SMALL = 2 };
+int32_t asdg_local_mode(const asdg_problem* pb);
 
 /* Subdomain index of the last ENOTSPD failure (-1 = coarse, -2 = none). */
 int32_t asdg_failed_subdomain(const asdg_problem* pb);

@@ -70,6 +70,7 @@ _SIGS = {
                                        C.POINTER(C.c_double)]),
     "asdg_export_coarse": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "asdg_failed_subdomain": (C.c_int32, [C.c_void_p]),
+    "asdg_local_mode": (C.c_int32, [C.c_void_p]),
     "asdg_export_factor_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "asdg_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "asdg_export_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
@@ -79,7 +80,9 @@ _SIGS = {
     "asdg_pcg_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
-TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE = 0, 1, 2, 3, 4
+TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF = \
+    0, 1, 2, 3, 4, 5
+LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 
 
 def lib():
@@ -215,6 +218,20 @@ class Problem:
                 L[b * T:(b + 1) * T, j * T:(j + 1) * T] = t
         return np.tril(L)[:n, :n]
 
+    def small_inverse(self, sub: int) -> np.ndarray:
+        """A_i^{-1} of subdomain ``sub`` in small-subdomain mode (every
+        subdomain <= 64 DoFs), as formed on the device."""
+        n = int(self._sub_sizes()[sub])
+        dt = np.float32 if self.precision == FP32_LOCAL else np.float64
+        buf = np.empty(n * n, dtype=dt)
+        self._check(self._L.asdg_export_factor_tiles(self.h, sub, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+        return buf.reshape(n, n).astype(np.float64)
+
+    def is_small(self) -> bool:
+        """True when the plan uses whole small inverses (every subdomain at
+        most 64 DoFs and ASDG_TUNE_SMALL_OFF not set)."""
+        return int(self._L.asdg_local_mode(self.h)) == LOCAL_SMALL
+
     def _sub_sizes(self):
         return self._subsizes
 
@@ -322,13 +339,16 @@ class Problem:
         return a.reshape(n0, n0)
 
 
-def setup_problem(P, precision=FP64, device="cuda", factor=True, local_inverse=False):
+def setup_problem(P, precision=FP64, device="cuda", factor=True, local_inverse=False, small=True):
     """Assemble + plan (+ bind/factor/coarse if a device is given) for an
-    ``inputs.Problem``."""
+    ``inputs.Problem``. small=False keeps subdomains of <= 64 DoFs on the
+    tile path."""
     pr = Problem()
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
     if local_inverse:
         pr.set_tuning(TUNE_LOCAL_INVERSE, 1)
+    if not small:
+        pr.set_tuning(TUNE_SMALL_OFF, 1)
     pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
             coarse_mesh=P.coarse_mesh)
     if device is not None:

@@ -120,6 +120,11 @@ struct asdg_problem {
   int n_cu = 256;
   int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
   int local_inverse = 0, inv_planned = 0;  // explicit local inverses (set before asdg_plan)
+  // small-subdomain mode: every n_i <= TILE; A_i^{-1} stored whole (n_i^2 words at subs[i].tile0) and
+  // applied inside the prolongation; no tiles, no local launch
+  int small_off = 0;
+  bool small = false;
+  int64_t small_words = 0;
   std::vector<int4> inv_tasks;
   std::vector<int32_t> cell_sub;
   // captured iteration chunk
@@ -219,8 +224,24 @@ void plan_local(asdg_problem* pb) {
     nbmax = std::max(nbmax, s.nb);
     pb->max_n = std::max(pb->max_n, s.n);
   }
-  pb->n_tiles = tiles;
+  int64_t words = 0;
+  for (const SubDesc& d : pb->subs) words += (int64_t)d.n * d.n;
+  pb->small = !pb->small_off && pb->max_n <= TILE && words < 0x7fffffff;
   pb->tile_meta.clear();
+  pb->chol_tasks.clear();
+  pb->trsv_tasks.clear();
+  if (pb->small) {
+    int64_t off = 0;
+    for (SubDesc& d : pb->subs) {
+      d.tile0 = (int32_t)off;  // word offset of the whole inverse
+      off += (int64_t)d.n * d.n;
+    }
+    pb->small_words = words;
+    pb->n_tiles = 0;
+    return;
+  }
+  pb->small_words = 0;
+  pb->n_tiles = tiles;
   pb->tile_meta.reserve(tiles);
   for (int32_t i = 0; i < ns; ++i)
     for (int b = 0; b < pb->subs[i].nb; ++b)
@@ -320,7 +341,7 @@ asdg_status enqueue_coarse_solve(asdg_problem* pb, const DevState* st_done, hipS
 
 LocalParts local_parts(asdg_problem* pb) {
   return LocalParts{pb->ptr<int32_t>(0, pb->o0.cell_sub), pb->ptr<SubDesc>(1, pb->o1.subs),
-                    pb->ptr<void>(3, pb->o3.part)};
+                    pb->small ? pb->ptr<void>(1, pb->o1.tiles) : pb->ptr<void>(3, pb->o3.part), pb->small ? 1 : 0};
 }
 
 // z = P^{-1} r and partials of r.z. iteration: the prolongation also takes
@@ -338,7 +359,9 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
                                pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), st_done, s));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
-  if (pb->inv_planned) {
+  if (pb->small) {
+    // local solves happen inside the prolongation
+  } else if (pb->inv_planned) {
     HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
                                  pb->ptr<void>(3, pb->o3.part), st, s));
@@ -360,7 +383,7 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
                             pb->has_coarse ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                             pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
                             pb->ptr<double>(3, pb->o3.z0), pb->ptr<void>(3, pb->o3.zl),
-                            pb->inv_planned ? &lp : nullptr, pb->f32, r, pb->ptr<double>(3, pb->o3.z), red,
+                            pb->inv_planned || pb->small ? &lp : nullptr, pb->f32, r, pb->ptr<double>(3, pb->o3.z), red,
                             st_done, iteration ? spmv_parts(pb->n()) : 0, iteration ? vec_parts(pb->n()) : 0, s));
   return ASDG_OK;
 }
@@ -377,7 +400,7 @@ asdg_status enqueue_iteration(asdg_problem* pb, hipStream_t s, hipEvent_t ev0, h
   double* rz2 = pb->ptr<double>(3, pb->o3.rz2);
   HIPCHK(pb, launch_spmv(np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
                          pb->ptr<double>(0, pb->o0.blocks), p, q, red, st, s));
-  const bool sweeps = !pb->inv_planned;  // only the sweeps consume yl/zl
+  const bool sweeps = !pb->inv_planned && !pb->small;  // only the sweeps consume yl/zl
   HIPCHK(pb, launch_update_xr(pb->n(), st, red, spmv_parts(pb->n()), rz2, pb->ptr<double>(3, pb->o3.ah), p, q, x,
                               r, sweeps ? pb->ptr<void>(3, pb->o3.yl) : nullptr,
                               sweeps ? pb->ptr<void>(3, pb->o3.zl) : nullptr, pb->f32, s));
@@ -587,7 +610,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
     plan_coarse_factor(pb);
   }
   plan_local(pb);
-  pb->inv_planned = pb->local_inverse;
+  pb->inv_planned = pb->local_inverse && !pb->small;
   pb->inv_tasks.clear();
   if (pb->inv_planned) {
     // X = L^{-1} tasks (i, j, b), j <= b, in row order: every X_kj with k < b comes first
@@ -612,7 +635,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o0.rhs = L0.add(8 * n);
   pb->o0.perm = L0.add(4 * N);
   pb->o0.cell_sub = L0.add(4 * N);
-  pb->o1.tiles = L1.add((size_t)pb->n_tiles * TILE * TILE * w);
+  pb->o1.tiles = L1.add(pb->small ? (size_t)pb->small_words * w : (size_t)pb->n_tiles * TILE * TILE * w);
   pb->o1.subs = L1.add(sizeof(SubDesc) * pb->subs.size());
   pb->o1.chol = L1.add(sizeof(int4) * pb->chol_tasks.size());
   pb->o1.trsv = L1.add(sizeof(int4) * pb->trsv_tasks.size());
@@ -764,6 +787,22 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   pb->failed_sub = -2;
   pb->stage = 3;
+  if (pb->small) {
+    DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+    HIPCHK(pb, launch_reset_queues(st, s));
+    HIPCHK(pb, launch_small_inverse(pb->f32, pb->A.n_sub, pb->A.np, pb->max_n, pb->ptr<SubDesc>(1, pb->o1.subs),
+                                    pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
+                                    pb->ptr<double>(0, pb->o0.blocks), pb->ptr<void>(1, pb->o1.tiles), st, s));
+    DevState h;
+    asdg_status e = read_state(pb, s, h);
+    if (e != ASDG_OK) return e;
+    if (h.chol_fail != 0x7fffffff) {
+      pb->failed_sub = h.chol_fail;
+      FAIL(pb, ASDG_ENOTSPD, "local matrix of subdomain " + std::to_string(h.chol_fail) + " is not positive definite");
+    }
+    pb->stage = 4;
+    return ASDG_OK;
+  }
   HIPCHK(pb, launch_gather_tiles(pb->A.np, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.row_ptr),
                                  pb->ptr<int32_t>(0, pb->o0.col), pb->ptr<double>(0, pb->o0.blocks),
@@ -929,7 +968,9 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                                  pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
                                  pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.y0),
                                  pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), nullptr, s));
-    if (loc && pb->inv_planned) {
+    if (loc && pb->small) {
+      // local solves happen inside the prolongation
+    } else if (loc && pb->inv_planned) {
       HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                    pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
                                    pb->ptr<void>(3, pb->o3.part), nullptr, s));
@@ -949,7 +990,8 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
     HIPCHK(pb, launch_prolong(np, crs ? pb->C.nq : 3, N, crs ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                               pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),
                               pb->ptr<double>(3, pb->o3.z0), loc ? pb->ptr<void>(3, pb->o3.zl) : nullptr,
-                              loc && pb->inv_planned ? &lp : nullptr, pb->f32, r, z, nullptr, nullptr, 0, 0, s));
+                              loc && (pb->inv_planned || pb->small) ? &lp : nullptr, pb->f32, r, z, nullptr, nullptr,
+                              0, 0, s));
     HIPCHK(pb, launch_unpermute_out(np, N, perm, z, d_out, s));
   }
   DevState h;
@@ -1022,8 +1064,13 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
     if (sub >= pb->A.n_sub) FAIL(pb, ASDG_EINVAL, "subdomain out of range");
     const SubDesc& d = pb->subs[sub];
     const size_t w = pb->f32 ? 4 : 8;
-    src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * TILE * TILE * w;
-    nbytes = (size_t)d.nb * (d.nb + 1) / 2 * TILE * TILE * w;
+    if (pb->small) {
+      src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * w;
+      nbytes = (size_t)d.n * d.n * w;
+    } else {
+      src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * TILE * TILE * w;
+      nbytes = (size_t)d.nb * (d.nb + 1) / 2 * TILE * TILE * w;
+    }
   }
   if (out_bytes < nbytes) FAIL(pb, ASDG_ENOMEM, "output too small");
   HIPCHK(pb, hipDeviceSynchronize());
@@ -1051,6 +1098,11 @@ asdg_status asdg_export_trace(asdg_problem* pb, int32_t* tasks, uint64_t* times,
   return ASDG_OK;
 }
 
+int32_t asdg_local_mode(const asdg_problem* pb) {
+  if (!pb || pb->stage < 2) return -1;
+  return pb->small ? ASDG_LOCAL_SMALL : pb->inv_planned ? ASDG_LOCAL_INVERSE : ASDG_LOCAL_SWEEPS;
+}
+
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   if (!pb) return ASDG_EINVAL;
   if (value < 0 || value > 65536) FAIL(pb, ASDG_EINVAL, "tuning value out of range");
@@ -1059,6 +1111,7 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_CHOL_GRID) pb->chol_grid = value;
   else if (what == ASDG_TUNE_TRACE) pb->trace = value;
   else if (what == ASDG_TUNE_LOCAL_INVERSE) pb->local_inverse = value ? 1 : 0;
+  else if (what == ASDG_TUNE_SMALL_OFF) pb->small_off = value ? 1 : 0;
   else FAIL(pb, ASDG_EINVAL, "unknown tuning key");
   pb->drop_graph();
   return ASDG_OK;

@@ -224,6 +224,76 @@ __global__ __launch_bounds__(256) void k_symv_tiles(int32_t n_tiles, const int4*
   if (j < b) pt[TILE + 4 * c4 + r0] = ca[0];
 }
 
+// ---------------------------------------------------------------- small subdomains
+// Subdomains of at most 64 DoFs (the case of one element per subdomain):
+// one wave per subdomain gathers A_i from the block rows into LDS (FP64),
+// factors it A_i = L L^T, forms X = L^{-1} row by row (lane = column) and
+// writes A_i^{-1} = X^T X whole (n_i x n_i row-major, at word offset
+// sd.tile0). Entry (i, j) and (j, i) add the same products in the same
+// order, so the stored inverse is exactly symmetric. A non-positive pivot
+// reports the subdomain through st->chol_fail (smallest index wins).
+template <typename T>
+__global__ __launch_bounds__(64) void k_small_inverse(int32_t n_sub, int np, int ld, const SubDesc* __restrict__ subs,
+                                                      const int32_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ blocks, T* __restrict__ S,
+                                                      DevState* st) {
+  extern __shared__ double sm[];
+  const int isub = blockIdx.x, lane = threadIdx.x;
+  const SubDesc sd = subs[isub];
+  const int n = sd.n, c0 = sd.dof0 / np, nc = n / np;
+  double* A = sm;           // [n][ld]
+  double* X = sm + n * ld;  // [n][ld]
+  for (int e = lane; e < n * ld; e += 64) A[e] = 0.0;
+  wave_sync();
+  for (int cc = 0; cc < nc; ++cc) {
+    const int c = c0 + cc;
+    for (int k = row_ptr[c]; k < row_ptr[c + 1]; ++k) {
+      const int cj = col[k] - c0;
+      if (cj < 0 || cj >= nc) continue;  // coupling to another subdomain
+      for (int e = lane; e < np * np; e += 64) {
+        const int a = e / np, b = e - a * np;
+        A[(cc * np + a) * ld + cj * np + b] = blocks[(size_t)k * np * np + e];
+      }
+    }
+  }
+  wave_sync();
+  for (int k = 0; k < n; ++k) {
+    const double d = A[k * ld + k];
+    if (!(d > 0.0)) {
+      if (lane == 0) atomicMin(&st->chol_fail, isub);
+      return;  // d is the same for every lane: the whole wave leaves
+    }
+    const double lkk = sqrt(d);
+    wave_sync();
+    if (lane == k) A[k * ld + k] = lkk;
+    else if (lane > k && lane < n) A[lane * ld + k] /= lkk;
+    wave_sync();
+    if (lane > k && lane < n) {
+      const double lik = A[lane * ld + k];
+      for (int j = k + 1; j <= lane; ++j) A[lane * ld + j] -= lik * A[j * ld + k];
+    }
+    wave_sync();
+  }
+  // X = L^{-1}: lane j owns column j; X_ij = (delta_ij - sum_{k=j}^{i-1} L_ik X_kj) / L_ii
+  for (int i = 0; i < n; ++i) {
+    if (lane <= i) {
+      double acc = lane == i ? 1.0 : 0.0;
+      for (int k = lane; k < i; ++k) acc -= A[i * ld + k] * X[k * ld + lane];
+      X[i * ld + lane] = acc / A[i * ld + i];
+    }
+  }
+  wave_sync();
+  if (lane < n) {
+    T* Si = S + sd.tile0 + (size_t)lane * n;
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = max(lane, j); k < n; ++k) acc += X[k * ld + lane] * X[k * ld + j];
+      Si[j] = (T)acc;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- coarse
 // Dense symmetric A_0^{-1} (row-major n0 x n0) from its packed lower tiles
 // (single "subdomain" at tile 0; diagonal tiles stored whole).
@@ -306,6 +376,25 @@ hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const S
   else
     hipLaunchKernelGGL(k_symv_tiles<double>, g, bl, 0, s, n_tiles, meta, subs, (const double*)S, r, (double*)part,
                        st);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_inverse(int f32, int32_t n_sub, int np, int max_n, const SubDesc* subs, const int32_t* row_ptr,
+                                const int32_t* col, const double* blocks, void* S, DevState* st, hipStream_t s) {
+  if (n_sub <= 0) return hipSuccess;
+  if (max_n < 1 || max_n > TILE) return hipErrorInvalidValue;
+  const int ld = max_n + 1;
+  const size_t sh = 2 * (size_t)max_n * ld * sizeof(double);
+  hipError_t e;
+  if (f32) {
+    if ((e = big_lds(k_small_inverse<float>, sh)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small_inverse<float>, dim3(n_sub), dim3(64), sh, s, n_sub, np, ld, subs, row_ptr, col, blocks,
+                       (float*)S, st);
+  } else {
+    if ((e = big_lds(k_small_inverse<double>, sh)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_small_inverse<double>, dim3(n_sub), dim3(64), sh, s, n_sub, np, ld, subs, row_ptr, col,
+                       blocks, (double*)S, st);
+  }
   return hipGetLastError();
 }
 

@@ -191,17 +191,18 @@ __global__ __launch_bounds__(256) void k_restrict(int32_t n_coarse, int splits, 
 }
 
 // z = z_loc + P_0 z0 (either part optional), and r.z. The local part is
-// either a vector zl, or (G) the sum, in a fixed order, of the packed
+// (L = 0) a vector zl; (L = 1) the sum, in a fixed order, of the packed
 // symmetric apply's per-tile partial vectors for the DoF's row:
 //   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>b} part(j,b).cols[rho]
-// with d = dof0 + 64 b + rho in its subdomain.
+// with d = dof0 + 64 b + rho in its subdomain; or (L = 2) row `loc` of a
+// small subdomain's whole inverse times r_i (n_i <= 64 terms, FP64 sums).
 //
 // With `red`, partials of r.z. With n_pq > 0 (a PCG iteration), work-group 0
 // also sums the partials of p.Ap and ||r||^2 left by the operator apply and
 // the residual update, counts the iteration and takes the stopping decision
 // (abort > breakdown > converged > iteration limit). No other work-group of
 // this launch reads the fields it writes.
-template <int NP, int NQ, typename T, bool G>
+template <int NP, int NQ, typename T, int L>
 __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __restrict__ pptr,
                                                  const int32_t* __restrict__ pcol, const double* __restrict__ P,
                                                  const double* __restrict__ z0, const T* __restrict__ zl,
@@ -239,7 +240,13 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
     const int64_t cell = d / NP;
     const int a = (int)(d - cell * NP);
     double v = 0.0;
-    if (G) {
+    if (L == 2) {
+      const SubDesc sd = subs[cell_sub[cell]];
+      const int loc = (int)(d - sd.dof0);
+      const T* Srow = part + sd.tile0 + (size_t)loc * sd.n;
+      const double* ri = r + sd.dof0;
+      for (int b = 0; b < sd.n; ++b) v += (double)Srow[b] * ri[b];
+    } else if (L == 1) {
       const SubDesc sd = subs[cell_sub[cell]];
       const int loc = (int)(d - sd.dof0);
       const int b = loc / TILE, rho = loc - b * TILE;
@@ -384,12 +391,15 @@ static void prolong_tt(int32_t N, const int32_t* pptr, const int32_t* pcol, cons
                        const void* zl, const LocalParts* lp, const double* r, double* z, Reduction* red,
                        DevState* st, int n_pq, int n_rr, hipStream_t s) {
   dim3 g(prolong_parts((int64_t)N * NP)), b(256);
-  if (lp)
-    hipLaunchKernelGGL((k_prolong<NP, NQ, T, true>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub,
-                       lp->subs, (const T*)lp->part, r, z, red, st, n_pq, n_rr);
+  if (lp && lp->small)
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, 2>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub, lp->subs,
+                       (const T*)lp->part, r, z, red, st, n_pq, n_rr);
+  else if (lp)
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, 1>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub, lp->subs,
+                       (const T*)lp->part, r, z, red, st, n_pq, n_rr);
   else
-    hipLaunchKernelGGL((k_prolong<NP, NQ, T, false>), g, b, 0, s, N, pptr, pcol, P, z0, (const T*)zl, nullptr,
-                       nullptr, nullptr, r, z, red, st, n_pq, n_rr);
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, 0>), g, b, 0, s, N, pptr, pcol, P, z0, (const T*)zl, nullptr, nullptr,
+                       nullptr, r, z, red, st, n_pq, n_rr);
 }
 
 template <int NP, int NQ>

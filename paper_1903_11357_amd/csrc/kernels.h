@@ -77,7 +77,8 @@ hipError_t launch_restrict(int np, int nq, int32_t n_coarse, int splits, const i
 struct LocalParts {
   const int32_t* cell_sub;  // subdomain of each cell
   const SubDesc* subs;
-  const void* part;  // 2*TILE entries per stored tile (rows, then columns)
+  const void* part;  // 2*TILE entries per stored tile (rows, then columns); small: the inverses
+  int small;         // 1: z_loc = A_i^{-1} r_i from whole small inverses (launch_small_inverse)
 };
 // n_pq > 0: a PCG iteration; work-group 0 sums n_pq partials of p.Ap and
 // n_rr of ||r||^2, counts the iteration and takes the stopping decision.
@@ -106,6 +107,12 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
 // launch_prolong with LocalParts.
 hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
                              const double* r, void* part, const DevState* st, hipStream_t s);
+
+// Subdomains of at most 64 DoFs: A_i^{-1} whole (n_i x n_i row-major) at
+// word offset subs[i].tile0, formed by one wave per subdomain (max_n =
+// largest n_i, sizes the LDS).
+hipError_t launch_small_inverse(int f32, int32_t n_sub, int np, int max_n, const SubDesc* subs, const int32_t* row_ptr,
+                                const int32_t* col, const double* blocks, void* S, DevState* st, hipStream_t s);
 
 // Coarse level with an explicit inverse: expand the packed lower tiles of
 // A_0^{-1} to a dense row-major matrix; y = D x, one wave per row.

@@ -340,6 +340,16 @@ def make_config(name: str) -> Problem:
     if name == "C4":
         return voronoi_problem(131072, 3, p=2, bx=32, by=16, q=1, nonnested_coarse=64,
                                log10_rho_range=4.0, f=f_one, name="C4")
+    if name == "C4h":
+        # C4's mesh, coefficients and load with one element per subdomain and
+        # the 512 bins as nested agglomerated coarse cells (aligned with the
+        # rho jumps), q=1: the setting of the paper's experiments (Sec. 7)
+        P = make_config("C4")
+        P.coarse_of_cell = P.subdomain.copy()
+        P.coarse_mesh = None
+        P.subdomain = np.arange(P.mesh.n_cells, dtype=np.int32)
+        P.name = "C4h"
+        return P
     raise KeyError(name)
 
 

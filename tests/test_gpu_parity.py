@@ -210,15 +210,17 @@ def test_indefinite_local_matrix_reports_enotspd():
     assert 0 <= pr.failed_subdomain() < 4
 
 
-def test_example5_printed_condition_number_on_gpu():
+@pytest.mark.parametrize("small", [True, False], ids=["small", "tiles"])
+def test_example5_printed_condition_number_on_gpu(small):
     """Massively parallel setting (one subdomain per element), 32x32 squares,
     coarse 4x4-square agglomerates, p = q = 1, f = 1: the Lanczos estimate of
-    the GPU solve reproduces Fig. 6's printed 43.6818."""
+    the GPU solve reproduces Fig. 6's printed 43.6818, with the whole small
+    inverses and with the tile path."""
     from paper_1903_11357_amd import asdg
 
     P = I.squares_problem(32, 1, 1, 4, q=1, f=I.f_one)
     P.subdomain = np.arange(32 * 32, dtype=np.int32)
-    pr = asdg.setup_problem(P, asdg.FP64, device="cuda:0")
+    pr = asdg.setup_problem(P, asdg.FP64, device="cuda:0", small=small)
     x, st = pr.solve(rtol=1e-8)
     K = st["lambda_max"] / st["lambda_min"]
     print("K =", K, "iterations", st["iterations"])
@@ -273,3 +275,130 @@ def test_pcg_fp32_local_inverse_solution_within_1e8(name):
     erra = math.sqrt(e @ (orc.A @ e)) / math.sqrt(xd @ (orc.A @ xd))
     print(f"{name}: fp32-local inverse iterations={st['iterations']} rel2={_rel(xg, xd):.2e} relA={erra:.2e}")
     assert _rel(xg, xd) <= 1e-8 and erra <= 1e-8
+
+
+# ---------------------------------------------------------------- small subdomains (<= 64 DoFs)
+def _per_element(P):
+    P.subdomain = np.arange(P.mesh.n_cells, dtype=np.int32)
+    return P
+
+
+SMALL_CASES = {
+    # one element per subdomain (the setting of Sec. 7), squares p=1, nested coarse 4x4 agglomerates
+    "sq_per_element": lambda: _per_element(I.squares_problem(16, 1, 1, 4, q=1)),
+    # one element per subdomain, Voronoi p=2, rho jumps 1e+-2, independent coarse Voronoi q=1
+    "vor_per_element": lambda: _per_element(I.voronoi_problem(300, 21, p=2, bx=4, by=4, q=1, nonnested_coarse=7,
+                                                              log10_rho_range=2.0)),
+    # ragged multi-element subdomains of 6..36 DoFs, Voronoi p=1, 8x8 bins, nested q=1
+    "vor_small_bins": lambda: I.voronoi_problem(400, 22, p=1, bx=8, by=8, q=1),
+}
+
+
+def _setup_small(name, precision):
+    import torch
+
+    from oracle import OracleSolver
+    from paper_1903_11357_amd import asdg
+
+    key = ("small", name, precision)
+    if key not in _cache:
+        if ("small", name, "oracle") not in _cache:
+            P = SMALL_CASES[name]()
+            assert np.bincount(P.subdomain).max() * P.n_p <= 64
+            _cache[("small", name, "oracle")] = (P, OracleSolver(P))
+        P, orc = _cache[("small", name, "oracle")]
+        print(f"[setup] small {name} precision={precision} n={P.n_dofs}", flush=True)
+        pr = asdg.setup_problem(P, precision, device="cuda:0")
+        torch.cuda.synchronize()
+        _cache[key] = (P, orc, pr)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_local_apply_matches_oracle_and_is_symmetric(name, prec):
+    import torch
+
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup_small(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL)
+    u = _vec(pr.n, 11)
+    v = _vec(pr.n, 12)
+    lu = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(u).cuda()).cpu().numpy()
+    lv = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = orc.M.local_apply(u)
+    k = max(np.linalg.cond(orc.A[d][:, d].toarray()) for d in orc.M.dofs)
+    tol = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * k
+    assert _rel(lu, ref) <= tol, (_rel(lu, ref), tol)
+    # the stored inverses are exactly symmetric; the FP64 sums of their rows
+    # add the same products in different orders
+    assert abs(v @ lu - u @ lv) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(lv)
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_small_inverse_times_local_matrix_is_identity(name):
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup_small(name, asdg.FP64)
+    for i in sorted({0, len(orc.M.dofs) // 2, len(orc.M.dofs) - 1}):
+        d = orc.M.dofs[i]
+        Ai = orc.A[d][:, d].toarray()
+        Si = pr.small_inverse(i)
+        assert np.array_equal(Si, Si.T)
+        assert np.abs(Si @ Ai - np.eye(len(d))).max() <= 1e-10 * np.linalg.cond(Ai)
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_small_pcg_fp64_matches_oracle(name):
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup_small(name, asdg.FP64)
+    x, st = pr.solve(rtol=1e-8)
+    _check_pcg_parity("small/" + name, orc, st, x.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_small_pcg_fp32_solution_within_1e8(name):
+    import scipy.sparse.linalg as spla
+
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup_small(name, asdg.FP32_LOCAL)
+    x, st = pr.solve(rtol=1e-12, max_iter=5000)
+    xd = spla.spsolve(orc.A.tocsc(), orc.b)
+    xg = x.cpu().numpy()
+    e = xg - xd
+    erra = math.sqrt(e @ (orc.A @ e)) / math.sqrt(xd @ (orc.A @ xd))
+    print(f"{name}: fp32-local small iterations={st['iterations']} rel2={_rel(xg, xd):.2e} relA={erra:.2e}")
+    assert _rel(xg, xd) <= 1e-8 and erra <= 1e-8
+
+
+def test_small_mode_equals_tile_path():
+    """The whole small inverses and the tile Cholesky sweeps apply the same
+    local solvers."""
+    import torch
+
+    from paper_1903_11357_amd import asdg
+
+    P, orc, pr = _setup_small("vor_small_bins", asdg.FP64)
+    pt = asdg.setup_problem(P, asdg.FP64, device="cuda:0", small=False)
+    u = torch.from_numpy(_vec(pr.n, 13)).cuda()
+    a = pr.apply(asdg.APPLY_PRECOND, u).cpu().numpy()
+    b = pt.apply(asdg.APPLY_PRECOND, u).cpu().numpy()
+    assert _rel(a, b) <= 1e-12, _rel(a, b)
+
+
+def test_small_not_spd_reports_subdomain():
+    """A penalty far below the coercivity threshold makes single-element
+    local matrices indefinite: ENOTSPD with the failing subdomain."""
+    from paper_1903_11357_amd import asdg
+
+    P = _per_element(I.squares_problem(8, 2, 1, 4, q=1, c_sigma=0.01))
+    pr = asdg.Problem()
+    pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    pr.plan(asdg.FP64, 1, coarse_of_cell=P.coarse_of_cell)
+    pr.bind("cuda:0")
+    with pytest.raises(asdg.AsdgError) as e:
+        pr.factor()
+    assert e.value.status == asdg.ENOTSPD
+    assert 0 <= pr.failed_subdomain() < 64
