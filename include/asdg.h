@@ -233,9 +233,12 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * experiments), each A_i^{-1} is formed whole on the device (n_i x n_i,
  * row-major, factor precision) and applied inside the prolongation kernel;
  * asdg_export_factor_tiles then returns that n_i x n_i inverse. 1 = use the
- * tile path for such subdomains too. */
+ * tile path for such subdomains too.
+ * NO_PRECOND (study aid, any time before a solve): 1 = asdg_pcg_solve runs
+ * plain CG (identity preconditioner), so the Lanczos estimate in the stats
+ * is K(A_h) rather than K(P_ad); asdg_apply is unaffected. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
-       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5 };
+       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Task trace of the last batched local solve launched while

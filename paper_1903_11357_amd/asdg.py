@@ -80,8 +80,8 @@ _SIGS = {
     "asdg_pcg_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
-TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF = \
-    0, 1, 2, 3, 4, 5
+TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
+    TUNE_NO_PRECOND = 0, 1, 2, 3, 4, 5, 6
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 
 
@@ -91,6 +91,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libasdg.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        # torch first: the library must resolve to the HIP runtime torch has
+        # loaded, because the device buffers and streams it is given are torch's
+        # (loaded the other way round, the process ends up with two runtimes)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

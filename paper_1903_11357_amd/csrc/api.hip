@@ -123,6 +123,7 @@ struct asdg_problem {
   // small-subdomain mode: every n_i <= TILE; A_i^{-1} stored whole (n_i^2 words at subs[i].tile0) and
   // applied inside the prolongation; no tiles, no local launch
   int small_off = 0;
+  int no_precond = 0;  // identity preconditioner (plain CG; Lanczos then estimates K(A))
   bool small = false;
   int64_t small_words = 0;
   std::vector<int4> inv_tasks;
@@ -351,6 +352,15 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
   const int np = pb->A.np;
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   const double* r = pb->ptr<double>(3, pb->o3.r);
+  if (pb->no_precond) {
+    const LocalParts id{nullptr, nullptr, nullptr, 2};
+    if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
+    if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
+    HIPCHK(pb, launch_prolong(np, 3, pb->A.n_cells, nullptr, nullptr, nullptr, nullptr, nullptr, &id, pb->f32, r,
+                              pb->ptr<double>(3, pb->o3.z), red, st_done, iteration ? spmv_parts(pb->n()) : 0,
+                              iteration ? vec_parts(pb->n()) : 0, s));
+    return ASDG_OK;
+  }
   if (pb->has_coarse) {
     HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->rsplits, pb->ptr<int32_t>(2, pb->o2.tptr),
                                pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
@@ -1112,6 +1122,7 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_TRACE) pb->trace = value;
   else if (what == ASDG_TUNE_LOCAL_INVERSE) pb->local_inverse = value ? 1 : 0;
   else if (what == ASDG_TUNE_SMALL_OFF) pb->small_off = value ? 1 : 0;
+  else if (what == ASDG_TUNE_NO_PRECOND) pb->no_precond = value ? 1 : 0;
   else FAIL(pb, ASDG_EINVAL, "unknown tuning key");
   pb->drop_graph();
   return ASDG_OK;

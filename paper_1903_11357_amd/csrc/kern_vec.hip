@@ -195,7 +195,8 @@ __global__ __launch_bounds__(256) void k_restrict(int32_t n_coarse, int splits, 
 // symmetric apply's per-tile partial vectors for the DoF's row:
 //   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>b} part(j,b).cols[rho]
 // with d = dof0 + 64 b + rho in its subdomain; or (L = 2) row `loc` of a
-// small subdomain's whole inverse times r_i (n_i <= 64 terms, FP64 sums).
+// small subdomain's whole inverse times r_i (n_i <= 64 terms, FP64 sums);
+// or (L = 3) r itself (identity preconditioner, no coarse part).
 //
 // With `red`, partials of r.z. With n_pq > 0 (a PCG iteration), work-group 0
 // also sums the partials of p.Ap and ||r||^2 left by the operator apply and
@@ -240,7 +241,9 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
     const int64_t cell = d / NP;
     const int a = (int)(d - cell * NP);
     double v = 0.0;
-    if (L == 2) {
+    if (L == 3) {
+      v = r[d];  // identity preconditioner (plain CG)
+    } else if (L == 2) {
       const SubDesc sd = subs[cell_sub[cell]];
       const int loc = (int)(d - sd.dof0);
       const T* Srow = part + sd.tile0 + (size_t)loc * sd.n;
@@ -391,7 +394,10 @@ static void prolong_tt(int32_t N, const int32_t* pptr, const int32_t* pcol, cons
                        const void* zl, const LocalParts* lp, const double* r, double* z, Reduction* red,
                        DevState* st, int n_pq, int n_rr, hipStream_t s) {
   dim3 g(prolong_parts((int64_t)N * NP)), b(256);
-  if (lp && lp->small)
+  if (lp && lp->small == 2)
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, 3>), g, b, 0, s, N, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, r, z, red, st, n_pq, n_rr);
+  else if (lp && lp->small)
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, 2>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub, lp->subs,
                        (const T*)lp->part, r, z, red, st, n_pq, n_rr);
   else if (lp)

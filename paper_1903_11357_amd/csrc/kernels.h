@@ -78,7 +78,8 @@ struct LocalParts {
   const int32_t* cell_sub;  // subdomain of each cell
   const SubDesc* subs;
   const void* part;  // 2*TILE entries per stored tile (rows, then columns); small: the inverses
-  int small;         // 1: z_loc = A_i^{-1} r_i from whole small inverses (launch_small_inverse)
+  int small;         // 1: z_loc = A_i^{-1} r_i from whole small inverses (launch_small_inverse);
+                     // 2: z = r (identity preconditioner; the coarse part is skipped too)
 };
 // n_pq > 0: a PCG iteration; work-group 0 sums n_pq partials of p.Ap and
 // n_rr of ||r||^2, counts the iteration and takes the stopping decision.

@@ -1,0 +1,88 @@
+"""The condition-number study harness on the GPU: K(P_ad) and iteration
+counts against the oracle's CG on the same problems, plain CG (K(A_h))
+against the oracle, and the trends the analysis predicts (Sec. 5 condition
+number bound K = O(H^2/h^2), flat in aligned coefficient jumps)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_run(P, identity=False):
+    from oracle import OracleSolver
+    from oracle.pcg import pcg
+
+    orc = OracleSolver(P)
+    if identity:
+        _, info = pcg(orc.A, orc.b, lambda r: r.copy(), rtol=1e-8, max_iter=20000)
+    else:
+        _, info = orc.solve(rtol=1e-8)
+    return info
+
+
+def _check(gpu, info):
+    Ko = info.condition_estimate()
+    print(f"K gpu={gpu.K:.6g} oracle={Ko:.6g} iterations gpu={gpu.iterations} oracle={info.iterations}")
+    assert abs(gpu.iterations - info.iterations) <= 1
+    # both estimates come from the same CG coefficients up to rounding
+    assert abs(gpu.K / Ko - 1.0) <= 1e-6
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_study_nested_K_matches_oracle(p):
+    from paper_1903_11357_amd import study
+
+    mesh = study.fine_grid(256, 3)
+    P = study.per_element(mesh, p, coarse_of_cell=study.agglomerates(mesh, 4))
+    _check(study.run(P), _oracle_run(P))
+
+
+def test_study_nonnested_K_matches_oracle():
+    from paper_1903_11357_amd import study
+
+    mesh = study.fine_grid(300, 4)
+    P = study.per_element(mesh, 1, coarse_mesh=study.fine_grid(20, 5))
+    _check(study.run(P), _oracle_run(P))
+
+
+def test_study_plain_cg_K_of_A_matches_oracle():
+    from paper_1903_11357_amd import study
+
+    mesh = study.fine_grid(200, 6)
+    P = study.per_element(mesh, 2, coarse_of_cell=study.agglomerates(mesh, 2))
+    _check(study.run(P, identity=True), _oracle_run(P, identity=True))
+
+
+def test_example2_trends():
+    """Fixed H, h halved: K grows (about 4x); fixed H/h: K about constant."""
+    from paper_1903_11357_amd import study
+
+    table, plain = study.example2(p=1, n_finest=1024, levels=3)
+    print(study.table_example2(1, table, plain, 3))
+    assert all(r.converged for r in table.values())
+    # rows: (m, k) -> (m, k-1) halves h at fixed H
+    for (m, k), r in table.items():
+        if (m, k - 1) in table:
+            ratio = table[(m, k - 1)].K / r.K
+            assert 2.0 < ratio < 8.0, ((m, k), ratio)
+    # diagonals: H/h = 2^(m-k) fixed
+    for d in (1, 2):
+        ks = [table[(k + d, k)].K for k in range(3) if (k + d, k) in table]
+        assert max(ks) / min(ks) < 2.0, (d, ks)
+    # plain CG: K(A_h) grows like h^-2 (4x per halving asymptotically; the
+    # 64-element grid is pre-asymptotic), not like h^-1 or h^-3
+    for k in (1, 2):
+        ratio = plain[k - 1].K / plain[k].K
+        assert 2.5 < ratio < 7.5, (k, ratio)
+
+
+def test_example1_alignment():
+    """Jumps aligned with the coarse agglomerates leave K flat; jumps across
+    fine elements make it grow with rho_e."""
+    from paper_1903_11357_amd import study
+
+    res = study.example1(p=1, n_fine=400, bins=4, rho_e=(1e1, 1e4))
+    al, na = res["aligned"], res["not aligned"]
+    print({k: (al[k].K, na[k].K) for k in al})
+    assert al[1e4].K / al[1e1].K < 2.0
+    assert na[1e4].K / na[1e1].K > 100.0
