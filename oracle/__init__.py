@@ -15,6 +15,7 @@ Modules follow the paper's structure:
   clip        -- convex polygon intersection for non-nested coarse meshes
   schwarz     -- local solvers, coarse space, L2 prolongation, Galerkin A_0 (Sec. 3)
   pcg         -- ASPCG and the Lanczos condition estimate (Sec. 7 protocol)
+  tet         -- the 3D case: tetrahedra, triangle faces, nested coarse transfer
 
 Pinning status of every function is listed in each module header.
 """

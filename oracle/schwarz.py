@@ -120,10 +120,12 @@ class TwoLevelSchwarz:
     """M^{-1} = P_0 A_0^{-1} P_0^T + sum_i R_i^T A_i^{-1} R_i."""
 
     def __init__(self, A, mesh, p, geo, subdomain, q=None, coarse_of_cell=None,
-                 coarse_mesh=None, coarse=True, local=True):
+                 coarse_mesh=None, coarse=True, local=True, P0=None, npb=None):
+        """P0 (with npb, the DoFs per cell): a prolongation built elsewhere
+        (the 3D nested transfer of oracle/tet.py)."""
         self.A = A
         self.n = A.shape[0]
-        self.npb = n_basis(p)
+        self.npb = n_basis(p) if npb is None else npb
         self.dofs = subdomain_dofs(np.asarray(subdomain), self.npb) if local else []
         self.factors = []
         for d in self.dofs:
@@ -131,7 +133,9 @@ class TwoLevelSchwarz:
             self.factors.append(la.cho_factor(Ai, lower=True))
         self.P0 = None
         if coarse:
-            if coarse_mesh is not None:
+            if P0 is not None:
+                self.P0, self.cbox = P0, None
+            elif coarse_mesh is not None:
                 self.P0, self.cbox = prolongation_nonnested(mesh, p, q, geo, coarse_mesh)
             else:
                 self.P0, self.cbox = prolongation_nested(mesh, p, q, geo, np.asarray(coarse_of_cell))

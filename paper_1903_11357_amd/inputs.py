@@ -285,7 +285,13 @@ class Problem:
         return int(self.subdomain.max()) + 1
 
     @property
+    def dim(self) -> int:
+        return getattr(self.mesh, "dim", 2)
+
+    @property
     def n_p(self) -> int:
+        if self.dim == 3:
+            return (self.p + 1) * (self.p + 2) * (self.p + 3) // 6
         return (self.p + 1) * (self.p + 2) // 2
 
     @property
@@ -326,6 +332,122 @@ def voronoi_problem(n_cells: int, seed: int, p: int, bx: int, by: int, q: int,
     return Problem(name=name, mesh=mesh, p=p, c_sigma=10.0, rho=rho, subdomain=sub,
                    q=q, coarse_of_cell=None if coarse_mesh is not None else sub.copy(),
                    coarse_mesh=coarse_mesh, f=f)
+
+
+# ---------------------------------------------------------------- 3D (tetrahedra)
+@dataclasses.dataclass
+class TetMesh:
+    """Conforming tetrahedral mesh: shared vertex ids, four per cell."""
+
+    xyz: np.ndarray   # [n_vertices, 3] float64
+    tets: np.ndarray  # [n_cells, 4] int32
+    dim: int = 3
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.tets.shape[0])
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def vertex_mean(self) -> np.ndarray:
+        return self.xyz[self.tets].mean(axis=1)
+
+
+# the six orderings of the axes; Kuhn simplex s of a cube walks from its
+# lowest to its highest corner along the axes in the order KUHN[s]
+KUHN = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def cube_tet_mesh(n: int, jitter: float = 0.0, seed: int = 0) -> TetMesh:
+    """The unit cube as n^3 cubes of 6 Kuhn tetrahedra each (6 n^3 cells;
+    cell 6 c + s is simplex s of cube c = (k n + j) n + i). Kuhn
+    triangulations of the n- and 2n-grids are nested, so the tetrahedra of
+    a coarser grid are agglomerates of finer ones. jitter > 0 moves interior
+    vertices by U[-jitter, jitter] h per coordinate (h = 1/n)."""
+    g = np.arange(n + 1) / n
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        inner = np.all((xyz > 0.5 / n) & (xyz < 1.0 - 0.5 / n), axis=1)
+        xyz[inner] += rng.uniform(-jitter, jitter, size=(int(inner.sum()), 3)) / n
+
+    def vid(i, j, k):
+        return (k * (n + 1) + j) * (n + 1) + i
+
+    ii, jj, kk = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    i0, j0, k0 = kk.ravel(), jj.ravel(), ii.ravel()  # cube c = (k n + j) n + i
+    order = np.argsort((k0 * n + j0) * n + i0, kind="stable")
+    i0, j0, k0 = i0[order], j0[order], k0[order]
+    tets = np.empty((n ** 3, 6, 4), dtype=np.int64)
+    for s, ax in enumerate(KUHN):
+        c = np.stack([i0, j0, k0], axis=1)
+        verts = [vid(c[:, 0], c[:, 1], c[:, 2])]
+        for a in ax:
+            c = c.copy()
+            c[:, a] += 1
+            verts.append(vid(c[:, 0], c[:, 1], c[:, 2]))
+        tets[:, s, :] = np.stack(verts, axis=1)
+    tets = tets.reshape(-1, 4)
+    P = xyz[tets]
+    det = np.einsum("ij,ij->i", np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), P[:, 3] - P[:, 0])
+    flip = det < 0
+    tets[flip, 1], tets[flip, 2] = tets[flip, 2].copy(), tets[flip, 1].copy()
+    if jitter > 0.0 and np.abs(det).min() < 0.2 / (6.0 * n ** 3):
+        raise ValueError("jitter too large: a tetrahedron nearly degenerates")
+    return TetMesh(xyz=xyz, tets=tets.astype(np.int32))
+
+
+def kuhn_agglomerates(mesh: TetMesh, n_coarse: int) -> np.ndarray:
+    """Coarse id of every tetrahedron: the Kuhn tetrahedron of the
+    n_coarse-grid that contains its centroid (6 n_coarse^3 nested
+    agglomerates when the fine grid refines the coarse one)."""
+    c = mesh.vertex_mean() * n_coarse
+    cube = np.minimum(np.floor(c).astype(np.int64), n_coarse - 1)
+    fr = c - cube
+    order = np.argsort(-fr, axis=1, kind="stable")  # axes by decreasing fractional part
+    perm_id = {ax: s for s, ax in enumerate(KUHN)}
+    s = np.array([perm_id[tuple(o)] for o in order.tolist()], dtype=np.int64)
+    cid = (cube[:, 2] * n_coarse + cube[:, 1]) * n_coarse + cube[:, 0]
+    return (6 * cid + s).astype(np.int32)
+
+
+def box_agglomerates(mesh: TetMesh, b: int) -> np.ndarray:
+    """Coarse id of every tetrahedron: its centroid's cell of a b^3 grid of
+    boxes (non-empty boxes renumbered consecutively)."""
+    c = np.minimum(np.floor(mesh.vertex_mean() * b).astype(np.int64), b - 1)
+    return compact_labels(((c[:, 2] * b + c[:, 1]) * b + c[:, 0]).astype(np.int32))
+
+
+def f_sin3(p: np.ndarray) -> np.ndarray:
+    """f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) (u = sin sin sin, rho = 1)."""
+    return 3.0 * np.pi ** 2 * np.sin(np.pi * p[..., 0]) * np.sin(np.pi * p[..., 1]) * np.sin(np.pi * p[..., 2])
+
+
+def u_sin3(p: np.ndarray) -> np.ndarray:
+    return np.sin(np.pi * p[..., 0]) * np.sin(np.pi * p[..., 1]) * np.sin(np.pi * p[..., 2])
+
+
+def grad_u_sin3(p: np.ndarray) -> np.ndarray:
+    s = np.sin(np.pi * p)
+    c = np.cos(np.pi * p)
+    return np.pi * np.stack([c[..., 0] * s[..., 1] * s[..., 2], s[..., 0] * c[..., 1] * s[..., 2],
+                             s[..., 0] * s[..., 1] * c[..., 2]], axis=-1)
+
+
+def tet_problem(n: int, p: int, n_coarse: int, q: Optional[int] = None, per_element: bool = True,
+                sub_boxes: int = 0, jitter: float = 0.0, seed: int = 0, f=f_sin3, name: str = "tet") -> Problem:
+    """Cube of 6 n^3 Kuhn tetrahedra, coarse grid = the 6 n_coarse^3 Kuhn
+    tetrahedra of the n_coarse-grid (nested agglomerates, n divisible by
+    n_coarse); subdomains: one element each, or sub_boxes^3 boxes."""
+    mesh = cube_tet_mesh(n, jitter=jitter, seed=seed)
+    sub = (np.arange(mesh.n_cells, dtype=np.int32) if per_element or not sub_boxes
+           else box_agglomerates(mesh, sub_boxes))
+    return Problem(name=name, mesh=mesh, p=p, c_sigma=10.0, rho=np.ones(mesh.n_cells), subdomain=sub,
+                   q=p if q is None else q, coarse_of_cell=kuhn_agglomerates(mesh, n_coarse), coarse_mesh=None,
+                   f=f)
 
 
 def make_config(name: str) -> Problem:
