@@ -78,7 +78,19 @@ typedef struct {
   const int32_t* cell_vertices;  /* [cell_ptr[n_cells]]                     */
 } asdg_mesh;
 
-/* Vectorised right-hand side: out[k] = f(xy[2k], xy[2k+1]) for k < n. */
+/* Conforming tetrahedral mesh (the 3D case of Sec. 2): cell c has the
+ * vertices tets[4c .. 4c+3]; neighbouring cells share vertex ids and whole
+ * triangular faces; unmatched faces must lie on the bounding box of the
+ * vertices (a box-shaped domain). Any vertex order. */
+typedef struct {
+  int32_t n_vertices;
+  const double* xyz;     /* [n_vertices][3]                                 */
+  int32_t n_cells;
+  const int32_t* tets;   /* [n_cells][4]                                    */
+} asdg_tet_mesh;
+
+/* Vectorised right-hand side: out[k] = f(xy[2k], xy[2k+1]) for k < n
+ * (tetrahedral meshes: f(xyz[3k], xyz[3k+1], xyz[3k+2])). */
 typedef void (*asdg_field_fn)(int64_t n, const double* xy, double* out, void* user);
 
 typedef struct {
@@ -121,6 +133,18 @@ const char* asdg_last_error(const asdg_problem* pb);
 asdg_status asdg_assemble(asdg_problem* pb, const asdg_mesh* fine, int32_t p, double c_sigma,
                           const double* rho, const int32_t* subdomain, asdg_field_fn f,
                           void* f_user);
+
+/* Host-side SIPG assembly on a tetrahedral mesh (Sec. 2 for d = 3: the
+ * same flux form and penalty, triangular faces, h = cell diameter, n_p =
+ * (p+1)(p+2)(p+3)/6). p: 1 <= p <= 3; other arguments as asdg_assemble. The
+ * coarse space of such a problem must be given by coarse_of_cell (nested
+ * agglomerates of the tetrahedra) in asdg_plan.
+ * Errors: EINVAL for p or c_sigma out of range, non-positive rho, a
+ * degenerate tetrahedron, a face shared by more than two cells or an
+ * unmatched face inside the domain, or an unused subdomain id. */
+asdg_status asdg_assemble_tet(asdg_problem* pb, const asdg_tet_mesh* fine, int32_t p, double c_sigma,
+                              const double* rho, const int32_t* subdomain, asdg_field_fn f,
+                              void* f_user);
 
 /* Coarse space choice and device footprint (Sec. 3, V_0, eqs. (R0T), (A0)).
  * precision:      local factor precision.

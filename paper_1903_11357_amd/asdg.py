@@ -45,6 +45,11 @@ class PcgStats(C.Structure):
                 ("t_local_ms", C.c_double), ("n_local", C.c_int32), ("failed_subdomain", C.c_int32)]
 
 
+class TetMesh_(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("xyz", C.POINTER(C.c_double)), ("n_cells", C.c_int32),
+                ("tets", C.POINTER(C.c_int32))]
+
+
 FIELD_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
 
 _lib = None
@@ -56,6 +61,8 @@ _SIGS = {
     "asdg_last_error": (C.c_char_p, [C.c_void_p]),
     "asdg_assemble": (C.c_int, [C.c_void_p, C.POINTER(Mesh_), C.c_int32, C.c_double, C.POINTER(C.c_double),
                                 C.POINTER(C.c_int32), FIELD_FN, C.c_void_p]),
+    "asdg_assemble_tet": (C.c_int, [C.c_void_p, C.POINTER(TetMesh_), C.c_int32, C.c_double, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int32), FIELD_FN, C.c_void_p]),
     "asdg_plan": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Mesh_),
                             C.POINTER(C.c_size_t)]),
     "asdg_bind": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t), C.c_void_p]),
@@ -143,19 +150,30 @@ class Problem:
 
     # ---------------------------------------------------------------- setup
     def assemble(self, mesh, p: int, c_sigma: float, rho, subdomain, f: Optional[Callable] = None):
-        m, keep = _mesh_struct(mesh)
+        dim = getattr(mesh, "dim", 2)
         rho = np.ascontiguousarray(rho, dtype=np.float64)
         sub = np.ascontiguousarray(subdomain, dtype=np.int32)
 
         def cb(n, xy_p, out_p, user):
-            xy = np.ctypeslib.as_array(xy_p, shape=(n, 2))
+            xy = np.ctypeslib.as_array(xy_p, shape=(n, dim))
             out = np.ctypeslib.as_array(out_p, shape=(n,))
             out[:] = f(xy) if f is not None else 0.0
 
         self._cb = FIELD_FN(cb)
-        self._check(self._L.asdg_assemble(self.h, C.byref(m), p, c_sigma, _dptr(rho, C.c_double),
-                                          _dptr(sub, C.c_int32), self._cb, None))
-        self._subsizes = np.bincount(sub) * ((p + 1) * (p + 2) // 2)
+        if dim == 3:
+            xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+            tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+            m = TetMesh_(xyz.shape[0], _dptr(xyz, C.c_double), tets.shape[0], _dptr(tets, C.c_int32))
+            keep = (xyz, tets)
+            self._check(self._L.asdg_assemble_tet(self.h, C.byref(m), p, c_sigma, _dptr(rho, C.c_double),
+                                                  _dptr(sub, C.c_int32), self._cb, None))
+            npb = (p + 1) * (p + 2) * (p + 3) // 6
+        else:
+            m, keep = _mesh_struct(mesh)
+            self._check(self._L.asdg_assemble(self.h, C.byref(m), p, c_sigma, _dptr(rho, C.c_double),
+                                              _dptr(sub, C.c_int32), self._cb, None))
+            npb = (p + 1) * (p + 2) // 2
+        self._subsizes = np.bincount(sub) * npb
         del keep
         info = self.info()
         self.n_cells, self.n_p, self.n = int(info[0]), int(info[1]), int(info[2])

@@ -69,6 +69,16 @@ void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e
 }
 
 // Copy of a caller mesh (the fine mesh is needed again by asdg_plan).
+struct TetCopy {
+  std::vector<double> xyz;
+  std::vector<int32_t> tets;
+  void assign(const asdg_tet_mesh& m) {
+    xyz.assign(m.xyz, m.xyz + 3 * (size_t)m.n_vertices);
+    tets.assign(m.tets, m.tets + 4 * (size_t)m.n_cells);
+  }
+  TetView view() const { return TetView{(int32_t)(xyz.size() / 3), xyz.data(), (int32_t)(tets.size() / 4), tets.data()}; }
+};
+
 struct MeshCopy {
   std::vector<double> xy;
   std::vector<int32_t> ptr, verts;
@@ -87,6 +97,7 @@ struct MeshCopy {
 struct asdg_problem {
   std::string err;
   MeshCopy fine;
+  TetCopy tet;  // 3D fine mesh (A.dim == 3)
   int stage = 0;  // 1 assembled, 2 planned, 3 bound, 4 factored
   bool coarse_ready = false;
   Assembled A;
@@ -199,6 +210,28 @@ asdg_status asdg_assemble(asdg_problem* pb, const asdg_mesh* fine, int32_t p, do
   for (int32_t r = 0; r < pb->A.n_cells; ++r)
     for (int a = 0; a < np; ++a) pb->rhs_caller[(size_t)pb->A.perm[r] * np + a] = pb->A.rhs[(size_t)r * np + a];
   pb->fine.assign(*fine);  // kept for the coarse transfer
+  pb->tet = TetCopy();
+  pb->stage = 1;
+  return ASDG_OK;
+}
+
+asdg_status asdg_assemble_tet(asdg_problem* pb, const asdg_tet_mesh* fine, int32_t p, double c_sigma,
+                              const double* rho, const int32_t* subdomain, asdg_field_fn f, void* f_user) {
+  if (!pb) return ASDG_EINVAL;
+  if (!fine || !fine->xyz || !fine->tets || !rho || !subdomain || fine->n_cells < 1 || fine->n_vertices < 4)
+    FAIL(pb, ASDG_EINVAL, "null or empty input");
+  pb->drop_graph();
+  pb->stage = 0;
+  pb->coarse_ready = false;
+  TetView tv{fine->n_vertices, fine->xyz, fine->n_cells, fine->tets};
+  std::string e = assemble_sipg_tet(tv, p, c_sigma, rho, subdomain, f, f_user, pb->A);
+  if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
+  const int np = pb->A.np;
+  pb->rhs_caller.assign(pb->A.rhs.size(), 0.0);
+  for (int32_t r = 0; r < pb->A.n_cells; ++r)
+    for (int a = 0; a < np; ++a) pb->rhs_caller[(size_t)pb->A.perm[r] * np + a] = pb->A.rhs[(size_t)r * np + a];
+  pb->tet.assign(*fine);  // kept for the coarse transfer
+  pb->fine = MeshCopy();
   pb->stage = 1;
   return ASDG_OK;
 }
@@ -614,7 +647,13 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
       cm = MeshView{coarse_mesh->n_vertices, coarse_mesh->xy, coarse_mesh->n_cells, coarse_mesh->cell_ptr,
                     coarse_mesh->cell_vertices};
     }
-    std::string e = build_coarse(pb->fine.view(), pb->A, q, coarse_of_cell, coarse_mesh ? &cm : nullptr, pb->C);
+    std::string e;
+    if (pb->A.dim == 3) {
+      if (coarse_mesh) FAIL(pb, ASDG_EINVAL, "tetrahedral meshes take nested agglomerates (coarse_of_cell)");
+      e = build_coarse_tet(pb->tet.view(), pb->A, q, coarse_of_cell, pb->C);
+    } else {
+      e = build_coarse(pb->fine.view(), pb->A, q, coarse_of_cell, coarse_mesh ? &cm : nullptr, pb->C);
+    }
     if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
     pb->n0 = pb->C.n_coarse * pb->C.nq;
     plan_coarse_factor(pb);

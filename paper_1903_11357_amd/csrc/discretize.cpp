@@ -32,8 +32,6 @@
 
 namespace asdg {
 
-namespace {
-
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
   unsigned hw = std::thread::hardware_concurrency();
   int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 16));
@@ -50,6 +48,8 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
   }
   for (auto& x : th) x.join();
 }
+
+namespace {
 
 struct QuadPoint {
   double x, y, w;
@@ -139,6 +139,8 @@ std::vector<double> clip_polygon(const std::vector<double>& subject, const std::
 }
 
 // Small dense SPD solve (Cholesky), matrix n x n row-major, rhs n x k.
+}  // namespace
+
 bool spd_solve(int n, std::vector<double> M, double* B, int k) {
   for (int j = 0; j < n; ++j) {
     double d = M[j * n + j];
@@ -166,6 +168,8 @@ bool spd_solve(int n, std::vector<double> M, double* B, int k) {
   }
   return true;
 }
+
+namespace {
 
 bool on_boundary_side(double ax, double ay, double bx, double by) {
   const double tol = 1e-12;
@@ -337,6 +341,119 @@ void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx
   }
 }
 
+// Subdomain-major permutation (stable), BSR structure and rows of the SIPG
+// system from per-cell volume blocks vol [N][np*np] and loads rhs_c [N][np]
+// (caller order) and per-face blocks fblk [F][4][np*np] of the faces
+// pm = (plus, minus) (minus < 0: boundary face, block 0 only). Rows add the
+// volume block, then the cell's faces in face-index order (deterministic).
+std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::vector<std::pair<int32_t, int32_t>>& pm,
+                            const std::vector<double>& vol, const std::vector<double>& rhs_c,
+                            const std::vector<double>& fblk) {
+  const int32_t N = A.n_cells;
+  const int np = A.np;
+  // subdomains and subdomain-major permutation (stable)
+  int32_t nsub = 0;
+  for (int32_t c = 0; c < N; ++c) {
+    if (subdomain[c] < 0) return "negative subdomain id";
+    nsub = std::max(nsub, subdomain[c] + 1);
+  }
+  A.n_sub = nsub;
+  A.sub_ptr.assign(nsub + 1, 0);
+  for (int32_t c = 0; c < N; ++c) A.sub_ptr[subdomain[c] + 1]++;
+  for (int32_t i = 0; i < nsub; ++i) {
+    if (A.sub_ptr[i + 1] == 0) return "subdomain id " + std::to_string(i) + " is unused";
+    A.sub_ptr[i + 1] += A.sub_ptr[i];
+  }
+  A.perm.assign(N, 0);
+  A.iperm.assign(N, 0);
+  {
+    std::vector<int32_t> fill(A.sub_ptr.begin(), A.sub_ptr.end() - 1);
+    for (int32_t c = 0; c < N; ++c) {
+      int32_t r = fill[subdomain[c]]++;
+      A.perm[r] = c;
+      A.iperm[c] = r;
+    }
+  }
+
+  // per-cell face lists (caller order), in face-index order
+  std::vector<int32_t> cf_ptr(N + 1, 0);
+  for (const auto& F : pm) {
+    cf_ptr[F.first + 1]++;
+    if (F.second >= 0) cf_ptr[F.second + 1]++;
+  }
+  for (int32_t c = 0; c < N; ++c) cf_ptr[c + 1] += cf_ptr[c];
+  std::vector<int32_t> cf(cf_ptr[N]);
+  {
+    std::vector<int32_t> fill(cf_ptr.begin(), cf_ptr.end() - 1);
+    for (int32_t fidx = 0; fidx < (int32_t)pm.size(); ++fidx) {
+      const auto& F = pm[fidx];
+      cf[fill[F.first]++] = 2 * fidx;  // side +
+      if (F.second >= 0) cf[fill[F.second]++] = 2 * fidx + 1;  // side -
+    }
+  }
+
+  // BSR structure, internal order
+  A.row_ptr.assign(N + 1, 0);
+  std::vector<std::vector<int32_t>> cols(N);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      int32_t c = A.perm[r];
+      auto& cl = cols[r];
+      cl.push_back((int32_t)r);
+      for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
+        const auto& F = pm[cf[k] >> 1];
+        if (F.second < 0) continue;
+        int32_t other = (cf[k] & 1) ? F.first : F.second;
+        cl.push_back(A.iperm[other]);
+      }
+      std::sort(cl.begin(), cl.end());
+      cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+    }
+  });
+  for (int32_t r = 0; r < N; ++r) A.row_ptr[r + 1] = A.row_ptr[r] + (int32_t)cols[r].size();
+  A.col_idx.resize(A.row_ptr[N]);
+  for (int32_t r = 0; r < N; ++r) std::copy(cols[r].begin(), cols[r].end(), A.col_idx.begin() + A.row_ptr[r]);
+  cols.clear();
+  cols.shrink_to_fit();
+
+  // accumulate rows (internal order), deterministic order: volume, then the
+  // cell's faces in face-index order
+  A.blocks.assign((size_t)A.row_ptr[N] * np * np, 0.0);
+  A.rhs.assign((size_t)N * np, 0.0);
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      int32_t c = A.perm[r];
+      int32_t rs = A.row_ptr[r], re = A.row_ptr[r + 1];
+      auto slot = [&](int32_t col) {
+        int32_t k = (int32_t)(std::lower_bound(A.col_idx.begin() + rs, A.col_idx.begin() + re, col) -
+                              A.col_idx.begin());
+        return &A.blocks[(size_t)k * np * np];
+      };
+      double* D = slot((int32_t)r);
+      const double* Vb = &vol[(size_t)c * np * np];
+      for (int e = 0; e < np * np; ++e) D[e] += Vb[e];
+      for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
+        int32_t fi = cf[k] >> 1;
+        int t = cf[k] & 1;
+        const auto& F = pm[fi];
+        const double* Bk = &fblk[(size_t)fi * 4 * np * np];
+        if (F.second < 0) {
+          for (int e = 0; e < np * np; ++e) D[e] += Bk[e];
+          continue;
+        }
+        const double* Btt = Bk + (t * 2 + t) * np * np;
+        for (int e = 0; e < np * np; ++e) D[e] += Btt[e];
+        int32_t other = t ? F.first : F.second;
+        double* O = slot(A.iperm[other]);
+        const double* Bts = Bk + (t * 2 + (1 - t)) * np * np;
+        for (int e = 0; e < np * np; ++e) O[e] += Bts[e];
+      }
+      for (int a = 0; a < np; ++a) A.rhs[(size_t)r * np + a] = rhs_c[(size_t)c * np + a];
+    }
+  });
+  return "";
+}
+
 std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const double* rho,
                           const int32_t* subdomain,
                           void (*f)(int64_t, const double*, double*, void*), void* f_user,
@@ -347,6 +464,9 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   if (N < 1) return "empty mesh";
   for (int32_t c = 0; c < N; ++c)
     if (!(rho[c] > 0.0) || !std::isfinite(rho[c])) return "rho must be positive and finite";
+  A.dim = 2;
+  A.box3.clear();
+  A.diam3.clear();
   A.p = p;
   A.np = n_basis(p);
   A.c_sigma = c_sigma;
@@ -384,71 +504,6 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
         !on_boundary_side(mesh.xy[2 * F.v0], mesh.xy[2 * F.v0 + 1], mesh.xy[2 * F.v1], mesh.xy[2 * F.v1 + 1]))
       return "non-conforming mesh: unmatched edge inside the domain";
   }
-
-  // subdomains and subdomain-major permutation (stable)
-  int32_t nsub = 0;
-  for (int32_t c = 0; c < N; ++c) {
-    if (subdomain[c] < 0) return "negative subdomain id";
-    nsub = std::max(nsub, subdomain[c] + 1);
-  }
-  A.n_sub = nsub;
-  A.sub_ptr.assign(nsub + 1, 0);
-  for (int32_t c = 0; c < N; ++c) A.sub_ptr[subdomain[c] + 1]++;
-  for (int32_t i = 0; i < nsub; ++i) {
-    if (A.sub_ptr[i + 1] == 0) return "subdomain id " + std::to_string(i) + " is unused";
-    A.sub_ptr[i + 1] += A.sub_ptr[i];
-  }
-  A.perm.assign(N, 0);
-  A.iperm.assign(N, 0);
-  {
-    std::vector<int32_t> fill(A.sub_ptr.begin(), A.sub_ptr.end() - 1);
-    for (int32_t c = 0; c < N; ++c) {
-      int32_t r = fill[subdomain[c]]++;
-      A.perm[r] = c;
-      A.iperm[c] = r;
-    }
-  }
-
-  // per-cell face lists (caller order), in face-index order
-  std::vector<int32_t> cf_ptr(N + 1, 0);
-  for (const Face& F : A.faces) {
-    cf_ptr[F.plus + 1]++;
-    if (F.minus >= 0) cf_ptr[F.minus + 1]++;
-  }
-  for (int32_t c = 0; c < N; ++c) cf_ptr[c + 1] += cf_ptr[c];
-  std::vector<int32_t> cf(cf_ptr[N]);
-  {
-    std::vector<int32_t> fill(cf_ptr.begin(), cf_ptr.end() - 1);
-    for (int32_t fidx = 0; fidx < (int32_t)A.faces.size(); ++fidx) {
-      const Face& F = A.faces[fidx];
-      cf[fill[F.plus]++] = 2 * fidx;  // side +
-      if (F.minus >= 0) cf[fill[F.minus]++] = 2 * fidx + 1;  // side -
-    }
-  }
-
-  // BSR structure, internal order
-  A.row_ptr.assign(N + 1, 0);
-  std::vector<std::vector<int32_t>> cols(N);
-  parallel_for(N, [&](int64_t lo, int64_t hi) {
-    for (int64_t r = lo; r < hi; ++r) {
-      int32_t c = A.perm[r];
-      auto& cl = cols[r];
-      cl.push_back((int32_t)r);
-      for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
-        const Face& F = A.faces[cf[k] >> 1];
-        if (F.minus < 0) continue;
-        int32_t other = (cf[k] & 1) ? F.plus : F.minus;
-        cl.push_back(A.iperm[other]);
-      }
-      std::sort(cl.begin(), cl.end());
-      cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
-    }
-  });
-  for (int32_t r = 0; r < N; ++r) A.row_ptr[r + 1] = A.row_ptr[r] + (int32_t)cols[r].size();
-  A.col_idx.resize(A.row_ptr[N]);
-  for (int32_t r = 0; r < N; ++r) std::copy(cols[r].begin(), cols[r].end(), A.col_idx.begin() + A.row_ptr[r]);
-  cols.clear();
-  cols.shrink_to_fit();
 
   const int m = p + 2;
   std::vector<double> gq, wq;
@@ -556,42 +611,95 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
     }
   });
 
-  // accumulate rows (internal order), deterministic order: volume, then the
-  // cell's faces in face-index order
-  A.blocks.assign((size_t)A.row_ptr[N] * np * np, 0.0);
-  A.rhs.assign((size_t)N * np, 0.0);
+  std::vector<std::pair<int32_t, int32_t>> pm(A.faces.size());
+  for (size_t fi = 0; fi < A.faces.size(); ++fi) pm[fi] = {A.faces[fi].plus, A.faces[fi].minus};
+  return finish_assembly(A, subdomain, pm, vol, rhs_c, fblk);
+}
+
+// P_0 as CSR by internal fine cell from per-caller-cell block lists
+// (coarse cells bcol[c], np x nq blocks bval[c]), its transposed lists, and
+// the Galerkin A_0 = P_0^T A P_0 (dense). C.q, C.nq, C.n_coarse are set.
+void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& bcol,
+                   const std::vector<std::vector<double>>& bval, Coarse& C) {
+  const int32_t N = A.n_cells;
+  const int np = A.np, nq = C.nq;
+  // CSR by internal fine cell
+  C.ptr.assign(N + 1, 0);
+  for (int32_t r = 0; r < N; ++r) C.ptr[r + 1] = C.ptr[r] + (int32_t)bcol[A.perm[r]].size();
+  C.col.resize(C.ptr[N]);
+  C.val.resize((size_t)C.ptr[N] * np * nq);
+  for (int32_t r = 0; r < N; ++r) {
+    int32_t c = A.perm[r];
+    std::copy(bcol[c].begin(), bcol[c].end(), C.col.begin() + C.ptr[r]);
+    std::copy(bval[c].begin(), bval[c].end(), C.val.begin() + (size_t)C.ptr[r] * np * nq);
+  }
+  // transposed lists (coarse cell -> entries in increasing fine order)
+  const int32_t nc = C.n_coarse;
+  C.tptr.assign(nc + 1, 0);
+  for (int32_t e = 0; e < C.ptr[N]; ++e) C.tptr[C.col[e] + 1]++;
+  for (int32_t j = 0; j < nc; ++j) C.tptr[j + 1] += C.tptr[j];
+  C.tcell.resize(C.ptr[N]);
+  C.tblk.resize(C.ptr[N]);
+  {
+    std::vector<int32_t> fill(C.tptr.begin(), C.tptr.end() - 1);
+    for (int32_t r = 0; r < N; ++r)
+      for (int32_t e = C.ptr[r]; e < C.ptr[r + 1]; ++e) {
+        int32_t k = fill[C.col[e]]++;
+        C.tcell[k] = r;
+        C.tblk[k] = e;
+      }
+  }
+
+  // Galerkin A_0 = P_0^T A P_0. W_r = sum over row blocks A[r, s] P_0[s, :]
+  // (per fine row, sparse over coarse cells), then rows of A_0 per coarse cell.
+  std::vector<std::vector<int32_t>> wcol(N);
+  std::vector<std::vector<double>> wval(N);
   parallel_for(N, [&](int64_t lo, int64_t hi) {
     for (int64_t r = lo; r < hi; ++r) {
-      int32_t c = A.perm[r];
-      int32_t rs = A.row_ptr[r], re = A.row_ptr[r + 1];
-      auto slot = [&](int32_t col) {
-        int32_t k = (int32_t)(std::lower_bound(A.col_idx.begin() + rs, A.col_idx.begin() + re, col) -
-                              A.col_idx.begin());
-        return &A.blocks[(size_t)k * np * np];
-      };
-      double* D = slot((int32_t)r);
-      const double* Vb = &vol[(size_t)c * np * np];
-      for (int e = 0; e < np * np; ++e) D[e] += Vb[e];
-      for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
-        int32_t fi = cf[k] >> 1;
-        int t = cf[k] & 1;
-        const Face& F = A.faces[fi];
-        const double* Bk = &fblk[(size_t)fi * 4 * np * np];
-        if (F.minus < 0) {
-          for (int e = 0; e < np * np; ++e) D[e] += Bk[e];
-          continue;
+      auto& wc = wcol[r];
+      auto& wv = wval[r];
+      for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
+        int32_t s = A.col_idx[k];
+        const double* Ab = &A.blocks[(size_t)k * np * np];
+        for (int32_t e = C.ptr[s]; e < C.ptr[s + 1]; ++e) {
+          int32_t J = C.col[e];
+          size_t pos = std::find(wc.begin(), wc.end(), J) - wc.begin();
+          if (pos == wc.size()) {
+            wc.push_back(J);
+            wv.resize(wv.size() + (size_t)np * nq, 0.0);
+          }
+          double* W = &wv[pos * np * nq];
+          const double* Pb = &C.val[(size_t)e * np * nq];
+          for (int a = 0; a < np; ++a)
+            for (int d = 0; d < nq; ++d) {
+              double acc = 0.0;
+              for (int b = 0; b < np; ++b) acc += Ab[b * np + a] * Pb[b * nq + d];
+              W[a * nq + d] += acc;
+            }
         }
-        const double* Btt = Bk + (t * 2 + t) * np * np;
-        for (int e = 0; e < np * np; ++e) D[e] += Btt[e];
-        int32_t other = t ? F.plus : F.minus;
-        double* O = slot(A.iperm[other]);
-        const double* Bts = Bk + (t * 2 + (1 - t)) * np * np;
-        for (int e = 0; e < np * np; ++e) O[e] += Bts[e];
       }
-      for (int a = 0; a < np; ++a) A.rhs[(size_t)r * np + a] = rhs_c[(size_t)c * np + a];
     }
   });
-  return "";
+  const int64_t n0 = (int64_t)nc * nq;
+  C.a0.assign((size_t)(n0 * n0), 0.0);
+  parallel_for(nc, [&](int64_t lo, int64_t hi) {
+    for (int64_t J = lo; J < hi; ++J) {
+      for (int32_t k = C.tptr[J]; k < C.tptr[J + 1]; ++k) {
+        int32_t r = C.tcell[k];
+        const double* Pb = &C.val[(size_t)C.tblk[k] * np * nq];
+        for (size_t t = 0; t < wcol[r].size(); ++t) {
+          int32_t K = wcol[r][t];
+          const double* W = &wval[r][t * np * nq];
+          for (int c = 0; c < nq; ++c)
+            for (int d = 0; d < nq; ++d) {
+              double acc = 0.0;
+              for (int a = 0; a < np; ++a) acc += Pb[a * nq + c] * W[a * nq + d];
+              C.a0[(size_t)(J * nq + c) * n0 + (size_t)K * nq + d] += acc;
+            }
+        }
+      }
+    }
+  });
 }
 
 std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const int32_t* coarse_of_cell,
@@ -709,83 +817,7 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
       if (bcol[c].empty()) return "fine cell " + std::to_string(c) + " not covered by the coarse mesh";
   }
 
-  // CSR by internal fine cell
-  C.ptr.assign(N + 1, 0);
-  for (int32_t r = 0; r < N; ++r) C.ptr[r + 1] = C.ptr[r] + (int32_t)bcol[A.perm[r]].size();
-  C.col.resize(C.ptr[N]);
-  C.val.resize((size_t)C.ptr[N] * np * nq);
-  for (int32_t r = 0; r < N; ++r) {
-    int32_t c = A.perm[r];
-    std::copy(bcol[c].begin(), bcol[c].end(), C.col.begin() + C.ptr[r]);
-    std::copy(bval[c].begin(), bval[c].end(), C.val.begin() + (size_t)C.ptr[r] * np * nq);
-  }
-  // transposed lists (coarse cell -> entries in increasing fine order)
-  const int32_t nc = C.n_coarse;
-  C.tptr.assign(nc + 1, 0);
-  for (int32_t e = 0; e < C.ptr[N]; ++e) C.tptr[C.col[e] + 1]++;
-  for (int32_t j = 0; j < nc; ++j) C.tptr[j + 1] += C.tptr[j];
-  C.tcell.resize(C.ptr[N]);
-  C.tblk.resize(C.ptr[N]);
-  {
-    std::vector<int32_t> fill(C.tptr.begin(), C.tptr.end() - 1);
-    for (int32_t r = 0; r < N; ++r)
-      for (int32_t e = C.ptr[r]; e < C.ptr[r + 1]; ++e) {
-        int32_t k = fill[C.col[e]]++;
-        C.tcell[k] = r;
-        C.tblk[k] = e;
-      }
-  }
-
-  // Galerkin A_0 = P_0^T A P_0. W_r = sum over row blocks A[r, s] P_0[s, :]
-  // (per fine row, sparse over coarse cells), then rows of A_0 per coarse cell.
-  std::vector<std::vector<int32_t>> wcol(N);
-  std::vector<std::vector<double>> wval(N);
-  parallel_for(N, [&](int64_t lo, int64_t hi) {
-    for (int64_t r = lo; r < hi; ++r) {
-      auto& wc = wcol[r];
-      auto& wv = wval[r];
-      for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
-        int32_t s = A.col_idx[k];
-        const double* Ab = &A.blocks[(size_t)k * np * np];
-        for (int32_t e = C.ptr[s]; e < C.ptr[s + 1]; ++e) {
-          int32_t J = C.col[e];
-          size_t pos = std::find(wc.begin(), wc.end(), J) - wc.begin();
-          if (pos == wc.size()) {
-            wc.push_back(J);
-            wv.resize(wv.size() + (size_t)np * nq, 0.0);
-          }
-          double* W = &wv[pos * np * nq];
-          const double* Pb = &C.val[(size_t)e * np * nq];
-          for (int a = 0; a < np; ++a)
-            for (int d = 0; d < nq; ++d) {
-              double acc = 0.0;
-              for (int b = 0; b < np; ++b) acc += Ab[b * np + a] * Pb[b * nq + d];
-              W[a * nq + d] += acc;
-            }
-        }
-      }
-    }
-  });
-  const int64_t n0 = (int64_t)nc * nq;
-  C.a0.assign((size_t)(n0 * n0), 0.0);
-  parallel_for(nc, [&](int64_t lo, int64_t hi) {
-    for (int64_t J = lo; J < hi; ++J) {
-      for (int32_t k = C.tptr[J]; k < C.tptr[J + 1]; ++k) {
-        int32_t r = C.tcell[k];
-        const double* Pb = &C.val[(size_t)C.tblk[k] * np * nq];
-        for (size_t t = 0; t < wcol[r].size(); ++t) {
-          int32_t K = wcol[r][t];
-          const double* W = &wval[r][t * np * nq];
-          for (int c = 0; c < nq; ++c)
-            for (int d = 0; d < nq; ++d) {
-              double acc = 0.0;
-              for (int a = 0; a < np; ++a) acc += Pb[a * nq + c] * W[a * nq + d];
-              C.a0[(size_t)(J * nq + c) * n0 + (size_t)K * nq + d] += acc;
-            }
-        }
-      }
-    }
-  });
+  finish_coarse(A, bcol, bval, C);
   return "";
 }
 

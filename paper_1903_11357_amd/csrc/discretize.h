@@ -3,13 +3,19 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace asdg {
 
 struct Box {
   double x0, x1, y0, y1;
+};
+
+struct Box3 {
+  double x0, x1, y0, y1, z0, z1;
 };
 
 // Polygon mesh view (caller's arrays).
@@ -50,8 +56,11 @@ struct Assembled {
   std::vector<int32_t> col_idx;
   std::vector<double> blocks;    // per block np*np, element (a,b) at b*np + a
   std::vector<double> rhs;       // internal order
-  CellGeom geom;                 // caller order
-  std::vector<Face> faces;       // caller cell ids
+  CellGeom geom;                 // caller order (2D)
+  std::vector<Face> faces;       // caller cell ids (2D)
+  int dim = 2;
+  std::vector<Box3> box3;        // caller order (3D)
+  std::vector<double> diam3;     // caller order (3D)
 };
 
 // Returns empty string on success, otherwise an error message.
@@ -76,5 +85,38 @@ struct Coarse {
 
 std::string build_coarse(const MeshView& fine, const Assembled& A, int q,
                          const int32_t* coarse_of_cell, const MeshView* coarse_mesh, Coarse& out);
+
+// ---- 3D: tetrahedral meshes (discretize3.cpp)
+// Tetrahedral mesh view (caller's arrays): tets [n_cells][4] vertex ids.
+struct TetView {
+  int32_t n_vertices;
+  const double* xyz;
+  int32_t n_cells;
+  const int32_t* tets;
+};
+
+// Scaled Legendre basis of total degree p on a box, ordered by degree d,
+// then k = 0..d, then j = 0..d-k, i = d-j-k (exponents of x, y, z).
+int n_basis3(int p);
+void basis_eval3(int p, const Box3& B, double x, double y, double z, double* val, double* gx, double* gy,
+                 double* gz);
+
+// 3D SIPG system; fills out.box3 / out.diam3 (caller order) and sets out.dim = 3.
+std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const double* rho,
+                              const int32_t* subdomain,
+                              void (*f)(int64_t, const double*, double*, void*), void* f_user, Assembled& out);
+
+// Nested coarse transfer for agglomerates of tetrahedra (coarse_of_cell).
+std::string build_coarse_tet(const TetView& fine, const Assembled& A, int q, const int32_t* coarse_of_cell,
+                             Coarse& out);
+
+// ---- shared by the 2D and 3D builders (internal)
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn);
+bool spd_solve(int n, std::vector<double> M, double* B, int k);
+std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::vector<std::pair<int32_t, int32_t>>& pm,
+                            const std::vector<double>& vol, const std::vector<double>& rhs_c,
+                            const std::vector<double>& fblk);
+void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& bcol,
+                   const std::vector<std::vector<double>>& bval, Coarse& C);
 
 }  // namespace asdg

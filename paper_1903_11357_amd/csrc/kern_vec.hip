@@ -328,6 +328,9 @@ hipError_t launch_spmv(int np, int32_t N, const int32_t* row_ptr, const int32_t*
     case 6: hipLaunchKernelGGL(k_spmv<6>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     case 10: hipLaunchKernelGGL(k_spmv<10>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     case 15: hipLaunchKernelGGL(k_spmv<15>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    // tetrahedra: p = 1, 3 (p = 2 shares n_p = 10 with p = 3 in 2D)
+    case 4: hipLaunchKernelGGL(k_spmv<4>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 20: hipLaunchKernelGGL(k_spmv<20>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -385,6 +388,7 @@ hipError_t launch_restrict(int np, int nq, int32_t nc, int splits, const int32_t
   if (splits < 1 || (int64_t)nc * splits > 0x7fffffff) return hipErrorInvalidValue;
 #define R_(A, B) ASDG_PQ_SWITCH(A, B, (restrict_t<A, B>(nc, splits, tptr, tcell, tblk, P, r, out, y0, z0, st, s)))
   R_(3, 3) R_(6, 3) R_(6, 6) R_(10, 3) R_(10, 6) R_(10, 10) R_(15, 3) R_(15, 6) R_(15, 10) R_(15, 15)
+  R_(4, 4) R_(10, 4) R_(20, 4) R_(20, 10) R_(20, 20)
 #undef R_
   return hipErrorInvalidValue;
 }
@@ -421,11 +425,12 @@ static void prolong_t(int32_t N, const int32_t* pptr, const int32_t* pcol, const
 hipError_t launch_prolong(int np, int nq, int32_t N, const int32_t* pptr, const int32_t* pcol, const double* P,
                           const double* z0, const void* zl, const LocalParts* lp, int f32, const double* r, double* z,
                           Reduction* red, DevState* st, int n_pq, int n_rr, hipStream_t s) {
-  if (!pptr) nq = 3;  // no coarse level: any instantiation, the loop is skipped
+  if (!pptr) nq = (np == 4 || np == 20) ? 4 : 3;  // no coarse level: any instantiation, the loop is skipped
   if (n_pq > 0 && (!red || !st)) return hipErrorInvalidValue;
 #define P_(A, B) \
   ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, lp, f32, r, z, red, st, n_pq, n_rr, s)))
   P_(3, 3) P_(6, 3) P_(6, 6) P_(10, 3) P_(10, 6) P_(10, 10) P_(15, 3) P_(15, 6) P_(15, 10) P_(15, 15)
+  P_(4, 4) P_(10, 4) P_(20, 4) P_(20, 10) P_(20, 20)
 #undef P_
   return hipErrorInvalidValue;
 }
