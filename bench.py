@@ -39,6 +39,12 @@ WORKLOADS = {
           "nested coarse = subdomains, q=2",
     "C4": "Voronoi 131072 cells (seed 3), p=2, 786432 DoFs, 512 subdomains (32x16 bins), "
           "rho per subdomain 10^U[-4,4], non-nested coarse Voronoi of 64 cells, q=1, f=1",
+    "T1": "unit cube, 32^3 cubes of 6 Kuhn tetrahedra (196608 cells), p=1, 786432 DoFs, one element per "
+          "subdomain, 384 nested Kuhn agglomerates (coarse grid 4^3 cubes), q=1, f = 3 pi^2 sin sin sin",
+    "T1b": "the T1 mesh and load with 512 box subdomains (8^3 boxes of 384 tetrahedra, 1536 DoFs each), 384 nested "
+           "Kuhn agglomerates, p=q=1, 786432 DoFs",
+    "T3": "unit cube, 16^3 cubes of 6 Kuhn tetrahedra (24576 cells), p=3, 491520 DoFs, one element per subdomain, "
+          "384 nested Kuhn agglomerates, q=3 (7680 coarse DoFs)",
     "C4h": "C4's mesh, rho (10^U[-4,4] per 32x16 bin) and load with one element per subdomain (131072 "
            "subdomains of 6 DoFs) and the 512 bins as nested agglomerated coarse cells, q=1 (1536 coarse DoFs)",
 }

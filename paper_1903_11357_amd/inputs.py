@@ -472,6 +472,16 @@ def make_config(name: str) -> Problem:
         P.subdomain = np.arange(P.mesh.n_cells, dtype=np.int32)
         P.name = "C4h"
         return P
+    if name == "T1":
+        # 32^3 cubes of 6 Kuhn tetrahedra (196608 cells), p = q = 1, one element per
+        # subdomain, 384 nested Kuhn agglomerates: the design of Example 3
+        return tet_problem(32, 1, 4, name="T1")
+    if name == "T1b":
+        # the T1 mesh with 512 box subdomains (8^3 boxes of 384 tetrahedra, 1536 DoFs)
+        return tet_problem(32, 1, 4, per_element=False, sub_boxes=8, name="T1b")
+    if name == "T3":
+        # 16^3 cubes (24576 tetrahedra), p = q = 3, one element per subdomain, 384 agglomerates
+        return tet_problem(16, 3, 4, name="T3")
     raise KeyError(name)
 
 

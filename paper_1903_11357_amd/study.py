@@ -15,6 +15,10 @@ nested coarse grids:
   and grow like rho_e otherwise.
 - example2: nested agglomerates, H/h sweeps (Example 2, Tables 3-4): K grows
   like (H/h)^2 along a row and stays roughly constant along diagonals.
+- example3: tetrahedral fine grids of the unit cube (6 n^3 Kuhn tetrahedra)
+  with the tetrahedra of coarser grids as nested agglomerates (Example 3,
+  Tables 5-6): K grows like (H/h)^2 along a row and stays roughly constant
+  along diagonals; plain CG rows give K(A_h).
 - example4: independent (non-nested) coarse Voronoi grids (Example 4).
 - unpreconditioned CG on each fine grid: K(A_h) and its iteration count (the
   extra rows of Example 3's tables).
@@ -125,6 +129,37 @@ def example4(p: int = 1, fine=(256, 1024, 4096), coarse=(16, 64, 256), seed: int
     return out
 
 
+def example3(p: int = 1, fine=(4, 8, 16, 32), coarse=(2, 4, 8), device: str = "cuda:0", with_identity: bool = True,
+             max_coarse_dofs: int = 16384):
+    """Cube meshes of 6 n^3 tetrahedra for n in `fine`, coarse grids of the
+    6 nc^3 Kuhn tetrahedra for nc in `coarse` (nc < n, n divisible by nc),
+    one element per subdomain, q = p. Coarse spaces above max_coarse_dofs
+    are skipped (A_0 is formed dense on the host). Returns
+    ({(N_H, N_h): Run}, {N_h: Run of plain CG})."""
+    nq = (p + 1) * (p + 2) * (p + 3) // 6
+    table, plain = {}, {}
+    for n in fine:
+        for nc in coarse:
+            if nc >= n or n % nc or 6 * nc ** 3 * nq > max_coarse_dofs:
+                continue
+            table[(6 * nc ** 3, 6 * n ** 3)] = run(I.tet_problem(n, p, nc), device=device)
+        if with_identity:
+            plain[6 * n ** 3] = run(I.tet_problem(n, p, 1), identity=True, device=device)
+    return table, plain
+
+
+def table_example3(p: int, table, plain) -> str:
+    nh = sorted({k[1] for k in table} | set(plain))
+    nH = sorted({k[0] for k in table})
+    lines = [f"K(P_ad) (CG iterations), tetrahedra, nested Kuhn agglomerates, p = q = {p}",
+             "| N_H \\ N_h | " + " | ".join(str(v) for v in nh) + " |", "|---" * (len(nh) + 1) + "|"]
+    for H in nH:
+        lines.append(f"| {H} | " + " | ".join(_fmt(table[(H, h)]) if (H, h) in table else "-" for h in nh) + " |")
+    if plain:
+        lines.append("| K(A_h), plain CG | " + " | ".join(_fmt(plain[h]) if h in plain else "-" for h in nh) + " |")
+    return "\n".join(lines)
+
+
 def _fmt(r: Run) -> str:
     return f"{r.K:.4g} ({r.iterations})" + ("" if r.converged else "*")
 
@@ -144,7 +179,7 @@ def table_example2(p: int, table, plain, levels: int) -> str:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--example", type=int, choices=(1, 2, 4), default=2)
+    ap.add_argument("--example", type=int, choices=(1, 2, 3, 4), default=2)
     ap.add_argument("--p", type=int, default=1)
     ap.add_argument("--n-finest", type=int, default=4096)
     ap.add_argument("--levels", type=int, default=4)
@@ -160,6 +195,14 @@ def main(argv=None):
             print("|---" * (len(keys) + 1) + "|")
             for row, d in res.items():
                 print(f"| {row}, p={a.p} | " + " | ".join(_fmt(d[k]) for k in keys) + " |")
+    elif a.example == 3:
+        fine = (4, 8, 16, 32) if a.p == 1 else (4, 8, 16)
+        table, plain = example3(a.p, fine=fine)
+        if a.json:
+            print(json.dumps({"table": {f"{H}/{h}": vars(v) for (H, h), v in table.items()},
+                              "plain": {str(h): vars(v) for h, v in plain.items()}}))
+        else:
+            print(table_example3(a.p, table, plain))
     elif a.example == 2:
         table, plain = example2(a.p, a.n_finest, a.levels)
         if a.json:

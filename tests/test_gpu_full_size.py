@@ -23,6 +23,13 @@ def _oracle(name):
         P = I.make_config(name)
         if name == "C4h":  # same mesh, rho, p and load as C4: same operator
             _, A, b, geo = _oracle("C4")
+        elif name == "T1b":  # same mesh, p and load as T1
+            _, A, b, geo = _oracle("T1")
+        elif P.dim == 3:
+            from oracle.tet import assemble3
+
+            A, b, geo, _ = assemble3(P.mesh, P.p, P.rho, P.c_sigma, P.f)
+            A = A.tocsr()
         else:
             A, b, geo, _ = assemble(P.mesh, P.p, P.rho, P.c_sigma, P.f)
             A = A.tocsr()
@@ -209,6 +216,68 @@ def test_full_small_solve_true_residual_C4h(prec):
     a_inf = float(abs(A).sum(axis=1).max())
     gap = st["iterations"] * 2.0 ** -53 * (a_inf * np.linalg.norm(xg) + nb) / nb
     print(f"C4h {prec}: iterations={st['iterations']} recursive={st['rel_res']:.3e} true={true_res:.3e} "
+          f"gap bound={gap:.3e}")
+    assert st["converged"] == 1
+    assert true_res <= 1e-8 * 1.05 + gap, (true_res, gap)
+
+
+# ---------------------------------------------------------------- tetrahedra (T1, T1b, T3)
+@pytest.mark.parametrize("name", ["T1", "T3"])
+def test_full_tet_operator_apply(name):
+    import torch
+
+    from paper_1903_11357_amd import asdg
+
+    P, A, b, _ = _oracle(name)
+    pr = _gpu(name, asdg.FP64)
+    v = np.random.default_rng(7).standard_normal(pr.n)
+    out = pr.apply(asdg.APPLY_OPERATOR, torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = A @ v
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["T1", "T3", "T1b"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_tet_local_solves_sampled(name, prec):
+    """Sampled subdomains of the local solves: single tetrahedra (whole
+    small inverses) for T1/T3, 1536-DoF boxes (explicit tile inverses) for T1b."""
+    import scipy.linalg as la
+    import torch
+
+    from paper_1903_11357_amd import asdg
+
+    P, A, b, _ = _oracle(name)
+    pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, inverse=(name == "T1b"))
+    v = np.random.default_rng(8).standard_normal(pr.n)
+    z = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()
+    npb = P.n_p
+    for i in _sample_subdomains(P.subdomain, k=8, seed=9):
+        cells = np.flatnonzero(P.subdomain == i)
+        d = (cells[:, None] * npb + np.arange(npb)[None, :]).ravel()
+        Ai = A[d][:, d].toarray()
+        zi = la.cho_solve(la.cho_factor(Ai, lower=True), v[d])
+        if prec == "fp64":
+            tol = 1e-10
+        else:
+            ev = la.eigvalsh(Ai)
+            tol = 64 * 2.0 ** -24 * ev[-1] / ev[0]
+        assert _rel(z[d], zi) <= tol, (i, _rel(z[d], zi), tol)
+
+
+@pytest.mark.parametrize("name", ["T1", "T3", "T1b"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_tet_solve_true_residual(name, prec):
+    from paper_1903_11357_amd import asdg
+
+    P, A, b, _ = _oracle(name)
+    pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, inverse=(name == "T1b"))
+    x, st = pr.solve(rtol=1e-8, check_every=32)
+    xg = x.cpu().numpy()
+    nb = np.linalg.norm(b)
+    true_res = np.linalg.norm(b - A @ xg) / nb
+    a_inf = float(abs(A).sum(axis=1).max())
+    gap = st["iterations"] * 2.0 ** -53 * (a_inf * np.linalg.norm(xg) + nb) / nb
+    print(f"{name} {prec}: iterations={st['iterations']} recursive={st['rel_res']:.3e} true={true_res:.3e} "
           f"gap bound={gap:.3e}")
     assert st["converged"] == 1
     assert true_res <= 1e-8 * 1.05 + gap, (true_res, gap)

@@ -86,3 +86,36 @@ def test_example1_alignment():
     print({k: (al[k].K, na[k].K) for k in al})
     assert al[1e4].K / al[1e1].K < 2.0
     assert na[1e4].K / na[1e1].K > 100.0
+
+
+def test_tet_study_K_matches_oracle():
+    """K(P_ad) of the 3D study problem (one element per subdomain, nested
+    Kuhn agglomerates) equals the oracle's estimate."""
+    from paper_1903_11357_amd import inputs as I
+    from paper_1903_11357_amd import study
+
+    P = I.tet_problem(4, 2, 2)
+    _check(study.run(P), _oracle_run(P))
+
+
+def test_example3_trends():
+    """Tetrahedra: fixed coarse grid, h halved: K grows (about 4x); fixed
+    H/h: K about constant; K(A_h) grows like h^-2."""
+    from paper_1903_11357_amd import study
+
+    table, plain = study.example3(p=1, fine=(2, 4, 8, 16), coarse=(1, 2, 4))
+    print(study.table_example3(1, table, plain))
+    assert all(r.converged for r in table.values())
+    for (H, h), r in table.items():
+        if (H, 8 * h) in table:  # N_h grows 8x when h halves
+            ratio = table[(H, 8 * h)].K / r.K
+            assert 2.0 < ratio < 8.0, ((H, h), ratio)
+    for (H, h), r in table.items():
+        if (8 * H, 8 * h) in table:
+            ratio = table[(8 * H, 8 * h)].K / r.K
+            assert 0.5 < ratio < 2.0, ((H, h), ratio)
+    # K(A_h): from 384 cells on (the 48-cell grid is almost all boundary cells)
+    hs = [h for h in sorted(plain) if h >= 384]
+    for a, b in zip(hs, hs[1:]):
+        ratio = plain[b].K / plain[a].K
+        assert 2.5 < ratio < 7.5, (a, b, ratio)
