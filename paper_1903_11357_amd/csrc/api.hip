@@ -143,6 +143,10 @@ struct asdg_problem {
   hipGraphExec_t gexec = nullptr;
   int g_k = 0, g_timed = 0;
   hipStream_t own_stream = nullptr;
+  // the coarse correction (restriction + dense coarse solve) runs on side_stream
+  // beside the local solves; fork/join through events (graph edges when captured)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<hipEvent_t> ev;  // 2 per captured iteration (local solve start/end)
   hipEvent_t t0 = nullptr, t1 = nullptr;
   // non-blocking solve state
@@ -166,6 +170,9 @@ struct asdg_problem {
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     if (own_stream) (void)hipStreamDestroy(own_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     if (chunk_ev) (void)hipEventDestroy(chunk_ev);
     if (h_state) (void)hipHostFree(h_state);
   }
@@ -394,12 +401,25 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
                               iteration ? vec_parts(pb->n()) : 0, s));
     return ASDG_OK;
   }
+  // with a local launch of its own and the dense coarse solve, the coarse
+  // correction runs beside the local solves on the side stream
+  const bool side = pb->has_coarse && pb->coarse_dense && !pb->small && pb->side_stream;
+  const hipStream_t sc = side ? pb->side_stream : s;
+  if (side) {
+    HIPCHK(pb, hipEventRecord(pb->fork_ev, s));
+    HIPCHK(pb, hipStreamWaitEvent(sc, pb->fork_ev, 0));
+  }
   if (pb->has_coarse) {
     HIPCHK(pb, launch_restrict(np, pb->C.nq, pb->C.n_coarse, pb->rsplits, pb->ptr<int32_t>(2, pb->o2.tptr),
                                pb->ptr<int32_t>(2, pb->o2.tcell), pb->ptr<int32_t>(2, pb->o2.tblk),
                                pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
                                pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.y0),
-                               pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), st_done, s));
+                               pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), st_done, sc));
+  }
+  if (side) {
+    asdg_status ce = enqueue_coarse_solve(pb, st_done, sc);
+    if (ce != ASDG_OK) return ce;
+    HIPCHK(pb, hipEventRecord(pb->join_ev, sc));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
   if (pb->small) {
@@ -417,7 +437,9 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
                          pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
   }
   if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
-  if (pb->has_coarse) {
+  if (side) {
+    HIPCHK(pb, hipStreamWaitEvent(s, pb->join_ev, 0));
+  } else if (pb->has_coarse) {
     asdg_status ce = enqueue_coarse_solve(pb, st_done, s);
     if (ce != ASDG_OK) return ce;
   }
@@ -759,6 +781,11 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   hipDeviceProp_t prop;
   HIPCHK(pb, hipGetDeviceProperties(&prop, dev));
   pb->n_cu = std::max(1, prop.multiProcessorCount);
+  if (!pb->side_stream) {
+    HIPCHK(pb, hipStreamCreateWithFlags(&pb->side_stream, hipStreamNonBlocking));
+    HIPCHK(pb, hipEventCreateWithFlags(&pb->fork_ev, hipEventDisableTiming));
+    HIPCHK(pb, hipEventCreateWithFlags(&pb->join_ev, hipEventDisableTiming));
+  }
   hipStream_t s = (hipStream_t)stream;
   const Assembled& A = pb->A;
   auto up = [&](int b, size_t off, const void* src, size_t nbytes) {
