@@ -193,7 +193,7 @@ def cpu_baseline(P, n_iter):
                       f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
 
 
-def serving_bench(n_requests, seed=5, workers=16):
+def serving_bench(n_requests, seed=5, workers=16, local_inverse=False):
     """Continuous batching (C5 shape): requests with log-uniform 4096..65536
     Voronoi cells, p in {1,2,3}, ~64 cells per subdomain, rho = 10^U[-2,2]
     per subdomain, random sine-series RHS, nested coarse q=1, FP32-local.
@@ -212,7 +212,8 @@ def serving_bench(n_requests, seed=5, workers=16):
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         problems = list(ex.map(inputs.serving_problem, descs))
     t_gen = time.perf_counter() - t
-    srv = Server(precision=asdg.FP32_LOCAL, max_active=16, check_every=16, setup_workers=8)
+    srv = Server(precision=asdg.FP32_LOCAL, max_active=16, check_every=16, setup_workers=8,
+                 local_inverse=local_inverse)
     burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems)])
     cap = latency_stats(burst)
     rate = 0.8 * cap["solves_per_s"]
@@ -226,7 +227,8 @@ def serving_bench(n_requests, seed=5, workers=16):
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
             "solves_per_s": st["solves_per_s"], "iterations_mean": st["iterations_mean"],
             "all_converged": st["all_converged"] and cap["all_converged"], "peak_active": srv.peak_active,
-            "input_generation_s": t_gen, "precision": "fp32-local"}
+            "input_generation_s": t_gen, "precision": "fp32-local",
+            "local_solves": "explicit inverses" if local_inverse else "triangular sweeps"}
 
 
 def main():
@@ -247,6 +249,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=64,
                     help="requests of the continuous-batching run (0 = skip)")
     ap.add_argument("--only-serving", action="store_true")
+    ap.add_argument("--serving-local", default="sweeps", choices=("sweeps", "inverse"),
+                    help="local solvers of the served requests (short solves: setup dominates)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -268,7 +272,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if a.only_serving:
-        print(json.dumps({"serving": serving_bench(a.serving_requests)}), flush=True)
+        print(json.dumps({"serving": serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse")}),
+              flush=True)
         return
     P = inputs.make_config(a.workload)
     if a.max_iter:
@@ -316,7 +321,7 @@ def main():
         out["fp32_local_speedup_per_solve"] = f64["ms_per_step"] / f32["ms_per_step"]
     if a.serving_requests > 0:
         print("[bench] serving", file=sys.stderr, flush=True)
-        out["serving"] = serving_bench(a.serving_requests)
+        out["serving"] = serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse")
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, a.cpu_iters)

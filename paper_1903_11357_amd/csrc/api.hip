@@ -524,8 +524,10 @@ asdg_status enqueue_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_op
   return ASDG_OK;
 }
 
+// Reads the alpha/beta history on stream s (never the legacy stream: another
+// thread may be capturing a graph, which forbids implicit legacy-stream syncs).
 asdg_status fill_stats(asdg_problem* pb, const DevState& h, double solve_ms, double t_local, int n_local,
-                       asdg_pcg_stats* stats) {
+                       asdg_pcg_stats* stats, hipStream_t s) {
   if (!stats) return ASDG_OK;
   std::memset(stats, 0, sizeof(*stats));
   stats->iterations = h.it;
@@ -538,8 +540,10 @@ asdg_status fill_stats(asdg_problem* pb, const DevState& h, double solve_ms, dou
   const int ka = std::min(h.it, HIST);
   if (ka >= 1) {
     std::vector<double> al(ka), be(std::max(ka - 1, 0));
-    HIPCHK(pb, hipMemcpy(al.data(), pb->ptr<double>(3, pb->o3.ah), 8 * ka, hipMemcpyDeviceToHost));
-    if (ka > 1) HIPCHK(pb, hipMemcpy(be.data(), pb->ptr<double>(3, pb->o3.bh), 8 * (ka - 1), hipMemcpyDeviceToHost));
+    HIPCHK(pb, hipMemcpyAsync(al.data(), pb->ptr<double>(3, pb->o3.ah), 8 * ka, hipMemcpyDeviceToHost, s));
+    if (ka > 1)
+      HIPCHK(pb, hipMemcpyAsync(be.data(), pb->ptr<double>(3, pb->o3.bh), 8 * (ka - 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(pb, hipStreamSynchronize(s));
     std::vector<double> d(ka), off(std::max(ka - 1, 0));
     d[0] = 1.0 / al[0];
     for (int j = 1; j < ka; ++j) d[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
@@ -641,7 +645,7 @@ asdg_status asdg_pcg_finish(asdg_problem* pb, double* d_x, asdg_pcg_stats* stats
   float ms = 0.f;
   HIPCHK(pb, hipEventElapsedTime(&ms, pb->t0, pb->t1));
   pb->solve_open = false;
-  asdg_status e = fill_stats(pb, pb->hs, ms, 0.0, 0, stats);
+  asdg_status e = fill_stats(pb, pb->hs, ms, 0.0, 0, stats, (hipStream_t)stream);
   if (e != ASDG_OK) return e;
   return status_of(pb, pb->hs);
 }
@@ -1007,7 +1011,7 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
   HIPCHK(pb, hipEventSynchronize(pb->t1));
   float solve_ms = 0.f;
   HIPCHK(pb, hipEventElapsedTime(&solve_ms, pb->t0, pb->t1));
-  e = fill_stats(pb, h, solve_ms, t_local, n_local, stats);
+  e = fill_stats(pb, h, solve_ms, t_local, n_local, stats, s);
   if (e != ASDG_OK) return e;
   return status_of(pb, h);
 }

@@ -188,13 +188,11 @@ hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const Su
                        st, queue);
   } else {
     const size_t sh = 2 * TILE * LDA * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_cholesky<double>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    // set once per process (a function-local static: initialised once even
+    // when several host threads factorise at the same time)
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_cholesky<double>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(k_cholesky<double>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (double*)tiles, flags,
                        st, queue);
   }

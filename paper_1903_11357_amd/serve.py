@@ -6,7 +6,9 @@ time. The server
     runs without the Python lock),
   * admits an assembled request when a slot is free and its exact device
     footprint (the four buffer sizes reported by asdg_plan) fits the HBM
-    budget, then binds its buffers, factorises and sets up the coarse level,
+    budget, then binds its buffers, factorises (triangular sweeps, or
+    explicit local inverses with local_inverse=True) and sets up the coarse
+    level on the request's own stream,
   * keeps every admitted request's factors resident and advances all active
     solves in chunks of `check_every` PCG iterations, each on its own HIP
     stream (captured graphs), so the iterations of different requests are
@@ -55,19 +57,34 @@ class _Active:
         self.stream = stream
 
 
-def _host_setup(req, precision):
+def _host_setup(req, precision, local_inverse):
     P = req.problem
     pr = asdg.Problem()
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    if local_inverse:
+        pr.set_tuning(asdg.TUNE_LOCAL_INVERSE, 1)
     b = pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
                 coarse_mesh=P.coarse_mesh)
     return pr, int(sum(b))
 
 
+def _device_setup(pr, device):
+    """Buffers, factorisation and coarse level on a new stream of the request."""
+    import torch
+
+    stream = torch.cuda.Stream(device)
+    with torch.cuda.stream(stream):  # buffers belong to the request's stream
+        pr.bind(device, stream=stream)
+    pr.factor(stream=stream)
+    pr.setup_coarse(stream=stream)
+    return stream
+
+
 class Server:
     def __init__(self, device="cuda:0", precision=asdg.FP32_LOCAL, hbm_budget: Optional[int] = None,
                  max_active: int = 16, check_every: int = 16, setup_workers: int = 4,
-                 keep_solutions: bool = False, rtol: float = 1e-8, max_iter: int = 20000):
+                 keep_solutions: bool = False, rtol: float = 1e-8, max_iter: int = 20000,
+                 local_inverse: bool = False):
         import torch
 
         self.device = torch.device(device)
@@ -82,12 +99,11 @@ class Server:
         self.keep_solutions = keep_solutions
         self.rtol = rtol
         self.max_iter = max_iter
+        self.local_inverse = local_inverse
         self.peak_active = 0
         self.peak_bytes = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
-        import torch
-
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         pool = cf.ThreadPoolExecutor(max_workers=self.setup_workers)
         t0 = time.perf_counter()
@@ -103,7 +119,7 @@ class Server:
                 # arrivals -> host assembly
                 while nxt < len(reqs) and reqs[nxt].arrival <= t:
                     r = reqs[nxt]
-                    preparing.append((r, pool.submit(_host_setup, r, self.precision)))
+                    preparing.append((r, pool.submit(_host_setup, r, self.precision, self.local_inverse)))
                     nxt += 1
                 # admission in arrival order (no overtaking)
                 while preparing and preparing[0][1].done() and len(active) < self.max_active:
@@ -116,19 +132,14 @@ class Server:
                     if used + nbytes > self.hbm_budget:
                         break
                     preparing.pop(0)
-                    stream = torch.cuda.Stream(self.device)
-                    with torch.cuda.stream(stream):  # buffers belong to the request's stream
-                        pr.bind(self.device, stream=stream)
-                    pr.factor(stream=stream)
-                    pr.setup_coarse(stream=stream)
-                    pr.begin(rtol=self.rtol, max_iter=self.max_iter, check_every=self.check_every,
-                             stream=stream)
                     r.bytes = nbytes
-                    r.t_admitted = now()
                     used += nbytes
+                    self.peak_bytes = max(self.peak_bytes, used)
+                    stream = _device_setup(pr, self.device)
+                    pr.begin(rtol=self.rtol, max_iter=self.max_iter, check_every=self.check_every, stream=stream)
+                    r.t_admitted = now()
                     active.append(_Active(r, pr, stream))
                     self.peak_active = max(self.peak_active, len(active))
-                    self.peak_bytes = max(self.peak_bytes, used)
                 # advance / retire active solves
                 progressed = False
                 for a in list(active):
@@ -143,7 +154,11 @@ class Server:
                         r.iterations = st["iterations"]
                         r.status = st["status"]
                         if self.keep_solutions:
-                            r.x = x.clone()
+                            import torch
+
+                            with torch.cuda.stream(a.stream):
+                                r.x = x.clone()
+                            a.stream.synchronize()
                         used -= r.bytes
                         active.remove(a)
                         del a.pr
