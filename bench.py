@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PCG-ASM DoF-iters/sec at ~1M DoFs; solves/sec + p99 latency, FP32-local vs FP64"
 HBM_PEAK_GBS = 8000.0
+# dense MFMA peaks of MI355X (TFLOP/s)
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 WORKLOADS = {
     "C2": "Voronoi 16384 cells (seed 1), p=2, 98304 DoFs, 64 subdomains (8x8 centroid bins), "
@@ -90,7 +92,7 @@ def local_solve_bytes(pr, word_bytes, inverse=False):
     return factor + vec
 
 
-def run_mode(P, precision, steps, warmup, check_every, inverse=False):
+def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=True):
     import torch
 
     from paper_1903_11357_amd import asdg
@@ -109,6 +111,9 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False):
     pr.factor()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
+    tuned = pr.autotune() if autotune else None
+    torch.cuda.synchronize()
+    t3b = time.perf_counter()
     pr.setup_coarse()
     torch.cuda.synchronize()
     t4 = time.perf_counter()
@@ -143,6 +148,11 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False):
         total_graph = time.perf_counter() - tg0
     w = 4 if precision == asdg.FP32_LOCAL else 8
     small = pr.is_small()
+    # dense flops of the factorisation: Cholesky sum n_i^3/3, and with explicit
+    # inverses X = L^{-1} (n_i^3/3) and S = X^T X (n_i^3/3)
+    n_i = pr._sub_sizes().astype(float)
+    fl = float((n_i ** 3).sum()) / 3.0 * (3.0 if (inverse or small) else 1.0)
+    peak = MFMA_PEAK_TFLOPS["fp32" if precision == asdg.FP32_LOCAL else "fp64"]
     res = {
         "dof_iters_per_s": pr.n * sum(its) / total_graph,
         "iterations": its[-1],
@@ -154,7 +164,12 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False):
         "rel_res": st["rel_res"],
         "kappa_lanczos": st["lambda_max"] / st["lambda_min"] if st["lambda_min"] > 0 else None,
         "setup_s": {"assemble_plan_host": t1 - t0, "bind_upload": t2 - t1, "factor": t3 - t2,
-                    "coarse": t4 - t3},
+                    "autotune": t3b - t3, "coarse": t4 - t3b},
+        "autotune": tuned,
+        "factor_mfma": {"flops": fl, "tflops": fl / (t3 - t2) / 1e12, "peak_tflops": peak,
+                        "frac": fl / (t3 - t2) / 1e12 / peak,
+                        "note": "dense flops over the wall time of asdg_factor (gather, Cholesky"
+                                + (", inverse formation" if inverse else "") + ", status reads)"},
         "local_solve": ({"representation": "whole small inverses applied inside k_prolong (no launch of its own)",
                          "bytes_per_apply": float((pr._sub_sizes().astype(float) ** 2).sum()) * w}
                         if small else
@@ -170,18 +185,26 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False):
 def cpu_baseline(P, n_iter):
     """The FP64 oracle (NumPy/SciPy) timed on the host: setup untimed, then
     n_iter PCG iterations of the same workload, as DoF-iterations/s."""
-    import numpy as np
+    from oracle import OracleSolver
 
-    from oracle.pcg import pcg
-    from oracle.schwarz import TwoLevelSchwarz
-    from oracle.sipg import assemble
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        import contextlib
 
-    A, b, geo, _ = assemble(P.mesh, P.p, P.rho, P.c_sigma, P.f)
-    M = TwoLevelSchwarz(A, P.mesh, P.p, geo, P.subdomain, q=P.q, coarse_of_cell=P.coarse_of_cell,
-                        coarse_mesh=P.coarse_mesh)
+        def threadpool_limits(n):
+            return contextlib.nullcontext()
+
+    orc = OracleSolver(P)
+    A, M = orc.A, orc.M
     t = time.perf_counter()
-    pcg(A, b, M.apply, fixed_iters=n_iter)
+    orc.solve(fixed_iters=n_iter)
     dt = time.perf_counter() - t
+    t1 = time.perf_counter()
+    with threadpool_limits(1):
+        orc.solve(fixed_iters=1)
+    dt1 = time.perf_counter() - t1
+    sfb = sparse_factor_bound(A, M)
     try:
         from threadpoolctl import threadpool_info
 
@@ -190,7 +213,34 @@ def cpu_baseline(P, n_iter):
         threads = os.cpu_count() or 1
     return {"value": A.shape[0] * n_iter / dt, "unit": "DoF-iters/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_iter} PCG iterations of the full workload (oracle setup untimed), "
-                      f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
+                      f"{dt:.1f} s on {os.cpu_count()} host CPUs",
+            "one_thread": {"value": A.shape[0] / dt1, "sample": f"1 PCG iteration, {dt1:.2f} s, BLAS limited to "
+                                                                 f"1 thread"}}, sfb
+
+
+def sparse_factor_bound(A, M, sample=32, seed=0):
+    """Bytes a sparse factor of the same A_i would move, as a lower-bound
+    context for the dense packed factors: SuperLU with a minimum-degree
+    ordering of A_i + A_i^T and diagonal pivoting, nnz(L) per subdomain on a
+    seeded sample of subdomains, scaled to all of them by the dense
+    lower-triangle sizes. Values in FP32 plus one int32 row index each."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(M.dofs), size=min(sample, len(M.dofs)), replace=False)
+    nnz = dense = 0.0
+    for i in pick:
+        d = M.dofs[i]
+        lu = spla.splu(A[d][:, d].tocsc(), permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                       options={"SymmetricMode": True})
+        nnz += lu.L.nnz
+        dense += len(d) * (len(d) + 1) / 2
+    all_dense = float(sum(len(d) * (len(d) + 1) / 2 for d in M.dofs))
+    ratio = nnz / dense
+    return {"sample_subdomains": int(len(pick)), "nnz_L_over_dense_lower": ratio,
+            "sparse_L_bytes_fp32": ratio * all_dense * (4 + 4), "dense_lower_bytes_fp32": all_dense * 4,
+            "ordering": "SuperLU MMD_AT_PLUS_A, symmetric mode"}
 
 
 def serving_bench(n_requests, seed=5, workers=16, local_inverse=False):
@@ -244,6 +294,8 @@ def main():
     ap.add_argument("--local", default="inverse,sweeps",
                     help="local-solve representations, the first is the headline: inverse (packed "
                          "A_i^{-1}, one pass) and/or sweeps (Cholesky forward/backward sweeps)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no asdg_autotune after the factorisation)")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap PCG iterations (profiling runs; 0 = the workload's own limit)")
     ap.add_argument("--serving-requests", type=int, default=64,
@@ -284,7 +336,8 @@ def main():
         for m in a.modes.split(","):
             prec = asdg.FP32_LOCAL if m == "fp32" else asdg.FP64
             key = m if loc == "inverse" else f"{m}-sweeps"
-            modes[key] = run_mode(P, prec, a.steps, a.warmup, a.check_every, inverse=(loc == "inverse"))
+            modes[key] = run_mode(P, prec, a.steps, a.warmup, a.check_every, inverse=(loc == "inverse"),
+                                  autotune=not a.no_autotune)
             print(f"[bench] {key}: {json.dumps(modes[key])}", file=sys.stderr, flush=True)
     first = a.local.split(",")[0]
     hk = lambda m: m if first == "inverse" else f"{m}-sweeps"  # noqa: E731
@@ -324,7 +377,7 @@ def main():
         out["serving"] = serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse")
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(P, a.cpu_iters)
+        out["cpu_baseline"], out["sparse_factor_bound"] = cpu_baseline(P, a.cpu_iters)
     print(json.dumps(out), flush=True)
 
 

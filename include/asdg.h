@@ -260,10 +260,43 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * tile path for such subdomains too.
  * NO_PRECOND (study aid, any time before a solve): 1 = asdg_pcg_solve runs
  * plain CG (identity preconditioner), so the Lanczos estimate in the stats
- * is K(A_h) rather than K(P_ad); asdg_apply is unaffected. */
+ * is K(A_h) rather than K(P_ad); asdg_apply is unaffected.
+ * INV_WG_PER_CU: persistent work-groups per compute unit of the formation
+ * of the explicit inverses. SYMV_WAVES: tiles (waves) per work-group of
+ * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL).
+ * No launch shape changes the arithmetic: results are identical for every
+ * setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
-       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6 };
+       ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
+       ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
+
+/* Launch shapes chosen by asdg_autotune and the best times measured. */
+typedef struct {
+  int32_t chol_wg_per_cu, inv_wg_per_cu, trsv_wg_per_cu, symv_waves;
+  double factor_ms; /* asdg_factor with the chosen shapes (0 if not tuned) */
+  double local_ms;  /* one batched local solve with the chosen shape (0 if not tuned) */
+  int32_t candidates; /* configurations timed */
+} asdg_tune_report;
+
+/* Own launch-shape autotuner (the batched factorisation and local-solve
+ * launches of Sec. 3's local solvers): times every candidate on this
+ * problem with HIP events on `stream` (median of three runs) and keeps the
+ * fastest, through the same settings as asdg_set_tuning.
+ * ASDG_AUTOTUNE_FACTOR (after asdg_bind): work-groups per compute unit of
+ * the Cholesky launch (1, 2) and, with explicit inverses, of the inverse
+ * formation (1-4 FP32, 1-2 FP64); runs asdg_factor 3 times per candidate
+ * and leaves the problem factorised. ASDG_AUTOTUNE_LOCAL (after
+ * asdg_factor, or together with FACTOR): waves per work-group of the packed
+ * apply (1, 2, 4, 8) or work-groups per compute unit of the triangular
+ * sweeps (1-4); overwrites the solver's internal vectors (not the factors
+ * or the coarse level). Problems whose subdomains all have at most 64 DoFs
+ * (whole small inverses) have no such launches: nothing is timed. Results
+ * of later solves are identical for every choice. rep may be NULL.
+ * Errors: EINVAL (flags), ESTATE (stage, or a solve in progress), EHIP,
+ * and those of asdg_factor. */
+enum { ASDG_AUTOTUNE_FACTOR = 1, ASDG_AUTOTUNE_LOCAL = 2 };
+asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tune_report* rep);
 
 /* Task trace of the last batched local solve launched while
  * ASDG_TUNE_TRACE = 1 (profiling aid). tasks: [n][4] int32 (subdomain,

@@ -45,6 +45,12 @@ class PcgStats(C.Structure):
                 ("t_local_ms", C.c_double), ("n_local", C.c_int32), ("failed_subdomain", C.c_int32)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("chol_wg_per_cu", C.c_int32), ("inv_wg_per_cu", C.c_int32), ("trsv_wg_per_cu", C.c_int32),
+                ("symv_waves", C.c_int32), ("factor_ms", C.c_double), ("local_ms", C.c_double),
+                ("candidates", C.c_int32)]
+
+
 class TetMesh_(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("xyz", C.POINTER(C.c_double)), ("n_cells", C.c_int32),
                 ("tets", C.POINTER(C.c_int32))]
@@ -80,6 +86,7 @@ _SIGS = {
     "asdg_local_mode": (C.c_int32, [C.c_void_p]),
     "asdg_export_factor_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "asdg_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "asdg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(TuneReport)]),
     "asdg_export_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double)]),
     "asdg_pcg_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgOpts), C.c_void_p]),
@@ -88,7 +95,8 @@ _SIGS = {
     "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
-    TUNE_NO_PRECOND = 0, 1, 2, 3, 4, 5, 6
+    TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES = 0, 1, 2, 3, 4, 5, 6, 7, 8
+AUTOTUNE_FACTOR, AUTOTUNE_LOCAL = 1, 2
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 
 
@@ -217,6 +225,14 @@ class Problem:
 
     def set_tuning(self, what: int, value: int):
         self._check(self._L.asdg_set_tuning(self.h, what, value))
+
+    def autotune(self, what: int = AUTOTUNE_FACTOR | AUTOTUNE_LOCAL, stream=None) -> dict:
+        """Times the launch-shape candidates of the factorisation and/or the
+        batched local solves on this problem and keeps the fastest
+        (asdg_autotune); returns the chosen shapes and best times."""
+        r = TuneReport()
+        self._check(self._L.asdg_autotune(self.h, what, self._stream(stream), C.byref(r)))
+        return {k: getattr(r, k) for k, _ in TuneReport._fields_}
 
     def factor_dense(self, sub: int) -> np.ndarray:
         """Dense lower-triangular factor of subdomain ``sub`` (-1: coarse),

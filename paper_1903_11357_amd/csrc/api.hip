@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "asdg.h"
@@ -130,6 +131,7 @@ struct asdg_problem {
   int32_t failed_sub = -2;
   int n_cu = 256;
   int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
+  int inv_per_cu = 0, symv_waves = 0;                                // 0: defaults
   int local_inverse = 0, inv_planned = 0;  // explicit local inverses (set before asdg_plan)
   // small-subdomain mode: every n_i <= TILE; A_i^{-1} stored whole (n_i^2 words at subs[i].tile0) and
   // applied inside the prolongation; no tiles, no local launch
@@ -247,6 +249,66 @@ asdg_status asdg_assemble_tet(asdg_problem* pb, const asdg_tet_mesh* fine, int32
 
 namespace {
 
+// Longest path (in units of one 64x64x64 tile product) from each task
+// (j, b) of a tile Cholesky with nb block columns to the end of the
+// factorisation: task (j, b) runs j updates, then the diagonal factor and
+// inverse (about ten units) or one product with inv(L_jj); its consumers
+// are (j', b) for j < j' <= b and (b, b') for b' >= b, and the diagonal
+// task feeds (j, b') for b' > j. Entry [j * nb + b].
+static std::vector<int32_t> cholesky_levels(int nb) {
+  std::vector<int32_t> lv((size_t)nb * nb, 0);
+  for (int j = nb - 1; j >= 0; --j)
+    for (int b = nb - 1; b >= j; --b) {
+      int32_t m = 0;
+      if (b == j) {
+        for (int b2 = j + 1; b2 < nb; ++b2) m = std::max(m, lv[j * nb + b2]);
+      } else {
+        for (int j2 = j + 1; j2 <= b; ++j2) m = std::max(m, lv[j2 * nb + b]);
+        for (int b2 = b; b2 < nb; ++b2) m = std::max(m, lv[b * nb + b2]);
+      }
+      lv[j * nb + b] = m + j + (b == j ? 10 : 1);
+    }
+  return lv;
+}
+
+// The same for X = L^{-1}: task (j, b) runs b - j updates and one product
+// with D_b (a copy when b == j); its consumers are (j, b') for b' > b.
+static std::vector<int32_t> inverse_levels(int nb) {
+  std::vector<int32_t> lv((size_t)nb * nb, 0);
+  for (int j = 0; j < nb; ++j)
+    for (int b = nb - 1; b >= j; --b) {
+      int32_t m = 0;
+      for (int b2 = b + 1; b2 < nb; ++b2) m = std::max(m, lv[j * nb + b2]);
+      lv[j * nb + b] = m + (b - j) + 1;
+    }
+  return lv;
+}
+
+// Tasks (i, j, b), j <= b < nb_i, of every subdomain, longest path first
+// (ties by subdomain, column, row); every dependency has a strictly longer
+// path, so it precedes its consumers.
+static std::vector<int4> order_tasks(const std::vector<SubDesc>& subs, std::vector<int32_t> (*levels)(int)) {
+  struct K { int32_t lv, i, j, b; };
+  std::vector<K> ks;
+  std::map<int, std::vector<int32_t>> memo;
+  for (int32_t i = 0; i < (int32_t)subs.size(); ++i) {
+    const int nb = subs[i].nb;
+    auto it = memo.find(nb);
+    if (it == memo.end()) it = memo.emplace(nb, levels(nb)).first;
+    for (int j = 0; j < nb; ++j)
+      for (int b = j; b < nb; ++b) ks.push_back({it->second[(size_t)j * nb + b], i, j, b});
+  }
+  std::sort(ks.begin(), ks.end(), [](const K& x, const K& y) {
+    if (x.lv != y.lv) return x.lv > y.lv;
+    if (x.i != y.i) return x.i < y.i;
+    if (x.j != y.j) return x.j < y.j;
+    return x.b < y.b;
+  });
+  std::vector<int4> out(ks.size());
+  for (size_t k = 0; k < ks.size(); ++k) out[k] = make_int4(ks[k].i, ks[k].j, ks[k].b, 0);
+  return out;
+}
+
 void plan_local(asdg_problem* pb) {
   const Assembled& A = pb->A;
   const int np = A.np;
@@ -287,20 +349,12 @@ void plan_local(asdg_problem* pb) {
   for (int32_t i = 0; i < ns; ++i)
     for (int b = 0; b < pb->subs[i].nb; ++b)
       for (int j = 0; j <= b; ++j) pb->tile_meta.push_back(make_int4(i, b, j, 0));
-  // factorisation tasks: (i, j, b) ordered by (nbmax - nb_i + j, i, b); every
-  // dependency (same i, smaller column, or same column and b' = j < b) comes first
+  // factorisation tasks (i, j, b): longest path to the end first (ties by
+  // subdomain, column, row); every dependency has a strictly longer path, so
+  // it precedes its consumers in the queue
+  pb->chol_tasks = order_tasks(pb->subs, cholesky_levels);
   struct K { int64_t key; int4 t; };
   std::vector<K> ks;
-  ks.reserve(tiles);
-  for (int32_t i = 0; i < ns; ++i) {
-    int nb = pb->subs[i].nb;
-    for (int j = 0; j < nb; ++j)
-      for (int b = j; b < nb; ++b)
-        ks.push_back({(((int64_t)(nbmax - nb + j) * ns + i) << 20) | b, make_int4(i, j, b, 0)});
-  }
-  std::stable_sort(ks.begin(), ks.end(), [](const K& a, const K& b) { return a.key < b.key; });
-  pb->chol_tasks.resize(ks.size());
-  for (size_t k = 0; k < ks.size(); ++k) pb->chol_tasks[k] = ks[k].t;
   // sweep tasks: forward b at step b, backward b at step 2nb-1-b; all
   // subdomains start together, tasks of one step are contiguous in the queue
   ks.clear();
@@ -387,6 +441,27 @@ LocalParts local_parts(asdg_problem* pb) {
 
 // z = P^{-1} r and partials of r.z. iteration: the prolongation also takes
 // the PCG stopping decision (see launch_prolong).
+// The batched local solves of a tile path (packed inverses or triangular
+// sweeps) on r; st_done (may be NULL) lets the packed apply skip its work
+// once the solve has stopped.
+asdg_status enqueue_local(asdg_problem* pb, hipStream_t s, const DevState* st_done) {
+  DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+  const double* r = pb->ptr<double>(3, pb->o3.r);
+  if (pb->inv_planned) {
+    HIPCHK(pb, launch_symv_tiles(pb->f32, pb->symv_waves > 0 ? pb->symv_waves : 4, (int32_t)pb->n_tiles,
+                                 pb->ptr<int4>(1, pb->o1.meta), pb->ptr<SubDesc>(1, pb->o1.subs),
+                                 pb->ptr<void>(1, pb->o1.tiles), r, pb->ptr<void>(3, pb->o3.part), st_done, s));
+  } else {
+    const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
+                                             (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
+    HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
+                           pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
+                           pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
+                           pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
+  }
+  return ASDG_OK;
+}
+
 asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, Reduction* red, bool iteration,
                             hipEvent_t ev0, hipEvent_t ev1) {
   const int np = pb->A.np;
@@ -422,19 +497,9 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
     HIPCHK(pb, hipEventRecord(pb->join_ev, sc));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
-  if (pb->small) {
-    // local solves happen inside the prolongation
-  } else if (pb->inv_planned) {
-    HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
-                                 pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
-                                 pb->ptr<void>(3, pb->o3.part), st, s));
-  } else {
-  const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
-                                                 (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
-  HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
-                         pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
-                         pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
-                         pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
+  if (!pb->small) {  // (small subdomains: the local solves happen inside the prolongation)
+    asdg_status le = enqueue_local(pb, s, st);
+    if (le != ASDG_OK) return le;
   }
   if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
   if (side) {
@@ -688,13 +753,9 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->inv_planned = pb->local_inverse && !pb->small;
   pb->inv_tasks.clear();
   if (pb->inv_planned) {
-    // X = L^{-1} tasks (i, j, b), j <= b, in row order: every X_kj with k < b comes first
-    int nbmax = 0;
-    for (const SubDesc& d : pb->subs) nbmax = std::max(nbmax, d.nb);
-    for (int b = 0; b < nbmax; ++b)
-      for (int32_t i = 0; i < pb->A.n_sub; ++i)
-        if (b < pb->subs[i].nb)
-          for (int j = 0; j <= b; ++j) pb->inv_tasks.push_back(make_int4(i, j, b, 0));
+    // X = L^{-1} tasks (i, j, b), j <= b: longest path to the end first, so
+    // every X_kj with k < b precedes X_bj
+    pb->inv_tasks = order_tasks(pb->subs, inverse_levels);
   }
   pb->cell_sub.assign(pb->A.n_cells, 0);
   for (int32_t i = 0; i < pb->A.n_sub; ++i)
@@ -844,7 +905,7 @@ static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int32_
   int32_t* flags = pb->ptr<int32_t>(3, pb->o3.flags);
   HIPCHK(pb, launch_fill_i32(flags, n_tiles, 0, s));
   HIPCHK(pb, launch_reset_queues(st, s));
-  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : (f32 ? 4 : 2);
+  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;  // the kernel's occupancy (registers)
   int64_t gmax = pb->chol_grid > 0 ? pb->chol_grid : (int64_t)pb->n_cu * per_cu;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tasks, gmax));
   HIPCHK(pb, launch_cholesky(f32, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
@@ -894,7 +955,7 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
     DevState* st = pb->ptr<DevState>(3, pb->o3.st);
     HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_tiles, 0, s));
     HIPCHK(pb, launch_reset_queues(st, s));
-    const int per_cu = pb->f32 ? 4 : 2;
+    const int per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);  // default: the occupancy
     const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)pb->inv_tasks.size(), (int64_t)pb->n_cu * per_cu));
     const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>(pb->n_tiles, (int64_t)pb->n_cu * per_cu * 4));
     HIPCHK(pb, launch_inverse(pb->f32, (int32_t)pb->inv_tasks.size(), pb->ptr<int4>(1, pb->o1.inv),
@@ -1048,19 +1109,9 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
                                  pb->ptr<double>(2, pb->o2.pval), r, pb->ptr<double>(3, pb->o3.r0),
                                  pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.y0),
                                  pb->coarse_dense ? nullptr : pb->ptr<double>(3, pb->o3.z0), nullptr, s));
-    if (loc && pb->small) {
-      // local solves happen inside the prolongation
-    } else if (loc && pb->inv_planned) {
-      HIPCHK(pb, launch_symv_tiles(pb->f32, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
-                                   pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
-                                   pb->ptr<void>(3, pb->o3.part), nullptr, s));
-    } else if (loc) {
-      const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
-                                                 (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
-      HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
-                             pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
-                             pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
-                         pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
+    if (loc && !pb->small) {  // (small subdomains: the local solves happen inside the prolongation)
+      asdg_status le = enqueue_local(pb, s, nullptr);
+      if (le != ASDG_OK) return le;
     }
     if (crs) {
       asdg_status ce = enqueue_coarse_solve(pb, nullptr, s);
@@ -1193,8 +1244,120 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_LOCAL_INVERSE) pb->local_inverse = value ? 1 : 0;
   else if (what == ASDG_TUNE_SMALL_OFF) pb->small_off = value ? 1 : 0;
   else if (what == ASDG_TUNE_NO_PRECOND) pb->no_precond = value ? 1 : 0;
-  else FAIL(pb, ASDG_EINVAL, "unknown tuning key");
+  else if (what == ASDG_TUNE_INV_WG_PER_CU) pb->inv_per_cu = value;
+  else if (what == ASDG_TUNE_SYMV_WAVES) {
+    if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+      FAIL(pb, ASDG_EINVAL, "waves per work-group of the packed apply must be 1, 2, 4 or 8");
+    pb->symv_waves = value;
+  } else FAIL(pb, ASDG_EINVAL, "unknown tuning key");
   pb->drop_graph();
+  return ASDG_OK;
+}
+
+// Launch-shape autotuner: every candidate is timed on this problem with
+// HIP events on the caller's stream (median of three runs), the fastest is
+// kept. The candidates change only which work-group does which task, never
+// the arithmetic, so results are the same for every choice.
+asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tune_report* rep) {
+  if (!pb) return ASDG_EINVAL;
+  if (what & ~(ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL)) FAIL(pb, ASDG_EINVAL, "unknown autotune flags");
+  if ((what & ASDG_AUTOTUNE_FACTOR) && pb->stage < 3) FAIL(pb, ASDG_ESTATE, "autotune before asdg_bind");
+  if ((what & ASDG_AUTOTUNE_LOCAL) && !(what & ASDG_AUTOTUNE_FACTOR) && pb->stage < 4)
+    FAIL(pb, ASDG_ESTATE, "autotune of the local solves before asdg_factor");
+  if (pb->solve_open) FAIL(pb, ASDG_ESTATE, "autotune while a solve is in progress");
+  hipStream_t s = (hipStream_t)stream;
+  asdg_tune_report R;
+  std::memset(&R, 0, sizeof(R));
+  hipEvent_t e0, e1;
+  HIPCHK(pb, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    FAIL(pb, ASDG_EHIP, "hipEventCreate failed");
+  }
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  auto median3 = [](float x, float y, float z) { return std::max(std::min(x, y), std::min(std::max(x, y), z)); };
+  // one timed factorisation (gather, Cholesky, inverse formation)
+  auto time_factor = [&](float& ms) -> asdg_status {
+    HIPCHK(pb, hipEventRecord(e0, s));
+    asdg_status e = asdg_factor(pb, stream);
+    if (e != ASDG_OK) return e;
+    HIPCHK(pb, hipEventRecord(e1, s));
+    HIPCHK(pb, hipEventSynchronize(e1));
+    HIPCHK(pb, hipEventElapsedTime(&ms, e0, e1));
+    return ASDG_OK;
+  };
+  auto tune = [&](int* knob, const std::vector<int>& cand, auto&& run, double& best_ms) -> asdg_status {
+    int best = cand.front();
+    best_ms = 1e300;
+    for (int c : cand) {
+      *knob = c;
+      float t[3];
+      for (float& x : t) {
+        asdg_status e = run(x);
+        if (e != ASDG_OK) return e;
+      }
+      const float m = median3(t[0], t[1], t[2]);
+      ++R.candidates;
+      if (m < best_ms) {
+        best_ms = m;
+        best = c;
+      }
+    }
+    *knob = best;
+    return ASDG_OK;
+  };
+  if ((what & ASDG_AUTOTUNE_FACTOR) && !pb->small) {
+    double ms = 0.0;
+    asdg_status e = tune(&pb->chol_per_cu, {1, 2}, time_factor, ms);
+    if (e != ASDG_OK) return e;
+    if (pb->inv_planned) {
+      e = tune(&pb->inv_per_cu, pb->f32 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{1, 2}, time_factor, ms);
+      if (e != ASDG_OK) return e;
+    }
+    e = asdg_factor(pb, stream);  // leave the problem factorised with the chosen shapes
+    if (e != ASDG_OK) return e;
+    R.factor_ms = ms;
+  }
+  if ((what & ASDG_AUTOTUNE_LOCAL) && !pb->small) {
+    // input: zeros permuted into r (this also sets the sweeps' not-yet-written markers)
+    double* q = pb->ptr<double>(3, pb->o3.q);
+    DevState* st = pb->ptr<DevState>(3, pb->o3.st);
+    HIPCHK(pb, hipMemsetAsync(q, 0, sizeof(double) * pb->n(), s));
+    auto time_local = [&](float& ms) -> asdg_status {
+      HIPCHK(pb, launch_permute_in(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm), q,
+                                   pb->ptr<double>(3, pb->o3.r), nullptr, pb->ptr<void>(3, pb->o3.yl),
+                                   pb->ptr<void>(3, pb->o3.zl), pb->f32, nullptr, nullptr, 0.0, 0, s));
+      HIPCHK(pb, launch_reset_queues(st, s));
+      HIPCHK(pb, hipEventRecord(e0, s));
+      asdg_status e = enqueue_local(pb, s, nullptr);
+      if (e != ASDG_OK) return e;
+      HIPCHK(pb, hipEventRecord(e1, s));
+      HIPCHK(pb, hipEventSynchronize(e1));
+      HIPCHK(pb, hipEventElapsedTime(&ms, e0, e1));
+      return ASDG_OK;
+    };
+    double ms = 0.0;
+    asdg_status e = pb->inv_planned ? tune(&pb->symv_waves, {1, 2, 4, 8}, time_local, ms)
+                                    : tune(&pb->trsv_per_cu, {1, 2, 3, 4}, time_local, ms);
+    if (e != ASDG_OK) return e;
+    DevState h;
+    e = read_state(pb, s, h);
+    if (e != ASDG_OK) return e;
+    if (h.abort) FAIL(pb, ASDG_EHIP, "local solve wait budget exhausted during autotuning");
+    R.local_ms = ms;
+  }
+  R.chol_wg_per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
+  R.inv_wg_per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);
+  R.trsv_wg_per_cu = pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2;
+  R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : 4;
+  pb->drop_graph();
+  if (rep) *rep = R;
   return ASDG_OK;
 }
 

@@ -8,12 +8,14 @@
 //   b == j: L_jj = chol(S) in LDS, store inv(L_jj) in the diagonal slot
 //   b >  j: L_bj = S inv(L_jj)^T                           (MFMA)
 // and raises the tile's flag. Tasks are dequeued from an atomic counter in
-// a host order where every dependency precedes its consumer; a task waits
-// (bounded) only on flags of tasks already dequeued by running work-groups.
-// Producers write tiles with device-coherent stores and raise the flag only
-// after those stores have completed; consumers read tiles produced in the
-// same launch with device-coherent loads, so no cache write-back or
-// invalidation is needed.
+// a host order where every dependency precedes its consumer (the host
+// sorts them by their longest path to the end of the factorisation); a
+// task waits (bounded) only on flags of tasks already dequeued by running
+// work-groups. Producers write tiles with device-coherent stores and raise
+// the flag only after those stores have completed; consumers read tiles
+// produced in the same launch with device-coherent loads, so no cache
+// write-back or invalidation is needed. The operands of update k + 1 are
+// loaded into registers while the MFMA work of update k runs.
 //
 // MFMA tiles: TILE = 64, four waves per work-group, each wave owns a 32x32
 // quadrant. FP32: v_mfma_f32_32x32x2f32; FP64: 2x2 v_mfma_f64_16x16x4f64.
@@ -51,18 +53,30 @@ __global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* _
     T* base = tiles + (size_t)sd.tile0 * TT;
     int32_t* fl = flags + sd.tile0;
     T* Cg = base + (size_t)(b * (b + 1) / 2 + j) * TT;
+    const int rb = b * (b + 1) / 2, rj = j * (j + 1) / 2;  // first tiles of block rows b and j
 
     Quad<T> acc;
 #pragma unroll
     for (int e = 0; e < 16; ++e)
       acc.set(e, Cg[(R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane)]);
 
+    TileRegs<T> ga, gb;
+    if (j > 0) {
+      wait_flag(fl + rb, st);
+      wait_flag(fl + rj, st);
+      ga.load_coherent(base + (size_t)rb * TT);
+      gb.load_coherent(base + (size_t)rj * TT);
+    }
     for (int k = 0; k < j; ++k) {
-      wait_flag(fl + b * (b + 1) / 2 + k, st);
-      wait_flag(fl + j * (j + 1) / 2 + k, st);
-      tile_to_lds(base + (size_t)(b * (b + 1) / 2 + k) * TT, As, true);
-      tile_to_lds(base + (size_t)(j * (j + 1) / 2 + k) * TT, Bs, true);
+      ga.put(As);
+      gb.put(Bs);
       __syncthreads();
+      if (k + 1 < j) {
+        wait_flag(fl + rb + k + 1, st);
+        wait_flag(fl + rj + k + 1, st);
+        ga.load_coherent(base + (size_t)(rb + k + 1) * TT);
+        gb.load_coherent(base + (size_t)(rj + k + 1) * TT);
+      }
       acc.mma(As, Bs, R0, C0, lane, T(-1));
       __syncthreads();
     }
@@ -85,6 +99,7 @@ __global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* _
         __syncthreads();
         if (tid > kk && tid < TILE) As[tid * LDA + kk] /= As[kk * LDA + kk];
         __syncthreads();
+        // trailing update of the lower triangle: thread (ii, jj) pairs with jj <= ii
         const int m = TILE - kk - 1;
         for (int e = tid; e < m * m; e += blockDim.x) {
           const int ii = kk + 1 + e / m, jj = kk + 1 + e % m;
@@ -114,8 +129,8 @@ __global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* _
       for (int e = tid; e < TILE * TILE; e += blockDim.x) store_agent(Cg + e, Bs[(e / TILE) * LDA + (e % TILE)]);
     } else {
       // L_bj = S inv(L_jj)^T
-      wait_flag(fl + j * (j + 1) / 2 + j, st);
-      tile_to_lds(base + (size_t)(j * (j + 1) / 2 + j) * TT, Bs, true);
+      wait_flag(fl + rj + j, st);
+      tile_to_lds(base + (size_t)(rj + j) * TT, Bs, true);
 #pragma unroll
       for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
       __syncthreads();
@@ -127,7 +142,7 @@ __global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* _
     }
     wait_own_stores();
     __syncthreads();
-    if (tid == 0) store_agent(fl + b * (b + 1) / 2 + j, 1);
+    if (tid == 0) store_agent(fl + rb + j, 1);
     __syncthreads();
   }
 }

@@ -33,6 +33,13 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Ordering of LDS traffic between the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Waits until every earlier memory operation of this thread has completed.
 // Data written with store_agent() is then visible device-wide, so a flag or
 // counter updated afterwards publishes it without an L2 write-back.

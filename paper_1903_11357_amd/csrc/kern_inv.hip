@@ -4,7 +4,8 @@
 //
 // Setup, after the tile Cholesky (diagonal tiles hold D_b = inv(L_bb)):
 //   X = L^{-1}:  X_bb = D_b,  X_bj = -D_b sum_{k=j}^{b-1} L_bk X_kj  (b > j)
-//     tasks in row order, one persistent launch, per-tile flags (MFMA);
+//     tasks ordered by their longest path to the end, one persistent
+//     launch, per-tile flags (MFMA);
 //   S = X^T X:   S_bj = sum_{k=b}^{nb-1} X_kb^T X_kj  (b >= j), independent
 //     tiles (MFMA), written over the factor tiles.
 // Apply: every lower tile S_bj (b > j) is read once and contributes S_bj r_j
@@ -53,11 +54,20 @@ __global__ __launch_bounds__(256) void k_inv_lower(int32_t n_tasks, const int4* 
     } else {
       Quad<T> acc;
       acc.zero();
+      // operands of step k + 1 are loaded into registers during the MFMA work of step k
+      TileRegs<T> gl, gx;
+      wait_flag(fl + j * (j + 1) / 2 + j, st);
+      gl.load(Lb + (size_t)(b * (b + 1) / 2 + j) * TT);
+      gx.load_coherent(Xb + (size_t)(j * (j + 1) / 2 + j) * TT);
       for (int k = j; k < b; ++k) {
-        wait_flag(fl + k * (k + 1) / 2 + j, st);
-        tile_to_lds(Lb + (size_t)(b * (b + 1) / 2 + k) * TT, As, false);    // L_bk
-        tile_to_lds_t(Xb + (size_t)(k * (k + 1) / 2 + j) * TT, Bs, true);  // Bs[c][m] = X_kj[m][c]
+        gl.put(As);    // L_bk
+        gx.put_t(Bs);  // Bs[c][m] = X_kj[m][c]
         __syncthreads();
+        if (k + 1 < b) {
+          wait_flag(fl + (k + 1) * (k + 2) / 2 + j, st);
+          gl.load(Lb + (size_t)(b * (b + 1) / 2 + k + 1) * TT);
+          gx.load_coherent(Xb + (size_t)((k + 1) * (k + 2) / 2 + j) * TT);
+        }
         acc.mma(As, Bs, R0, C0, lane, T(1));
         __syncthreads();
       }
@@ -96,10 +106,17 @@ __global__ __launch_bounds__(256) void k_inv_gram(int32_t n_tiles, const int4* _
     const T* Xb = X + (size_t)sd.tile0 * TT;
     Quad<T> acc;
     acc.zero();
+    TileRegs<T> ga, gb;
+    ga.load(Xb + (size_t)(b * (b + 1) / 2 + b) * TT);
+    gb.load(Xb + (size_t)(b * (b + 1) / 2 + j) * TT);
     for (int k = b; k < sd.nb; ++k) {
-      tile_to_lds_t(Xb + (size_t)(k * (k + 1) / 2 + b) * TT, As, false);  // As[r][m] = X_kb[m][r]
-      tile_to_lds_t(Xb + (size_t)(k * (k + 1) / 2 + j) * TT, Bs, false);  // Bs[c][m] = X_kj[m][c]
+      ga.put_t(As);  // As[r][m] = X_kb[m][r]
+      gb.put_t(Bs);  // Bs[c][m] = X_kj[m][c]
       __syncthreads();
+      if (k + 1 < sd.nb) {
+        ga.load(Xb + (size_t)((k + 1) * (k + 2) / 2 + b) * TT);
+        gb.load(Xb + (size_t)((k + 1) * (k + 2) / 2 + j) * TT);
+      }
       acc.mma(As, Bs, R0, C0, lane, T(1));
       __syncthreads();
     }
@@ -150,24 +167,18 @@ struct TileRow<double> {
   __device__ static void lds4(const double* p, double (&o)[4]) { load(p, o); }
 };
 
-// Ordering of LDS traffic between the lanes of one wave.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Phase 1: part[t] = (S_bj r_j, S_bj^T r_b) for tile t = (b, j); the second
 // half is written only for off-diagonal tiles (diagonal tiles are stored
 // whole). Entries of r beyond the subdomain's n are taken as zero.
-template <typename T>
-__global__ __launch_bounds__(256) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
-                                                    const SubDesc* __restrict__ subs, const T* __restrict__ S,
-                                                    const double* __restrict__ r, T* __restrict__ part,
-                                                    const DevState* st) {
-  __shared__ __align__(16) T s_r[4][2 * TILE];
+// WPB waves (tiles) per work-group, a launch-shape choice of the autotuner.
+template <typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
+                                                         const SubDesc* __restrict__ subs, const T* __restrict__ S,
+                                                         const double* __restrict__ r, T* __restrict__ part,
+                                                         const DevState* st) {
+  __shared__ __align__(16) T s_r[WPB][2 * TILE];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int t = blockIdx.x * 4 + w;
+  const int t = blockIdx.x * WPB + w;
   if ((st && st->done) || t >= n_tiles) return;
   const int c4 = lane & 15, r0 = lane >> 4;
   T a[16][4];
@@ -367,15 +378,28 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
   return hipGetLastError();
 }
 
-hipError_t launch_symv_tiles(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
+template <int WPB>
+static void symv_tiles_wpb(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
+                           const double* r, void* part, const DevState* st, hipStream_t s) {
+  const dim3 g((n_tiles + WPB - 1) / WPB), bl(64 * WPB);
+  if (f32)
+    hipLaunchKernelGGL((k_symv_tiles<float, WPB>), g, bl, 0, s, n_tiles, meta, subs, (const float*)S, r,
+                       (float*)part, st);
+  else
+    hipLaunchKernelGGL((k_symv_tiles<double, WPB>), g, bl, 0, s, n_tiles, meta, subs, (const double*)S, r,
+                       (double*)part, st);
+}
+
+hipError_t launch_symv_tiles(int f32, int waves, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
                              const double* r, void* part, const DevState* st, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  const dim3 g((n_tiles + 3) / 4), bl(256);
-  if (f32)
-    hipLaunchKernelGGL(k_symv_tiles<float>, g, bl, 0, s, n_tiles, meta, subs, (const float*)S, r, (float*)part, st);
-  else
-    hipLaunchKernelGGL(k_symv_tiles<double>, g, bl, 0, s, n_tiles, meta, subs, (const double*)S, r, (double*)part,
-                       st);
+  switch (waves) {
+    case 1: symv_tiles_wpb<1>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    case 2: symv_tiles_wpb<2>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    case 4: symv_tiles_wpb<4>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    case 8: symv_tiles_wpb<8>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

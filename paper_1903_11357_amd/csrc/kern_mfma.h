@@ -100,5 +100,39 @@ __device__ __forceinline__ void tile_to_lds_t(const T* g, T* s, bool coherent) {
   }
 }
 
+// A tile (global, row-major TILE x TILE) held in registers by a work-group
+// of 256 threads: thread t keeps elements t + 256 i, i < 16. Loading the
+// next operands into registers before the MFMA work on the current ones
+// overlaps global latency with compute.
+template <typename T>
+struct TileRegs {
+  static constexpr int N = TILE * TILE / 256;
+  T v[N];
+  __device__ void load(const T* g) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = g[threadIdx.x + 256 * i];
+  }
+  __device__ void load_coherent(const T* g) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = load_agent(g + threadIdx.x + 256 * i);
+  }
+  // s[r][c] = g[r][c]
+  __device__ void put(T* s) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      s[(e / TILE) * LDA + (e % TILE)] = v[i];
+    }
+  }
+  // s[c][r] = g[r][c]
+  __device__ void put_t(T* s) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      s[(e % TILE) * LDA + (e / TILE)] = v[i];
+    }
+  }
+};
+
 }  // namespace mfma
 }  // namespace asdg
