@@ -263,17 +263,21 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * is K(A_h) rather than K(P_ad); asdg_apply is unaffected.
  * INV_WG_PER_CU: persistent work-groups per compute unit of the formation
  * of the explicit inverses. SYMV_WAVES: tiles (waves) per work-group of
- * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL).
+ * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL). TASK_CHUNK:
+ * queue order of the factorisation and inverse-formation tasks, 0 = all
+ * subdomains interleaved (longest remaining path first), c > 0 = groups of
+ * c consecutive subdomains one after the other (a smaller working set);
+ * after asdg_bind it takes effect at the next asdg_factor.
  * No launch shape changes the arithmetic: results are identical for every
  * setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
        ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
-       ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8 };
+       ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Launch shapes chosen by asdg_autotune and the best times measured. */
 typedef struct {
-  int32_t chol_wg_per_cu, inv_wg_per_cu, trsv_wg_per_cu, symv_waves;
+  int32_t chol_wg_per_cu, inv_wg_per_cu, trsv_wg_per_cu, symv_waves, task_chunk;
   double factor_ms; /* asdg_factor with the chosen shapes (0 if not tuned) */
   double local_ms;  /* one batched local solve with the chosen shape (0 if not tuned) */
   int32_t candidates; /* configurations timed */
@@ -284,9 +288,11 @@ typedef struct {
  * problem with HIP events on `stream` (median of three runs) and keeps the
  * fastest, through the same settings as asdg_set_tuning.
  * ASDG_AUTOTUNE_FACTOR (after asdg_bind): work-groups per compute unit of
- * the Cholesky launch (1, 2) and, with explicit inverses, of the inverse
- * formation (1-4 FP32, 1-2 FP64); runs asdg_factor 3 times per candidate
- * and leaves the problem factorised. ASDG_AUTOTUNE_LOCAL (after
+ * the Cholesky launch (1, 2), the task order (TASK_CHUNK 0, 256, 64, 16,
+ * those below the subdomain count) and, with explicit inverses,
+ * work-groups per compute unit of the inverse formation (1-4 FP32, 1-2
+ * FP64); runs asdg_factor 3 times per candidate and leaves the problem
+ * factorised. ASDG_AUTOTUNE_LOCAL (after
  * asdg_factor, or together with FACTOR): waves per work-group of the packed
  * apply (1, 2, 4, 8) or work-groups per compute unit of the triangular
  * sweeps (1-4); overwrites the solver's internal vectors (not the factors

@@ -47,7 +47,8 @@ class PcgStats(C.Structure):
 
 class TuneReport(C.Structure):
     _fields_ = [("chol_wg_per_cu", C.c_int32), ("inv_wg_per_cu", C.c_int32), ("trsv_wg_per_cu", C.c_int32),
-                ("symv_waves", C.c_int32), ("factor_ms", C.c_double), ("local_ms", C.c_double),
+                ("symv_waves", C.c_int32), ("task_chunk", C.c_int32), ("factor_ms", C.c_double),
+                ("local_ms", C.c_double),
                 ("candidates", C.c_int32)]
 
 
@@ -95,7 +96,7 @@ _SIGS = {
     "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
-    TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES = 0, 1, 2, 3, 4, 5, 6, 7, 8
+    TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES, TUNE_TASK_CHUNK = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
 AUTOTUNE_FACTOR, AUTOTUNE_LOCAL = 1, 2
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 

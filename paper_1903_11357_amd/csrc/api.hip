@@ -132,6 +132,8 @@ struct asdg_problem {
   int n_cu = 256;
   int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
   int inv_per_cu = 0, symv_waves = 0;                                // 0: defaults
+  int task_chunk = 0;        // subdomains per group of the factorisation task order (0: all at once)
+  bool tasks_dirty = false;  // task lists reordered after asdg_bind, not yet uploaded
   int local_inverse = 0, inv_planned = 0;  // explicit local inverses (set before asdg_plan)
   // small-subdomain mode: every n_i <= TILE; A_i^{-1} stored whole (n_i^2 words at subs[i].tile0) and
   // applied inside the prolongation; no tiles, no local launch
@@ -286,9 +288,11 @@ static std::vector<int32_t> inverse_levels(int nb) {
 
 // Tasks (i, j, b), j <= b < nb_i, of every subdomain, longest path first
 // (ties by subdomain, column, row); every dependency has a strictly longer
-// path, so it precedes its consumers.
-static std::vector<int4> order_tasks(const std::vector<SubDesc>& subs, std::vector<int32_t> (*levels)(int)) {
-  struct K { int32_t lv, i, j, b; };
+// path, so it precedes its consumers. chunk > 0: subdomains in groups of
+// chunk consecutive ones, group by group (a smaller working set at a time).
+static std::vector<int4> order_tasks(const std::vector<SubDesc>& subs, std::vector<int32_t> (*levels)(int),
+                                     int chunk) {
+  struct K { int32_t g, lv, i, j, b; };
   std::vector<K> ks;
   std::map<int, std::vector<int32_t>> memo;
   for (int32_t i = 0; i < (int32_t)subs.size(); ++i) {
@@ -296,9 +300,10 @@ static std::vector<int4> order_tasks(const std::vector<SubDesc>& subs, std::vect
     auto it = memo.find(nb);
     if (it == memo.end()) it = memo.emplace(nb, levels(nb)).first;
     for (int j = 0; j < nb; ++j)
-      for (int b = j; b < nb; ++b) ks.push_back({it->second[(size_t)j * nb + b], i, j, b});
+      for (int b = j; b < nb; ++b) ks.push_back({chunk > 0 ? i / chunk : 0, it->second[(size_t)j * nb + b], i, j, b});
   }
   std::sort(ks.begin(), ks.end(), [](const K& x, const K& y) {
+    if (x.g != y.g) return x.g < y.g;
     if (x.lv != y.lv) return x.lv > y.lv;
     if (x.i != y.i) return x.i < y.i;
     if (x.j != y.j) return x.j < y.j;
@@ -352,7 +357,7 @@ void plan_local(asdg_problem* pb) {
   // factorisation tasks (i, j, b): longest path to the end first (ties by
   // subdomain, column, row); every dependency has a strictly longer path, so
   // it precedes its consumers in the queue
-  pb->chol_tasks = order_tasks(pb->subs, cholesky_levels);
+  pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, pb->task_chunk);
   struct K { int64_t key; int4 t; };
   std::vector<K> ks;
   // sweep tasks: forward b at step b, backward b at step 2nb-1-b; all
@@ -755,7 +760,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   if (pb->inv_planned) {
     // X = L^{-1} tasks (i, j, b), j <= b: longest path to the end first, so
     // every X_kj with k < b precedes X_bj
-    pb->inv_tasks = order_tasks(pb->subs, inverse_levels);
+    pb->inv_tasks = order_tasks(pb->subs, inverse_levels, pb->task_chunk);
   }
   pb->cell_sub.assign(pb->A.n_cells, 0);
   for (int32_t i = 0; i < pb->A.n_sub; ++i)
@@ -943,6 +948,15 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
     }
     pb->stage = 4;
     return ASDG_OK;
+  }
+  if (pb->tasks_dirty) {
+    // reordered task lists (same size); the status read below completes the copies
+    HIPCHK(pb, hipMemcpyAsync(pb->buf[1] + pb->o1.chol, pb->chol_tasks.data(), sizeof(int4) * pb->chol_tasks.size(),
+                              hipMemcpyHostToDevice, s));
+    if (pb->inv_planned)
+      HIPCHK(pb, hipMemcpyAsync(pb->buf[1] + pb->o1.inv, pb->inv_tasks.data(), sizeof(int4) * pb->inv_tasks.size(),
+                                hipMemcpyHostToDevice, s));
+    pb->tasks_dirty = false;
   }
   HIPCHK(pb, launch_gather_tiles(pb->A.np, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.row_ptr),
@@ -1245,6 +1259,14 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_SMALL_OFF) pb->small_off = value ? 1 : 0;
   else if (what == ASDG_TUNE_NO_PRECOND) pb->no_precond = value ? 1 : 0;
   else if (what == ASDG_TUNE_INV_WG_PER_CU) pb->inv_per_cu = value;
+  else if (what == ASDG_TUNE_TASK_CHUNK) {
+    pb->task_chunk = value;
+    if (pb->stage >= 2 && !pb->small) {
+      pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, value);
+      if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, value);
+      if (pb->stage >= 3) pb->tasks_dirty = true;  // uploaded by the next asdg_factor
+    }
+  }
   else if (what == ASDG_TUNE_SYMV_WAVES) {
     if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
       FAIL(pb, ASDG_EINVAL, "waves per work-group of the packed apply must be 1, 2, 4 or 8");
@@ -1316,6 +1338,25 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     double ms = 0.0;
     asdg_status e = tune(&pb->chol_per_cu, {1, 2}, time_factor, ms);
     if (e != ASDG_OK) return e;
+    {
+      // task order: all subdomains interleaved, or in groups (smaller working set)
+      int chunk = pb->task_chunk;
+      auto reorder = [&](float& ms1) -> asdg_status {
+        pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, chunk);
+        if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, chunk);
+        pb->tasks_dirty = true;
+        return time_factor(ms1);
+      };
+      std::vector<int> cand{0};
+      for (int c : {256, 64, 16})
+        if (c < pb->A.n_sub) cand.push_back(c);
+      e = tune(&chunk, cand, reorder, ms);
+      if (e != ASDG_OK) return e;
+      pb->task_chunk = chunk;
+      pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, chunk);
+      if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, chunk);
+      pb->tasks_dirty = true;
+    }
     if (pb->inv_planned) {
       e = tune(&pb->inv_per_cu, pb->f32 ? std::vector<int>{1, 2, 3, 4} : std::vector<int>{1, 2}, time_factor, ms);
       if (e != ASDG_OK) return e;
@@ -1356,6 +1397,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   R.inv_wg_per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);
   R.trsv_wg_per_cu = pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2;
   R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : 4;
+  R.task_chunk = pb->task_chunk;
   pb->drop_graph();
   if (rep) *rep = R;
   return ASDG_OK;

@@ -28,7 +28,7 @@ namespace {
 using namespace mfma;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* __restrict__ tasks,
+__global__ __launch_bounds__(256, 2) void k_cholesky(int32_t n_tasks, const int4* __restrict__ tasks,
                                                   const SubDesc* __restrict__ subs, T* tiles, int32_t* flags,
                                                   DevState* st, int32_t* queue) {
   extern __shared__ unsigned char smem_raw[];
@@ -130,9 +130,10 @@ __global__ __launch_bounds__(256) void k_cholesky(int32_t n_tasks, const int4* _
     } else {
       // L_bj = S inv(L_jj)^T
       wait_flag(fl + rj + j, st);
-      tile_to_lds(base + (size_t)(rj + j) * TT, Bs, true);
+      gb.load_coherent(base + (size_t)(rj + j) * TT);
 #pragma unroll
       for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
+      gb.put(Bs);
       __syncthreads();
       acc.zero();
       acc.mma(As, Bs, R0, C0, lane, T(1));

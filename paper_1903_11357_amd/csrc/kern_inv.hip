@@ -25,7 +25,7 @@ constexpr size_t TT = (size_t)TILE * TILE;
 
 // ---------------------------------------------------------------- X = L^{-1}
 template <typename T>
-__global__ __launch_bounds__(256) void k_inv_lower(int32_t n_tasks, const int4* __restrict__ tasks,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_inv_lower(int32_t n_tasks, const int4* __restrict__ tasks,
                                                    const SubDesc* __restrict__ subs, const T* __restrict__ L,
                                                    T* X, int32_t* flags, DevState* st, int32_t* queue) {
   extern __shared__ unsigned char smem_raw[];
@@ -49,8 +49,9 @@ __global__ __launch_bounds__(256) void k_inv_lower(int32_t n_tasks, const int4* 
     T* out = Xb + (size_t)(b * (b + 1) / 2 + j) * TT;
     if (b == j) {
       // X_bb = D_b
-      const T* D = Lb + (size_t)(b * (b + 1) / 2 + b) * TT;
-      for (int e = tid; e < TILE * TILE; e += blockDim.x) store_agent(out + e, D[e]);
+      TileRegs<T> d;
+      d.load(Lb + (size_t)(b * (b + 1) / 2 + b) * TT);
+      d.store_coherent(out);
     } else {
       Quad<T> acc;
       acc.zero();
@@ -67,6 +68,8 @@ __global__ __launch_bounds__(256) void k_inv_lower(int32_t n_tasks, const int4* 
           wait_flag(fl + (k + 1) * (k + 2) / 2 + j, st);
           gl.load(Lb + (size_t)(b * (b + 1) / 2 + k + 1) * TT);
           gx.load_coherent(Xb + (size_t)((k + 1) * (k + 2) / 2 + j) * TT);
+        } else {
+          gl.load(Lb + (size_t)(b * (b + 1) / 2 + b) * TT);  // D_b, for the last product
         }
         acc.mma(As, Bs, R0, C0, lane, T(1));
         __syncthreads();
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(256) void k_inv_lower(int32_t n_tasks, const int4* 
       // X_bj = -D_b acc: Bs[c][m] = acc[m][c], As = D_b
 #pragma unroll
       for (int e = 0; e < 16; ++e) Bs[(C0 + Quad<T>::col(e, lane)) * LDA + R0 + Quad<T>::row(e, lane)] = acc.get(e);
-      tile_to_lds(Lb + (size_t)(b * (b + 1) / 2 + b) * TT, As, false);
+      gl.put(As);
       __syncthreads();
       acc.zero();
       acc.mma(As, Bs, R0, C0, lane, T(-1));

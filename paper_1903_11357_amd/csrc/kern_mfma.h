@@ -82,24 +82,6 @@ __device__ __forceinline__ void wait_flag(const int32_t* f, DevState* st) {
   __syncthreads();
 }
 
-// Cooperative copy of a tile (global, row-major TILE x TILE) into LDS.
-template <typename T>
-__device__ __forceinline__ void tile_to_lds(const T* g, T* s, bool coherent) {
-  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
-    const T v = coherent ? load_agent(g + e) : g[e];
-    s[(e / TILE) * LDA + (e % TILE)] = v;
-  }
-}
-
-// Cooperative transposed copy: s[c][r] = g[r][c].
-template <typename T>
-__device__ __forceinline__ void tile_to_lds_t(const T* g, T* s, bool coherent) {
-  for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
-    const T v = coherent ? load_agent(g + e) : g[e];
-    s[(e % TILE) * LDA + (e / TILE)] = v;
-  }
-}
-
 // A tile (global, row-major TILE x TILE) held in registers by a work-group
 // of 256 threads: thread t keeps elements t + 256 i, i < 16. Loading the
 // next operands into registers before the MFMA work on the current ones
@@ -115,6 +97,10 @@ struct TileRegs {
   __device__ void load_coherent(const T* g) {
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = load_agent(g + threadIdx.x + 256 * i);
+  }
+  __device__ void store_coherent(T* g) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) store_agent(g + threadIdx.x + 256 * i, v[i]);
   }
   // s[r][c] = g[r][c]
   __device__ void put(T* s) const {

@@ -39,10 +39,12 @@ def test_autotune_keeps_results_bitwise(precision, inverse):
     if inverse:
         assert rep["inv_wg_per_cu"] in ((1, 2, 3, 4) if precision == "fp32" else (1, 2))
         assert rep["symv_waves"] in (1, 2, 4, 8)
-        assert rep["candidates"] == 2 + (4 if precision == "fp32" else 2) + 4
+        # Cholesky shapes 2, task orders 1 (4 subdomains: no grouping below that), inverse formation, packed apply 4
+        assert rep["candidates"] == 2 + 1 + (4 if precision == "fp32" else 2) + 4
     else:
         assert rep["trsv_wg_per_cu"] in (1, 2, 3, 4)
-        assert rep["candidates"] == 2 + 4
+        assert rep["candidates"] == 2 + 1 + 4
+    assert rep["task_chunk"] == 0
     pr.setup_coarse()
     x1, st1 = pr.solve(rtol=1e-8)
     assert st1["iterations"] == st0["iterations"]
