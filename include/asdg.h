@@ -263,7 +263,8 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * is K(A_h) rather than K(P_ad); asdg_apply is unaffected.
  * INV_WG_PER_CU: persistent work-groups per compute unit of the formation
  * of the explicit inverses. SYMV_WAVES: tiles (waves) per work-group of
- * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL). TASK_CHUNK:
+ * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL; default 1 in
+ * FP32-local mode, 4 in FP64 mode). TASK_CHUNK:
  * queue order of the factorisation and inverse-formation tasks, 0 = all
  * subdomains interleaved (longest remaining path first), c > 0 = groups of
  * c consecutive subdomains one after the other (a smaller working set);

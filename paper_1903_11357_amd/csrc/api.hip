@@ -453,9 +453,10 @@ asdg_status enqueue_local(asdg_problem* pb, hipStream_t s, const DevState* st_do
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   const double* r = pb->ptr<double>(3, pb->o3.r);
   if (pb->inv_planned) {
-    HIPCHK(pb, launch_symv_tiles(pb->f32, pb->symv_waves > 0 ? pb->symv_waves : 4, (int32_t)pb->n_tiles,
-                                 pb->ptr<int4>(1, pb->o1.meta), pb->ptr<SubDesc>(1, pb->o1.subs),
-                                 pb->ptr<void>(1, pb->o1.tiles), r, pb->ptr<void>(3, pb->o3.part), st_done, s));
+    const int waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
+    HIPCHK(pb, launch_symv_tiles(pb->f32, waves, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+                                 pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
+                                 pb->ptr<void>(3, pb->o3.part), st_done, s));
   } else {
     const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
                                              (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
@@ -1396,7 +1397,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   R.chol_wg_per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
   R.inv_wg_per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);
   R.trsv_wg_per_cu = pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2;
-  R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : 4;
+  R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
   R.task_chunk = pb->task_chunk;
   pb->drop_graph();
   if (rep) *rep = R;
