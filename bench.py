@@ -243,12 +243,13 @@ def sparse_factor_bound(A, M, sample=32, seed=0):
             "ordering": "SuperLU MMD_AT_PLUS_A, symmetric mode"}
 
 
-def serving_bench(n_requests, seed=5, workers=16, local_inverse=False):
+def serving_bench(n_requests, seed=5, workers=16, local_inverse=False, loads=(0.8,)):
     """Continuous batching (C5 shape): requests with log-uniform 4096..65536
     Voronoi cells, p in {1,2,3}, ~64 cells per subdomain, rho = 10^U[-2,2]
     per subdomain, random sine-series RHS, nested coarse q=1, FP32-local.
-    First all requests at once (capacity), then a Poisson stream at 80% of
-    that capacity; latency = arrival to completion."""
+    First all requests at once (capacity), then Poisson streams at the given
+    fractions of that capacity; latency = arrival to completion. The top
+    level reports the first load, `sweep` all of them."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
 
@@ -262,23 +263,32 @@ def serving_bench(n_requests, seed=5, workers=16, local_inverse=False):
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         problems = list(ex.map(inputs.serving_problem, descs))
     t_gen = time.perf_counter() - t
+    print(f"[bench] serving: {n_requests} requests generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
     srv = Server(precision=asdg.FP32_LOCAL, max_active=16, check_every=16, setup_workers=8,
                  local_inverse=local_inverse)
     burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems)])
     cap = latency_stats(burst)
-    rate = 0.8 * cap["solves_per_s"]
-    rng = np.random.default_rng(seed + 1)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
-    stream = srv.run([Request(i, P, float(a)) for i, (P, a) in enumerate(zip(problems, arrivals))])
-    st = latency_stats(stream)
+    print(f"[bench] serving: capacity {cap['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    sweep = []
+    for k, load in enumerate(loads):
+        rate = load * cap["solves_per_s"]
+        rng = np.random.default_rng(seed + 1 + k)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+        st = latency_stats(srv.run([Request(i, P, float(a)) for i, (P, a) in enumerate(zip(problems, arrivals))]))
+        st.update({"load": load, "arrival_rate_per_s": rate})
+        sweep.append(st)
+        print(f"[bench] serving: load {load}: p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+    st = sweep[0]
     dofs = [P.n_dofs for P in problems]
     return {"requests": n_requests, "dofs_min": int(min(dofs)), "dofs_max": int(max(dofs)),
-            "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate_per_s": rate,
+            "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate_per_s": st["arrival_rate_per_s"],
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
             "solves_per_s": st["solves_per_s"], "iterations_mean": st["iterations_mean"],
-            "all_converged": st["all_converged"] and cap["all_converged"], "peak_active": srv.peak_active,
-            "input_generation_s": t_gen, "precision": "fp32-local",
-            "local_solves": "explicit inverses" if local_inverse else "triangular sweeps"}
+            "all_converged": all(x["all_converged"] for x in sweep) and cap["all_converged"],
+            "peak_active": srv.peak_active, "input_generation_s": t_gen, "precision": "fp32-local",
+            "local_solves": "explicit inverses" if local_inverse else "triangular sweeps",
+            "capacity_run": cap, "sweep": sweep}
 
 
 def main():
@@ -303,6 +313,8 @@ def main():
     ap.add_argument("--only-serving", action="store_true")
     ap.add_argument("--serving-local", default="sweeps", choices=("sweeps", "inverse"),
                     help="local solvers of the served requests (short solves: setup dominates)")
+    ap.add_argument("--serving-loads", default="0.8",
+                    help="Poisson arrival rates as fractions of the measured capacity, comma-separated")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -324,7 +336,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if a.only_serving:
-        print(json.dumps({"serving": serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse")}),
+        print(json.dumps({"serving": serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse",
+                                        loads=tuple(float(v) for v in a.serving_loads.split(",")))}),
               flush=True)
         return
     P = inputs.make_config(a.workload)
@@ -374,7 +387,8 @@ def main():
         out["fp32_local_speedup_per_solve"] = f64["ms_per_step"] / f32["ms_per_step"]
     if a.serving_requests > 0:
         print("[bench] serving", file=sys.stderr, flush=True)
-        out["serving"] = serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse")
+        out["serving"] = serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse",
+                                        loads=tuple(float(v) for v in a.serving_loads.split(",")))
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"], out["sparse_factor_bound"] = cpu_baseline(P, a.cpu_iters)

@@ -249,13 +249,28 @@ class SineSeries:
     def __init__(self, coef):
         self.coef = np.asarray(coef, dtype=np.float64)
 
-    def __call__(self, xy: np.ndarray) -> np.ndarray:
-        out = np.zeros(xy.shape[0])
-        for k in range(self.coef.shape[0]):
-            sk = np.sin((k + 1) * math.pi * xy[:, 0])
-            for l in range(self.coef.shape[1]):
-                out += self.coef[k, l] * sk * np.sin((l + 1) * math.pi * xy[:, 1])
+    @staticmethod
+    def _sines(t: np.ndarray, K: int) -> np.ndarray:
+        """[K, n] with row k-1 = sin(k pi t), by the three-term recurrence
+        sin((k+1)a) = 2 cos(a) sin(ka) - sin((k-1)a): one sin and one cos per
+        point instead of K sines."""
+        a = math.pi * t
+        out = np.empty((K, t.shape[0]))
+        out[0] = np.sin(a)
+        if K > 1:
+            c2 = 2.0 * np.cos(a)
+            np.multiply(c2, out[0], out=out[1])
+            for k in range(2, K):
+                np.multiply(c2, out[k - 1], out=out[k])
+                out[k] -= out[k - 2]
         return out
+
+    def __call__(self, xy: np.ndarray) -> np.ndarray:
+        sx = self._sines(np.ascontiguousarray(xy[:, 0]), self.coef.shape[0])
+        sy = self._sines(np.ascontiguousarray(xy[:, 1]), self.coef.shape[1])
+        t = self.coef @ sy  # [K, n]: sum_l c_kl sin(l pi y)
+        t *= sx
+        return t.sum(axis=0)
 
 
 def make_f_series(coef: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:

@@ -175,8 +175,15 @@ class Server:
 def latency_stats(done: List[Request]) -> dict:
     lat = np.array([r.latency for r in done])
     span = max(r.t_done for r in done) - min(r.arrival for r in done)
+    # where the latency goes: host assembly (arrival -> assembled), waiting for
+    # a slot or HBM (assembled -> admitted, includes the device setup), solve
+    asm = np.array([r.t_assembled - r.arrival for r in done])
+    adm = np.array([r.t_admitted - r.t_assembled for r in done])
+    dev = np.array([r.t_done - r.t_admitted for r in done])
     return {"n": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
             "solves_per_s": len(done) / span if span > 0 else None,
             "iterations_mean": float(np.mean([r.iterations for r in done])),
-            "all_converged": all(r.status == "OK" for r in done)}
+            "all_converged": all(r.status == "OK" for r in done),
+            "mean_assembly_ms": float(asm.mean() * 1e3), "mean_admission_ms": float(adm.mean() * 1e3),
+            "mean_solve_ms": float(dev.mean() * 1e3)}
