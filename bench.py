@@ -39,6 +39,8 @@ WORKLOADS = {
           "nested coarse = subdomains, q=1",
     "C3": "Voronoi 65536 cells (seed 2), p=3, 655360 DoFs, 256 uneven subdomains (warped bins), "
           "nested coarse = subdomains, q=2",
+    "C3x": "Voronoi 104858 cells (seed 4), p=3, 1048580 DoFs, 256 uneven subdomains (warped bins, 2060..8920 "
+           "DoFs), nested coarse = subdomains, q=2 (labelled extra at ~1M DoFs)",
     "C4": "Voronoi 131072 cells (seed 3), p=2, 786432 DoFs, 512 subdomains (32x16 bins), "
           "rho per subdomain 10^U[-4,4], non-nested coarse Voronoi of 64 cells, q=1, f=1",
     "T1": "unit cube, 32^3 cubes of 6 Kuhn tetrahedra (196608 cells), p=1, 786432 DoFs, one element per "

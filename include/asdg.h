@@ -286,14 +286,15 @@ typedef struct {
 
 /* Own launch-shape autotuner (the batched factorisation and local-solve
  * launches of Sec. 3's local solvers): times every candidate on this
- * problem with HIP events on `stream` (median of three runs) and keeps the
- * fastest, through the same settings as asdg_set_tuning.
+ * problem with HIP events on `stream` (median of three runs, or one run
+ * when it takes more than 20 ms) and keeps the fastest, through the same
+ * settings as asdg_set_tuning.
  * ASDG_AUTOTUNE_FACTOR (after asdg_bind): work-groups per compute unit of
- * the Cholesky launch (1, 2), the task order (TASK_CHUNK 0, 256, 64, 16,
- * those below the subdomain count) and, with explicit inverses,
+ * the Cholesky launch (1, 2), the task order (TASK_CHUNK 0, and 64 when
+ * there are more than 64 subdomains) and, with explicit inverses,
  * work-groups per compute unit of the inverse formation (1-4 FP32, 1-2
- * FP64); runs asdg_factor 3 times per candidate and leaves the problem
- * factorised. ASDG_AUTOTUNE_LOCAL (after
+ * FP64); runs asdg_factor up to 3 times per candidate and leaves the
+ * problem factorised. ASDG_AUTOTUNE_LOCAL (after
  * asdg_factor, or together with FACTOR): waves per work-group of the packed
  * apply (1, 2, 4, 8) or work-groups per compute unit of the triangular
  * sweeps (1-4); overwrites the solver's internal vectors (not the factors

@@ -1278,8 +1278,8 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
 }
 
 // Launch-shape autotuner: every candidate is timed on this problem with
-// HIP events on the caller's stream (median of three runs), the fastest is
-// kept. The candidates change only which work-group does which task, never
+// HIP events on the caller's stream (median of three runs; one run when it
+// takes more than 20 ms), the fastest is kept. The candidates change only which work-group does which task, never
 // the arithmetic, so results are the same for every choice.
 asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tune_report* rep) {
   if (!pb) return ASDG_EINVAL;
@@ -1321,11 +1321,14 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     for (int c : cand) {
       *knob = c;
       float t[3];
-      for (float& x : t) {
-        asdg_status e = run(x);
-        if (e != ASDG_OK) return e;
+      asdg_status e = run(t[0]);
+      if (e != ASDG_OK) return e;
+      float m = t[0];
+      if (t[0] < 20.0f) {  // short runs: median of three
+        for (int k = 1; k < 3; ++k)
+          if ((e = run(t[k])) != ASDG_OK) return e;
+        m = median3(t[0], t[1], t[2]);
       }
-      const float m = median3(t[0], t[1], t[2]);
       ++R.candidates;
       if (m < best_ms) {
         best_ms = m;
@@ -1349,8 +1352,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
         return time_factor(ms1);
       };
       std::vector<int> cand{0};
-      for (int c : {256, 64, 16})
-        if (c < pb->A.n_sub) cand.push_back(c);
+      if (pb->A.n_sub > 64) cand.push_back(64);
       e = tune(&chunk, cand, reorder, ms);
       if (e != ASDG_OK) return e;
       pb->task_chunk = chunk;

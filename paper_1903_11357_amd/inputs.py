@@ -474,6 +474,10 @@ def make_config(name: str) -> Problem:
         return voronoi_problem(16384, 1, p=2, bx=8, by=8, q=1, name="C2")
     if name == "C3":
         return voronoi_problem(65536, 2, p=3, bx=16, by=16, q=2, warped=True, name="C3")
+    if name == "C3x":
+        # labelled extra at ~1M DoFs: C3's design (256 warped bins, nested q=2) on 104858 cells,
+        # p=3, 1048580 DoFs, subdomains of 2060..8920 DoFs
+        return voronoi_problem(104858, 4, p=3, bx=16, by=16, q=2, warped=True, name="C3x")
     if name == "C4":
         return voronoi_problem(131072, 3, p=2, bx=32, by=16, q=1, nonnested_coarse=64,
                                log10_rho_range=4.0, f=f_one, name="C4")

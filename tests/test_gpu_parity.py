@@ -19,6 +19,8 @@ CASES = {
                                                   log10_rho_range=1.0),
     # larger subdomains (> 10 tile rows): 2x2 bins of 1200 cells at p=2 (~1800 DoFs)
     "vor_p2_big": lambda: I.voronoi_problem(1200, 12, p=2, bx=2, by=2, q=2),
+    # the highest degree the library takes: p=4 (15 DoFs per cell), 4 ragged subdomains, nested q=3
+    "vor_p4_q3": lambda: I.voronoi_problem(150, 9, p=4, bx=2, by=2, q=3),
 }
 
 _cache = {}
@@ -291,6 +293,9 @@ SMALL_CASES = {
                                                               log10_rho_range=2.0)),
     # ragged multi-element subdomains of 6..36 DoFs, Voronoi p=1, 8x8 bins, nested q=1
     "vor_small_bins": lambda: I.voronoi_problem(400, 22, p=1, bx=8, by=8, q=1),
+    # one element per subdomain at p=4 (n_i = 15), independent coarse Voronoi q=2
+    "vor_p4_per_element": lambda: _per_element(I.voronoi_problem(200, 23, p=4, bx=2, by=2, q=2,
+                                                                 nonnested_coarse=6)),
 }
 
 
