@@ -104,6 +104,19 @@ class Server:
         self.peak_bytes = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
+        # the host workers already run in parallel: BLAS inside user load
+        # callbacks stays single-threaded meanwhile (no oversubscription)
+        try:
+            from threadpoolctl import threadpool_limits
+        except ImportError:  # pragma: no cover
+            import contextlib
+
+            def threadpool_limits(limits):
+                return contextlib.nullcontext()
+        with threadpool_limits(limits=1):
+            return self._run(requests)
+
+    def _run(self, requests: List[Request]) -> List[Request]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         pool = cf.ThreadPoolExecutor(max_workers=self.setup_workers)
         t0 = time.perf_counter()
