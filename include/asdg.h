@@ -268,12 +268,16 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * queue order of the factorisation and inverse-formation tasks, 0 = all
  * subdomains interleaved (longest remaining path first), c > 0 = groups of
  * c consecutive subdomains one after the other (a smaller working set);
- * after asdg_bind it takes effect at the next asdg_factor.
+ * after asdg_bind it takes effect at the next asdg_factor. HOST_THREADS:
+ * at most this many host threads for asdg_assemble / asdg_assemble_tet /
+ * asdg_plan on this handle (0 = hardware threads, at most 16), for callers
+ * that already run several handles' setup in parallel.
  * No launch shape changes the arithmetic: results are identical for every
  * setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
        ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
-       ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9 };
+       ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9,
+       ASDG_TUNE_HOST_THREADS = 10 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Launch shapes chosen by asdg_autotune and the best times measured. */

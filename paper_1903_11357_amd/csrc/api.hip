@@ -133,6 +133,7 @@ struct asdg_problem {
   int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
   int inv_per_cu = 0, symv_waves = 0;                                // 0: defaults
   int task_chunk = 0;        // subdomains per group of the factorisation task order (0: all at once)
+  int host_threads = 0;      // cap on host threads of assembly and planning (0: default)
   bool tasks_dirty = false;  // task lists reordered after asdg_bind, not yet uploaded
   int local_inverse = 0, inv_planned = 0;  // explicit local inverses (set before asdg_plan)
   // small-subdomain mode: every n_i <= TILE; A_i^{-1} stored whole (n_i^2 words at subs[i].tile0) and
@@ -214,6 +215,7 @@ asdg_status asdg_assemble(asdg_problem* pb, const asdg_mesh* fine, int32_t p, do
   pb->stage = 0;
   pb->coarse_ready = false;
   MeshView mv{fine->n_vertices, fine->xy, fine->n_cells, fine->cell_ptr, fine->cell_vertices};
+  HostThreadCap cap(pb->host_threads);
   std::string e = assemble_sipg(mv, p, c_sigma, rho, subdomain, f, f_user, pb->A);
   if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
   const int np = pb->A.np;
@@ -235,6 +237,7 @@ asdg_status asdg_assemble_tet(asdg_problem* pb, const asdg_tet_mesh* fine, int32
   pb->stage = 0;
   pb->coarse_ready = false;
   TetView tv{fine->n_vertices, fine->xyz, fine->n_cells, fine->tets};
+  HostThreadCap cap(pb->host_threads);
   std::string e = assemble_sipg_tet(tv, p, c_sigma, rho, subdomain, f, f_user, pb->A);
   if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
   const int np = pb->A.np;
@@ -725,6 +728,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
                       const asdg_mesh* coarse_mesh, size_t bytes[4]) {
   if (!pb) return ASDG_EINVAL;
   if (pb->stage < 1) FAIL(pb, ASDG_ESTATE, "asdg_plan before asdg_assemble");
+  HostThreadCap cap(pb->host_threads);
   if (precision != ASDG_FP64 && precision != ASDG_FP32_LOCAL) FAIL(pb, ASDG_EINVAL, "unknown precision");
   if (!bytes) FAIL(pb, ASDG_EINVAL, "bytes is null");
   if (q < 0 || q > pb->A.p) FAIL(pb, ASDG_EINVAL, "coarse degree q must satisfy 1 <= q <= p (or 0: no coarse level)");
@@ -1260,6 +1264,7 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_SMALL_OFF) pb->small_off = value ? 1 : 0;
   else if (what == ASDG_TUNE_NO_PRECOND) pb->no_precond = value ? 1 : 0;
   else if (what == ASDG_TUNE_INV_WG_PER_CU) pb->inv_per_cu = value;
+  else if (what == ASDG_TUNE_HOST_THREADS) pb->host_threads = value;
   else if (what == ASDG_TUNE_TASK_CHUNK) {
     pb->task_chunk = value;
     if (pb->stage >= 2 && !pb->small) {

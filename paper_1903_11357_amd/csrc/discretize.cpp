@@ -32,9 +32,17 @@
 
 namespace asdg {
 
+namespace {
+thread_local int tl_thread_cap = 0;
+}
+
+HostThreadCap::HostThreadCap(int n) : prev_(tl_thread_cap) { tl_thread_cap = n; }
+HostThreadCap::~HostThreadCap() { tl_thread_cap = prev_; }
+
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
   unsigned hw = std::thread::hardware_concurrency();
   int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 16));
+  if (tl_thread_cap > 0) nt = std::min<int64_t>(nt, tl_thread_cap);
   if (n < 2048 || nt == 1) {
     fn(0, n);
     return;

@@ -112,6 +112,17 @@ std::string build_coarse_tet(const TetView& fine, const Assembled& A, int q, con
 
 // ---- shared by the 2D and 3D builders (internal)
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn);
+
+// Caps the threads parallel_for starts from the calling thread while the
+// object lives (0 = the default: hardware threads, at most 16).
+class HostThreadCap {
+ public:
+  explicit HostThreadCap(int n);
+  ~HostThreadCap();
+
+ private:
+  int prev_;
+};
 bool spd_solve(int n, std::vector<double> M, double* B, int k);
 std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::vector<std::pair<int32_t, int32_t>>& pm,
                             const std::vector<double>& vol, const std::vector<double>& rhs_c,

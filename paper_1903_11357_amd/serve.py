@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import dataclasses
+import os
 import time
 from typing import List, Optional
 
@@ -57,9 +58,11 @@ class _Active:
         self.stream = stream
 
 
-def _host_setup(req, precision, local_inverse):
+def _host_setup(req, precision, local_inverse, host_threads=0):
     P = req.problem
     pr = asdg.Problem()
+    if host_threads:
+        pr.set_tuning(asdg.TUNE_HOST_THREADS, host_threads)
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
     if local_inverse:
         pr.set_tuning(asdg.TUNE_LOCAL_INVERSE, 1)
@@ -84,7 +87,7 @@ class Server:
     def __init__(self, device="cuda:0", precision=asdg.FP32_LOCAL, hbm_budget: Optional[int] = None,
                  max_active: int = 16, check_every: int = 16, setup_workers: int = 4,
                  keep_solutions: bool = False, rtol: float = 1e-8, max_iter: int = 20000,
-                 local_inverse: bool = False):
+                 local_inverse: bool = False, host_threads: Optional[int] = None):
         import torch
 
         self.device = torch.device(device)
@@ -100,6 +103,15 @@ class Server:
         self.rtol = rtol
         self.max_iter = max_iter
         self.local_inverse = local_inverse
+        # host threads per request setup: each worker's share of the host
+        # (OMP_NUM_THREADS when set, as on shared machines, else the CPUs
+        # this process may run on)
+        if host_threads is None:
+            share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+            if share <= 0:
+                share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+            host_threads = max(1, share // max(1, setup_workers))
+        self.host_threads = host_threads
         self.peak_active = 0
         self.peak_bytes = 0
 
@@ -132,7 +144,8 @@ class Server:
                 # arrivals -> host assembly
                 while nxt < len(reqs) and reqs[nxt].arrival <= t:
                     r = reqs[nxt]
-                    preparing.append((r, pool.submit(_host_setup, r, self.precision, self.local_inverse)))
+                    preparing.append((r, pool.submit(_host_setup, r, self.precision, self.local_inverse,
+                                                     self.host_threads)))
                     nxt += 1
                 # admission in arrival order (no overtaking)
                 while preparing and preparing[0][1].done() and len(active) < self.max_active:
