@@ -144,3 +144,40 @@ def test_tet_input_validation():
     pr.assemble(P.mesh, 1, 10.0, P.rho, P.subdomain, P.f)
     with pytest.raises(asdg.AsdgError):
         pr.plan(asdg.FP64, 1, coarse_mesh=I.square_mesh(2))  # tetrahedra take nested agglomerates only
+
+
+def test_host_thread_cap_gives_identical_assembly():
+    """ASDG_TUNE_HOST_THREADS only changes how many host threads assemble:
+    operator, load vector and coarse operator are bitwise the same."""
+    P = I.voronoi_problem(3000, 31, p=2, bx=3, by=3, q=1, log10_rho_range=2.0)
+    out = []
+    for threads in (0, 1, 3):
+        pr = asdg.Problem()
+        pr.set_tuning(asdg.TUNE_HOST_THREADS, threads)
+        pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+        pr.plan(asdg.FP64, P.q, coarse_of_cell=P.coarse_of_cell)
+        A = pr.export_operator()
+        A.sort_indices()
+        out.append((A.indptr, A.indices, A.data, pr.export_rhs(), pr.export_coarse()))
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_tuning_and_autotune_argument_errors():
+    """Host-side checks of the launch-shape settings and the autotuner (no
+    device needed: they fail before any device work)."""
+    pr = asdg.Problem()
+    with pytest.raises(asdg.AsdgError):
+        pr.set_tuning(asdg.TUNE_SYMV_WAVES, 3)
+    with pytest.raises(asdg.AsdgError):
+        pr.set_tuning(99, 1)
+    with pytest.raises(asdg.AsdgError):
+        pr.set_tuning(asdg.TUNE_HOST_THREADS, -1)
+    for w in (0, 1, 2, 4, 8):
+        pr.set_tuning(asdg.TUNE_SYMV_WAVES, w)
+    L = asdg.lib()
+    rep = asdg.TuneReport()
+    assert L.asdg_autotune(pr.h, asdg.AUTOTUNE_FACTOR, None, ctypes.byref(rep)) == asdg.ESTATE  # not bound
+    assert L.asdg_autotune(pr.h, 4, None, ctypes.byref(rep)) == asdg.EINVAL
+    assert L.asdg_autotune(None, asdg.AUTOTUNE_LOCAL, None, None) == asdg.EINVAL
