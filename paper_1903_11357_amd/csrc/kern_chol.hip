@@ -62,20 +62,20 @@ __global__ __launch_bounds__(256, 2) void k_cholesky(int32_t n_tasks, const int4
 
     TileRegs<T> ga, gb;
     if (j > 0) {
-      wait_flag(fl + rb, st);
-      wait_flag(fl + rj, st);
+      wait_flags(fl + rb, fl + rj, st);
       ga.load_coherent(base + (size_t)rb * TT);
       gb.load_coherent(base + (size_t)rj * TT);
     }
     for (int k = 0; k < j; ++k) {
       ga.put(As);
       gb.put(Bs);
-      __syncthreads();
+      // the barrier of the wait also makes the tiles just written visible to all waves
       if (k + 1 < j) {
-        wait_flag(fl + rb + k + 1, st);
-        wait_flag(fl + rj + k + 1, st);
+        wait_flags(fl + rb + k + 1, fl + rj + k + 1, st);
         ga.load_coherent(base + (size_t)(rb + k + 1) * TT);
         gb.load_coherent(base + (size_t)(rj + k + 1) * TT);
+      } else {
+        __syncthreads();
       }
       acc.mma(As, Bs, R0, C0, lane, T(-1));
       __syncthreads();

@@ -63,12 +63,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_inv_lower(int32
       for (int k = j; k < b; ++k) {
         gl.put(As);    // L_bk
         gx.put_t(Bs);  // Bs[c][m] = X_kj[m][c]
-        __syncthreads();
+        // the barrier of the wait also makes the tiles just written visible to all waves
         if (k + 1 < b) {
           wait_flag(fl + (k + 1) * (k + 2) / 2 + j, st);
           gl.load(Lb + (size_t)(b * (b + 1) / 2 + k + 1) * TT);
           gx.load_coherent(Xb + (size_t)((k + 1) * (k + 2) / 2 + j) * TT);
         } else {
+          __syncthreads();
           gl.load(Lb + (size_t)(b * (b + 1) / 2 + b) * TT);  // D_b, for the last product
         }
         acc.mma(As, Bs, R0, C0, lane, T(1));

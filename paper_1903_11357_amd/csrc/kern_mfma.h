@@ -69,6 +69,20 @@ struct Quad<double> {
   }
 };
 
+// Thread 0 waits (bounded) until both flags are raised; one barrier.
+__device__ __forceinline__ void wait_flags(const int32_t* f0, const int32_t* f1, DevState* st) {
+  if (threadIdx.x == 0) {
+    int ok = load_agent(f0) != 0 && load_agent(f1) != 0;
+    for (int64_t budget = WAIT_BUDGET; !ok && budget > 0; --budget) {
+      __builtin_amdgcn_s_sleep(2);
+      ok = load_agent(f0) != 0 && load_agent(f1) != 0;
+      if (!ok && (budget & 255) == 0 && load_agent(&st->abort)) break;
+    }
+    if (!ok) store_agent(&st->abort, 1);
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void wait_flag(const int32_t* f, DevState* st) {
   if (threadIdx.x == 0) {
     int ok = load_agent(f) != 0;
