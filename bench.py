@@ -63,7 +63,7 @@ def measured_traffic(workload, mode, local="sweeps"):
     kern = "k_symv" if local == "inverse" else "k_trsv"
     path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_{mode}_hbm_traffic.md")
     src = os.path.join(ROOT, "paper_1903_11357_amd", "csrc",
-                       "kern_inv.hip" if local == "inverse" else "kern_trsv.hip")
+                       "kern_symv.hip" if local == "inverse" else "kern_trsv.hip")
     if not os.path.exists(path):
         return None
     meta = {}

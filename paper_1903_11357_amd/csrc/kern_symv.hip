@@ -1,0 +1,153 @@
+// Application of the explicit local inverses S_i = A_i^{-1} (the exact
+// local solvers of Sec. 3 applied as one packed symmetric matrix-vector
+// product per subdomain): z_i = S_i r_i.
+//
+// Every lower tile S_bj (b > j) is read once and contributes S_bj r_j to
+// block row b and S_bj^T r_b to block row j; the diagonal tiles (stored
+// whole) contribute S_bb r_b. This kernel writes these 64-vectors per tile;
+// the prolongation kernel adds them per DoF in a fixed order (deterministic,
+// no atomics). No sequential chain: every tile is independent.
+#include "kern_common.h"
+
+namespace asdg {
+
+namespace {
+
+constexpr size_t TT = (size_t)TILE * TILE;
+
+// One wave per stored tile S_bj. Lane l = 16 r0 + c4 holds rows r0 + 4k
+// (k < 16), columns 4 c4 .. 4 c4 + 3 of the tile: every load instruction of
+// the wave reads four whole 256-byte rows. The 64 row sums (S_bj r_j) and the
+// 64 column sums (S_bj^T r_b) are finished by butterfly reduce-scatters over
+// lane bits 0-3 and 4-5, so each lane ends with one row sum (row r0 + 4 c4)
+// and one column sum (column 4 c4 + r0): no LDS reduction, no barrier.
+// The FP32 tiles are streamed with non-temporal loads (they are read once
+// per application); for FP64 plain loads measured faster.
+template <typename T>
+struct TileRow;
+template <>
+struct TileRow<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static void load(const float* p, float (&o)[4]) {
+    const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+  __device__ static void lds4(const float* p, float (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct TileRow<double> {
+  __device__ static void load(const double* p, double (&o)[4]) {
+    const double2 u = reinterpret_cast<const double2*>(p)[0], v = reinterpret_cast<const double2*>(p)[1];
+    o[0] = u.x;
+    o[1] = u.y;
+    o[2] = v.x;
+    o[3] = v.y;
+  }
+  __device__ static void lds4(const double* p, double (&o)[4]) { load(p, o); }
+};
+
+// Phase 1: part[t] = (S_bj r_j, S_bj^T r_b) for tile t = (b, j); the second
+// half is written only for off-diagonal tiles (diagonal tiles are stored
+// whole). Entries of r beyond the subdomain's n are taken as zero.
+// WPB waves (tiles) per work-group, a launch-shape choice of the autotuner.
+template <typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
+                                                         const SubDesc* __restrict__ subs, const T* __restrict__ S,
+                                                         const double* __restrict__ r, T* __restrict__ part,
+                                                         const DevState* st) {
+  __shared__ __align__(16) T s_r[WPB][2 * TILE];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * WPB + w;
+  if ((st && st->done) || t >= n_tiles) return;
+  const int c4 = lane & 15, r0 = lane >> 4;
+  T a[16][4];
+  const T* base = S + (size_t)t * TT + r0 * TILE + 4 * c4;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) TileRow<T>::load(base + 4 * TILE * k, a[k]);
+  const int4 m = meta[t];
+  const SubDesc sd = subs[m.x];
+  const int b = m.y, j = m.z;
+  const int gj = j * TILE + lane, gb = b * TILE + lane;
+  T* sr = s_r[w];
+  sr[lane] = gj < sd.n ? (T)r[sd.dof0 + gj] : T(0);
+  // r_b stored so that rows r0 + 4k (k = 0..15) are contiguous at 16 r0
+  sr[TILE + (lane & 3) * 16 + (lane >> 2)] = gb < sd.n ? (T)r[sd.dof0 + gb] : T(0);
+  wave_sync();
+  T rj[4], rb[16];
+  TileRow<T>::lds4(sr + 4 * c4, rj);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T v[4];
+    TileRow<T>::lds4(sr + TILE + 16 * r0 + 4 * q, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rb[4 * q + e] = v[e];
+  }
+  T ra[16], ca[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    ra[k] = a[k][0] * rj[0] + a[k][1] * rj[1] + a[k][2] * rj[2] + a[k][3] * rj[3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ca[c] += a[k][c] * rb[k];
+  }
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1) {
+    const bool hi = lane & h;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const T send = hi ? ra[i] : ra[i + h];
+      const T keep = hi ? ra[i + h] : ra[i];
+      ra[i] = keep + __shfl_xor(send, h, 64);
+    }
+  }
+#pragma unroll
+  for (int h = 2; h >= 1; h >>= 1) {
+    const bool hi = lane & (16 * h);
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const T send = hi ? ca[i] : ca[i + h];
+      const T keep = hi ? ca[i + h] : ca[i];
+      ca[i] = keep + __shfl_xor(send, 16 * h, 64);
+    }
+  }
+  T* pt = part + (size_t)t * 2 * TILE;
+  pt[r0 + 4 * c4] = ra[0];
+  if (j < b) pt[TILE + 4 * c4 + r0] = ca[0];
+}
+
+}  // namespace
+
+template <int WPB>
+static void symv_tiles_wpb(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
+                           const double* r, void* part, const DevState* st, hipStream_t s) {
+  const dim3 g((n_tiles + WPB - 1) / WPB), bl(64 * WPB);
+  if (f32)
+    hipLaunchKernelGGL((k_symv_tiles<float, WPB>), g, bl, 0, s, n_tiles, meta, subs, (const float*)S, r,
+                       (float*)part, st);
+  else
+    hipLaunchKernelGGL((k_symv_tiles<double, WPB>), g, bl, 0, s, n_tiles, meta, subs, (const double*)S, r,
+                       (double*)part, st);
+}
+
+hipError_t launch_symv_tiles(int f32, int waves, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
+                             const double* r, void* part, const DevState* st, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (waves) {
+    case 1: symv_tiles_wpb<1>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    case 2: symv_tiles_wpb<2>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    case 4: symv_tiles_wpb<4>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    case 8: symv_tiles_wpb<8>(f32, n_tiles, meta, subs, S, r, part, st, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace asdg

@@ -99,7 +99,8 @@ hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* tile_meta, c
 hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
                            int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
 
-// Explicit local inverses and their packed symmetric apply (kern_inv.hip).
+// Explicit local inverses (kern_inv.hip) and their packed symmetric apply
+// (kern_symv.hip).
 hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
                           const SubDesc* subs, void* L, void* X, int32_t* flags, DevState* st, int32_t* queue,
                           int grid_lower, int grid_gram, hipStream_t s);
