@@ -3,10 +3,12 @@
 // product per subdomain): z_i = S_i r_i.
 //
 // Every lower tile S_bj (b > j) is read once and contributes S_bj r_j to
-// block row b and S_bj^T r_b to block row j; the diagonal tiles (stored
-// whole) contribute S_bb r_b. This kernel writes these 64-vectors per tile;
-// the prolongation kernel adds them per DoF in a fixed order (deterministic,
-// no atomics). No sequential chain: every tile is independent.
+// block row b and S_bj^T r_b to block row j. The diagonal tiles are stored
+// whole but read only on and below the diagonal: with L_b that lower part,
+// S_bb r_b = L_b r_b + (L_b - diag)^T r_b, again a row-sum and a column-sum
+// vector. This kernel writes these 64-vectors per tile; the prolongation
+// kernel adds them per DoF in a fixed order (deterministic, no atomics). No
+// sequential chain: every tile is independent.
 #include "kern_common.h"
 
 namespace asdg {
@@ -69,13 +71,24 @@ __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const 
   const int t = blockIdx.x * WPB + w;
   if ((st && st->done) || t >= n_tiles) return;
   const int c4 = lane & 15, r0 = lane >> 4;
+  const int4 m = meta[t];
+  const int b = m.y, j = m.z;
+  const bool diag = j == b;
+  // diagonal tiles: rows r0 + 4k are read only in the 16-byte pieces that
+  // reach the diagonal (column offset 4 c4 - 4k <= r0)
+  const int cut = diag ? 4 * c4 - r0 : -64;
   T a[16][4];
   const T* base = S + (size_t)t * TT + r0 * TILE + 4 * c4;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) TileRow<T>::load(base + 4 * TILE * k, a[k]);
-  const int4 m = meta[t];
+  for (int k = 0; k < 16; ++k) {
+    if (cut <= 4 * k) {
+      TileRow<T>::load(base + 4 * TILE * k, a[k]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[k][e] = T(0);
+    }
+  }
   const SubDesc sd = subs[m.x];
-  const int b = m.y, j = m.z;
   const int gj = j * TILE + lane, gb = b * TILE + lane;
   T* sr = s_r[w];
   sr[lane] = gj < sd.n ? (T)r[sd.dof0 + gj] : T(0);
@@ -91,12 +104,20 @@ __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const 
 #pragma unroll
     for (int e = 0; e < 4; ++e) rb[4 * q + e] = v[e];
   }
+  // diagonal tiles: row sums over columns c <= r, column sums over rows
+  // r > c (with cut + e = c - r for the element (r, c) = (r0 + 4k, 4 c4 + e))
   T ra[16], ca[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    ra[k] = a[k][0] * rj[0] + a[k][1] * rj[1] + a[k][2] * rj[2] + a[k][3] * rj[3];
+    T lo[4], sl[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) ca[c] += a[k][c] * rb[k];
+    for (int e = 0; e < 4; ++e) {
+      lo[e] = cut + e <= 4 * k ? a[k][e] : T(0);
+      sl[e] = cut + e < 4 * k ? a[k][e] : T(0);
+    }
+    ra[k] = lo[0] * rj[0] + lo[1] * rj[1] + lo[2] * rj[2] + lo[3] * rj[3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ca[c] += sl[c] * rb[k];
   }
 #pragma unroll
   for (int h = 8; h >= 1; h >>= 1) {
@@ -120,7 +141,7 @@ __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const 
   }
   T* pt = part + (size_t)t * 2 * TILE;
   pt[r0 + 4 * c4] = ra[0];
-  if (j < b) pt[TILE + 4 * c4 + r0] = ca[0];
+  pt[TILE + 4 * c4 + r0] = ca[0];
 }
 
 }  // namespace

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_restrict(int32_t n_coarse, int splits, 
 // z = z_loc + P_0 z0 (either part optional), and r.z. The local part is
 // (L = 0) a vector zl; (L = 1) the sum, in a fixed order, of the packed
 // symmetric apply's per-tile partial vectors for the DoF's row:
-//   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>b} part(j,b).cols[rho]
+//   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>=b} part(j,b).cols[rho]
 // with d = dof0 + 64 b + rho in its subdomain; or (L = 2) row `loc` of a
 // small subdomain's whole inverse times r_i (n_i <= 64 terms, FP64 sums);
 // or (L = 3) r itself (identity preconditioner, no coarse part).
@@ -255,6 +255,7 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
       const int b = loc / TILE, rho = loc - b * TILE;
       const T* pr = part + (size_t)(sd.tile0 + b * (b + 1) / 2) * 2 * TILE + rho;
       for (int j = 0; j <= b; ++j) v += (double)pr[(size_t)j * 2 * TILE];
+      v += (double)pr[(size_t)b * 2 * TILE + TILE];  // strictly lower part of the diagonal tile, transposed
       for (int j = b + 1; j < sd.nb; ++j)
         v += (double)part[(size_t)(sd.tile0 + j * (j + 1) / 2 + b) * 2 * TILE + TILE + rho];
     } else if (zl) {

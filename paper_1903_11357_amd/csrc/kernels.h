@@ -105,8 +105,9 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
                           const SubDesc* subs, void* L, void* X, int32_t* flags, DevState* st, int32_t* queue,
                           int grid_lower, int grid_gram, hipStream_t s);
 // Phase 1 of the packed symmetric apply: per stored tile (b, j), the row
-// sums S_bj r_j and (b > j) the column sums S_bj^T r_b; summed per DoF by
-// launch_prolong with LocalParts. waves: tiles (waves) per work-group, 1,
+// sums S_bj r_j and the column sums S_bj^T r_b (diagonal tiles: row sums of
+// the lower triangle with the diagonal, column sums of the strict lower
+// triangle); summed per DoF by launch_prolong with LocalParts. waves: tiles (waves) per work-group, 1,
 // 2, 4 or 8 (hipErrorInvalidValue otherwise).
 hipError_t launch_symv_tiles(int f32, int waves, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
                              const double* r, void* part, const DevState* st, hipStream_t s);
