@@ -286,6 +286,7 @@ typedef struct {
   double factor_ms; /* asdg_factor with the chosen shapes (0 if not tuned) */
   double local_ms;  /* one batched local solve with the chosen shape (0 if not tuned) */
   int32_t candidates; /* configurations timed */
+  int32_t from_cache; /* 1: shapes taken from the process's tuning cache, nothing timed */
 } asdg_tune_report;
 
 /* Own launch-shape autotuner (the batched factorisation and local-solve
@@ -305,10 +306,26 @@ typedef struct {
  * or the coarse level). Problems whose subdomains all have at most 64 DoFs
  * (whole small inverses) have no such launches: nothing is timed. Results
  * of later solves are identical for every choice. rep may be NULL.
+ * Results of a FACTOR | LOCAL run are kept in a process-wide cache keyed
+ * by device architecture, precision, local-solve representation and size
+ * class (subdomain count to a power of two, largest and mean tile rows per
+ * subdomain). With ASDG_AUTOTUNE_REUSE and a cache hit nothing is timed:
+ * the cached shapes are applied (and asdg_factor run once for FACTOR) and
+ * rep->from_cache is 1.
  * Errors: EINVAL (flags), ESTATE (stage, or a solve in progress), EHIP,
  * and those of asdg_factor. */
-enum { ASDG_AUTOTUNE_FACTOR = 1, ASDG_AUTOTUNE_LOCAL = 2 };
+enum { ASDG_AUTOTUNE_FACTOR = 1, ASDG_AUTOTUNE_LOCAL = 2, ASDG_AUTOTUNE_REUSE = 4 };
 asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tune_report* rep);
+
+/* The tuning cache as text, one line per size class (key, then Cholesky,
+ * inverse-formation and sweep work-groups per CU, packed-apply waves,
+ * task-order chunk, best factorisation and local-solve ms). save writes
+ * the whole cache (EINVAL if the file cannot be written); load adds the
+ * entries of a file written by save (n_entries: how many; EINVAL and
+ * nothing added if it cannot be read or a line is malformed). Both are
+ * safe to call from any thread. */
+asdg_status asdg_tune_cache_save(const char* path);
+asdg_status asdg_tune_cache_load(const char* path, int32_t* n_entries);
 
 /* Task trace of the last batched local solve launched while
  * ASDG_TUNE_TRACE = 1 (profiling aid). tasks: [n][4] int32 (subdomain,

@@ -49,7 +49,7 @@ class TuneReport(C.Structure):
     _fields_ = [("chol_wg_per_cu", C.c_int32), ("inv_wg_per_cu", C.c_int32), ("trsv_wg_per_cu", C.c_int32),
                 ("symv_waves", C.c_int32), ("task_chunk", C.c_int32), ("factor_ms", C.c_double),
                 ("local_ms", C.c_double),
-                ("candidates", C.c_int32)]
+                ("candidates", C.c_int32), ("from_cache", C.c_int32)]
 
 
 class TetMesh_(C.Structure):
@@ -88,6 +88,8 @@ _SIGS = {
     "asdg_export_factor_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "asdg_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "asdg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(TuneReport)]),
+    "asdg_tune_cache_save": (C.c_int, [C.c_char_p]),
+    "asdg_tune_cache_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int32)]),
     "asdg_export_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double)]),
     "asdg_pcg_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgOpts), C.c_void_p]),
@@ -98,7 +100,7 @@ _SIGS = {
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
     TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES, TUNE_TASK_CHUNK, TUNE_HOST_THREADS = \
     0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
-AUTOTUNE_FACTOR, AUTOTUNE_LOCAL = 1, 2
+AUTOTUNE_FACTOR, AUTOTUNE_LOCAL, AUTOTUNE_REUSE = 1, 2, 4
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 
 
@@ -377,6 +379,23 @@ class Problem:
         a = np.empty(n0 * n0)
         self._check(self._L.asdg_export_coarse(self.h, _dptr(a, C.c_double)))
         return a.reshape(n0, n0)
+
+
+def tune_cache_save(path: str) -> None:
+    """Writes the process's autotuning cache (asdg_tune_cache_save)."""
+    st = lib().asdg_tune_cache_save(os.fsencode(path))
+    if st != OK:
+        raise AsdgError(st, f"cannot write the tuning cache to {path}")
+
+
+def tune_cache_load(path: str) -> int:
+    """Adds the entries of a saved tuning cache (asdg_tune_cache_load);
+    returns how many."""
+    n = C.c_int32(0)
+    st = lib().asdg_tune_cache_load(os.fsencode(path), C.byref(n))
+    if st != OK:
+        raise AsdgError(st, f"cannot read a tuning cache from {path}")
+    return int(n.value)
 
 
 def setup_problem(P, precision=FP64, device="cuda", factor=True, local_inverse=False, small=True):

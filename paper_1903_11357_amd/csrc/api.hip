@@ -14,7 +14,9 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <cstdio>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "asdg.h"
@@ -134,6 +136,7 @@ struct asdg_problem {
   int inv_per_cu = 0, symv_waves = 0;                                // 0: defaults
   int task_chunk = 0;        // subdomains per group of the factorisation task order (0: all at once)
   int host_threads = 0;      // cap on host threads of assembly and planning (0: default)
+  std::string arch;          // device architecture name (set by asdg_bind)
   bool tasks_dirty = false;  // task lists reordered after asdg_bind, not yet uploaded
   int local_inverse = 0, inv_planned = 0;  // explicit local inverses (set before asdg_plan)
   // small-subdomain mode: every n_i <= TILE; A_i^{-1} stored whole (n_i^2 words at subs[i].tile0) and
@@ -856,6 +859,7 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   hipDeviceProp_t prop;
   HIPCHK(pb, hipGetDeviceProperties(&prop, dev));
   pb->n_cu = std::max(1, prop.multiProcessorCount);
+  pb->arch = prop.gcnArchName;
   if (!pb->side_stream) {
     HIPCHK(pb, hipStreamCreateWithFlags(&pb->side_stream, hipStreamNonBlocking));
     HIPCHK(pb, hipEventCreateWithFlags(&pb->fork_ev, hipEventDisableTiming));
@@ -1282,13 +1286,40 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   return ASDG_OK;
 }
 
+// Autotuner results shared by all handles of the process, keyed by device
+// architecture, precision, local-solve representation and size class
+// (number of subdomains to a power of two, largest and mean tile rows).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, asdg_tune_report> g_tune_cache;
+
+std::string tune_key(const asdg_problem* pb) {
+  double nb_sum = 0.0;
+  int nb_max = 0;
+  for (const SubDesc& d : pb->subs) {
+    nb_sum += d.nb;
+    nb_max = std::max(nb_max, d.nb);
+  }
+  const int ns = (int)pb->subs.size();
+  int ns_log2 = 0;
+  while ((1 << (ns_log2 + 1)) <= ns) ++ns_log2;
+  char k[256];
+  std::snprintf(k, sizeof(k), "%s|%s|%s|ns2^%d|nbmax%d|nbmean%d", pb->arch.empty() ? "?" : pb->arch.c_str(),
+                pb->f32 ? "fp32" : "fp64", pb->inv_planned ? "inverse" : "sweeps", ns_log2, nb_max,
+                (int)std::lround(nb_sum / std::max(ns, 1)));
+  return k;
+}
+}  // namespace
+
 // Launch-shape autotuner: every candidate is timed on this problem with
 // HIP events on the caller's stream (median of three runs; one run when it
 // takes more than 20 ms), the fastest is kept. The candidates change only which work-group does which task, never
 // the arithmetic, so results are the same for every choice.
 asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tune_report* rep) {
   if (!pb) return ASDG_EINVAL;
-  if (what & ~(ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL)) FAIL(pb, ASDG_EINVAL, "unknown autotune flags");
+  if ((what & ~(ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL | ASDG_AUTOTUNE_REUSE)) ||
+      !(what & (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL)))
+    FAIL(pb, ASDG_EINVAL, "autotune flags: FACTOR and/or LOCAL, optionally REUSE");
   if ((what & ASDG_AUTOTUNE_FACTOR) && pb->stage < 3) FAIL(pb, ASDG_ESTATE, "autotune before asdg_bind");
   if ((what & ASDG_AUTOTUNE_LOCAL) && !(what & ASDG_AUTOTUNE_FACTOR) && pb->stage < 4)
     FAIL(pb, ASDG_ESTATE, "autotune of the local solves before asdg_factor");
@@ -1296,6 +1327,43 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   hipStream_t s = (hipStream_t)stream;
   asdg_tune_report R;
   std::memset(&R, 0, sizeof(R));
+  const std::string key = tune_key(pb);
+  if (what & ASDG_AUTOTUNE_REUSE) {
+    asdg_tune_report C;
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        C = it->second;
+        hit = true;
+      }
+    }
+    if (hit) {
+      // the shapes found before for this size class, no timing
+      if (what & ASDG_AUTOTUNE_FACTOR) {
+        pb->chol_per_cu = C.chol_wg_per_cu;
+        pb->inv_per_cu = C.inv_wg_per_cu;
+        if (C.task_chunk != pb->task_chunk && !pb->small) {
+          pb->task_chunk = C.task_chunk;
+          pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, C.task_chunk);
+          if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, C.task_chunk);
+          pb->tasks_dirty = true;
+        }
+        asdg_status e = asdg_factor(pb, stream);
+        if (e != ASDG_OK) return e;
+      }
+      if (what & ASDG_AUTOTUNE_LOCAL) {
+        pb->trsv_per_cu = C.trsv_wg_per_cu;
+        pb->symv_waves = C.symv_waves;
+      }
+      pb->drop_graph();
+      C.candidates = 0;
+      C.from_cache = 1;
+      if (rep) *rep = C;
+      return ASDG_OK;
+    }
+  }
   hipEvent_t e0, e1;
   HIPCHK(pb, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1407,7 +1475,53 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
   R.task_chunk = pb->task_chunk;
   pb->drop_graph();
+  if ((what & (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL)) == (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL) && !pb->small) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = R;
+  }
   if (rep) *rep = R;
+  return ASDG_OK;
+}
+
+asdg_status asdg_tune_cache_save(const char* path) {
+  if (!path) return ASDG_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return ASDG_EINVAL;
+  for (const auto& kv : g_tune_cache) {
+    const asdg_tune_report& R = kv.second;
+    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
+                 R.trsv_wg_per_cu, R.symv_waves, R.task_chunk, R.factor_ms, R.local_ms);
+  }
+  return std::fclose(f) == 0 ? ASDG_OK : ASDG_EINVAL;
+}
+
+asdg_status asdg_tune_cache_load(const char* path, int32_t* n_entries) {
+  if (!path) return ASDG_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return ASDG_EINVAL;
+  std::map<std::string, asdg_tune_report> add;
+  char key[256];
+  asdg_tune_report R;
+  bool ok = true;
+  for (;;) {
+    std::memset(&R, 0, sizeof(R));
+    const int got = std::fscanf(f, "%255s %d %d %d %d %d %lf %lf", key, &R.chol_wg_per_cu, &R.inv_wg_per_cu,
+                                &R.trsv_wg_per_cu, &R.symv_waves, &R.task_chunk, &R.factor_ms, &R.local_ms);
+    if (got == EOF) break;
+    const bool waves_ok = R.symv_waves == 1 || R.symv_waves == 2 || R.symv_waves == 4 || R.symv_waves == 8;
+    if (got != 8 || !waves_ok || R.chol_wg_per_cu < 1 || R.chol_wg_per_cu > 64 || R.inv_wg_per_cu < 1 ||
+        R.inv_wg_per_cu > 64 || R.trsv_wg_per_cu < 1 || R.trsv_wg_per_cu > 64 || R.task_chunk < 0) {
+      ok = false;
+      break;
+    }
+    add[key] = R;
+  }
+  std::fclose(f);
+  if (!ok) return ASDG_EINVAL;  // nothing is taken from a malformed file
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : add) g_tune_cache[kv.first] = kv.second;
+  if (n_entries) *n_entries = (int32_t)add.size();
   return ASDG_OK;
 }
 

@@ -59,7 +59,7 @@ def test_autotune_local_only_and_errors():
     with pytest.raises(asdg.AsdgError):
         pr.autotune(asdg.AUTOTUNE_LOCAL)  # before asdg_factor
     with pytest.raises(asdg.AsdgError):
-        pr.autotune(4)  # unknown flag
+        pr.autotune(8)  # unknown flag
     with pytest.raises(asdg.AsdgError):
         pr.set_tuning(asdg.TUNE_SYMV_WAVES, 3)
     pr.factor()
@@ -77,3 +77,35 @@ def test_autotune_local_only_and_errors():
         pr.set_tuning(asdg.TUNE_SYMV_WAVES, w)
         xw, _ = pr.solve(rtol=1e-8)
         assert np.array_equal(xw.cpu().numpy(), x0)
+
+
+def test_autotune_cache_reuse_same_size_class(tmp_path):
+    """A second problem of the same size class takes the cached shapes
+    without timing anything, and solves exactly like a tuned one; the cache
+    survives a save / load round trip."""
+    from paper_1903_11357_amd import asdg
+
+    P = _problem()
+    first = asdg.setup_problem(P, asdg.FP32_LOCAL, device="cuda:0", local_inverse=True, factor=False)
+    rep1 = first.autotune(asdg.AUTOTUNE_FACTOR | asdg.AUTOTUNE_LOCAL)
+    assert rep1["from_cache"] == 0 and rep1["candidates"] > 0
+    first.setup_coarse()
+    x1, st1 = first.solve(rtol=1e-8)
+    x1 = x1.cpu().numpy()
+    del first
+
+    second = asdg.setup_problem(P, asdg.FP32_LOCAL, device="cuda:0", local_inverse=True, factor=False)
+    rep2 = second.autotune(asdg.AUTOTUNE_FACTOR | asdg.AUTOTUNE_LOCAL | asdg.AUTOTUNE_REUSE)
+    assert rep2["from_cache"] == 1 and rep2["candidates"] == 0
+    for k in ("chol_wg_per_cu", "inv_wg_per_cu", "symv_waves", "task_chunk"):
+        assert rep2[k] == rep1[k], k
+    second.setup_coarse()
+    x2, st2 = second.solve(rtol=1e-8)
+    assert st2["iterations"] == st1["iterations"]
+    assert np.array_equal(x2.cpu().numpy(), x1)
+
+    path = tmp_path / "tune.txt"
+    asdg.tune_cache_save(str(path))
+    assert asdg.tune_cache_load(str(path)) >= 1
+    text = path.read_text()
+    assert "|fp32|inverse|" in text
