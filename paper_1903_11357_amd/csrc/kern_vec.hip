@@ -58,6 +58,82 @@ __global__ __launch_bounds__(256) void k_spmv(int32_t N, const int32_t* __restri
   if (red) partial_store(dot, red + RED_PQ, scratch);
 }
 
+// Even n_p (2D p = 2, 3; tetrahedra p = 1, 2, 3): the lanes of a wave in
+// groups of n_p per cell (64 / n_p cells per wave, the remaining lanes
+// idle). Lane a of a cell reads the 16-byte pieces a + n_p i (i < n_p / 2)
+// of each n_p x n_p block, so the group's loads cover contiguous 16 n_p
+// bytes; those pieces are rows rho + 2i (rho = 2a / n_p) at columns
+// c = 2 (a mod n_p/2), c + 1, and only p[c], p[c+1] of the neighbour are
+// needed. Each lane keeps n_p / 2 partial row sums over all blocks of the
+// row; the n_p / 2 lanes sharing a row parity add them (LDS, fixed order).
+// Column indices are fetched U at a time ahead of the block and p loads.
+template <int NP>
+__global__ __launch_bounds__(256) void k_spmv_even(int32_t N, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ blocks,
+                                                   const double* __restrict__ p, double* __restrict__ q,
+                                                   Reduction* red, const DevState* st) {
+  static_assert(NP % 2 == 0 && NP <= 64, "even block size");
+  constexpr int H = NP / 2, CPW = 64 / NP, U = NP <= 10 ? 4 : 2;
+  __shared__ double scratch[4];
+  __shared__ double s_part[4][CPW * NP * H];
+  if (st && st->done) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ci = lane / NP, a = lane - ci * NP;
+  const int cp = 2 * (a % H);
+  const int ngroups = (N + CPW - 1) / CPW;
+  double* sp = s_part[w];
+  double dot = 0.0;
+  for (int g = blockIdx.x * 4 + w; g < ngroups; g += gridDim.x * 4) {
+    const int cell = g * CPW + ci;
+    const bool on = ci < CPW && cell < N;
+    double acc[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) acc[i] = 0.0;
+    if (on) {
+      const int k0 = row_ptr[cell], k1 = row_ptr[cell + 1];
+      for (int kb = k0; kb < k1; kb += U) {
+        int cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = kb + u < k1 ? col[kb + u] : -1;
+        double2 pv[U], bb[U][H];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (cc[u] >= 0) {
+            pv[u] = *reinterpret_cast<const double2*>(p + (size_t)cc[u] * NP + cp);
+            const double2* B = reinterpret_cast<const double2*>(blocks + (size_t)(kb + u) * NP * NP) + a;
+#pragma unroll
+            for (int i = 0; i < H; ++i) bb[u][i] = B[NP * i];
+          } else {
+            pv[u] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int i = 0; i < H; ++i) bb[u][i] = make_double2(0.0, 0.0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int i = 0; i < H; ++i) acc[i] += bb[u][i].x * pv[u].x + bb[u][i].y * pv[u].y;
+      }
+#pragma unroll
+      for (int i = 0; i < H; ++i) sp[(ci * NP + a) * H + i] = acc[i];
+    }
+    wave_sync();
+    if (on) {
+      // row a = (a & 1) + 2 (a >> 1): sum over the lanes of that parity
+      const int rr = a & 1, ii = a >> 1;
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < H; ++m) v += sp[(ci * NP + rr * H + m) * H + ii];
+      const int64_t d = (int64_t)cell * NP + a;
+      q[d] = v;
+      dot += p[d] * v;
+    }
+    wave_sync();
+  }
+  if (red) partial_store(dot, red + RED_PQ, scratch);
+}
+
 // r = permuted b, x = 0, triangular-sweep outputs = sentinel; with `st`,
 // ||b||^2 and the initial PCG state.
 template <typename T>
@@ -326,12 +402,12 @@ hipError_t launch_spmv(int np, int32_t N, const int32_t* row_ptr, const int32_t*
   dim3 g(spmv_parts((int64_t)N * np)), b(256);
   switch (np) {
     case 3: hipLaunchKernelGGL(k_spmv<3>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
-    case 6: hipLaunchKernelGGL(k_spmv<6>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
-    case 10: hipLaunchKernelGGL(k_spmv<10>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 6: hipLaunchKernelGGL(k_spmv_even<6>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 10: hipLaunchKernelGGL(k_spmv_even<10>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     case 15: hipLaunchKernelGGL(k_spmv<15>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     // tetrahedra: p = 1, 3 (p = 2 shares n_p = 10 with p = 3 in 2D)
-    case 4: hipLaunchKernelGGL(k_spmv<4>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
-    case 20: hipLaunchKernelGGL(k_spmv<20>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 4: hipLaunchKernelGGL(k_spmv_even<4>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 20: hipLaunchKernelGGL(k_spmv_even<20>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
