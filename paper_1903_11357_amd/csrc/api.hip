@@ -488,9 +488,13 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
                               iteration ? vec_parts(pb->n()) : 0, s));
     return ASDG_OK;
   }
-  // with a local launch of its own and the dense coarse solve, the coarse
-  // correction runs beside the local solves on the side stream
-  const bool side = pb->has_coarse && pb->coarse_dense && !pb->small && pb->side_stream;
+  // with the dense coarse solve, the coarse correction runs beside the local
+  // solves on the side stream. Small subdomains of at least 10 DoFs get a
+  // launch of their own for that, into q, which is free between the
+  // residual update and the next operator apply; below that the extra
+  // launch and pass over q cost more than the overlap gains (measured), and
+  // their solves stay inside the prolongation.
+  const bool side = pb->has_coarse && pb->coarse_dense && pb->side_stream && (!pb->small || pb->max_n >= 10);
   const hipStream_t sc = side ? pb->side_stream : s;
   if (side) {
     HIPCHK(pb, hipEventRecord(pb->fork_ev, s));
@@ -509,10 +513,15 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
     HIPCHK(pb, hipEventRecord(pb->join_ev, sc));
   }
   if (ev0) HIPCHK(pb, hipEventRecord(ev0, s));
-  if (!pb->small) {  // (small subdomains: the local solves happen inside the prolongation)
+  double* zloc = pb->ptr<double>(3, pb->o3.q);
+  if (!pb->small) {
     asdg_status le = enqueue_local(pb, s, st);
     if (le != ASDG_OK) return le;
-  }
+  } else if (side) {
+    const LocalParts lp = local_parts(pb);
+    HIPCHK(pb, launch_prolong(np, 3, pb->A.n_cells, nullptr, nullptr, nullptr, nullptr, nullptr, &lp, pb->f32, r,
+                              zloc, nullptr, st_done, 0, 0, s));
+  }  // (small subdomains without the side stream: solved inside the prolongation)
   if (ev1) HIPCHK(pb, hipEventRecord(ev1, s));
   if (side) {
     HIPCHK(pb, hipStreamWaitEvent(s, pb->join_ev, 0));
@@ -520,7 +529,11 @@ asdg_status enqueue_precond(asdg_problem* pb, hipStream_t s, DevState* st_done, 
     asdg_status ce = enqueue_coarse_solve(pb, st_done, s);
     if (ce != ASDG_OK) return ce;
   }
-  const LocalParts lp = local_parts(pb);
+  LocalParts lp = local_parts(pb);
+  if (pb->small && side) {
+    lp.part = zloc;
+    lp.small = 3;
+  }
   HIPCHK(pb, launch_prolong(np, pb->has_coarse ? pb->C.nq : 3, pb->A.n_cells,
                             pb->has_coarse ? pb->ptr<int32_t>(2, pb->o2.pptr) : nullptr,
                             pb->ptr<int32_t>(2, pb->o2.pcol), pb->ptr<double>(2, pb->o2.pval),

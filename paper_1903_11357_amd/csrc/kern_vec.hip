@@ -272,7 +272,9 @@ __global__ __launch_bounds__(256) void k_restrict(int32_t n_coarse, int splits, 
 //   z_loc[d] = sum_{j<=b} part(b,j).rows[rho] + sum_{j>=b} part(j,b).cols[rho]
 // with d = dof0 + 64 b + rho in its subdomain; or (L = 2) row `loc` of a
 // small subdomain's whole inverse times r_i (n_i <= 64 terms, FP64 sums);
-// or (L = 3) r itself (identity preconditioner, no coarse part).
+// or (L = 3) r itself (identity preconditioner, no coarse part); or (L = 4)
+// an FP64 vector zd computed before (the small-subdomain solves run as a
+// launch of their own beside the coarse correction).
 //
 // With `red`, partials of r.z. With n_pq > 0 (a PCG iteration), work-group 0
 // also sums the partials of p.Ap and ||r||^2 left by the operator apply and
@@ -285,8 +287,9 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
                                                  const double* __restrict__ z0, const T* __restrict__ zl,
                                                  const int32_t* __restrict__ cell_sub,
                                                  const SubDesc* __restrict__ subs, const T* __restrict__ part,
-                                                 const double* __restrict__ r, double* __restrict__ z,
-                                                 Reduction* red, DevState* st, int n_pq, int n_rr) {
+                                                 const double* __restrict__ zd, const double* __restrict__ r,
+                                                 double* __restrict__ z, Reduction* red, DevState* st, int n_pq,
+                                                 int n_rr) {
   __shared__ double scratch[4];
   if (st && st->done) return;
   if (n_pq > 0 && blockIdx.x == 0) {
@@ -319,6 +322,8 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
     double v = 0.0;
     if (L == 3) {
       v = r[d];  // identity preconditioner (plain CG)
+    } else if (L == 4) {
+      v = zd[d];
     } else if (L == 2) {
       const SubDesc sd = subs[cell_sub[cell]];
       const int loc = (int)(d - sd.dof0);
@@ -475,18 +480,21 @@ static void prolong_tt(int32_t N, const int32_t* pptr, const int32_t* pcol, cons
                        const void* zl, const LocalParts* lp, const double* r, double* z, Reduction* red,
                        DevState* st, int n_pq, int n_rr, hipStream_t s) {
   dim3 g(prolong_parts((int64_t)N * NP)), b(256);
-  if (lp && lp->small == 2)
+  if (lp && lp->small == 3)
+    hipLaunchKernelGGL((k_prolong<NP, NQ, T, 4>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, nullptr, nullptr,
+                       nullptr, (const double*)lp->part, r, z, red, st, n_pq, n_rr);
+  else if (lp && lp->small == 2)
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, 3>), g, b, 0, s, N, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, r, z, red, st, n_pq, n_rr);
+                       nullptr, nullptr, nullptr, r, z, red, st, n_pq, n_rr);
   else if (lp && lp->small)
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, 2>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub, lp->subs,
-                       (const T*)lp->part, r, z, red, st, n_pq, n_rr);
+                       (const T*)lp->part, nullptr, r, z, red, st, n_pq, n_rr);
   else if (lp)
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, 1>), g, b, 0, s, N, pptr, pcol, P, z0, nullptr, lp->cell_sub, lp->subs,
-                       (const T*)lp->part, r, z, red, st, n_pq, n_rr);
+                       (const T*)lp->part, nullptr, r, z, red, st, n_pq, n_rr);
   else
     hipLaunchKernelGGL((k_prolong<NP, NQ, T, 0>), g, b, 0, s, N, pptr, pcol, P, z0, (const T*)zl, nullptr, nullptr,
-                       nullptr, r, z, red, st, n_pq, n_rr);
+                       nullptr, nullptr, r, z, red, st, n_pq, n_rr);
 }
 
 template <int NP, int NQ>

@@ -79,7 +79,8 @@ struct LocalParts {
   const SubDesc* subs;
   const void* part;  // 2*TILE entries per stored tile (rows, then columns); small: the inverses
   int small;         // 1: z_loc = A_i^{-1} r_i from whole small inverses (launch_small_inverse);
-                     // 2: z = r (identity preconditioner; the coarse part is skipped too)
+                     // 2: z = r (identity preconditioner; the coarse part is skipped too);
+                     // 3: z_loc given as an FP64 vector in `part`
 };
 // n_pq > 0: a PCG iteration; work-group 0 sums n_pq partials of p.Ap and
 // n_rr of ||r||^2, counts the iteration and takes the stopping decision.
