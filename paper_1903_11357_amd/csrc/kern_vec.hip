@@ -329,14 +329,18 @@ __global__ __launch_bounds__(256) void k_prolong(int32_t N, const int32_t* __res
       const int loc = (int)(d - sd.dof0);
       const T* Srow = part + sd.tile0 + (size_t)loc * sd.n;
       const double* ri = r + sd.dof0;
+#pragma unroll 8
       for (int b = 0; b < sd.n; ++b) v += (double)Srow[b] * ri[b];
     } else if (L == 1) {
       const SubDesc sd = subs[cell_sub[cell]];
       const int loc = (int)(d - sd.dof0);
       const int b = loc / TILE, rho = loc - b * TILE;
       const T* pr = part + (size_t)(sd.tile0 + b * (b + 1) / 2) * 2 * TILE + rho;
+      // (unrolled so the independent loads are in flight together; the sums stay in order)
+#pragma unroll 8
       for (int j = 0; j <= b; ++j) v += (double)pr[(size_t)j * 2 * TILE];
       v += (double)pr[(size_t)b * 2 * TILE + TILE];  // strictly lower part of the diagonal tile, transposed
+#pragma unroll 8
       for (int j = b + 1; j < sd.nb; ++j)
         v += (double)part[(size_t)(sd.tile0 + j * (j + 1) / 2 + b) * 2 * TILE + TILE + rho];
     } else if (zl) {
