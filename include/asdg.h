@@ -271,13 +271,17 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * after asdg_bind it takes effect at the next asdg_factor. HOST_THREADS:
  * at most this many host threads for asdg_assemble / asdg_assemble_tet /
  * asdg_plan on this handle (0 = hardware threads, at most 16), for callers
- * that already run several handles' setup in parallel.
+ * that already run several handles' setup in parallel. COARSE_PACKED (set
+ * before asdg_plan): storage of the explicit coarse inverse A_0^{-1} (used
+ * for n0 <= 8192): 0 = packed lower tiles from n0 >= 4096 on, dense below
+ * (default); 1 = always packed; 2 = always dense. The packed form is
+ * applied by tiles (half the bytes), the dense one by one product.
  * No launch shape changes the arithmetic: results are identical for every
  * setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
        ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
        ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9,
-       ASDG_TUNE_HOST_THREADS = 10 };
+       ASDG_TUNE_HOST_THREADS = 10, ASDG_TUNE_COARSE_PACKED = 11 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Launch shapes chosen by asdg_autotune and the best times measured. */

@@ -125,9 +125,13 @@ struct asdg_problem {
   struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv, cS, cX, cinv, cmeta, cinvt; } o2{};
   // coarse solve by a dense explicit A_0^{-1} (n0 <= kCoarseDenseMax) instead of the triangular sweeps
   bool coarse_dense = false;
+  // with the explicit inverse: applied from its packed lower tiles (half the
+  // bytes, three small launches) instead of the expanded dense matrix
+  bool coarse_packed = false;
+  int coarse_packed_mode = 0;  // 0: packed from kCoarsePackedMin on, 1: always packed, 2: always dense
   int rsplits = 1;  // work-groups per coarse cell in the restriction (partials added by the dense coarse solve)
   std::vector<int4> cmeta, cinv_tasks;
-  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace, part; } o3{};
+  struct { size_t x, r, p, q, z, yl, zl, r0, y0, z0, red, st, rz2, ah, bh, flags, trace, part, cpart; } o3{};
   size_t bytes[4] = {0, 0, 0, 0};
   char* buf[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t failed_sub = -2;
@@ -387,6 +391,7 @@ void plan_local(asdg_problem* pb) {
 // the two triangular sweeps over the packed factor, without their chain of
 // dependent tile rows.
 constexpr int32_t kCoarseDenseMax = 8192;
+constexpr int32_t kCoarsePackedMin = 4096;  // below, one dense product beats the packed pass and its two extra launches
 
 void plan_coarse_factor(asdg_problem* pb) {
   const int32_t n0 = pb->n0;
@@ -410,6 +415,8 @@ void plan_coarse_factor(asdg_problem* pb) {
   for (int b = 0; b < nb; ++b) pb->ctrsv_tasks.push_back(make_int4(0, 0, b, 0));
   for (int b = nb - 1; b >= 0; --b) pb->ctrsv_tasks.push_back(make_int4(0, 1, b, 0));
   pb->coarse_dense = n0 <= kCoarseDenseMax;
+  pb->coarse_packed = pb->coarse_dense && (pb->coarse_packed_mode == 1 ||
+                                           (pb->coarse_packed_mode == 0 && n0 >= kCoarsePackedMin));
   // restriction: about 512 (entry, row) pairs per work-group, at most 32 work-groups per coarse cell
   if (pb->coarse_dense) {
     const int64_t pairs = (int64_t)pb->C.tptr.back() * pb->A.np;
@@ -431,6 +438,21 @@ void plan_coarse_factor(asdg_problem* pb) {
 
 // z0 = A_0^{-1} r0: dense explicit inverse, or the two triangular sweeps.
 asdg_status enqueue_coarse_solve(asdg_problem* pb, const DevState* st_done, hipStream_t s) {
+  if (pb->coarse_packed) {
+    // r0 (sum of the restriction splits) into y0, the packed symmetric
+    // product by tiles, then the per-entry sums of the tile partials
+    const double* r0 = pb->ptr<double>(3, pb->o3.r0);
+    if (pb->rsplits > 1) {
+      HIPCHK(pb, launch_sum_splits(pb->n0, pb->rsplits, r0, pb->ptr<double>(3, pb->o3.y0), st_done, s));
+      r0 = pb->ptr<double>(3, pb->o3.y0);
+    }
+    HIPCHK(pb, launch_symv_tiles(0, 4, (int32_t)pb->n_ctiles, pb->ptr<int4>(2, pb->o2.cmeta),
+                                 pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.cS), r0,
+                                 pb->ptr<void>(3, pb->o3.cpart), st_done, s));
+    HIPCHK(pb, launch_tile_partials_sum(pb->n0, (pb->n0 + TILE - 1) / TILE, pb->ptr<double>(3, pb->o3.cpart),
+                                        pb->ptr<double>(3, pb->o3.z0), st_done, s));
+    return ASDG_OK;
+  }
   if (pb->coarse_dense) {
     HIPCHK(pb, launch_dense_mv(pb->n0, pb->rsplits, pb->ptr<double>(2, pb->o2.cinv), pb->ptr<double>(3, pb->o3.r0),
                                pb->ptr<double>(3, pb->o3.z0), st_done, s));
@@ -821,7 +843,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
     if (pb->coarse_dense) {
       pb->o2.cS = L2.add(8 * pb->ctiles_host.size());
       pb->o2.cX = L2.add(8 * pb->ctiles_host.size());
-      pb->o2.cinv = L2.add(8 * (size_t)pb->n0 * pb->n0);
+      pb->o2.cinv = pb->coarse_packed ? 0 : L2.add(8 * (size_t)pb->n0 * pb->n0);
       pb->o2.cmeta = L2.add(sizeof(int4) * pb->cmeta.size());
       pb->o2.cinvt = L2.add(sizeof(int4) * pb->cinv_tasks.size());
     }
@@ -839,6 +861,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o3.r0 = L3.add(8 * n0 * (pb->has_coarse ? pb->rsplits : 1));
   pb->o3.y0 = L3.add(8 * n0);
   pb->o3.z0 = L3.add(8 * n0);
+  pb->o3.cpart = L3.add(pb->has_coarse && pb->coarse_packed ? 8 * 2 * TILE * (size_t)pb->n_ctiles : 0);
   pb->o3.red = L3.add(sizeof(Reduction) * N_RED);
   pb->o3.st = L3.add(sizeof(DevState));
   pb->o3.rz2 = L3.add(16);
@@ -1033,7 +1056,8 @@ asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
                               (int32_t)pb->n_ctiles, pb->ptr<int4>(2, pb->o2.cmeta), pb->ptr<SubDesc>(2, pb->o2.csub),
                               pb->ptr<void>(2, pb->o2.cS), pb->ptr<void>(2, pb->o2.cX),
                               pb->ptr<int32_t>(3, pb->o3.flags), st, &st->q_chol, g, g, s));
-    HIPCHK(pb, launch_expand_sym(pb->n0, pb->ptr<double>(2, pb->o2.cS), pb->ptr<double>(2, pb->o2.cinv), s));
+    if (!pb->coarse_packed)
+      HIPCHK(pb, launch_expand_sym(pb->n0, pb->ptr<double>(2, pb->o2.cS), pb->ptr<double>(2, pb->o2.cinv), s));
     DevState h;
     e = read_state(pb, s, h);
     if (e != ASDG_OK) return e;
@@ -1282,6 +1306,10 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_NO_PRECOND) pb->no_precond = value ? 1 : 0;
   else if (what == ASDG_TUNE_INV_WG_PER_CU) pb->inv_per_cu = value;
   else if (what == ASDG_TUNE_HOST_THREADS) pb->host_threads = value;
+  else if (what == ASDG_TUNE_COARSE_PACKED) {
+    if (value > 2) FAIL(pb, ASDG_EINVAL, "coarse inverse storage: 0 automatic, 1 packed, 2 dense");
+    pb->coarse_packed_mode = value;
+  }
   else if (what == ASDG_TUNE_TASK_CHUNK) {
     pb->task_chunk = value;
     if (pb->stage >= 2 && !pb->small) {

@@ -9,6 +9,8 @@
 // vector. This kernel writes these 64-vectors per tile; the prolongation
 // kernel adds them per DoF in a fixed order (deterministic, no atomics). No
 // sequential chain: every tile is independent.
+#include <algorithm>
+
 #include "kern_common.h"
 
 namespace asdg {
@@ -144,7 +146,55 @@ __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const 
   pt[TILE + 4 * c4 + r0] = ca[0];
 }
 
+// Per-DoF sums of the tile partials of one packed symmetric matrix of
+// order n with nb tile rows (tile (b, j) at b(b+1)/2 + j), in the same fixed
+// order as the local solves' prolongation: row sums of tiles (b, 0..b), the
+// diagonal tile's column sums, then column sums of tiles (b+1..nb-1, b).
+__global__ __launch_bounds__(256) void k_tile_partials_sum(int32_t n, int32_t nb, const double* __restrict__ part,
+                                                           double* __restrict__ out, const DevState* st) {
+  if (st && st->done) return;
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < n; d += gridDim.x * blockDim.x) {
+    const int b = d / TILE, rho = d - b * TILE;
+    const double* pr = part + (size_t)(b * (b + 1) / 2) * 2 * TILE + rho;
+    double v = 0.0;
+#pragma unroll 8
+    for (int j = 0; j <= b; ++j) v += pr[(size_t)j * 2 * TILE];
+    v += pr[(size_t)b * 2 * TILE + TILE];
+#pragma unroll 8
+    for (int j = b + 1; j < nb; ++j) v += part[(size_t)(j * (j + 1) / 2 + b) * 2 * TILE + TILE + rho];
+    out[d] = v;
+  }
+}
+
+// out[i] = sum over s < splits of in[s n + i], in order of s.
+__global__ __launch_bounds__(256) void k_sum_splits(int32_t n, int splits, const double* __restrict__ in,
+                                                    double* __restrict__ out, const DevState* st) {
+  if (st && st->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < splits; ++s) v += in[(size_t)s * n + i];
+    out[i] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_tile_partials_sum(int32_t n, int32_t nb, const double* part, double* out, const DevState* st,
+                                    hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if ((int64_t)nb * TILE < n) return hipErrorInvalidValue;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_tile_partials_sum, dim3(grid), dim3(256), 0, s, n, nb, part, out, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_splits(int32_t n, int splits, const double* in, double* out, const DevState* st, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (splits < 1) return hipErrorInvalidValue;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_sum_splits, dim3(grid), dim3(256), 0, s, n, splits, in, out, st);
+  return hipGetLastError();
+}
 
 template <int WPB>
 static void symv_tiles_wpb(int f32, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,

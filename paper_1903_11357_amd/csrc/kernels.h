@@ -112,6 +112,13 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
 // 2, 4 or 8 (hipErrorInvalidValue otherwise).
 hipError_t launch_symv_tiles(int f32, int waves, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
                              const double* r, void* part, const DevState* st, hipStream_t s);
+// Per-DoF sums of the FP64 tile partials of one packed symmetric matrix of
+// order n (nb tile rows), in the fixed order of the local prolongation
+// (the packed coarse inverse).
+hipError_t launch_tile_partials_sum(int32_t n, int32_t nb, const double* part, double* out, const DevState* st,
+                                    hipStream_t s);
+// out[i] = sum_s in[s n + i] (the restriction's split partial vectors).
+hipError_t launch_sum_splits(int32_t n, int splits, const double* in, double* out, const DevState* st, hipStream_t s);
 
 // Subdomains of at most 64 DoFs: A_i^{-1} whole (n_i x n_i row-major) at
 // word offset subs[i].tile0, formed by one wave per subdomain (max_n =
