@@ -202,6 +202,21 @@ __global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Redu
                                                    T* __restrict__ yl, T* __restrict__ zl) {
   __shared__ double scratch[4];
   if (st->done) return;
+  // the operands of this thread's first KX elements are loaded before the
+  // reduction, so their latency overlaps it
+  constexpr int KX = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, d0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double xv[KX], pv[KX], rv0[KX], qv[KX];
+#pragma unroll
+  for (int u = 0; u < KX; ++u) {
+    const int64_t d = d0 + u * stride;
+    if (d < n) {
+      xv[u] = x[d];
+      pv[u] = p[d];
+      rv0[u] = r[d];
+      qv[u] = q[d];
+    }
+  }
   const double pq = partials_sum(red + RED_PQ, n_pq, scratch);
   const int it = st->it;
   const double alpha = pq > 0.0 ? rz2[it & 1] / pq : 0.0;
@@ -211,12 +226,26 @@ __global__ __launch_bounds__(256) void k_update_xr(int64_t n, DevState* st, Redu
     st->q_coarse = 0;
   }
   double acc = 0.0;
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+  for (int u = 0; u < KX; ++u) {
+    const int64_t d = d0 + u * stride;
+    if (d < n) {
+      x[d] = xv[u] + alpha * pv[u];
+      const double rv = rv0[u] - alpha * qv[u];
+      r[d] = rv;
+      acc += rv * rv;
+      if (yl) {  // re-arm the sweep dataflow vectors
+        yl[d] = sentinel<T>();
+        zl[d] = sentinel<T>();
+      }
+    }
+  }
+  for (int64_t d = d0 + KX * stride; d < n; d += stride) {
     x[d] += alpha * p[d];
     const double rv = r[d] - alpha * q[d];
     r[d] = rv;
     acc += rv * rv;
-    if (yl) {  // re-arm the sweep dataflow vectors
+    if (yl) {
       yl[d] = sentinel<T>();
       zl[d] = sentinel<T>();
     }
@@ -366,11 +395,27 @@ __global__ __launch_bounds__(256) void k_update_p(int64_t n, DevState* st, const
                                                   const double* __restrict__ z, double* __restrict__ p, int init) {
   __shared__ double scratch[4];
   if (st->done) return;
+  // this thread's first KP elements of z and p are loaded before the reduction
+  constexpr int KP = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, d0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double zv[KP], pv[KP];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int64_t d = d0 + u * stride;
+    if (d < n) {
+      zv[u] = z[d];
+      pv[u] = init ? 0.0 : p[d];
+    }
+  }
   const double rz_new = partials_sum(red + RED_RZ, n_rz, scratch);
   if (init) {
     if (blockIdx.x == 0 && threadIdx.x == 0) rz2[0] = rz_new;
-    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
-      p[d] = z[d];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+      const int64_t d = d0 + u * stride;
+      if (d < n) p[d] = zv[u];
+    }
+    for (int64_t d = d0 + KP * stride; d < n; d += stride) p[d] = z[d];
     return;
   }
   const int it = st->it;
@@ -379,8 +424,12 @@ __global__ __launch_bounds__(256) void k_update_p(int64_t n, DevState* st, const
     rz2[it & 1] = rz_new;
     if (it - 1 < HIST) beta_hist[it - 1] = beta;
   }
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x)
-    p[d] = z[d] + beta * p[d];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int64_t d = d0 + u * stride;
+    if (d < n) p[d] = zv[u] + beta * pv[u];
+  }
+  for (int64_t d = d0 + KP * stride; d < n; d += stride) p[d] = z[d] + beta * p[d];
 }
 
 __global__ void k_fill_i32(int32_t* dst, int64_t n, int32_t v) {
