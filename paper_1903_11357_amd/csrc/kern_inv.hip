@@ -218,19 +218,32 @@ __global__ __launch_bounds__(256) void k_dense_mv(int32_t n, int splits, const d
                                                   const DevState* st) {
   extern __shared__ double xs[];
   if (st && st->done) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // the row's first KD entries per lane are loaded before the prologue
+  constexpr int KD = 8;
+  const double* Dr = D + (size_t)(row < n ? row : 0) * n;
+  double dv[KD];
+#pragma unroll
+  for (int u = 0; u < KD; ++u) {
+    const int j = lane + 64 * u;
+    dv[u] = j < n ? Dr[j] : 0.0;
+  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double v = 0.0;
     for (int sp = 0; sp < splits; ++sp) v += xp[(size_t)sp * n + i];
     xs[i] = v;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
-  const double* Dr = D + (size_t)row * n;
   double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < KD; ++u) {
+    const int j = lane + 64 * u;
+    if (j < n) acc += dv[u] * xs[j];
+  }
 #pragma unroll 8
-  for (int j = lane; j < n; j += 64) acc += Dr[j] * xs[j];
+  for (int j = lane + 64 * KD; j < n; j += 64) acc += Dr[j] * xs[j];
   acc = warp_sum(acc);
   if (lane == 0) y[row] = acc;
 }

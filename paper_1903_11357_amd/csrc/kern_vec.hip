@@ -274,6 +274,7 @@ __global__ __launch_bounds__(256) void k_restrict(int32_t n_coarse, int splits, 
 #pragma unroll
   for (int c = 0; c < NQ; ++c) acc[c] = 0.0;
   const int k0 = tptr[J], pairs = (tptr[J + 1] - k0) * NP;
+#pragma unroll 4
   for (int i = sp * blockDim.x + threadIdx.x; i < pairs; i += splits * blockDim.x) {
     const int kk = i / NP, a = i - kk * NP;
     const int k = k0 + kk;
