@@ -263,8 +263,13 @@ def serving_bench(n_requests, seed=5, workers=16, local_inverse=False, loads=(0.
 
     descs = inputs.serving_requests(n_requests, seed=seed)
     t = time.perf_counter()
+    problems = []
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        problems = list(ex.map(inputs.serving_problem, descs))
+        for P in ex.map(inputs.serving_problem, descs, chunksize=4):
+            problems.append(P)
+            if len(problems) % 256 == 0:
+                print(f"[bench] serving: {len(problems)} of {n_requests} requests generated", file=sys.stderr,
+                      flush=True)
     t_gen = time.perf_counter() - t
     print(f"[bench] serving: {n_requests} requests generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
     srv = Server(precision=asdg.FP32_LOCAL, max_active=16, check_every=16, setup_workers=8,
