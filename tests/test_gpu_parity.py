@@ -436,3 +436,42 @@ def test_coarse_inverse_storage_forced(name, mode):
     assert _rel(crs, orc.M.coarse_apply(v)) <= 1e-10
     x, st = pr.solve(rtol=1e-8)
     _check_pcg_parity(f"{name}/coarse-{mode}", orc, st, x.cpu().numpy())
+
+
+@pytest.mark.parametrize("inverse", [False, True], ids=["sweeps", "inverse"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_large_subdomain(prec, inverse):
+    """A single subdomain of 6000 DoFs (94 tile rows, 4465 stored tiles): the
+    longest dependency chains of the factorisation, the inverse formation
+    and the sweeps. Local apply against the oracle's direct solve; FP64 PCG
+    against the oracle's iterates; FP32-local PCG by its true residual."""
+    import torch
+
+    from oracle import OracleSolver
+    from paper_1903_11357_amd import asdg
+
+    key = ("one_large", "oracle")
+    if key not in _cache:
+        P = I.voronoi_problem(1000, 33, p=2, bx=1, by=1, q=1)
+        orc = OracleSolver(P)
+        ev = np.linalg.eigvalsh(orc.A.toarray())
+        _cache[key] = (P, orc, ev[-1] / ev[0])
+    P, orc, kappa = _cache[key]
+    assert P.n_sub == 1 and P.n_dofs == 6000
+    precision = asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL
+    print(f"[one large subdomain] {prec} inverse={inverse}", flush=True)
+    pr = asdg.setup_problem(P, precision, device="cuda:0", local_inverse=inverse)
+    v = _vec(pr.n, 4)
+    loc = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = orc.M.local_apply(v)
+    x, st = pr.solve(rtol=1e-8)
+    if prec == "fp64":
+        assert _rel(loc, ref) <= 1e-10, _rel(loc, ref)
+        _check_pcg_parity("one_large", orc, st, x.cpu().numpy())
+    else:
+        # one subdomain: A_1 = A, forward error <= c n u kappa(A) (c n taken as 64)
+        assert _rel(loc, ref) <= 64 * 2.0 ** -24 * kappa, _rel(loc, ref)
+        assert st["converged"] == 1
+        b = orc.b
+        res = np.linalg.norm(b - orc.A @ x.cpu().numpy()) / np.linalg.norm(b)
+        assert res <= 1.05e-8, res
