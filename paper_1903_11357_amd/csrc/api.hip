@@ -363,7 +363,8 @@ void plan_local(asdg_problem* pb) {
   pb->tile_meta.reserve(tiles);
   for (int32_t i = 0; i < ns; ++i)
     for (int b = 0; b < pb->subs[i].nb; ++b)
-      for (int j = 0; j <= b; ++j) pb->tile_meta.push_back(make_int4(i, b, j, 0));
+      for (int j = 0; j <= b; ++j)  // w: rows of tile row b inside the subdomain
+        pb->tile_meta.push_back(make_int4(i, b, j, std::min(TILE, pb->subs[i].n - TILE * b)));
   // factorisation tasks (i, j, b): longest path to the end first (ties by
   // subdomain, column, row); every dependency has a strictly longer path, so
   // it precedes its consumers in the queue
@@ -430,7 +431,7 @@ void plan_coarse_factor(asdg_problem* pb) {
   if (pb->coarse_dense) {
     for (int b = 0; b < nb; ++b)
       for (int j = 0; j <= b; ++j) {
-        pb->cmeta.push_back(make_int4(0, b, j, 0));
+        pb->cmeta.push_back(make_int4(0, b, j, std::min(TILE, n0 - TILE * b)));
         pb->cinv_tasks.push_back(make_int4(0, j, b, 0));  // row order: X_kj (k < b) precede X_bj
       }
   }

@@ -61,7 +61,10 @@ struct TileRow<double> {
 
 // Phase 1: part[t] = (S_bj r_j, S_bj^T r_b) for tile t = (b, j); the second
 // half is written only for off-diagonal tiles (diagonal tiles are stored
-// whole). Entries of r beyond the subdomain's n are taken as zero.
+// whole). Entries of r beyond the subdomain's n are taken as zero. meta[t].w
+// is the number of rows of tile row b inside the subdomain: the padding rows
+// of a ragged last tile row (zero, and identity on the diagonal, with r zero
+// there) contribute nothing to the sums that are read and are not loaded.
 // WPB waves (tiles) per work-group, a launch-shape choice of the autotuner.
 template <typename T, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
@@ -79,11 +82,12 @@ __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const 
   // diagonal tiles: rows r0 + 4k are read only in the 16-byte pieces that
   // reach the diagonal (column offset 4 c4 - 4k <= r0)
   const int cut = diag ? 4 * c4 - r0 : -64;
+  const int rows = m.w - r0;  // row r0 + 4k is inside the subdomain when 4k < rows
   T a[16][4];
   const T* base = S + (size_t)t * TT + r0 * TILE + 4 * c4;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    if (cut <= 4 * k) {
+    if (cut <= 4 * k && 4 * k < rows) {
       TileRow<T>::load(base + 4 * TILE * k, a[k]);
     } else {
 #pragma unroll

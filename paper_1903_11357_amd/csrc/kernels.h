@@ -108,8 +108,9 @@ hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n
 // Phase 1 of the packed symmetric apply: per stored tile (b, j), the row
 // sums S_bj r_j and the column sums S_bj^T r_b (diagonal tiles: row sums of
 // the lower triangle with the diagonal, column sums of the strict lower
-// triangle); summed per DoF by launch_prolong with LocalParts. waves: tiles (waves) per work-group, 1,
-// 2, 4 or 8 (hipErrorInvalidValue otherwise).
+// triangle); summed per DoF by launch_prolong with LocalParts. meta[t] = (subdomain, b, j, rows of tile
+// row b inside the subdomain). waves: tiles (waves) per work-group, 1, 2, 4 or 8 (hipErrorInvalidValue
+// otherwise).
 hipError_t launch_symv_tiles(int f32, int waves, int32_t n_tiles, const int4* meta, const SubDesc* subs, const void* S,
                              const double* r, void* part, const DevState* st, hipStream_t s);
 // Per-DoF sums of the FP64 tile partials of one packed symmetric matrix of
