@@ -16,6 +16,11 @@ metric = DoF-iterations per second = n_dofs * iterations / PCG wall time,
 for the FP32-local mode (local solvers stored and applied in FP32, everything
 else FP64) as `value`, with the plain FP64 mode beside it.
 
+Defaults: 2 warm-up solves, then 5 timed solves per mode (captured-graph
+replay); each mode also reports the per-solve times and their median, and
+one or two eager solves with HIP events around every local-apply launch for
+the kernel's roofline.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -23,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -122,32 +128,34 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
     x = torch.empty(pr.n, dtype=torch.float64, device="cuda:0")
     for _ in range(warmup):
         pr.solve(x=x, rtol=P.rtol, max_iter=P.max_iter, check_every=check_every, raise_on_noconv=False)
-    # kernel-timing pass: the same solves launched eagerly with HIP events
-    # around every local-solve launch, on the stream it is launched on
-    use_graph = False
+    # kernel-timing pass (untimed for the metric): the same solve launched
+    # eagerly with HIP events around every local-solve launch, on the stream
+    # it is launched on (events inside a captured graph bracket nothing)
+    n_eager = min(steps, 2)
     torch.cuda.synchronize()
-    its, lat, tl, nl = [], [], 0.0, 0
+    tl, nl, its_e = 0.0, 0, 0
     ta = time.perf_counter()
-    for _ in range(steps):
-        s0 = time.perf_counter()
+    for _ in range(n_eager):
         _, st = pr.solve(x=x, rtol=P.rtol, max_iter=P.max_iter, check_every=check_every, time_kernels=True,
-                         use_graph=use_graph, raise_on_noconv=False)
-        lat.append(time.perf_counter() - s0)
-        its.append(st["iterations"])
+                         use_graph=False, raise_on_noconv=False)
+        its_e += st["iterations"]
         tl += st["t_local_ms"]
         nl += st["n_local"]
     torch.cuda.synchronize()
-    tb = time.perf_counter()
-    total = tb - ta
-    total_graph = total
-    if not use_graph:
-        # headline pass: the same solves replayed as captured hipGraphs
-        torch.cuda.synchronize()
-        tg0 = time.perf_counter()
-        for _ in range(steps):
-            pr.solve(x=x, rtol=P.rtol, max_iter=P.max_iter, check_every=check_every, raise_on_noconv=False)
-        torch.cuda.synchronize()
-        total_graph = time.perf_counter() - tg0
+    total_eager = time.perf_counter() - ta
+    # timed pass: exactly `steps` solves replayed as captured hipGraphs,
+    # bracketed by device synchronisation (each solve returns after the
+    # host has read its final state)
+    its, lat = [], []
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        _, st = pr.solve(x=x, rtol=P.rtol, max_iter=P.max_iter, check_every=check_every, raise_on_noconv=False)
+        lat.append(time.perf_counter() - s0)
+        its.append(st["iterations"])
+    torch.cuda.synchronize()
+    total_graph = time.perf_counter() - tg0
     w = 4 if precision == asdg.FP32_LOCAL else 8
     small = pr.is_small()
     # dense flops of the factorisation: Cholesky sum n_i^3/3, and with explicit
@@ -160,8 +168,10 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
         "iterations": its[-1],
         "ms_per_step": 1e3 * total_graph / steps,
         "ms_per_iteration": 1e3 * total_graph / sum(its),
-        "timed_pass": {"mode": "graph" if use_graph else "eager", "ms_per_step": 1e3 * total / steps,
-                       "dof_iters_per_s": pr.n * sum(its) / total},
+        "solve_ms": [1e3 * v for v in lat],
+        "solve_ms_median": 1e3 * statistics.median(lat),
+        "kernel_timing_pass": {"mode": "eager", "solves": n_eager, "ms_per_step": 1e3 * total_eager / n_eager,
+                               "dof_iters_per_s": pr.n * its_e / total_eager},
         "converged": st["converged"],
         "rel_res": st["rel_res"],
         "kappa_lanczos": st["lambda_max"] / st["lambda_min"] if st["lambda_min"] > 0 else None,
@@ -302,12 +312,12 @@ def serving_bench(n_requests, seed=5, workers=16, local_inverse=False, loads=(0.
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--check-every", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--modes", default="fp32,fp64")
     ap.add_argument("--local", default="inverse,sweeps",
                     help="local-solve representations, the first is the headline: inverse (packed "
