@@ -189,6 +189,11 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
                          "algorithmic_bytes": local_solve_bytes(pr, w, inverse),
                          "representation": "explicit inverse" if inverse else "triangular sweeps"}),
     }
+    ls = res["local_solve"]
+    if ls.get("avg_ms"):
+        ls["achieved_gbs"] = ls["algorithmic_bytes"] / (ls["avg_ms"] * 1e-3) / 1e9
+        ls["frac_of_hbm_peak"] = ls["achieved_gbs"] / HBM_PEAK_GBS
+        ls["share_of_iteration"] = ls["avg_ms"] / res["ms_per_iteration"]
     del pr
     torch.cuda.empty_cache()
     return res
