@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <thread>
 #include <unordered_map>
 
@@ -316,10 +317,26 @@ void gauss_legendre01(int m, std::vector<double>& x, std::vector<double>& w) {
 
 int n_basis(int p) { return (p + 1) * (p + 2) / 2; }
 
-void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx, double* gy) {
-  double dx = B.x1 - B.x0, dy = B.y1 - B.y0;
-  double xi = 2.0 * (x - 0.5 * (B.x0 + B.x1)) / dx;
-  double eta = 2.0 * (y - 0.5 * (B.y0 + B.y1)) / dy;
+void basis_prepare(int p, const Box& B, BasisBox& bb) {
+  bb.p = p;
+  bb.dx = B.x1 - B.x0;
+  bb.dy = B.y1 - B.y0;
+  bb.cx = 0.5 * (B.x0 + B.x1);
+  bb.cy = 0.5 * (B.y0 + B.y1);
+  bb.sx = 2.0 / bb.dx;
+  bb.sy = 2.0 / bb.dy;
+  int a = 0;
+  for (int d = 0; d <= p; ++d)
+    for (int j = 0; j <= d; ++j, ++a) {
+      const int i = d - j;
+      bb.s[a] = std::sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (bb.dx * bb.dy));
+    }
+}
+
+void basis_eval(const BasisBox& bb, double x, double y, double* val, double* gx, double* gy) {
+  const int p = bb.p;
+  double xi = 2.0 * (x - bb.cx) / bb.dx;
+  double eta = 2.0 * (y - bb.cy) / bb.dy;
   double Lx[16], dLx[16], Ly[16], dLy[16];
   Lx[0] = 1.0;
   dLx[0] = 0.0;
@@ -341,10 +358,10 @@ void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx
   for (int d = 0; d <= p; ++d) {
     for (int j = 0; j <= d; ++j, ++a) {
       int i = d - j;
-      double s = std::sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) / (dx * dy));
+      const double s = bb.s[a];
       val[a] = s * Lx[i] * Ly[j];
-      if (gx) gx[a] = s * dLx[i] * (2.0 / dx) * Ly[j];
-      if (gy) gy[a] = s * Lx[i] * dLy[j] * (2.0 / dy);
+      if (gx) gx[a] = s * dLx[i] * bb.sx * Ly[j];
+      if (gy) gy[a] = s * Lx[i] * dLy[j] * bb.sy;
     }
   }
 }
@@ -355,8 +372,7 @@ void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx
 // pm = (plus, minus) (minus < 0: boundary face, block 0 only). Rows add the
 // volume block, then the cell's faces in face-index order (deterministic).
 std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::vector<std::pair<int32_t, int32_t>>& pm,
-                            const std::vector<double>& vol, const std::vector<double>& rhs_c,
-                            const std::vector<double>& fblk) {
+                            const double* vol, const double* rhs_c, const double* fblk) {
   const int32_t N = A.n_cells;
   const int np = A.np;
   // subdomains and subdomain-major permutation (stable)
@@ -462,6 +478,161 @@ std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::v
   return "";
 }
 
+namespace {
+
+// basis_eval with the degree fixed at compile time (same arithmetic, fully
+// unrolled loops)
+template <int P>
+inline void basis_eval_p(const BasisBox& bb, double x, double y, double* val, double* gx, double* gy) {
+  double xi = 2.0 * (x - bb.cx) / bb.dx;
+  double eta = 2.0 * (y - bb.cy) / bb.dy;
+  double Lx[P + 1], dLx[P + 1], Ly[P + 1], dLy[P + 1];
+  Lx[0] = 1.0;
+  dLx[0] = 0.0;
+  Ly[0] = 1.0;
+  dLy[0] = 0.0;
+  Lx[1] = xi;
+  dLx[1] = 1.0;
+  Ly[1] = eta;
+  dLy[1] = 1.0;
+#pragma GCC unroll 4
+  for (int k = 1; k < P; ++k) {
+    Lx[k + 1] = ((2 * k + 1) * xi * Lx[k] - k * Lx[k - 1]) / (k + 1);
+    Ly[k + 1] = ((2 * k + 1) * eta * Ly[k] - k * Ly[k - 1]) / (k + 1);
+    dLx[k + 1] = dLx[k - 1] + (2 * k + 1) * Lx[k];
+    dLy[k + 1] = dLy[k - 1] + (2 * k + 1) * Ly[k];
+  }
+  int a = 0;
+#pragma GCC unroll 5
+  for (int d = 0; d <= P; ++d) {
+#pragma GCC unroll 5
+    for (int j = 0; j <= d; ++j, ++a) {
+      int i = d - j;
+      const double s = bb.s[a];
+      val[a] = s * Lx[i] * Ly[j];
+      gx[a] = s * dLx[i] * bb.sx * Ly[j];
+      gy[a] = s * Lx[i] * dLy[j] * bb.sy;
+    }
+  }
+}
+
+// Volume blocks (rho grad v . grad u) and loads (f v) of cells c0 + [lo, hi),
+// points of cell c0 + cc at [pptr[cc], pptr[cc + 1]).
+template <int P>
+void volume_range(int64_t c0, int64_t lo, int64_t hi, const int64_t* pptr, const double* pts, const double* wts,
+                  const double* fv, const CellGeom& G, const double* rho, double* vol, double* rhs_c) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  double v[NP], gx[NP], gy[NP];
+  BasisBox bb;
+  for (int64_t cc = lo; cc < hi; ++cc) {
+    const int64_t c = c0 + cc;
+    double* K = vol + (size_t)c * NP * NP;
+    double* bl = rhs_c + (size_t)c * NP;
+    std::fill(K, K + NP * NP, 0.0);
+    std::fill(bl, bl + NP, 0.0);
+    basis_prepare(P, G.box[c], bb);
+    for (int64_t k = pptr[cc]; k < pptr[cc + 1]; ++k) {
+      basis_eval_p<P>(bb, pts[2 * k], pts[2 * k + 1], v, gx, gy);
+      const double w = wts[k];
+      const double wr = w * rho[c];
+      // the (a, b) and (b, a) terms are the same products: one triangle, mirrored below
+#pragma GCC unroll 15
+      for (int b = 0; b < NP; ++b)
+#pragma GCC unroll 15
+        for (int a = b; a < NP; ++a) K[b * NP + a] += wr * (gx[a] * gx[b] + gy[a] * gy[b]);
+      const double wf = w * fv[k];
+#pragma GCC unroll 15
+      for (int a = 0; a < NP; ++a) bl[a] += wf * v[a];
+    }
+    for (int b = 0; b < NP; ++b)
+      for (int a = 0; a < b; ++a) K[b * NP + a] = K[a * NP + b];
+  }
+}
+
+struct FaceCtx {
+  const MeshView* mesh;
+  const CellGeom* G;
+  const std::vector<Face>* faces;
+  const double* rho;
+  double c_sigma, pp;
+  int m;
+  const double* gq;
+  const double* wq;
+  double* fblk;
+};
+
+// Face blocks of faces [lo, hi): interior faces the four blocks (++, +-, -+,
+// --), boundary faces block 0; block (t, s) element (a, b) at b*np + a.
+template <int P>
+void face_range(const FaceCtx& X, int64_t lo, int64_t hi) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  double vp[NP], gxp[NP], gyp[NP], vm[NP], gxm[NP], gym[NP], gnp[NP], gnm[NP];
+  BasisBox bp, bm;
+  const MeshView& mesh = *X.mesh;
+  const CellGeom& G = *X.G;
+  for (int64_t fi = lo; fi < hi; ++fi) {
+    const Face& F = (*X.faces)[fi];
+    double ax = mesh.xy[2 * F.v0], ay = mesh.xy[2 * F.v0 + 1];
+    double bx = mesh.xy[2 * F.v1], by = mesh.xy[2 * F.v1 + 1];
+    double dx = bx - ax, dy = by - ay;
+    double L = std::sqrt(dx * dx + dy * dy);
+    double nx = dy / L, ny = -dx / L;
+    double* Bk = X.fblk + (size_t)fi * 4 * NP * NP;
+    std::fill(Bk, Bk + 4 * NP * NP, 0.0);
+    basis_prepare(P, G.box[F.plus], bp);
+    if (F.minus >= 0) {
+      basis_prepare(P, G.box[F.minus], bm);
+      double rp = X.rho[F.plus], rm = X.rho[F.minus];
+      double g = 2.0 * rp * rm / (rp + rm);
+      double hp = G.diam[F.plus], hm = G.diam[F.minus];
+      double hF = 2.0 * hp * hm / (hp + hm);
+      double sigma = X.c_sigma * g * X.pp / hF;
+      for (int q = 0; q < X.m; ++q) {
+        double x = ax + X.gq[q] * dx, y = ay + X.gq[q] * dy, w = L * X.wq[q];
+        basis_eval_p<P>(bp, x, y, vp, gxp, gyp);
+        basis_eval_p<P>(bm, x, y, vm, gxm, gym);
+        for (int a = 0; a < NP; ++a) {
+          gnp[a] = gxp[a] * nx + gyp[a] * ny;
+          gnm[a] = gxm[a] * nx + gym[a] * ny;
+        }
+        const double* V[2] = {vp, vm};
+        const double* GN[2] = {gnp, gnm};
+        const double eps[2] = {1.0, -1.0};
+        for (int t = 0; t < 2; ++t)
+          for (int s = 0; s < 2; ++s) {
+            double* blk = Bk + (t * 2 + s) * NP * NP;
+            double c1 = -0.5 * g * eps[t] * w, c2 = -0.5 * g * eps[s] * w;
+            double c3 = sigma * eps[t] * eps[s] * w;
+            const double* Vt = V[t];
+            const double* Vs = V[s];
+            const double* Gt = GN[t];
+            const double* Gs = GN[s];
+#pragma GCC unroll 15
+            for (int b = 0; b < NP; ++b)
+#pragma GCC unroll 15
+              for (int a = 0; a < NP; ++a)
+                blk[b * NP + a] += c1 * Vt[a] * Gs[b] + c2 * Gt[a] * Vs[b] + c3 * Vt[a] * Vs[b];
+          }
+      }
+    } else {
+      double r = X.rho[F.plus];
+      double sigma = X.c_sigma * r * X.pp / G.diam[F.plus];
+      for (int q = 0; q < X.m; ++q) {
+        double x = ax + X.gq[q] * dx, y = ay + X.gq[q] * dy, w = L * X.wq[q];
+        basis_eval_p<P>(bp, x, y, vp, gxp, gyp);
+        for (int a = 0; a < NP; ++a) gnp[a] = gxp[a] * nx + gyp[a] * ny;
+#pragma GCC unroll 15
+        for (int b = 0; b < NP; ++b)
+#pragma GCC unroll 15
+          for (int a = 0; a < NP; ++a)
+            Bk[b * NP + a] += w * (-r * vp[a] * gnp[b] - r * gnp[a] * vp[b] + sigma * vp[a] * vp[b]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
 std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const double* rho,
                           const int32_t* subdomain,
                           void (*f)(int64_t, const double*, double*, void*), void* f_user,
@@ -518,9 +689,9 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   gauss_legendre01(m, gq, wq);
   const double pp = (double)p * (double)p;
 
-  // volume blocks and load vector, caller order
-  std::vector<double> vol((size_t)N * np * np, 0.0);
-  std::vector<double> rhs_c((size_t)N * np, 0.0);
+  // volume blocks and load vector, caller order (zeroed per cell by volume_range)
+  std::unique_ptr<double[]> vol(new double[(size_t)N * np * np]);
+  std::unique_ptr<double[]> rhs_c(new double[(size_t)N * np]);
   {
     const int64_t chunk = 8192;
     for (int64_t c0 = 0; c0 < N; c0 += chunk) {
@@ -544,20 +715,12 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
       });
       if (f) f(pptr.back(), pts.data(), fv.data(), f_user);
       parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
-        double v[16], gx[16], gy[16];
-        for (int64_t cc = lo; cc < hi; ++cc) {
-          int64_t c = c0 + cc;
-          double* K = &vol[(size_t)c * np * np];
-          double* bl = &rhs_c[(size_t)c * np];
-          for (int64_t k = pptr[cc]; k < pptr[cc + 1]; ++k) {
-            basis_eval(p, G.box[c], pts[2 * k], pts[2 * k + 1], v, gx, gy);
-            double w = wts[k];
-            double wr = w * rho[c];
-            for (int b = 0; b < np; ++b)
-              for (int a = 0; a < np; ++a) K[b * np + a] += wr * (gx[a] * gx[b] + gy[a] * gy[b]);
-            double wf = w * fv[k];
-            for (int a = 0; a < np; ++a) bl[a] += wf * v[a];
-          }
+        const int64_t* pp_ = pptr.data();
+        switch (p) {
+          case 1: volume_range<1>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 2: volume_range<2>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 3: volume_range<3>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          default: volume_range<4>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
         }
       });
     }
@@ -566,62 +729,22 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   // face blocks: interior faces 4 blocks (++, +-, -+, --), boundary 1 block;
   // block (t, s) element (a, b) stored at b*np + a (a: test on t, b: trial on s)
   const int64_t NF = (int64_t)A.faces.size();
-  std::vector<double> fblk((size_t)NF * 4 * np * np, 0.0);
+  // not value-initialised: face_range zeroes each face's blocks in its own
+  // thread (a serial fill of this buffer cost as much as computing it)
+  std::unique_ptr<double[]> fblk(new double[(size_t)NF * 4 * np * np]);
+  const FaceCtx X{&mesh, &G, &A.faces, rho, c_sigma, pp, m, gq.data(), wq.data(), fblk.get()};
   parallel_for(NF, [&](int64_t lo, int64_t hi) {
-    double vp[16], gxp[16], gyp[16], vm[16], gxm[16], gym[16], gnp[16], gnm[16];
-    for (int64_t fi = lo; fi < hi; ++fi) {
-      const Face& F = A.faces[fi];
-      double ax = mesh.xy[2 * F.v0], ay = mesh.xy[2 * F.v0 + 1];
-      double bx = mesh.xy[2 * F.v1], by = mesh.xy[2 * F.v1 + 1];
-      double dx = bx - ax, dy = by - ay;
-      double L = std::sqrt(dx * dx + dy * dy);
-      double nx = dy / L, ny = -dx / L;
-      double* Bk = &fblk[(size_t)fi * 4 * np * np];
-      if (F.minus >= 0) {
-        double rp = rho[F.plus], rm = rho[F.minus];
-        double g = 2.0 * rp * rm / (rp + rm);
-        double hp = G.diam[F.plus], hm = G.diam[F.minus];
-        double hF = 2.0 * hp * hm / (hp + hm);
-        double sigma = c_sigma * g * pp / hF;
-        for (int q = 0; q < m; ++q) {
-          double x = ax + gq[q] * dx, y = ay + gq[q] * dy, w = L * wq[q];
-          basis_eval(p, G.box[F.plus], x, y, vp, gxp, gyp);
-          basis_eval(p, G.box[F.minus], x, y, vm, gxm, gym);
-          for (int a = 0; a < np; ++a) {
-            gnp[a] = gxp[a] * nx + gyp[a] * ny;
-            gnm[a] = gxm[a] * nx + gym[a] * ny;
-          }
-          const double* V[2] = {vp, vm};
-          const double* GN[2] = {gnp, gnm};
-          const double eps[2] = {1.0, -1.0};
-          for (int t = 0; t < 2; ++t)
-            for (int s = 0; s < 2; ++s) {
-              double* blk = Bk + (t * 2 + s) * np * np;
-              double c1 = -0.5 * g * eps[t] * w, c2 = -0.5 * g * eps[s] * w;
-              double c3 = sigma * eps[t] * eps[s] * w;
-              for (int b = 0; b < np; ++b)
-                for (int a = 0; a < np; ++a)
-                  blk[b * np + a] += c1 * V[t][a] * GN[s][b] + c2 * GN[t][a] * V[s][b] + c3 * V[t][a] * V[s][b];
-            }
-        }
-      } else {
-        double r = rho[F.plus];
-        double sigma = c_sigma * r * pp / G.diam[F.plus];
-        for (int q = 0; q < m; ++q) {
-          double x = ax + gq[q] * dx, y = ay + gq[q] * dy, w = L * wq[q];
-          basis_eval(p, G.box[F.plus], x, y, vp, gxp, gyp);
-          for (int a = 0; a < np; ++a) gnp[a] = gxp[a] * nx + gyp[a] * ny;
-          for (int b = 0; b < np; ++b)
-            for (int a = 0; a < np; ++a)
-              Bk[b * np + a] += w * (-r * vp[a] * gnp[b] - r * gnp[a] * vp[b] + sigma * vp[a] * vp[b]);
-        }
-      }
+    switch (p) {
+      case 1: face_range<1>(X, lo, hi); break;
+      case 2: face_range<2>(X, lo, hi); break;
+      case 3: face_range<3>(X, lo, hi); break;
+      default: face_range<4>(X, lo, hi); break;
     }
   });
 
   std::vector<std::pair<int32_t, int32_t>> pm(A.faces.size());
   for (size_t fi = 0; fi < A.faces.size(); ++fi) pm[fi] = {A.faces[fi].plus, A.faces[fi].minus};
-  return finish_assembly(A, subdomain, pm, vol, rhs_c, fblk);
+  return finish_assembly(A, subdomain, pm, vol.get(), rhs_c.get(), fblk.get());
 }
 
 // P_0 as CSR by internal fine cell from per-caller-cell block lists
@@ -730,8 +853,10 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
     double v[16];
     cell_points(fine, G, c, gq, wq, qp);
     M.assign(np * np, 0.0);
+    BasisBox fbb;
+    basis_prepare(A.p, G.box[c], fbb);
     for (auto& P : qp) {
-      basis_eval(A.p, G.box[c], P.x, P.y, v, nullptr, nullptr);
+      basis_eval(fbb, P.x, P.y, v, nullptr, nullptr);
       for (int a = 0; a < np; ++a)
         for (int b = 0; b < np; ++b) M[a * np + b] += P.w * v[a] * v[b];
     }
@@ -767,9 +892,12 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
         mass((int32_t)c, qp, M);
         int32_t j = coarse_of_cell[c];
         std::fill(B.begin(), B.end(), 0.0);
+        BasisBox fbb, cbb;
+        basis_prepare(A.p, G.box[c], fbb);
+        basis_prepare(q, cbox[j], cbb);
         for (auto& P : qp) {
-          basis_eval(A.p, G.box[c], P.x, P.y, v, nullptr, nullptr);
-          basis_eval(q, cbox[j], P.x, P.y, psi, nullptr, nullptr);
+          basis_eval(fbb, P.x, P.y, v, nullptr, nullptr);
+          basis_eval(cbb, P.x, P.y, psi, nullptr, nullptr);
           for (int a = 0; a < np; ++a)
             for (int b = 0; b < nq; ++b) B[a * nq + b] += P.w * v[a] * psi[b];
         }
@@ -808,9 +936,12 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
           cq.clear();
           polygon_points(Q, gq, wq, cq);
           std::fill(B.begin(), B.end(), 0.0);
+          BasisBox fbb, cbb;
+          basis_prepare(A.p, fb, fbb);
+          basis_prepare(q, cb, cbb);
           for (auto& X : cq) {
-            basis_eval(A.p, fb, X.x, X.y, v, nullptr, nullptr);
-            basis_eval(q, cb, X.x, X.y, psi, nullptr, nullptr);
+            basis_eval(fbb, X.x, X.y, v, nullptr, nullptr);
+            basis_eval(cbb, X.x, X.y, psi, nullptr, nullptr);
             for (int a = 0; a < np; ++a)
               for (int b = 0; b < nq; ++b) B[a * nq + b] += X.w * v[a] * psi[b];
           }

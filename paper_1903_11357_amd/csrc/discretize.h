@@ -30,9 +30,17 @@ struct MeshView {
 // Gauss-Legendre rule with m points on [0, 1] (weights sum to one).
 void gauss_legendre01(int m, std::vector<double>& x, std::vector<double>& w);
 
-// Scaled Legendre basis of total degree p on box B: n_p values and gradients.
+// Scaled Legendre basis of total degree p on box B: basis_prepare computes
+// the box's factors (centre, scalings, normalisations) once, basis_eval the
+// n_p values and gradients (either may be null) at a point.
 int n_basis(int p);
-void basis_eval(int p, const Box& B, double x, double y, double* val, double* gx, double* gy);
+struct BasisBox {
+  int p;
+  double dx, dy, cx, cy, sx, sy;
+  double s[15];
+};
+void basis_prepare(int p, const Box& B, BasisBox& bb);
+void basis_eval(const BasisBox& bb, double x, double y, double* val, double* gx, double* gy);
 
 struct CellGeom {
   std::vector<double> area, cx, cy, diam;
@@ -125,8 +133,7 @@ class HostThreadCap {
 };
 bool spd_solve(int n, std::vector<double> M, double* B, int k);
 std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::vector<std::pair<int32_t, int32_t>>& pm,
-                            const std::vector<double>& vol, const std::vector<double>& rhs_c,
-                            const std::vector<double>& fblk);
+                            const double* vol, const double* rhs_c, const double* fblk);
 void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& bcol,
                    const std::vector<std::vector<double>>& bval, Coarse& C);
 

@@ -315,7 +315,7 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
   });
   std::vector<std::pair<int32_t, int32_t>> pm(faces.size());
   for (size_t fi = 0; fi < faces.size(); ++fi) pm[fi] = {faces[fi].plus, faces[fi].minus};
-  return finish_assembly(A, subdomain, pm, vol, rhs_c, fblk);
+  return finish_assembly(A, subdomain, pm, vol.data(), rhs_c.data(), fblk.data());
 }
 
 std::string build_coarse_tet(const TetView& fine, const Assembled& A, int q, const int32_t* coarse_of_cell,
