@@ -28,7 +28,8 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function",
 ]
-CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall"]
+# the library's own functions are never interposed: let calls inside a file inline
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fno-semantic-interposition", "-I", INCLUDE, "-I", CSRC, "-Wall"]
 
 
 def _hipcc() -> str:
