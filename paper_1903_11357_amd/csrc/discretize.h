@@ -105,8 +105,16 @@ struct TetView {
 
 // Scaled Legendre basis of total degree p on a box, ordered by degree d,
 // then k = 0..d, then j = 0..d-k, i = d-j-k (exponents of x, y, z).
+// basis_prepare3 computes the box's factors once, basis_eval3 the values and
+// gradients (either may be null) at a point.
 int n_basis3(int p);
-void basis_eval3(int p, const Box3& B, double x, double y, double z, double* val, double* gx, double* gy,
+struct BasisBox3 {
+  int p;
+  double d[3], c[3], sc[3];
+  double s[20];
+};
+void basis_prepare3(int p, const Box3& B, BasisBox3& bb);
+void basis_eval3(const BasisBox3& bb, double x, double y, double z, double* val, double* gx, double* gy,
                  double* gz);
 
 // 3D SIPG system; fills out.box3 / out.diam3 (caller order) and sets out.dim = 3.

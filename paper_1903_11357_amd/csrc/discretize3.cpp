@@ -7,6 +7,7 @@
 // onto the tetrahedron (exact to total degree 2m - 3) and faces by the
 // collapsed triangle rule (exact to 2m - 2).
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <unordered_map>
 
@@ -78,11 +79,29 @@ const double* vtx(const TetView& m, int32_t v) { return m.xyz + 3 * (size_t)v; }
 
 int n_basis3(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
-void basis_eval3(int p, const Box3& B, double x, double y, double z, double* val, double* gx, double* gy,
+void basis_prepare3(int p, const Box3& B, BasisBox3& bb) {
+  bb.p = p;
+  bb.d[0] = B.x1 - B.x0;
+  bb.d[1] = B.y1 - B.y0;
+  bb.d[2] = B.z1 - B.z0;
+  bb.c[0] = 0.5 * (B.x0 + B.x1);
+  bb.c[1] = 0.5 * (B.y0 + B.y1);
+  bb.c[2] = 0.5 * (B.z0 + B.z1);
+  for (int e = 0; e < 3; ++e) bb.sc[e] = 2.0 / bb.d[e];
+  const double vol = bb.d[0] * bb.d[1] * bb.d[2];
+  int a = 0;
+  for (int dg = 0; dg <= p; ++dg)
+    for (int k = 0; k <= dg; ++k)
+      for (int j = 0; j <= dg - k; ++j, ++a) {
+        const int i = dg - j - k;
+        bb.s[a] = std::sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) * (2.0 * k + 1.0) / vol);
+      }
+}
+
+void basis_eval3(const BasisBox3& bb, double x, double y, double z, double* val, double* gx, double* gy,
                  double* gz) {
-  const double d[3] = {B.x1 - B.x0, B.y1 - B.y0, B.z1 - B.z0};
-  const double t[3] = {2.0 * (x - 0.5 * (B.x0 + B.x1)) / d[0], 2.0 * (y - 0.5 * (B.y0 + B.y1)) / d[1],
-                       2.0 * (z - 0.5 * (B.z0 + B.z1)) / d[2]};
+  const int p = bb.p;
+  const double t[3] = {2.0 * (x - bb.c[0]) / bb.d[0], 2.0 * (y - bb.c[1]) / bb.d[1], 2.0 * (z - bb.c[2]) / bb.d[2]};
   double L[3][8], dL[3][8];
   for (int e = 0; e < 3; ++e) {
     L[e][0] = 1.0;
@@ -96,17 +115,16 @@ void basis_eval3(int p, const Box3& B, double x, double y, double z, double* val
       dL[e][k + 1] = dL[e][k - 1] + (2 * k + 1) * L[e][k];
     }
   }
-  const double vol = d[0] * d[1] * d[2];
   int a = 0;
   for (int dg = 0; dg <= p; ++dg)
     for (int k = 0; k <= dg; ++k)
       for (int j = 0; j <= dg - k; ++j, ++a) {
         const int i = dg - j - k;
-        const double s = std::sqrt((2.0 * i + 1.0) * (2.0 * j + 1.0) * (2.0 * k + 1.0) / vol);
+        const double s = bb.s[a];
         val[a] = s * L[0][i] * L[1][j] * L[2][k];
-        if (gx) gx[a] = s * dL[0][i] * (2.0 / d[0]) * L[1][j] * L[2][k];
-        if (gy) gy[a] = s * L[0][i] * dL[1][j] * (2.0 / d[1]) * L[2][k];
-        if (gz) gz[a] = s * L[0][i] * L[1][j] * dL[2][k] * (2.0 / d[2]);
+        if (gx) gx[a] = s * dL[0][i] * bb.sc[0] * L[1][j] * L[2][k];
+        if (gy) gy[a] = s * L[0][i] * dL[1][j] * bb.sc[1] * L[2][k];
+        if (gz) gz[a] = s * L[0][i] * L[1][j] * dL[2][k] * bb.sc[2];
       }
 }
 
@@ -213,9 +231,9 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
   gauss_legendre01(m, gq, wq);
   const double pp = (double)p * (double)p;
 
-  // volume blocks and load vector, caller order
-  std::vector<double> vol((size_t)N * np * np, 0.0);
-  std::vector<double> rhs_c((size_t)N * np, 0.0);
+  // volume blocks and load vector, caller order (each cell's zeroed by its thread)
+  std::unique_ptr<double[]> vol(new double[(size_t)N * np * np]);
+  std::unique_ptr<double[]> rhs_c(new double[(size_t)N * np]);
   {
     const int64_t chunk = 8192, per = (int64_t)m * m * m;
     for (int64_t c0 = 0; c0 < N; c0 += chunk) {
@@ -237,18 +255,25 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
       if (f) f((c1 - c0) * per, pts.data(), fv.data(), f_user);
       parallel_for(c1 - c0, [&](int64_t lo_, int64_t hi_) {
         double v[MAXB], gx[MAXB], gy[MAXB], gz[MAXB];
+        BasisBox3 bb;
         for (int64_t cc = lo_; cc < hi_; ++cc) {
           const int64_t c = c0 + cc;
           double* K = &vol[(size_t)c * np * np];
           double* bl = &rhs_c[(size_t)c * np];
+          std::fill(K, K + np * np, 0.0);
+          std::fill(bl, bl + np, 0.0);
+          basis_prepare3(p, A.box3[c], bb);
           for (int64_t k = cc * per; k < (cc + 1) * per; ++k) {
-            basis_eval3(p, A.box3[c], pts[3 * k], pts[3 * k + 1], pts[3 * k + 2], v, gx, gy, gz);
+            basis_eval3(bb, pts[3 * k], pts[3 * k + 1], pts[3 * k + 2], v, gx, gy, gz);
             const double w = wts[k], wr = w * rho[c];
+            // the (a, b) and (b, a) terms are the same products: one triangle, mirrored below
             for (int b = 0; b < np; ++b)
-              for (int a = 0; a < np; ++a) K[b * np + a] += wr * (gx[a] * gx[b] + gy[a] * gy[b] + gz[a] * gz[b]);
+              for (int a = b; a < np; ++a) K[b * np + a] += wr * (gx[a] * gx[b] + gy[a] * gy[b] + gz[a] * gz[b]);
             const double wf = w * fv[k];
             for (int a = 0; a < np; ++a) bl[a] += wf * v[a];
           }
+          for (int b = 0; b < np; ++b)
+            for (int a = 0; a < b; ++a) K[b * np + a] = K[a * np + b];
         }
       });
     }
@@ -256,11 +281,13 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
 
   // face blocks (same layout as 2D: interior ++, +-, -+, --; boundary one block)
   const int64_t NF = (int64_t)faces.size();
-  std::vector<double> fblk((size_t)NF * 4 * np * np, 0.0);
+  // not value-initialised: each face's four blocks are zeroed by its thread
+  std::unique_ptr<double[]> fblk(new double[(size_t)NF * 4 * np * np]);
   parallel_for(NF, [&](int64_t lo_, int64_t hi_) {
     double vp[MAXB], gxp[MAXB], gyp[MAXB], gzp[MAXB], vm[MAXB], gxm[MAXB], gym[MAXB], gzm[MAXB];
     double gnp[MAXB], gnm[MAXB];
     std::vector<QP3> qp;
+    BasisBox3 bp, bm;
     for (int64_t fi = lo_; fi < hi_; ++fi) {
       const F3& F = faces[fi];
       const double *a = vtx(mesh, F.v[0]), *b = vtx(mesh, F.v[1]), *c = vtx(mesh, F.v[2]);
@@ -273,15 +300,18 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
       for (int e = 0; e < 3; ++e) n[e] = (side > 0 ? -n[e] : n[e]) / nn;  // outward from the plus cell
       tri_points(a, b, c, gq, wq, qp);
       double* Bk = &fblk[(size_t)fi * 4 * np * np];
+      std::fill(Bk, Bk + 4 * np * np, 0.0);
+      basis_prepare3(p, A.box3[F.plus], bp);
       if (F.minus >= 0) {
+        basis_prepare3(p, A.box3[F.minus], bm);
         const double rp = rho[F.plus], rm = rho[F.minus];
         const double g = 2.0 * rp * rm / (rp + rm);
         const double hp = A.diam3[F.plus], hm = A.diam3[F.minus];
         const double hF = 2.0 * hp * hm / (hp + hm);
         const double sigma = c_sigma * g * pp / hF;
         for (const QP3& q : qp) {
-          basis_eval3(p, A.box3[F.plus], q.x, q.y, q.z, vp, gxp, gyp, gzp);
-          basis_eval3(p, A.box3[F.minus], q.x, q.y, q.z, vm, gxm, gym, gzm);
+          basis_eval3(bp, q.x, q.y, q.z, vp, gxp, gyp, gzp);
+          basis_eval3(bm, q.x, q.y, q.z, vm, gxm, gym, gzm);
           for (int k = 0; k < np; ++k) {
             gnp[k] = gxp[k] * n[0] + gyp[k] * n[1] + gzp[k] * n[2];
             gnm[k] = gxm[k] * n[0] + gym[k] * n[1] + gzm[k] * n[2];
@@ -304,7 +334,7 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
         const double r = rho[F.plus];
         const double sigma = c_sigma * r * pp / A.diam3[F.plus];
         for (const QP3& q : qp) {
-          basis_eval3(p, A.box3[F.plus], q.x, q.y, q.z, vp, gxp, gyp, gzp);
+          basis_eval3(bp, q.x, q.y, q.z, vp, gxp, gyp, gzp);
           for (int k = 0; k < np; ++k) gnp[k] = gxp[k] * n[0] + gyp[k] * n[1] + gzp[k] * n[2];
           for (int bb = 0; bb < np; ++bb)
             for (int aa = 0; aa < np; ++aa)
@@ -315,7 +345,7 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
   });
   std::vector<std::pair<int32_t, int32_t>> pm(faces.size());
   for (size_t fi = 0; fi < faces.size(); ++fi) pm[fi] = {faces[fi].plus, faces[fi].minus};
-  return finish_assembly(A, subdomain, pm, vol.data(), rhs_c.data(), fblk.data());
+  return finish_assembly(A, subdomain, pm, vol.get(), rhs_c.get(), fblk.get());
 }
 
 std::string build_coarse_tet(const TetView& fine, const Assembled& A, int q, const int32_t* coarse_of_cell,
@@ -364,9 +394,12 @@ std::string build_coarse_tet(const TetView& fine, const Assembled& A, int q, con
       const int32_t j = coarse_of_cell[c];
       M.assign((size_t)np * np, 0.0);
       std::fill(B.begin(), B.end(), 0.0);
+      BasisBox3 fbb, cbb;
+      basis_prepare3(A.p, A.box3[c], fbb);
+      basis_prepare3(q, cbox[j], cbb);
       for (const QP3& P : qp) {
-        basis_eval3(A.p, A.box3[c], P.x, P.y, P.z, v, nullptr, nullptr, nullptr);
-        basis_eval3(q, cbox[j], P.x, P.y, P.z, psi, nullptr, nullptr, nullptr);
+        basis_eval3(fbb, P.x, P.y, P.z, v, nullptr, nullptr, nullptr);
+        basis_eval3(cbb, P.x, P.y, P.z, psi, nullptr, nullptr, nullptr);
         for (int a = 0; a < np; ++a) {
           for (int b = 0; b < np; ++b) M[a * np + b] += P.w * v[a] * v[b];
           for (int b = 0; b < nq; ++b) B[a * nq + b] += P.w * v[a] * psi[b];
