@@ -164,6 +164,26 @@ def test_host_thread_cap_gives_identical_assembly():
             assert np.array_equal(a, b)
 
 
+def test_host_thread_cap_gives_identical_tet_assembly():
+    """The same for tetrahedra (p = 2, box subdomains, nested coarse q = 1),
+    on a mesh large enough (3072 cells) that the host work is split over
+    threads."""
+    P = I.tet_problem(8, 2, 2, q=1, per_element=False, sub_boxes=2, jitter=0.1, seed=5)
+    assert P.mesh.n_cells >= 2048  # parallel_for splits loops from 2048 items on
+    out = []
+    for threads in (0, 1, 3):
+        pr = asdg.Problem()
+        pr.set_tuning(asdg.TUNE_HOST_THREADS, threads)
+        pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+        pr.plan(asdg.FP64, P.q, coarse_of_cell=P.coarse_of_cell)
+        A = pr.export_operator()
+        A.sort_indices()
+        out.append((A.indptr, A.indices, A.data, pr.export_rhs(), pr.export_coarse()))
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_tuning_and_autotune_argument_errors():
     """Host-side checks of the launch-shape settings and the autotuner (no
     device needed: they fail before any device work)."""
