@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <atomic>
 #include <memory>
 #include <thread>
 #include <unordered_map>
@@ -516,6 +517,28 @@ inline void basis_eval_p(const BasisBox& bb, double x, double y, double* val, do
   }
 }
 
+// Basis values only (the same arithmetic as basis_eval's values).
+template <int P>
+inline void basis_val_p(const BasisBox& bb, double x, double y, double* val) {
+  double xi = 2.0 * (x - bb.cx) / bb.dx;
+  double eta = 2.0 * (y - bb.cy) / bb.dy;
+  double Lx[P + 1], Ly[P + 1];
+  Lx[0] = 1.0;
+  Ly[0] = 1.0;
+  Lx[1] = xi;
+  Ly[1] = eta;
+#pragma GCC unroll 4
+  for (int k = 1; k < P; ++k) {
+    Lx[k + 1] = ((2 * k + 1) * xi * Lx[k] - k * Lx[k - 1]) / (k + 1);
+    Ly[k + 1] = ((2 * k + 1) * eta * Ly[k] - k * Ly[k - 1]) / (k + 1);
+  }
+  int a = 0;
+#pragma GCC unroll 5
+  for (int d = 0; d <= P; ++d)
+#pragma GCC unroll 5
+    for (int j = 0; j <= d; ++j, ++a) val[a] = bb.s[a] * Lx[d - j] * Ly[j];
+}
+
 // Volume blocks (rho grad v . grad u) and loads (f v) of cells c0 + [lo, hi),
 // points of cell c0 + cc at [pptr[cc], pptr[cc + 1]).
 template <int P>
@@ -833,6 +856,56 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
   });
 }
 
+namespace {
+
+// Nested coarse transfer of fine cells [lo, hi): the fine mass matrix M and
+// the projection right-hand side B (fine basis against the basis of the
+// cell's coarse element) at the cell's quadrature points, then B := M^{-1} B.
+// The fine basis values of the mass pass are reused for B.
+template <int P, int Q>
+void nested_range(const MeshView& fine, const CellGeom& G, const std::vector<double>& gq, const std::vector<double>& wq,
+                  const int32_t* coarse_of_cell, const std::vector<Box>& cbox, int64_t lo, int64_t hi,
+                  std::vector<std::vector<int32_t>>& bcol, std::vector<std::vector<double>>& bval,
+                  std::atomic<bool>& fail) {
+  constexpr int NP = (P + 1) * (P + 2) / 2, NQ = (Q + 1) * (Q + 2) / 2;
+  std::vector<QuadPoint> qp;
+  std::vector<double> vq, M(NP * NP);
+  double B[NP * NQ], psi[NQ];
+  BasisBox fbb, cbb;
+  for (int64_t c = lo; c < hi; ++c) {
+    cell_points(fine, G, (int32_t)c, gq, wq, qp);
+    basis_prepare(P, G.box[c], fbb);
+    vq.resize(qp.size() * NP);
+    std::fill(M.begin(), M.end(), 0.0);
+    for (size_t k = 0; k < qp.size(); ++k) {
+      double* v = &vq[k * NP];
+      basis_val_p<P>(fbb, qp[k].x, qp[k].y, v);
+      const double w = qp[k].w;
+#pragma GCC unroll 15
+      for (int a = 0; a < NP; ++a)
+#pragma GCC unroll 15
+        for (int b = 0; b < NP; ++b) M[a * NP + b] += w * v[a] * v[b];
+    }
+    const int32_t j = coarse_of_cell[c];
+    basis_prepare(Q, cbox[j], cbb);
+    std::fill(B, B + NP * NQ, 0.0);
+    for (size_t k = 0; k < qp.size(); ++k) {
+      basis_val_p<Q>(cbb, qp[k].x, qp[k].y, psi);
+      const double* v = &vq[k * NP];
+      const double w = qp[k].w;
+#pragma GCC unroll 15
+      for (int a = 0; a < NP; ++a)
+#pragma GCC unroll 15
+        for (int b = 0; b < NQ; ++b) B[a * NQ + b] += w * v[a] * psi[b];
+    }
+    if (!spd_solve(NP, M, B, NQ)) fail = true;
+    bcol[c] = {j};
+    bval[c].assign(B, B + NP * NQ);
+  }
+}
+
+}  // namespace
+
 std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const int32_t* coarse_of_cell,
                          const MeshView* cmesh, Coarse& C) {
   if (q < 1 || q > A.p) return "coarse degree q must satisfy 1 <= q <= p";
@@ -883,28 +956,22 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
     for (int32_t j = 0; j < nc; ++j)
       if (!used[j]) return "coarse id " + std::to_string(j) + " is unused";
     C.n_coarse = nc;
-    bool fail = false;
+    std::atomic<bool> fail{false};
     parallel_for(N, [&](int64_t lo, int64_t hi) {
-      std::vector<QuadPoint> qp;
-      std::vector<double> M, B(np * nq);
-      double v[16], psi[16];
-      for (int64_t c = lo; c < hi; ++c) {
-        mass((int32_t)c, qp, M);
-        int32_t j = coarse_of_cell[c];
-        std::fill(B.begin(), B.end(), 0.0);
-        BasisBox fbb, cbb;
-        basis_prepare(A.p, G.box[c], fbb);
-        basis_prepare(q, cbox[j], cbb);
-        for (auto& P : qp) {
-          basis_eval(fbb, P.x, P.y, v, nullptr, nullptr);
-          basis_eval(cbb, P.x, P.y, psi, nullptr, nullptr);
-          for (int a = 0; a < np; ++a)
-            for (int b = 0; b < nq; ++b) B[a * nq + b] += P.w * v[a] * psi[b];
-        }
-        if (!spd_solve(np, M, B.data(), nq)) fail = true;
-        bcol[c] = {j};
-        bval[c] = B;
+#define ASDG_NESTED(P_, Q_) nested_range<P_, Q_>(fine, G, gq, wq, coarse_of_cell, cbox, lo, hi, bcol, bval, fail)
+      switch (A.p * 8 + q) {
+        case 9: ASDG_NESTED(1, 1); break;
+        case 17: ASDG_NESTED(2, 1); break;
+        case 18: ASDG_NESTED(2, 2); break;
+        case 25: ASDG_NESTED(3, 1); break;
+        case 26: ASDG_NESTED(3, 2); break;
+        case 27: ASDG_NESTED(3, 3); break;
+        case 33: ASDG_NESTED(4, 1); break;
+        case 34: ASDG_NESTED(4, 2); break;
+        case 35: ASDG_NESTED(4, 3); break;
+        default: ASDG_NESTED(4, 4); break;
       }
+#undef ASDG_NESTED
     });
     if (fail) return "singular fine-cell mass matrix";
   } else {
@@ -916,7 +983,7 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
     cbox = CG.box;
     std::vector<std::vector<double>> cpoly(nc);
     for (int32_t j = 0; j < nc; ++j) cell_polygon(*cmesh, j, cpoly[j]);
-    bool fail = false;
+    std::atomic<bool> fail{false};
     parallel_for(N, [&](int64_t lo, int64_t hi) {
       std::vector<QuadPoint> qp, cq;
       std::vector<double> M, B(np * nq), P;
