@@ -35,6 +35,8 @@ CASES = {
     "voronoi_p3_nonnested": lambda: I.voronoi_problem(400, 8, p=3, bx=4, by=4, q=2, nonnested_coarse=9,
                                                       log10_rho_range=1.0),
     "voronoi_p4_q3": lambda: I.voronoi_problem(150, 9, p=4, bx=2, by=2, q=3),
+    # nested coarse of the full degree (q = p) on 9 agglomerates
+    "voronoi_p3_q3_nested": lambda: I.voronoi_problem(300, 11, p=3, bx=3, by=3, q=3, log10_rho_range=2.0),
 }
 
 
