@@ -19,7 +19,11 @@ Dirichlet data, u in H^1_0).
 
 Pins: symmetry; positive definiteness at C_sigma = 10 (Lemma 5.1); A applied
 to the global constant vanishes on every cell not touching the boundary;
-manufactured-solution L2 rate h^{p+1}; the printed condition number of the
+manufactured-solution L2 rate h^{p+1}, also across a coefficient jump 1 | 100
+along a mesh line with nonzero normal flux (fails for a face average that is
+not consistent for that flux); entries of A on two rectangles with unequal
+rho and h worked out by hand (fix the omega weights, the harmonic <rho>_F and
+<h>_F, and the boundary-face penalty); the printed condition number of the
 Example 5 nested square series (via the Schwarz module).
 """
 from __future__ import annotations

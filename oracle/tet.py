@@ -24,7 +24,10 @@ form of monomial moments of the reference tetrahedron (exact to 2m-3 and
 not beyond); orthonormality on a box and span of P_p; the mesh (volumes sum
 to one, every interior face shared by two cells, boundary faces on the
 cube's sides); SIPG symmetry, positive definiteness, vanishing of A 1 on
-cells away from the boundary, the manufactured-solution L2 rate p+1;
+cells away from the boundary, the manufactured-solution L2 rate p+1 (also
+across a coefficient jump 1 | 100 along a mesh plane); hand-worked entries
+across faces between tetrahedra of unequal rho and h (omega weights,
+harmonic <rho>_F and <h>_F);
 nested P_0 reproducing global polynomials of degree <= q; spectrum of the
 two-level preconditioner in (0, chi + 1].
 """

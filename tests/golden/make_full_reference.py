@@ -1,0 +1,77 @@
+"""Writes the FP64 oracle's reference solve of a full-size workload.
+
+Runs only the CPU oracle (``oracle/``) on the seeded synthetic workload
+built by ``paper_1903_11357_amd.inputs`` (problem data only, no method
+arithmetic): SIPG assembly (Sec. 2), the two-level Schwarz preconditioner
+(Sec. 3) and PCG from a zero initial guess to the relative residual 1e-8
+(Sec. 7 protocol). Stores, per workload, in ``<name>_oracle_fp64.npz``:
+
+  x             the oracle's iterate at its stopping iteration
+  iterations    stopping iteration count
+  rel_res       recursive residual ||r_k|| / ||b|| at the stop
+  true_rel_res  ||b - A x_k|| / ||b|| at the stop
+  history       recursive residual after every iteration
+  alphas, betas CG coefficients (Lanczos condition estimate)
+  lambda_min, lambda_max  Lanczos extreme eigenvalue estimates
+
+and a short text summary ``<name>_oracle_fp64.txt``. The GPU full-size tests
+and the benchmark compare their solutions with these.
+
+Usage: python tests/golden/make_full_reference.py C4      (about 40 min on one core)
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main(name: str) -> None:
+    from oracle import OracleSolver
+    from oracle.pcg import pcg
+    from paper_1903_11357_amd import inputs as I
+
+    t0 = time.time()
+    P = I.make_config(name)
+    print(f"[{name}] n={P.n_dofs} cells={P.mesh.n_cells} subdomains={P.n_sub}", flush=True)
+    orc = OracleSolver(P)
+    print(f"[{name}] oracle setup {time.time() - t0:.0f} s", flush=True)
+    calls = [0]
+    t1 = time.time()
+
+    def precond(r):
+        calls[0] += 1
+        if calls[0] % 100 == 0:
+            print(f"[{name}] iteration {calls[0]}  {time.time() - t1:.0f} s", flush=True)
+        return orc.M.apply(r)
+
+    x, info = pcg(orc.A, orc.b, precond, rtol=P.rtol, max_iter=P.max_iter)
+    t_pcg = time.time() - t1
+    lo, hi = info.lanczos()
+    out = os.path.join(HERE, f"{name}_oracle_fp64.npz")
+    np.savez_compressed(out, x=x, iterations=info.iterations, converged=info.converged,
+                        rel_res=info.rel_res, true_rel_res=info.true_rel_res,
+                        history=np.asarray(info.history), alphas=np.asarray(info.alphas),
+                        betas=np.asarray(info.betas), lambda_min=lo, lambda_max=hi,
+                        n=P.n_dofs)
+    with open(os.path.join(HERE, f"{name}_oracle_fp64.txt"), "w") as fh:
+        fh.write(f"# FP64 CPU oracle, workload {name} (n = {P.n_dofs}), PCG from x0 = 0 to\n"
+                 f"# ||r_k|| <= 1e-8 ||b|| (Sec. 7 protocol), two-level additive Schwarz (Sec. 3).\n"
+                 f"# Written by tests/golden/make_full_reference.py; x is in {name}_oracle_fp64.npz.\n")
+        fh.write(f"iterations {info.iterations}\nconverged {int(info.converged)}\n"
+                 f"rel_res {info.rel_res:.6e}\ntrue_rel_res {info.true_rel_res:.6e}\n"
+                 f"lambda_min {lo:.10e}\nlambda_max {hi:.10e}\ncondition {hi / lo:.6e}\n"
+                 f"x_norm {np.linalg.norm(x):.16e}\npcg_seconds {t_pcg:.0f}\n")
+    print(f"[{name}] iterations={info.iterations} rel_res={info.rel_res:.3e} "
+          f"true_rel_res={info.true_rel_res:.3e} K={hi / lo:.4e} pcg {t_pcg:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "C4")

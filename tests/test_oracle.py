@@ -180,12 +180,144 @@ def test_sipg_constant_in_kernel_of_interior_rows():
     assert (np.abs(r[touches]).max(axis=1) / row_scale[touches]).min() > 1e-4
 
 
-def test_sipg_penalty_is_harmonic_in_rho():
-    """Scaling rho by c scales A by c (every term is linear in rho)."""
+def test_sipg_linear_in_rho():
+    """Scaling rho by c scales A by c (every term is linear in rho). This
+    does not distinguish one average of rho from another; the two-cell test
+    below does."""
     mesh, rho = _small_voronoi_problem(p=1)
     A1, *_ = assemble(mesh, 1, rho, 10.0)
     A2, *_ = assemble(mesh, 1, 7.0 * rho, 10.0)
     assert abs(A2 - 7.0 * A1).max() < 1e-12 * abs(A2).max()
+
+
+def _two_rectangles(a):
+    """K+ = [0,a]x[0,1] (cell 0) and K- = [a,1]x[0,1] (cell 1), sharing the
+    edge x = a."""
+    xy = np.array([[0.0, 0.0], [a, 0.0], [1.0, 0.0], [1.0, 1.0], [a, 1.0], [0.0, 1.0]])
+    return I.Mesh(xy=xy, cell_ptr=np.array([0, 4, 8], dtype=np.int32),
+                  cell_vertices=np.array([0, 1, 4, 5, 1, 2, 3, 4], dtype=np.int32))
+
+
+def test_sipg_weighted_face_terms_two_cells():
+    """Entries of A on two rectangles with rho+ != rho- and h+ != h-, worked
+    out by hand from Sec. 2: eq. (Ah), the lifting of eq. (lifting) with
+    omega = rho-/(rho+ + rho-), the harmonic average <.>, and eq. (Sigma)
+    sigma_F = C_sigma <rho>_F p^2 / <h>_F (boundary faces: rho_K, h_K).
+
+    Geometry: K+ = [0,a]x[0,1], K- = [a,1]x[0,1], a = 1/3, b = 1 - a, p = 1,
+    C_sigma = 10, rho+ = 1, rho- = 100, h = diameters sqrt(a^2+1),
+    sqrt(b^2+1). Basis (orthonormal on each box): phi0 = 1/sqrt(dx dy),
+    phi_x = sqrt(3/(dx dy)) L_1(2(x - xc)/dx). On the shared edge (length 1,
+    n+ = (1,0)): phi0+ = 1/sqrt(a), phi0- = 1/sqrt(b), phi_x- = -sqrt(3/b)
+    with gradient sqrt(3/b)(2/b, 0); phi_x+ = +sqrt(3/a) with gradient
+    sqrt(3/a)(2/a, 0).
+
+    For rho constant per cell, rho grad u lies in [V_h]^2, so the lifting
+    term int rho grad u . R(jump v) equals -int_F jump(v) . {rho grad u}_w
+    (eq. (lifting) tested with eta = rho grad u). The omega-weights give
+    omega rho+ = (1 - omega) rho- = rho+ rho- / (rho+ + rho-) = 100/101.
+
+    (i)   A[0+, 0-]  = penalty only = -sigma_F / sqrt(a b).
+    (ii)  A[0+, x-]  = -(1/sqrt a)(100/101) sqrt(3/b)(2/b)
+                       + sigma_F sqrt(3/b)/sqrt(a)         (jump(u) = +sqrt(3/b) n+).
+    (iii) A[0+, 0+]  = sigma_F / a + sigma_B+ (1 + 2a) / a, sigma_B+ = 10 rho+/h+.
+    (iv)  A[0+, x+]  = boundary x = 0: -rho+ (grad u.n) v = +2 sqrt(3) rho+/a^2,
+                       penalty -sigma_B+ sqrt(3)/a (the edges y = 0, 1 give 0);
+                       shared edge: -(100/101) sqrt(3/a)(2/a)/sqrt(a) + sigma_F sqrt(3)/a.
+    Any other average of rho (arithmetic, or omega = 1/2) or of h changes
+    (i)-(iv) by far more than the tolerance (checked below)."""
+    a = 1.0 / 3.0
+    b = 1.0 - a
+    rp, rm = 1.0, 100.0
+    hp, hm = math.sqrt(a * a + 1.0), math.sqrt(b * b + 1.0)
+    mesh = _two_rectangles(a)
+    A, *_ = assemble(mesh, 1, np.array([rp, rm]), 10.0)
+    A = A.toarray()
+    # basis order for p = 1: (0,0), (1,0) [x-mode], (0,1) [y-mode]
+    c0p, cxp, c0m, cxm = 0, 1, 3, 4
+
+    def expected(rho_avg, h_avg, w_cons):
+        sF = 10.0 * rho_avg / h_avg
+        sBp = 10.0 * rp / hp
+        s3 = math.sqrt(3.0)
+        return {
+            (c0p, c0m): -sF / math.sqrt(a * b),
+            (c0p, cxm): -(1.0 / math.sqrt(a)) * w_cons * math.sqrt(3.0 / b) * (2.0 / b)
+                        + sF * math.sqrt(3.0 / b) / math.sqrt(a),
+            (c0p, c0p): sF / a + sBp * (1.0 + 2.0 * a) / a,
+            (c0p, cxp): 2.0 * s3 * rp / a ** 2 - sBp * s3 / a
+                        - w_cons * math.sqrt(3.0 / a) * (2.0 / a) / math.sqrt(a) + sF * s3 / a,
+        }
+
+    harm = lambda u, v: 2.0 * u * v / (u + v)
+    ref = expected(harm(rp, rm), harm(hp, hm), rp * rm / (rp + rm))
+    for (i, j), v in ref.items():
+        assert abs(A[i, j] - v) <= 1e-12 * abs(v), ((i, j), A[i, j], v)
+        assert A[j, i] == pytest.approx(A[i, j], rel=1e-13)
+    # the pin discriminates: another average moves some entry by more than
+    # 1e-3 relative (the harmonic and arithmetic means of h differ by 0.9%
+    # here), nine orders of magnitude above the tolerance
+    for alt in (expected(0.5 * (rp + rm), harm(hp, hm), rp * rm / (rp + rm)),
+                expected(harm(rp, rm), 0.5 * (hp + hm), rp * rm / (rp + rm)),
+                expected(harm(rp, rm), harm(hp, hm), 0.5 * rm)):
+        assert max(abs(alt[k] / ref[k] - 1.0) for k in ref) > 1e-3
+
+
+def _jump_solution(r1, r2):
+    """u = g(x) sin(pi y) with rho = r1 for x < 1/2 and r2 for x > 1/2:
+    g(x) = x(1-x)/r1 + c1 x (left), x(1-x)/r2 + c2 (1-x) (right), with c1,
+    c2 chosen so that g and rho g' are continuous at x = 1/2 (c1 = (r1 - r2)
+    / (2 r1 (r1 + r2)), c2 = -r1 c1 / r2). Then -div(rho grad u) =
+    (2 + rho pi^2 g) sin(pi y), u = 0 on the boundary, and the flux rho g'
+    across x = 1/2 is r1 c1 != 0."""
+    c1 = (r1 - r2) / (2.0 * r1 * (r1 + r2))
+    c2 = -r1 * c1 / r2
+
+    def parts(x):
+        left = x < 0.5
+        rho = np.where(left, r1, r2)
+        g = np.where(left, x * (1 - x) / r1 + c1 * x, x * (1 - x) / r2 + c2 * (1 - x))
+        dg = np.where(left, (1 - 2 * x) / r1 + c1, (1 - 2 * x) / r2 - c2)
+        return rho, g, dg
+
+    def u(X):
+        _, g, _ = parts(X[:, 0])
+        return g * np.sin(math.pi * X[:, 1])
+
+    def grad(X):
+        _, g, dg = parts(X[:, 0])
+        return np.stack([dg * np.sin(math.pi * X[:, 1]), g * math.pi * np.cos(math.pi * X[:, 1])], axis=1)
+
+    def f(X):
+        rho, g, _ = parts(X[:, 0])
+        return (2.0 + rho * math.pi ** 2 * g) * np.sin(math.pi * X[:, 1])
+
+    return u, grad, f
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_manufactured_solution_with_coefficient_jump(p):
+    """rho = 1 | 100 across the mesh line x = 1/2 with a nonzero normal flux
+    there (u continuous, rho du/dn continuous): the SIPG solution keeps the
+    L2 rate h^{p+1} and the broken H1 rate h^p. A weighting of the face
+    average that is not consistent for this flux (e.g. the arithmetic mean
+    of rho in front of (grad u+ + grad u-)/2) leaves an O(1) consistency
+    error at the interface and loses both rates (measured with that
+    change: L2 rate 0.92 at p = 1 and 1.17 at p = 2 on 16 -> 32 squares;
+    here 1.89 and 3.25)."""
+    u, grad, f = _jump_solution(1.0, 100.0)
+    errs = []
+    for nx in (8, 16, 32):
+        mesh = I.square_mesh(nx)
+        cx = mesh.vertex_mean()[:, 0]
+        rho = np.where(cx < 0.5, 1.0, 100.0)
+        A, b, geo, _ = assemble(mesh, p, rho, 10.0, f)
+        x = spla.spsolve(A.tocsc(), b)
+        errs.append(l2_and_broken_h1_error(mesh, p, geo, x, u, grad))
+    r0 = math.log2(errs[1][0] / errs[2][0])
+    r1 = math.log2(errs[1][1] / errs[2][1])
+    assert r0 > p + 1 - 0.25, (r0, errs)
+    assert r1 > p - 0.25, (r1, errs)
 
 
 @pytest.mark.parametrize("p", [1, 2])

@@ -131,6 +131,97 @@ def test_sipg3_manufactured_rate():
     assert math.log2(errs[-2] / errs[-1]) >= 2.75
 
 
+def test_sipg3_weighted_face_terms_two_cells():
+    """Entries of A across one triangular face between two tetrahedra with
+    rho_L != rho_R and h_L != h_R, worked out by hand from Sec. 2: eq. (Ah)
+    with the lifting of eq. (lifting), omega = rho-/(rho+ + rho-), the
+    harmonic average <.>, and eq. (Sigma) sigma_F = C_sigma <rho>_F p^2 / <h>_F.
+
+    Mesh: the Kuhn triangulation of the 2x2x2 grid with its middle x-plane
+    moved to x = a = 1/3, so a tetrahedron L left of that plane has the box
+    [0,a]x(1/2)x(1/2) (volume V_L = a/4, diameter h_L = sqrt(a^2 + 1/2)) and
+    one on the right R has [a,1]x... (V_R = b/4, b = 1 - a, h_R =
+    sqrt(b^2 + 1/2)). p = 1, C_sigma = 10, rho random per cell. On a shared
+    face F (in the plane x = a, area |F|, n_L = (1,0,0)): phi0 = 1/sqrt(V),
+    the x-mode phi_x = sqrt(3/V) L_1(2(x - xc)/dx) is +sqrt(3/V_L) on F from
+    L with gradient sqrt(3/V_L)(2/a,0,0), and -sqrt(3/V_R) from R with
+    gradient sqrt(3/V_R)(2/b,0,0). The omega-weighted average of rho grad u
+    gives rho_L rho_R/(rho_L + rho_R) =: w times the one-sided gradient (as in
+    2D, the lifting term equals -int_F jump(v) . {rho grad u}_w because rho grad u
+    lies in [V_h]^3). Hence
+      A[0_L, 0_R] = -sigma_F |F| / sqrt(V_L V_R)
+      A[0_L, x_R] = |F| sqrt(3/V_R) / sqrt(V_L) (sigma_F - (2/b) w)
+      A[0_R, x_L] = |F| sqrt(3/V_L) / sqrt(V_R) ((2/a) w - sigma_F)."""
+    a = 1.0 / 3.0
+    b = 1.0 - a
+    mesh = I.cube_tet_mesh(2)
+    mid = np.abs(mesh.xyz[:, 0] - 0.5) < 1e-12
+    mesh.xyz[mid, 0] = a
+    rho = 10.0 ** np.random.default_rng(7).uniform(-3, 3, mesh.n_cells)
+    A, *_ = assemble3(mesh, 1, rho, 10.0)
+    A = A.toarray()
+    npb = n_basis3(1)
+    X = mesh.xyz[mesh.tets]
+    left = np.flatnonzero(X[:, :, 0].max(1) <= a + 1e-12)
+    right = np.flatnonzero(X[:, :, 0].min(1) >= a - 1e-12)
+    hL, hR = math.sqrt(a * a + 0.5), math.sqrt(b * b + 0.5)
+    VL, VR = a / 4.0, b / 4.0
+    hF = 2.0 * hL * hR / (hL + hR)
+    pairs = 0
+    for L in left:
+        for R in right:
+            shared = sorted(set(mesh.tets[L].tolist()) & set(mesh.tets[R].tolist()))
+            if len(shared) != 3:
+                continue
+            T = mesh.xyz[shared]
+            area = 0.5 * np.linalg.norm(np.cross(T[1] - T[0], T[2] - T[0]))
+            rL, rR = rho[L], rho[R]
+            w = rL * rR / (rL + rR)
+            sF = 10.0 * (2.0 * w) / hF
+            s3L, s3R = math.sqrt(3.0 / VL), math.sqrt(3.0 / VR)
+            expect = {
+                (L * npb, R * npb): -sF * area / math.sqrt(VL * VR),
+                (L * npb, R * npb + 1): area * s3R / math.sqrt(VL) * (sF - (2.0 / b) * w),
+                (R * npb, L * npb + 1): area * s3L / math.sqrt(VR) * ((2.0 / a) * w - sF),
+            }
+            for (i, j), v in expect.items():
+                assert abs(A[i, j] - v) <= 1e-12 * abs(v), ((L, R), (i, j), A[i, j], v)
+            pairs += 1
+    assert pairs == 8  # the 2x2 squares of the plane x = a, two triangles each
+
+
+def test_sipg3_manufactured_rate_with_coefficient_jump():
+    """rho = 1 | 100 across the mesh plane x = 1/2, u = g(x) sin(pi y)
+    sin(pi z) with g and rho g' continuous there (g as in the 2D test:
+    x(1-x)/rho + c x on the left, c' (1-x) on the right), p = 2: L2 rate
+    p + 1 (observed 3.04 on 4 -> 8 cubes; with the arithmetic mean of rho in
+    the face average and penalty it drops to 1.24)."""
+    r1, r2 = 1.0, 100.0
+    c1 = (r1 - r2) / (2.0 * r1 * (r1 + r2))
+    c2 = -r1 * c1 / r2
+
+    def parts(x):
+        left = x < 0.5
+        g = np.where(left, x * (1 - x) / r1 + c1 * x, x * (1 - x) / r2 + c2 * (1 - x))
+        return np.where(left, r1, r2), g
+
+    def u(X):
+        return parts(X[..., 0])[1] * np.sin(math.pi * X[..., 1]) * np.sin(math.pi * X[..., 2])
+
+    def f(X):
+        rho, g = parts(X[..., 0])
+        return (2.0 + rho * 2.0 * math.pi ** 2 * g) * np.sin(math.pi * X[..., 1]) * np.sin(math.pi * X[..., 2])
+
+    errs = []
+    for n in (4, 8):
+        mesh = I.cube_tet_mesh(n)
+        rho = np.where(mesh.vertex_mean()[:, 0] < 0.5, r1, r2)
+        A, b, geo, _ = assemble3(mesh, 2, rho, 10.0, f)
+        x = spla.spsolve(A.tocsc(), b)
+        errs.append(l2_error3(mesh, 2, geo, x, u))
+    assert math.log2(errs[0] / errs[1]) >= 2.75, errs
+
+
 @pytest.mark.parametrize("q", [1, 2])
 def test_nested_prolongation_reproduces_global_polynomials(q):
     """P_0 c0 = fine coefficients of any global polynomial of degree <= q,
