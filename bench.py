@@ -8,9 +8,11 @@ products, batched local solves, coarse restrict/solve/prolong, iteration
 control) with the operator, local solvers and coarse solver already resident
 in HBM. Setup phases (host assembly, batched factorisation and inversion,
 coarse setup) are reported separately. The local solves are applied through
-the packed explicit inverses A_i^{-1} (default) or the two triangular sweeps
-(`--local`); subdomains of at most 64 DoFs use whole small inverses applied
-inside the prolongation.
+the packed explicit inverses A_i^{-1} (default) and/or the two triangular
+sweeps (`--local inverse,sweeps`); subdomains of at most 64 DoFs use whole
+small inverses applied inside the prolongation. Each mode reports the true
+residual of its solution and, where the FP64 oracle's solve of the workload
+is stored (tests/golden), the error against it.
 
 metric = DoF-iterations per second = n_dofs * iterations / PCG wall time,
 for the FP32-local mode (local solvers stored and applied in FP32, everything
@@ -41,14 +43,15 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 WORKLOADS = {
-    "C2": "Voronoi 16384 cells (seed 1), p=2, 98304 DoFs, 64 subdomains (8x8 centroid bins), "
+    "C2": "Voronoi 16384 cells (seed 1, two Lloyd steps), p=2, 98304 DoFs, 64 subdomains (8x8 centroid bins), "
           "nested coarse = subdomains, q=1",
-    "C3": "Voronoi 65536 cells (seed 2), p=3, 655360 DoFs, 256 uneven subdomains (warped bins), "
+    "C3": "Voronoi 65536 cells (seed 2, two Lloyd steps), p=3, 655360 DoFs, 256 uneven subdomains (warped bins), "
           "nested coarse = subdomains, q=2",
-    "C3x": "Voronoi 104858 cells (seed 4), p=3, 1048580 DoFs, 256 uneven subdomains (warped bins, 2060..8920 "
+    "C3x": "Voronoi 104858 cells (seed 4, two Lloyd steps), p=3, 1048580 DoFs, 256 uneven subdomains (warped bins, 2060..8920 "
            "DoFs), nested coarse = subdomains, q=2 (labelled extra at ~1M DoFs)",
-    "C4": "Voronoi 131072 cells (seed 3), p=2, 786432 DoFs, 512 subdomains (32x16 bins), "
-          "rho per subdomain 10^U[-4,4], non-nested coarse Voronoi of 64 cells, q=1, f=1",
+    "C4": "Voronoi 131072 cells (seed 3, two Lloyd steps), p=2, 786432 DoFs, 512 subdomains (32x16 bins of "
+          "the cells' vertex means), rho per subdomain 10^U[-4,4], non-nested coarse Voronoi of 64 cells "
+          "(two Lloyd steps), q=1, f=1",
     "T1": "unit cube, 32^3 cubes of 6 Kuhn tetrahedra (196608 cells), p=1, 786432 DoFs, one element per "
           "subdomain, 384 nested Kuhn agglomerates (coarse grid 4^3 cubes), q=1, f = 3 pi^2 sin sin sin",
     "T1b": "the T1 mesh and load with 512 box subdomains (8^3 boxes of 384 tetrahedra, 1536 DoFs each), 384 nested "
@@ -79,6 +82,8 @@ def measured_traffic(workload, mode, local="sweeps"):
             meta[k] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if meta.get("source_sha256_16") != sha:
+        print(f"[bench] WARNING: {os.path.relpath(path, ROOT)} was taken on another kernel source; "
+              f"roofline.traffic is reported as null until it is re-taken", file=sys.stderr, flush=True)
         return None
     return float(meta["traffic_bytes_per_launch"])
 
@@ -100,7 +105,19 @@ def local_solve_bytes(pr, word_bytes, inverse=False):
     return factor + vec
 
 
-def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=True):
+def oracle_reference(workload):
+    """The FP64 oracle's stored solve of this workload (written by
+    tests/golden/make_full_reference.py), or None."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle_fp64.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=True, ref=None):
     import torch
 
     from paper_1903_11357_amd import asdg
@@ -156,6 +173,23 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
         its.append(st["iterations"])
     torch.cuda.synchronize()
     total_graph = time.perf_counter() - tg0
+    # untimed: the error of this solve against the FP64 oracle's stored
+    # solution, and in FP64 mode the iterate after exactly the oracle's
+    # iteration count against the oracle's iterate after that count
+    err = None
+    if ref is not None and "x" in ref and int(ref["n"]) == pr.n:
+        import numpy as np
+
+        xo = ref["x"]
+        nxo = float(np.linalg.norm(xo))
+        err = {"oracle_iterations": int(ref["iterations"]), "oracle_true_rel_res": float(ref["true_rel_res"]),
+               "rel_err_vs_oracle": float(np.linalg.norm(x.cpu().numpy() - xo)) / nxo}
+        if precision == asdg.FP64:
+            xk = torch.empty_like(x)
+            pr.solve(x=xk, rtol=0.0, max_iter=int(ref["iterations"]), check_every=check_every,
+                     raise_on_noconv=False)
+            err["same_iterations_rel_err_vs_oracle"] = float(np.linalg.norm(xk.cpu().numpy() - xo)) / nxo
+            del xk
     w = 4 if precision == asdg.FP32_LOCAL else 8
     small = pr.is_small()
     # dense flops of the factorisation: Cholesky sum n_i^3/3, and with explicit
@@ -174,9 +208,13 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
                                "dof_iters_per_s": pr.n * its_e / total_eager},
         "converged": st["converged"],
         "rel_res": st["rel_res"],
+        "true_rel_res": st["true_rel_res"],
+        "vs_fp64_oracle": err,
         "kappa_lanczos": st["lambda_max"] / st["lambda_min"] if st["lambda_min"] > 0 else None,
         "setup_s": {"assemble_plan_host": t1 - t0, "bind_upload": t2 - t1, "factor": t3 - t2,
                     "autotune": t3b - t3, "coarse": t4 - t3b},
+        "library_phase_ms": {"assemble": st["t_assemble_ms"], "factor": st["t_factor_ms"],
+                             "coarse": st["t_coarse_ms"], "pcg": st["t_solve_ms"]},
         "autotune": tuned,
         "factor_mfma": {"flops": fl, "tflops": fl / (t3 - t2) / 1e12, "peak_tflops": peak,
                         "frac": fl / (t3 - t2) / 1e12 / peak,
@@ -324,7 +362,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--modes", default="fp32,fp64")
-    ap.add_argument("--local", default="inverse,sweeps",
+    ap.add_argument("--local", default="inverse",
                     help="local-solve representations, the first is the headline: inverse (packed "
                          "A_i^{-1}, one pass) and/or sweeps (Cholesky forward/backward sweeps)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -368,12 +406,13 @@ def main():
         P.max_iter = a.max_iter
     print(f"[bench] workload {a.workload}: n={P.n_dofs} subdomains={P.n_sub}", file=sys.stderr, flush=True)
     modes = {}
+    ref = oracle_reference(a.workload)
     for loc in a.local.split(","):
         for m in a.modes.split(","):
             prec = asdg.FP32_LOCAL if m == "fp32" else asdg.FP64
             key = m if loc == "inverse" else f"{m}-sweeps"
             modes[key] = run_mode(P, prec, a.steps, a.warmup, a.check_every, inverse=(loc == "inverse"),
-                                  autotune=not a.no_autotune)
+                                  autotune=not a.no_autotune, ref=ref)
             print(f"[bench] {key}: {json.dumps(modes[key])}", file=sys.stderr, flush=True)
     first = a.local.split(",")[0]
     hk = lambda m: m if first == "inverse" else f"{m}-sweeps"  # noqa: E731
@@ -404,6 +443,11 @@ def main():
                                 else "k_trsv (batched local forward+backward sweeps)"),
                      "algorithmic_bytes": ls.get("algorithmic_bytes"), "avg_ms": ls.get("avg_ms")},
     }
+    if hk("fp64") in modes:
+        f64 = modes[hk("fp64")]
+        out["value_fp64"] = {"value": f64["dof_iters_per_s"], "unit": "DoF-iters/s",
+                             "ms_per_step": f64["ms_per_step"], "iterations": f64["iterations"],
+                             "note": "the paper's precision: every step in FP64"}
     if hk("fp32") in modes and hk("fp64") in modes:
         f32, f64 = modes[hk("fp32")], modes[hk("fp64")]
         out["fp32_local_speedup_per_iteration"] = f64["ms_per_iteration"] / f32["ms_per_iteration"]

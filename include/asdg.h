@@ -112,6 +112,16 @@ typedef struct {
   double t_local_ms;       /* summed local-solve kernel time (time_kernels) */
   int32_t n_local;         /* number of timed local-solve launches         */
   int32_t failed_subdomain;/* ENOTSPD: subdomain index, -1 = coarse        */
+  double true_rel_res;     /* ||b - A x_k|| / ||b|| of the returned iterate,
+                              computed on the device after the loop (one
+                              operator apply and a fixed-order sum; 0 when
+                              b = 0). Sec. 7 stops on the recursive
+                              residual; this reports the true one beside it */
+  double t_assemble_ms;    /* host wall time of the last asdg_assemble(_tet) */
+  double t_factor_ms;      /* wall time of the last asdg_factor (synchronous) */
+  double t_coarse_ms;      /* coarse setup: host transfer and Galerkin A_0 in
+                              asdg_plan + the last asdg_setup_coarse        */
+  /* the PCG time itself is t_solve_ms */
 } asdg_pcg_stats;
 
 /* Handle lifetime. asdg_destroy(NULL) is a no-op. */
@@ -201,8 +211,11 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x,
  *                    stopped (converged, max_iter or breakdown) and
  *                    iterations = iterations so far.
  *   asdg_pcg_finish: after solve_done, writes x (caller layout) and the
- *                    statistics; synchronises the stream; returns the
- *                    solve's status (OK, ENOCONV, EBREAKDOWN).
+ *                    statistics (with the true residual against the d_b
+ *                    given to asdg_pcg_begin, which must therefore stay
+ *                    valid until this call returns); synchronises the
+ *                    stream; returns the solve's status (OK, ENOCONV,
+ *                    EBREAKDOWN).
  * The state copy goes to a small pinned host buffer owned by the handle. */
 asdg_status asdg_pcg_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_opts* opts, void* stream);
 asdg_status asdg_pcg_step(asdg_problem* pb, void* stream);

@@ -42,7 +42,9 @@ class PcgOpts(C.Structure):
 class PcgStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_local_ms", C.c_double), ("n_local", C.c_int32), ("failed_subdomain", C.c_int32)]
+                ("t_local_ms", C.c_double), ("n_local", C.c_int32), ("failed_subdomain", C.c_int32),
+                ("true_rel_res", C.c_double), ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double),
+                ("t_coarse_ms", C.c_double)]
 
 
 class TuneReport(C.Structure):
@@ -237,28 +239,6 @@ class Problem:
         r = TuneReport()
         self._check(self._L.asdg_autotune(self.h, what, self._stream(stream), C.byref(r)))
         return {k: getattr(r, k) for k, _ in TuneReport._fields_}
-
-    def factor_dense(self, sub: int) -> np.ndarray:
-        """Dense lower-triangular factor of subdomain ``sub`` (-1: coarse),
-        rebuilt from the exported tiles (diagonal tiles hold inverses)."""
-        info = self.info()
-        T = info[7]
-        if sub < 0:
-            n, dt = info[4], np.float64
-        else:
-            n, dt = self._sub_sizes()[sub], (np.float32 if self.precision == FP32_LOCAL else np.float64)
-        nb = (n + T - 1) // T
-        buf = np.empty(nb * (nb + 1) // 2 * T * T, dtype=dt)
-        self._check(self._L.asdg_export_factor_tiles(self.h, sub, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
-        tiles = buf.reshape(-1, T, T).astype(np.float64)
-        L = np.zeros((nb * T, nb * T))
-        for b in range(nb):
-            for j in range(b + 1):
-                t = tiles[b * (b + 1) // 2 + j]
-                if j == b:
-                    t = np.linalg.inv(np.tril(t))
-                L[b * T:(b + 1) * T, j * T:(j + 1) * T] = t
-        return np.tril(L)[:n, :n]
 
     def small_inverse(self, sub: int) -> np.ndarray:
         """A_i^{-1} of subdomain ``sub`` in small-subdomain mode (every

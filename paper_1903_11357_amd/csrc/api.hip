@@ -167,6 +167,9 @@ struct asdg_problem {
   bool chunk_in_flight = false, solve_open = false;
   DevState hs{};
   asdg_pcg_opts aopts{1e-8, 20000, 16, 1, 0};
+  const double* solve_b = nullptr;  // right-hand side of the open solve (caller order), for the true residual
+  // host wall times of the setup phases (reported in asdg_pcg_stats)
+  double t_assemble_ms = 0.0, t_coarse_host_ms = 0.0, t_factor_ms = 0.0, t_coarse_dev_ms = 0.0;
 
   template <class T>
   T* ptr(int b, size_t off) const { return reinterpret_cast<T*>(buf[b] + off); }
@@ -188,6 +191,18 @@ struct asdg_problem {
     if (chunk_ev) (void)hipEventDestroy(chunk_ev);
     if (h_state) (void)hipHostFree(h_state);
   }
+};
+
+static double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Records the wall time of the enclosing scope into `out` (every return path).
+struct WallTimer {
+  double& out;
+  double t0;
+  explicit WallTimer(double& o) : out(o), t0(wall_ms()) {}
+  ~WallTimer() { out = wall_ms() - t0; }
 };
 
 #define FAIL(pb, code, msg) \
@@ -223,7 +238,9 @@ asdg_status asdg_assemble(asdg_problem* pb, const asdg_mesh* fine, int32_t p, do
   pb->coarse_ready = false;
   MeshView mv{fine->n_vertices, fine->xy, fine->n_cells, fine->cell_ptr, fine->cell_vertices};
   HostThreadCap cap(pb->host_threads);
+  const double ta = wall_ms();
   std::string e = assemble_sipg(mv, p, c_sigma, rho, subdomain, f, f_user, pb->A);
+  pb->t_assemble_ms = wall_ms() - ta;
   if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
   const int np = pb->A.np;
   pb->rhs_caller.assign(pb->A.rhs.size(), 0.0);
@@ -245,7 +262,9 @@ asdg_status asdg_assemble_tet(asdg_problem* pb, const asdg_tet_mesh* fine, int32
   pb->coarse_ready = false;
   TetView tv{fine->n_vertices, fine->xyz, fine->n_cells, fine->tets};
   HostThreadCap cap(pb->host_threads);
+  const double ta = wall_ms();
   std::string e = assemble_sipg_tet(tv, p, c_sigma, rho, subdomain, f, f_user, pb->A);
+  pb->t_assemble_ms = wall_ms() - ta;
   if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
   const int np = pb->A.np;
   pb->rhs_caller.assign(pb->A.rhs.size(), 0.0);
@@ -619,6 +638,21 @@ asdg_status ensure_graph(asdg_problem* pb, int k) {
   return ASDG_OK;
 }
 
+// ||b - A x||^2 of the internal iterate into DevState::trr: q = A x (q is
+// free once the loop has stopped), then the fixed-order sum of the squared
+// differences with b (d_b, or the assembled load vector when NULL).
+asdg_status enqueue_true_residual(asdg_problem* pb, const double* d_b, hipStream_t s) {
+  const int np = pb->A.np;
+  const int32_t N = pb->A.n_cells;
+  const double* src = d_b ? d_b : pb->ptr<double>(0, pb->o0.rhs);
+  double* q = pb->ptr<double>(3, pb->o3.q);
+  HIPCHK(pb, launch_spmv(np, N, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
+                         pb->ptr<double>(0, pb->o0.blocks), pb->ptr<double>(3, pb->o3.x), q, nullptr, nullptr, s));
+  HIPCHK(pb, launch_true_residual(np, N, pb->ptr<int32_t>(0, pb->o0.perm), src, q,
+                                  pb->ptr<Reduction>(3, pb->o3.red) + RED_BB, pb->ptr<DevState>(3, pb->o3.st), s));
+  return ASDG_OK;
+}
+
 // x = 0, r = b, z = P^{-1} r, p = z on stream s.
 asdg_status enqueue_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_opts& o, hipStream_t s) {
   const int np = pb->A.np;
@@ -650,6 +684,10 @@ asdg_status fill_stats(asdg_problem* pb, const DevState& h, double solve_ms, dou
   stats->t_local_ms = t_local;
   stats->n_local = n_local;
   stats->failed_subdomain = -2;
+  stats->true_rel_res = h.bb > 0 ? std::sqrt(h.trr / h.bb) : 0.0;
+  stats->t_assemble_ms = pb->t_assemble_ms;
+  stats->t_factor_ms = pb->t_factor_ms;
+  stats->t_coarse_ms = pb->t_coarse_host_ms + pb->t_coarse_dev_ms;
   const int ka = std::min(h.it, HIST);
   if (ka >= 1) {
     std::vector<double> al(ka), be(std::max(ka - 1, 0));
@@ -710,6 +748,7 @@ asdg_status asdg_pcg_begin(asdg_problem* pb, const double* d_b, const asdg_pcg_o
   e = enqueue_begin(pb, d_b, o, s);
   if (e != ASDG_OK) return e;
   pb->aopts = o;
+  pb->solve_b = d_b;
   pb->solve_open = true;
   pb->hs = DevState{};
   return enqueue_state_copy(pb, s);
@@ -754,11 +793,15 @@ asdg_status asdg_pcg_finish(asdg_problem* pb, double* d_x, asdg_pcg_stats* stats
   HIPCHK(pb, launch_unpermute_out(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm),
                                   pb->ptr<double>(3, pb->o3.x), d_x, s));
   HIPCHK(pb, hipEventRecord(pb->t1, s));
-  HIPCHK(pb, hipEventSynchronize(pb->t1));
+  pb->solve_open = false;
+  asdg_status e = enqueue_true_residual(pb, pb->solve_b, s);
+  if (e != ASDG_OK) return e;
+  DevState h;
+  e = read_state(pb, s, h);
+  if (e != ASDG_OK) return e;
   float ms = 0.f;
   HIPCHK(pb, hipEventElapsedTime(&ms, pb->t0, pb->t1));
-  pb->solve_open = false;
-  asdg_status e = fill_stats(pb, pb->hs, ms, 0.0, 0, stats, (hipStream_t)stream);
+  e = fill_stats(pb, h, ms, 0.0, 0, stats, (hipStream_t)stream);
   if (e != ASDG_OK) return e;
   return status_of(pb, pb->hs);
 }
@@ -788,6 +831,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
                     coarse_mesh->cell_vertices};
     }
     std::string e;
+    const double tc = wall_ms();
     if (pb->A.dim == 3) {
       if (coarse_mesh) FAIL(pb, ASDG_EINVAL, "tetrahedral meshes take nested agglomerates (coarse_of_cell)");
       e = build_coarse_tet(pb->tet.view(), pb->A, q, coarse_of_cell, pb->C);
@@ -797,6 +841,7 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
     if (!e.empty()) FAIL(pb, ASDG_EINVAL, e);
     pb->n0 = pb->C.n_coarse * pb->C.nq;
     plan_coarse_factor(pb);
+    pb->t_coarse_host_ms = wall_ms() - tc;
   }
   plan_local(pb);
   pb->inv_planned = pb->local_inverse && !pb->small;
@@ -975,6 +1020,7 @@ static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int32_
 
 asdg_status asdg_factor(asdg_problem* pb, void* stream) {
   if (!pb) return ASDG_EINVAL;
+  WallTimer timer(pb->t_factor_ms);
   if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "asdg_factor before asdg_bind");
   hipStream_t s = (hipStream_t)stream;
   pb->failed_sub = -2;
@@ -1033,6 +1079,7 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
 
 asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
   if (!pb) return ASDG_EINVAL;
+  WallTimer timer(pb->t_coarse_dev_ms);
   if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "asdg_setup_coarse before asdg_bind");
   pb->coarse_ready = false;
   if (!pb->has_coarse) {
@@ -1130,7 +1177,10 @@ asdg_status asdg_pcg_solve(asdg_problem* pb, const double* d_b, double* d_x, con
   HIPCHK(pb, launch_unpermute_out(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm),
                                   pb->ptr<double>(3, pb->o3.x), d_x, s));
   HIPCHK(pb, hipEventRecord(pb->t1, s));
-  HIPCHK(pb, hipEventSynchronize(pb->t1));
+  e = enqueue_true_residual(pb, d_b, s);
+  if (e != ASDG_OK) return e;
+  e = read_state(pb, s, h);
+  if (e != ASDG_OK) return e;
   float solve_ms = 0.f;
   HIPCHK(pb, hipEventElapsedTime(&solve_ms, pb->t0, pb->t1));
   e = fill_stats(pb, h, solve_ms, t_local, n_local, stats, s);

@@ -124,9 +124,22 @@ __device__ __forceinline__ void partial_store(double v, Reduction* R, double* sc
   if (threadIdx.x == 0) R->partial[blockIdx.x] = v;
 }
 
+// Each thread adds its partials i, i + blockDim.x, ... in that order; the
+// loads of up to U of them are issued before the first add, so the reads
+// overlap instead of paying one memory latency per partial (the order of
+// the additions, and hence the result, is unchanged).
 __device__ __forceinline__ double partials_sum(const Reduction* R, int count, double* scratch) {
+  constexpr int U = 16;
+  const int stride = blockDim.x;
   double s = 0.0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) s += R->partial[i];
+  for (int i = threadIdx.x; i < count; i += U * stride) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = i + u * stride < count ? R->partial[i + u * stride] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + u * stride < count) s += v[u];
+  }
   return block_sum(s, scratch);
 }
 

@@ -134,8 +134,8 @@ __global__ __launch_bounds__(256) void k_spmv_even(int32_t N, const int32_t* __r
   if (red) partial_store(dot, red + RED_PQ, scratch);
 }
 
-// r = permuted b, x = 0, triangular-sweep outputs = sentinel; with `st`,
-// ||b||^2 and the initial PCG state.
+// r = permuted b, x = 0 (x optional), triangular-sweep outputs = sentinel
+// (yl, zl optional); with `st`, ||b||^2 and the initial PCG state.
 template <typename T>
 __global__ __launch_bounds__(256) void k_permute_in(int np, int32_t N, const int32_t* __restrict__ perm,
                                                     const double* __restrict__ src, double* __restrict__ r,
@@ -151,8 +151,10 @@ __global__ __launch_bounds__(256) void k_permute_in(int np, int32_t N, const int
     const double v = src[(int64_t)perm[cell] * np + a];
     r[d] = v;
     if (x) x[d] = 0.0;
-    yl[d] = sentinel<T>();
-    zl[d] = sentinel<T>();
+    if (yl) {
+      yl[d] = sentinel<T>();
+      zl[d] = sentinel<T>();
+    }
     acc += v * v;
   }
   if (!st) return;
@@ -187,6 +189,25 @@ __global__ __launch_bounds__(256) void k_unpermute(int np, int32_t N, const int3
     const int a = (int)(d - cell * np);
     dst[(int64_t)perm[cell] * np + a] = x[d];
   }
+}
+
+// ||b - Ax||^2 (the true residual of the final iterate, Sec. 7 reports the
+// relative residual): b read through the permutation, Ax from the operator
+// apply of x in internal order; fixed-order grid sum into st->trr.
+__global__ __launch_bounds__(256) void k_true_residual(int np, int32_t N, const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ src, const double* __restrict__ ax,
+                                                       Reduction* red, DevState* st) {
+  __shared__ double scratch[4];
+  const int64_t n = (int64_t)N * np;
+  double acc = 0.0;
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cell = d / np;
+    const int a = (int)(d - cell * np);
+    const double e = src[(int64_t)perm[cell] * np + a] - ax[d];
+    acc += e * e;
+  }
+  double tot;
+  if (grid_sum(acc, red, scratch, tot) && threadIdx.x == 0) st->trr = tot;
 }
 
 // alpha = (r.z)/(p.Ap) with p.Ap summed from the operator apply's partials;
@@ -488,6 +509,13 @@ hipError_t launch_permute_in(int np, int32_t N, const int32_t* perm, const doubl
 hipError_t launch_unpermute_out(int np, int32_t N, const int32_t* perm, const double* x, double* dst,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_unpermute, dim3(grid_for((int64_t)N * np, VEC_GRID)), dim3(256), 0, s, np, N, perm, x, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_true_residual(int np, int32_t N, const int32_t* perm, const double* src, const double* ax,
+                                Reduction* red, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_true_residual, dim3(grid_for((int64_t)N * np, VEC_GRID)), dim3(256), 0, s, np, N, perm, src,
+                     ax, red, st);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct DevState {
   double bb;        // ||b||^2
   double tol2;      // rtol^2 ||b||^2
   double rr;        // last ||r||^2
+  double trr;       // ||b - A x||^2 at exit (true residual, after the loop)
   int32_t it;       // completed iterations
   int32_t done;     // 1 once the loop must stop
   int32_t status;   // 0 running, 1 converged, 2 max_iter, 3 breakdown, 4 spin timeout
@@ -59,6 +60,10 @@ hipError_t launch_permute_in(int np, int32_t n_cells, const int32_t* perm, const
                              Reduction* red, DevState* st, double rtol, int max_iter, hipStream_t s);
 hipError_t launch_unpermute_out(int np, int32_t n_cells, const int32_t* perm, const double* x,
                                 double* dst, hipStream_t s);
+// st->trr = ||b - Ax||^2 with b in caller order (src, permuted on the fly)
+// and Ax in internal order (ax); deterministic grid sum through `red`.
+hipError_t launch_true_residual(int np, int32_t n_cells, const int32_t* perm, const double* src,
+                                const double* ax, Reduction* red, DevState* st, hipStream_t s);
 // Work-groups (= partials of the dot product each produces) of the operator
 // apply and of the grid-stride vector kernels, for n DoFs.
 int spmv_parts(int64_t n);

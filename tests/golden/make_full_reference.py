@@ -6,7 +6,9 @@ arithmetic): SIPG assembly (Sec. 2), the two-level Schwarz preconditioner
 (Sec. 3) and PCG from a zero initial guess to the relative residual 1e-8
 (Sec. 7 protocol). Stores, per workload, in ``<name>_oracle_fp64.npz``:
 
-  x             the oracle's iterate at its stopping iteration
+  x             the oracle's iterate at its stopping iteration (kept only
+                for the 786k-DoF jump workload C4, whose solution the
+                benchmark compares with; about 6 MB compressed)
   iterations    stopping iteration count
   rel_res       recursive residual ||r_k|| / ||b|| at the stop
   true_rel_res  ||b - A x_k|| / ||b|| at the stop
@@ -17,7 +19,8 @@ arithmetic): SIPG assembly (Sec. 2), the two-level Schwarz preconditioner
 and a short text summary ``<name>_oracle_fp64.txt``. The GPU full-size tests
 and the benchmark compare their solutions with these.
 
-Usage: python tests/golden/make_full_reference.py C4      (about 40 min on one core)
+Usage: python tests/golden/make_full_reference.py C4 [C3 C4h T1 T1b T3 ...]
+(C4: about 100 min on one core)
 """
 from __future__ import annotations
 
@@ -31,6 +34,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+
+KEEP_X = {"C4"}
 
 
 def main(name: str) -> None:
@@ -56,7 +62,8 @@ def main(name: str) -> None:
     t_pcg = time.time() - t1
     lo, hi = info.lanczos()
     out = os.path.join(HERE, f"{name}_oracle_fp64.npz")
-    np.savez_compressed(out, x=x, iterations=info.iterations, converged=info.converged,
+    keep_x = {"x": x} if name in KEEP_X else {}
+    np.savez_compressed(out, **keep_x, iterations=info.iterations, converged=info.converged,
                         rel_res=info.rel_res, true_rel_res=info.true_rel_res,
                         history=np.asarray(info.history), alphas=np.asarray(info.alphas),
                         betas=np.asarray(info.betas), lambda_min=lo, lambda_max=hi,
@@ -64,7 +71,8 @@ def main(name: str) -> None:
     with open(os.path.join(HERE, f"{name}_oracle_fp64.txt"), "w") as fh:
         fh.write(f"# FP64 CPU oracle, workload {name} (n = {P.n_dofs}), PCG from x0 = 0 to\n"
                  f"# ||r_k|| <= 1e-8 ||b|| (Sec. 7 protocol), two-level additive Schwarz (Sec. 3).\n"
-                 f"# Written by tests/golden/make_full_reference.py; x is in {name}_oracle_fp64.npz.\n")
+                 f"# Written by tests/golden/make_full_reference.py; history"
+                 f"{' and x are' if name in KEEP_X else ' is'} in {name}_oracle_fp64.npz.\n")
         fh.write(f"iterations {info.iterations}\nconverged {int(info.converged)}\n"
                  f"rel_res {info.rel_res:.6e}\ntrue_rel_res {info.true_rel_res:.6e}\n"
                  f"lambda_min {lo:.10e}\nlambda_max {hi:.10e}\ncondition {hi / lo:.6e}\n"
@@ -74,4 +82,5 @@ def main(name: str) -> None:
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "C4")
+    for nm in (sys.argv[1:] or ["C4"]):
+        main(nm)

@@ -21,6 +21,11 @@ CASES = {
     "vor_p2_big": lambda: I.voronoi_problem(1200, 12, p=2, bx=2, by=2, q=2),
     # the highest degree the library takes: p=4 (15 DoFs per cell), 4 ragged subdomains, nested q=3
     "vor_p4_q3": lambda: I.voronoi_problem(150, 9, p=4, bx=2, by=2, q=3),
+    # the regime of the 786k-DoF jump workload at reduced size: relaxed Voronoi of 4096 cells, p=2,
+    # 16x8 bins (128 ragged subdomains of 132..264 DoFs), rho = 10^U[-4,4] per subdomain (contrast
+    # up to 1e8) not aligned with an independent 16-cell coarse Voronoi mesh (non-nested, q=1), f=1
+    "C4r": lambda: I.voronoi_problem(4096, 31, p=2, bx=16, by=8, q=1, nonnested_coarse=16,
+                                     log10_rho_range=4.0, f=I.f_one),
 }
 
 _cache = {}
@@ -45,19 +50,49 @@ def _setup(name, precision, inverse=False):
     return _cache[key]
 
 
-def _kappa_local(name, orc):
-    key = (name, "kappa")
+def _kappas_local(name, orc):
+    """kappa_2(A_i) of every subdomain matrix."""
+    key = (name, "kappas")
     if key not in _cache:
-        k = 0.0
+        ks = []
         for d in orc.M.dofs:
             ev = np.linalg.eigvalsh(orc.A[d][:, d].toarray())
-            k = max(k, ev[-1] / ev[0])
-        _cache[key] = k
+            ks.append(ev[-1] / ev[0])
+        _cache[key] = np.array(ks)
     return _cache[key]
+
+
+def _kappa_local(name, orc):
+    return float(_kappas_local(name, orc).max())
 
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _assert_per_subdomain(name, orc, got, ref, prec, what):
+    """Local solves compared subdomain by subdomain (a wrong small subdomain
+    cannot hide under the norm of the whole vector): ||z_i - z_i^ref|| /
+    ||z_i^ref|| <= 1e-10 in FP64; in FP32-local mode the forward-error bound
+    of a backward-stable solve, c n u kappa(A_i) with u = 2^-24 and c n taken
+    as 64, with each subdomain's own kappa(A_i)."""
+    ks = _kappas_local(name, orc)
+    worst = 0.0
+    for i, d in enumerate(orc.M.dofs):
+        tol = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * ks[i]
+        e = _rel(got[d], ref[d])
+        worst = max(worst, e / tol)
+        assert e <= tol, (what, i, e, tol)
+    print(f"{name} {what} {prec}: worst subdomain error / bound = {worst:.2e}")
+
+
+def _oracle_run(orc, rtol=None, fixed=None):
+    """The oracle's PCG (assembled b), cached per oracle instance: to rtol,
+    or exactly `fixed` iterations."""
+    key = (id(orc), "run", rtol, fixed)
+    if key not in _cache:
+        _cache[key] = (orc, orc.solve(rtol=rtol, fixed_iters=fixed))
+    return _cache[key][1]
 
 
 def _vec(n, seed):
@@ -74,7 +109,10 @@ def test_operator_apply(name):
     v = _vec(pr.n, 1)
     out = pr.apply(asdg.APPLY_OPERATOR, torch.from_numpy(v).cuda()).cpu().numpy()
     ref = orc.A @ v
-    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+    # entry by entry against the rounding scale of that entry's own sum,
+    # (|A| |v|)_i, so rows of low-coefficient cells are held to their own scale
+    scale = abs(orc.A) @ np.abs(v)
+    assert np.all(np.abs(out - ref) <= 1e-13 * scale), float((np.abs(out - ref) / scale).max())
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
@@ -95,7 +133,7 @@ def test_local_coarse_and_preconditioner_apply(name, prec):
     # Cholesky solves have forward error <= c n u kappa(A_i); FP64 u = 2^-53,
     # FP32 u = 2^-24 (c n taken as 64 for these sizes)
     tol_l = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * _kappa_local(name, orc)
-    assert _rel(loc, ref_l) <= tol_l, _rel(loc, ref_l)
+    _assert_per_subdomain(name, orc, loc, ref_l, prec, "sweeps local apply")
     assert _rel(crs, ref_c) <= 1e-10, _rel(crs, ref_c)
     assert _rel(pre, ref_l + ref_c) <= tol_l, _rel(pre, ref_l + ref_c)
 
@@ -108,7 +146,22 @@ def test_pcg_fp64_matches_oracle(name):
     x, st = pr.solve(rtol=1e-8)
     infk = _check_pcg_parity(name, orc, st, x.cpu().numpy())
     Kg = st["lambda_max"] / st["lambda_min"]
-    assert abs(Kg / infk.condition_estimate() - 1.0) < 1e-4
+    assert abs(Kg / infk.condition_estimate() - 1.0) < K_NOISE
+    assert st["t_assemble_ms"] > 0.0 and st["t_factor_ms"] > 0.0 and st["t_coarse_ms"] > 0.0, st
+
+
+# Relative noise of the recursive residual late in a solve: two FP64
+# oracle runs that are equal in exact arithmetic (Cholesky vs explicit
+# local inverses, reversed DoF order in the local factors, transposed
+# operator storage) differ by up to 41% in ||r_k|| / ||b|| once it is below
+# 1e-6, and stop one iteration apart on four of the six parity cases
+# (tests/test_oracle_spread.py measures this on the CPU). The GPU is one
+# more such rounding variant.
+RES_NOISE = 0.5
+# Relative noise of the Lanczos condition estimate between such variants:
+# up to 1.6e-4 on C1 (22 iterations, lambda_min not yet converged), at most
+# 1e-7 on the other cases.
+K_NOISE = 1e-3
 
 
 def _check_pcg_parity(name, orc, st, xg, b=None):
@@ -116,31 +169,42 @@ def _check_pcg_parity(name, orc, st, xg, b=None):
 
     1. Iterate: after the GPU's iteration count k, the GPU iterate is within
        1e-10 (relative 2-norm) of the oracle's iterate after k iterations.
-    2. Trajectory: the GPU's final relative residual agrees with the
-       oracle's at iteration k to 25% of the tolerance. Late in a solve the
-       recursive residual (~1e-8 ||b||) carries rounding of order
-       kappa(A) u ||b||, which for these ill-conditioned cases is a sizeable
-       fraction of 1e-8.
-    3. Stopping: the same iteration as the oracle at rtol 1e-8 or, when the
-       two differ, at most 3 apart with the oracle's residual within 25% of
-       the tolerance at every iteration from the earlier of the two up to the
-       later one (exclusive). CG's residual norm is not monotone: where it
-       hovers at the threshold, rounding alone decides where it first
-       crosses."""
+    2. Residual: the GPU's final recursive residual equals the oracle's at
+       iteration k up to the relative noise RES_NOISE (relative to the
+       tolerance once below it: a solve that ends far below tol, as with one
+       subdomain and the coarse space, ends at rounding level); the true residual the
+       library reports equals ||b - A x|| / ||b|| of the returned x computed
+       here, up to the rounding of that difference, 64 u (||A||_inf ||x||_inf
+       + ||b||_inf) / ||b||_2 * sqrt(n).
+    3. Stopping: the GPU's stopping decision is the oracle's up to the same
+       noise: at the GPU's stop iteration the oracle's residual is at most
+       tol (1 + RES_NOISE), and at every earlier iteration at least
+       tol (1 - RES_NOISE). Equal stop iterations satisfy this; different
+       ones only where the oracle's residual stays within the noise band of
+       the tolerance."""
     tol = 1e-8
-    xo, info = orc.solve(rtol=tol, b=b)
+    if b is None:
+        xo, info = _oracle_run(orc, rtol=tol)
+    else:
+        xo, info = orc.solve(rtol=tol, b=b)
     kg, ko = st["iterations"], info.iterations
     assert st["converged"] == 1
-    xk, infk = orc.solve(fixed_iters=kg, b=b)
+    if b is None:
+        xk, infk = _oracle_run(orc, fixed=kg)
+    else:
+        xk, infk = orc.solve(fixed_iters=kg, b=b)
+    bb = orc.b if b is None else b
+    hk = infk.history
+    tres = np.linalg.norm(bb - orc.A @ xg) / np.linalg.norm(bb)
+    rb = 64 * 2.0 ** -53 * (abs(orc.A).sum(axis=1).max() * np.abs(xg).max() + np.abs(bb).max()) \
+        * np.sqrt(len(bb)) / np.linalg.norm(bb)
     print(f"{name}: iterations gpu={kg} oracle={ko} rel_err={_rel(xg, xk):.2e} "
-          f"res gpu={st['rel_res']:.4e} oracle@k={infk.history[-1]:.4e}")
+          f"res gpu={st['rel_res']:.4e} oracle@k={hk[-1]:.4e} true gpu={st['true_rel_res']:.4e} host={tres:.4e}")
     assert _rel(xg, xk) <= 1e-10, _rel(xg, xk)
-    assert abs(st["rel_res"] - infk.history[-1]) <= 0.25 * tol
-    if kg != ko:
-        assert abs(kg - ko) <= 3
-        hist = info.history if ko > kg else infk.history
-        band = hist[min(kg, ko) - 1:max(kg, ko) - 1]
-        assert all(abs(h / tol - 1.0) < 0.25 for h in band), band
+    assert abs(st["rel_res"] - hk[-1]) <= RES_NOISE * max(hk[-1], tol), (st["rel_res"], hk[-1])
+    assert abs(st["true_rel_res"] - tres) <= rb, (st["true_rel_res"], tres, rb)
+    assert hk[-1] <= tol * (1 + RES_NOISE), hk[-1]
+    assert all(h >= tol * (1 - RES_NOISE) for h in hk[:-1]), min(hk[:-1])
     return infk
 
 
@@ -246,7 +310,7 @@ def test_local_inverse_apply_matches_oracle_and_is_symmetric(name, prec):
     # an explicit inverse computed from the Cholesky factor carries relative
     # error ~ n u kappa(A_i), like the triangular solves
     tol = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * _kappa_local(name, orc)
-    assert _rel(lu, ref) <= tol, _rel(lu, ref)
+    _assert_per_subdomain(name, orc, lu, ref, prec, "inverse local apply")
     # the packed symmetric apply is symmetric up to rounding of the dot products
     eps = 1e-13 if prec == "fp64" else 1e-5
     assert abs(u @ lv - v @ lu) <= eps * np.linalg.norm(u) * np.linalg.norm(lv)
@@ -332,9 +396,7 @@ def test_small_local_apply_matches_oracle_and_is_symmetric(name, prec):
     lu = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(u).cuda()).cpu().numpy()
     lv = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()
     ref = orc.M.local_apply(u)
-    k = max(np.linalg.cond(orc.A[d][:, d].toarray()) for d in orc.M.dofs)
-    tol = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * k
-    assert _rel(lu, ref) <= tol, (_rel(lu, ref), tol)
+    _assert_per_subdomain("small/" + name, orc, lu, ref, prec, "small local apply")
     # the stored inverses are exactly symmetric; the FP64 sums of their rows
     # add the same products in different orders
     assert abs(v @ lu - u @ lv) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(lv)
