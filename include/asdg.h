@@ -233,6 +233,22 @@ enum { ASDG_APPLY_OPERATOR = 0, ASDG_APPLY_LOCAL = 1, ASDG_APPLY_COARSE = 2,
 asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, double* d_out,
                        void* stream);
 
+/* For callers that cannot allocate device memory or synchronise (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): out = A in (the ASDG_APPLY_OPERATOR step of asdg_apply, same
+ * kernels and results) with its staging vectors in a static device array of
+ * the library instead of the handle's bound scratch buffer, which it leaves
+ * untouched, so it may run while a non-blocking solve of the same handle is
+ * in flight. Calls no hipMalloc/hipFree and does not synchronise: the work
+ * is only enqueued on `stream`. The array holds 2 * 1572864 doubles (24 MiB)
+ * per GPU, for problems of at most 1572864 DoFs (EINVAL above that), kept
+ * until the process ends and shared by every call on that GPU: calls that
+ * overlap on one GPU (different streams, handles or threads) race, so order
+ * them (one stream, or events). d_in, d_out: [n] device vectors in caller
+ * layout. Errors: EINVAL (null vector, size), ESTATE (before asdg_bind),
+ * EHIP. */
+asdg_status asdg_apply_operator_static(asdg_problem* pb, const double* d_in, double* d_out, void* stream);
+
 /* Problem sizes: info[0] = n_cells, [1] = n_p, [2] = n (DoFs), [3] = n_sub,
  * [4] = n0 (coarse DoFs), [5] = nnz blocks of A, [6] = max subdomain DoFs,
  * [7] = tile size of the local factors. */

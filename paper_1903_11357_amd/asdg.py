@@ -80,6 +80,7 @@ _SIGS = {
     "asdg_pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PcgOpts), C.POINTER(PcgStats),
                                  C.c_void_p]),
     "asdg_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "asdg_apply_operator_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "asdg_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "asdg_export_rhs": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "asdg_export_operator": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -329,6 +330,18 @@ class Problem:
             out = torch.empty_like(v)
         self._check(self._L.asdg_apply(self.h, what, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
                                        self._stream(stream)))
+        return out
+
+    def apply_operator_static(self, v, out=None, stream=None):
+        """out = A v through asdg_apply_operator_static (no allocation, no
+        synchronisation inside the library; staging in its static device
+        array)."""
+        import torch
+
+        if out is None:
+            out = torch.empty_like(v)
+        self._check(self._L.asdg_apply_operator_static(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr()),
+                                                       self._stream(stream)))
         return out
 
     # ---------------------------------------------------------------- export

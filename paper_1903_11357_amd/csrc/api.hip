@@ -27,6 +27,36 @@ using namespace asdg;
 
 namespace {
 
+// Device workspace of asdg_apply_operator_static (the one entry point that
+// works without the caller's bound scratch buffer): the input and the
+// output of the operator apply in the internal, subdomain-major DoF order.
+// Host code never passes this name to a kernel; it uses the address that
+// hipGetSymbolAddress returns for the current device (static_scratch()).
+constexpr int64_t kStaticMaxDofs = 1572864;
+static __device__ __align__(256) double scratch[2 * kStaticMaxDofs];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy at its own address).
+hipError_t static_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 struct Layout {
   size_t size = 0;
   size_t add(size_t bytes) {
@@ -1240,6 +1270,28 @@ asdg_status asdg_apply(asdg_problem* pb, int32_t what, const double* d_in, doubl
   asdg_status e = read_state(pb, s, h);
   if (e != ASDG_OK) return e;
   if (h.abort) FAIL(pb, ASDG_EHIP, "wait budget exhausted");
+  return ASDG_OK;
+}
+
+asdg_status asdg_apply_operator_static(asdg_problem* pb, const double* d_in, double* d_out, void* stream) {
+  if (!pb) return ASDG_EINVAL;
+  if (!d_in || !d_out) FAIL(pb, ASDG_EINVAL, "null vector");
+  if (pb->stage < 3) FAIL(pb, ASDG_ESTATE, "apply before asdg_bind");
+  if (pb->n() > kStaticMaxDofs)
+    FAIL(pb, ASDG_EINVAL, "asdg_apply_operator_static takes at most " + std::to_string(kStaticMaxDofs) +
+                              " DoFs (problem has " + std::to_string(pb->n()) + ")");
+  double* ws = nullptr;
+  HIPCHK(pb, static_scratch(&ws));
+  hipStream_t s = (hipStream_t)stream;
+  const int np = pb->A.np;
+  const int32_t N = pb->A.n_cells;
+  const int32_t* perm = pb->ptr<int32_t>(0, pb->o0.perm);
+  double* in_w = ws;
+  double* out_w = ws + pb->n();
+  HIPCHK(pb, launch_permute_in(np, N, perm, d_in, in_w, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0.0, 0, s));
+  HIPCHK(pb, launch_spmv(np, N, pb->ptr<int32_t>(0, pb->o0.row_ptr), pb->ptr<int32_t>(0, pb->o0.col),
+                         pb->ptr<double>(0, pb->o0.blocks), in_w, out_w, nullptr, nullptr, s));
+  HIPCHK(pb, launch_unpermute_out(np, N, perm, out_w, d_out, s));
   return ASDG_OK;
 }
 
