@@ -305,12 +305,19 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * for n0 <= 8192): 0 = packed lower tiles from n0 >= 4096 on, dense below
  * (default); 1 = always packed; 2 = always dense. The packed form is
  * applied by tiles (half the bytes), the dense one by one product.
- * No launch shape changes the arithmetic: results are identical for every
- * setting. */
+ * FACTOR_SCHEDULE: how the local factorisation and inverse formation are
+ * spread over work-groups: 1 = one task per tile (a dependency-ordered
+ * queue with flag waits: one subdomain can occupy many work-groups);
+ * 2 = one work-group per subdomain for the Cholesky factorisation and per
+ * block column for X = L^{-1} (no waits; for many subdomains of similar
+ * size); 0 = automatic (2 when the largest subdomain's factorisation is at
+ * most 1.5 times an even share of the whole over the device's work-groups).
+ * No launch shape or schedule changes the arithmetic: results are
+ * identical for every setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
        ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
        ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9,
-       ASDG_TUNE_HOST_THREADS = 10, ASDG_TUNE_COARSE_PACKED = 11 };
+       ASDG_TUNE_HOST_THREADS = 10, ASDG_TUNE_COARSE_PACKED = 11, ASDG_TUNE_FACTOR_SCHEDULE = 12 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Launch shapes chosen by asdg_autotune and the best times measured. */
@@ -320,6 +327,7 @@ typedef struct {
   double local_ms;  /* one batched local solve with the chosen shape (0 if not tuned) */
   int32_t candidates; /* configurations timed */
   int32_t from_cache; /* 1: shapes taken from the process's tuning cache, nothing timed */
+  int32_t factor_schedule; /* ASDG_TUNE_FACTOR_SCHEDULE in effect (1 or 2; 0 with whole small inverses) */
 } asdg_tune_report;
 
 /* Own launch-shape autotuner (the batched factorisation and local-solve
@@ -327,9 +335,10 @@ typedef struct {
  * problem with HIP events on `stream` (median of three runs, or one run
  * when it takes more than 20 ms) and keeps the fastest, through the same
  * settings as asdg_set_tuning.
- * ASDG_AUTOTUNE_FACTOR (after asdg_bind): work-groups per compute unit of
- * the Cholesky launch (1, 2), the task order (TASK_CHUNK 0, and 64 when
- * there are more than 64 subdomains) and, with explicit inverses,
+ * ASDG_AUTOTUNE_FACTOR (after asdg_bind): the factorisation schedule
+ * (FACTOR_SCHEDULE 1, 2), work-groups per compute unit of
+ * the Cholesky launch (1, 2), the task order of the tile schedule
+ * (TASK_CHUNK 0, and 64 when there are more than 64 subdomains) and, with explicit inverses,
  * work-groups per compute unit of the inverse formation (1-4 FP32, 1-2
  * FP64); runs asdg_factor up to 3 times per candidate and leaves the
  * problem factorised. ASDG_AUTOTUNE_LOCAL (after

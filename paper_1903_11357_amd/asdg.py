@@ -51,7 +51,7 @@ class TuneReport(C.Structure):
     _fields_ = [("chol_wg_per_cu", C.c_int32), ("inv_wg_per_cu", C.c_int32), ("trsv_wg_per_cu", C.c_int32),
                 ("symv_waves", C.c_int32), ("task_chunk", C.c_int32), ("factor_ms", C.c_double),
                 ("local_ms", C.c_double),
-                ("candidates", C.c_int32), ("from_cache", C.c_int32)]
+                ("candidates", C.c_int32), ("from_cache", C.c_int32), ("factor_schedule", C.c_int32)]
 
 
 class TetMesh_(C.Structure):
@@ -101,8 +101,8 @@ _SIGS = {
     "asdg_pcg_finish": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(PcgStats), C.c_void_p]),
 }
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
-    TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES, TUNE_TASK_CHUNK, TUNE_HOST_THREADS, TUNE_COARSE_PACKED = \
-    0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+    TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES, TUNE_TASK_CHUNK, TUNE_HOST_THREADS, TUNE_COARSE_PACKED, \
+    TUNE_FACTOR_SCHEDULE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 AUTOTUNE_FACTOR, AUTOTUNE_LOCAL, AUTOTUNE_REUSE = 1, 2, 4
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 

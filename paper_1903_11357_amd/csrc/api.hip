@@ -151,7 +151,7 @@ struct asdg_problem {
   int64_t n_ctiles = 0;
   // buffer layout
   struct { size_t row_ptr, col, blocks, rhs, perm, cell_sub; } o0{};
-  struct { size_t tiles, subs, chol, trsv, meta, xtiles, inv; } o1{};
+  struct { size_t tiles, subs, chol, trsv, meta, xtiles, inv, subt, colt; } o1{};
   struct { size_t pptr, pcol, pval, tptr, tcell, tblk, ctiles, csub, cchol, ctrsv, cS, cX, cinv, cmeta, cinvt; } o2{};
   // coarse solve by a dense explicit A_0^{-1} (n0 <= kCoarseDenseMax) instead of the triangular sweeps
   bool coarse_dense = false;
@@ -169,6 +169,10 @@ struct asdg_problem {
   int chol_per_cu = 0, trsv_per_cu = 0, chol_grid = 0, trace = 0;  // 0: defaults
   int inv_per_cu = 0, symv_waves = 0;                                // 0: defaults
   int task_chunk = 0;        // subdomains per group of the factorisation task order (0: all at once)
+  // factorisation schedule: 0 automatic, 1 tile tasks (Cholesky and X = L^{-1}), 2 one work-group per
+  // subdomain (Cholesky) and per block column (X = L^{-1})
+  int factor_sched = 0;
+  std::vector<int4> sub_tasks, col_tasks;  // the schedule-2 queues, largest work first
   int host_threads = 0;      // cap on host threads of assembly and planning (0: default)
   std::string arch;          // device architecture name (set by asdg_bind)
   bool tasks_dirty = false;  // task lists reordered after asdg_bind, not yet uploaded
@@ -418,6 +422,24 @@ void plan_local(asdg_problem* pb) {
   // subdomain, column, row); every dependency has a strictly longer path, so
   // it precedes its consumers in the queue
   pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, pb->task_chunk);
+  // schedule 2: whole subdomains (Cholesky) and block columns (X = L^{-1}),
+  // largest work first (ties by index)
+  {
+    std::vector<int32_t> ord(ns);
+    for (int32_t i = 0; i < ns; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return pb->subs[a].nb > pb->subs[b].nb; });
+    pb->sub_tasks.resize(ns);
+    for (int32_t k = 0; k < ns; ++k) pb->sub_tasks[k] = make_int4(ord[k], 0, 0, 0);
+    struct C { int64_t w; int32_t i, j; };
+    std::vector<C> cs;
+    for (int32_t i = 0; i < ns; ++i) {
+      const int64_t nb = pb->subs[i].nb;
+      for (int j = 0; j < nb; ++j) cs.push_back({(nb - j) * (nb - j + 1) / 2, i, j});
+    }
+    std::stable_sort(cs.begin(), cs.end(), [](const C& a, const C& b) { return a.w > b.w; });
+    pb->col_tasks.resize(cs.size());
+    for (size_t k = 0; k < cs.size(); ++k) pb->col_tasks[k] = make_int4(cs[k].i, cs[k].j, 0, 0);
+  }
   struct K { int64_t key; int4 t; };
   std::vector<K> ks;
   // sweep tasks: forward b at step b, backward b at step 2nb-1-b; all
@@ -903,7 +925,9 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   if (pb->inv_planned) {
     pb->o1.xtiles = L1.add((size_t)pb->n_tiles * TILE * TILE * w);
     pb->o1.inv = L1.add(sizeof(int4) * pb->inv_tasks.size());
+    pb->o1.colt = L1.add(sizeof(int4) * pb->col_tasks.size());
   }
+  pb->o1.subt = L1.add(sizeof(int4) * std::max<size_t>(1, pb->sub_tasks.size()));
   if (pb->has_coarse) {
     const Coarse& C = pb->C;
     pb->o2.pptr = L2.add(4 * (N + 1));
@@ -997,7 +1021,11 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   HIPCHK(pb, up(0, pb->o0.rhs, pb->rhs_caller.data(), 8 * pb->rhs_caller.size()));
   HIPCHK(pb, up(0, pb->o0.perm, A.perm.data(), 4 * A.perm.size()));
   HIPCHK(pb, up(0, pb->o0.cell_sub, pb->cell_sub.data(), 4 * pb->cell_sub.size()));
-  if (pb->inv_planned) HIPCHK(pb, up(1, pb->o1.inv, pb->inv_tasks.data(), sizeof(int4) * pb->inv_tasks.size()));
+  if (pb->inv_planned) {
+    HIPCHK(pb, up(1, pb->o1.inv, pb->inv_tasks.data(), sizeof(int4) * pb->inv_tasks.size()));
+    HIPCHK(pb, up(1, pb->o1.colt, pb->col_tasks.data(), sizeof(int4) * pb->col_tasks.size()));
+  }
+  if (!pb->sub_tasks.empty()) HIPCHK(pb, up(1, pb->o1.subt, pb->sub_tasks.data(), sizeof(int4) * pb->sub_tasks.size()));
   HIPCHK(pb, up(1, pb->o1.subs, pb->subs.data(), sizeof(SubDesc) * pb->subs.size()));
   HIPCHK(pb, up(1, pb->o1.chol, pb->chol_tasks.data(), sizeof(int4) * pb->chol_tasks.size()));
   HIPCHK(pb, up(1, pb->o1.trsv, pb->trsv_tasks.data(), sizeof(int4) * pb->trsv_tasks.size()));
@@ -1025,16 +1053,35 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   return ASDG_OK;
 }
 
-static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int32_t n_tasks, const int4* tasks,
-                                const SubDesc* subs, void* tiles, int64_t n_tiles, int coarse) {
+// Factorisation schedule of the local matrices (1 tile tasks, 2 subdomain
+// and column tasks). Automatic: the subdomain schedule when the largest
+// subdomain's Cholesky (about nb^3/6 tile products) is no more than 1.5 times
+// an even share of all of them over the work-groups that fit on the device,
+// i.e. when one work-group per subdomain keeps the device busy to the end;
+// otherwise the tile tasks, which spread one subdomain over many work-groups.
+static int factor_schedule(const asdg_problem* pb) {
+  if (pb->factor_sched == 1 || pb->factor_sched == 2) return pb->factor_sched;
+  double total = 0.0, largest = 0.0;
+  for (const SubDesc& d : pb->subs) {
+    const double w = (double)d.nb * d.nb * d.nb;
+    total += w;
+    largest = std::max(largest, w);
+  }
+  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
+  const double slots = (double)pb->n_cu * per_cu;
+  return largest <= 1.5 * total / slots ? 2 : 1;
+}
+
+static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int per_sub, int32_t n_tasks,
+                                const int4* tasks, const SubDesc* subs, void* tiles, int64_t n_tiles, int coarse) {
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   int32_t* flags = pb->ptr<int32_t>(3, pb->o3.flags);
-  HIPCHK(pb, launch_fill_i32(flags, n_tiles, 0, s));
+  if (!per_sub) HIPCHK(pb, launch_fill_i32(flags, n_tiles, 0, s));
   HIPCHK(pb, launch_reset_queues(st, s));
   const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;  // the kernel's occupancy (registers)
   int64_t gmax = pb->chol_grid > 0 ? pb->chol_grid : (int64_t)pb->n_cu * per_cu;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tasks, gmax));
-  HIPCHK(pb, launch_cholesky(f32, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
+  HIPCHK(pb, launch_cholesky(f32, per_sub, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
   DevState h;
   asdg_status e = read_state(pb, s, h);
   if (e != ASDG_OK) return e;
@@ -1084,17 +1131,23 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.row_ptr),
                                  pb->ptr<int32_t>(0, pb->o0.col), pb->ptr<double>(0, pb->o0.blocks),
                                  pb->ptr<void>(1, pb->o1.tiles), pb->f32, s));
-  asdg_status e = run_cholesky(pb, s, pb->f32, (int32_t)pb->chol_tasks.size(), pb->ptr<int4>(1, pb->o1.chol),
-                               pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0);
+  const int sched = factor_schedule(pb);
+  const bool per_sub = sched == 2;
+  asdg_status e = per_sub ? run_cholesky(pb, s, pb->f32, 1, (int32_t)pb->sub_tasks.size(), pb->ptr<int4>(1, pb->o1.subt),
+                                         pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0)
+                          : run_cholesky(pb, s, pb->f32, 0, (int32_t)pb->chol_tasks.size(), pb->ptr<int4>(1, pb->o1.chol),
+                                         pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0);
   if (e != ASDG_OK) return e;
   if (pb->inv_planned) {
     DevState* st = pb->ptr<DevState>(3, pb->o3.st);
-    HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_tiles, 0, s));
+    if (!per_sub) HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_tiles, 0, s));
     HIPCHK(pb, launch_reset_queues(st, s));
     const int per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);  // default: the occupancy
-    const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)pb->inv_tasks.size(), (int64_t)pb->n_cu * per_cu));
+    const int64_t nt = per_sub ? (int64_t)pb->col_tasks.size() : (int64_t)pb->inv_tasks.size();
+    const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t)pb->n_cu * per_cu));
     const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>(pb->n_tiles, (int64_t)pb->n_cu * per_cu * 4));
-    HIPCHK(pb, launch_inverse(pb->f32, (int32_t)pb->inv_tasks.size(), pb->ptr<int4>(1, pb->o1.inv),
+    HIPCHK(pb, launch_inverse(pb->f32, per_sub ? 1 : 0, (int32_t)nt,
+                              per_sub ? pb->ptr<int4>(1, pb->o1.colt) : pb->ptr<int4>(1, pb->o1.inv),
                               (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta), pb->ptr<SubDesc>(1, pb->o1.subs),
                               pb->ptr<void>(1, pb->o1.tiles), pb->ptr<void>(1, pb->o1.xtiles),
                               pb->ptr<int32_t>(3, pb->o3.flags), st, &st->q_chol, g1, g2, s));
@@ -1119,7 +1172,7 @@ asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(pb, hipMemcpyAsync(pb->buf[2] + pb->o2.ctiles, pb->ctiles_host.data(), 8 * pb->ctiles_host.size(),
                             hipMemcpyHostToDevice, s));
-  asdg_status e = run_cholesky(pb, s, 0, (int32_t)pb->cchol_tasks.size(), pb->ptr<int4>(2, pb->o2.cchol),
+  asdg_status e = run_cholesky(pb, s, 0, 0, (int32_t)pb->cchol_tasks.size(), pb->ptr<int4>(2, pb->o2.cchol),
                                pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles), pb->n_ctiles, 1);
   if (e != ASDG_OK) return e;
   if (pb->coarse_dense) {
@@ -1130,7 +1183,7 @@ asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
     HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_ctiles, 0, s));
     HIPCHK(pb, launch_reset_queues(st, s));
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>(pb->n_ctiles, (int64_t)pb->n_cu * 2));
-    HIPCHK(pb, launch_inverse(0, (int32_t)pb->cinv_tasks.size(), pb->ptr<int4>(2, pb->o2.cinvt),
+    HIPCHK(pb, launch_inverse(0, 0, (int32_t)pb->cinv_tasks.size(), pb->ptr<int4>(2, pb->o2.cinvt),
                               (int32_t)pb->n_ctiles, pb->ptr<int4>(2, pb->o2.cmeta), pb->ptr<SubDesc>(2, pb->o2.csub),
                               pb->ptr<void>(2, pb->o2.cS), pb->ptr<void>(2, pb->o2.cX),
                               pb->ptr<int32_t>(3, pb->o3.flags), st, &st->q_chol, g, g, s));
@@ -1409,6 +1462,10 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
   else if (what == ASDG_TUNE_NO_PRECOND) pb->no_precond = value ? 1 : 0;
   else if (what == ASDG_TUNE_INV_WG_PER_CU) pb->inv_per_cu = value;
   else if (what == ASDG_TUNE_HOST_THREADS) pb->host_threads = value;
+  else if (what == ASDG_TUNE_FACTOR_SCHEDULE) {
+    if (value > 2) FAIL(pb, ASDG_EINVAL, "factorisation schedule: 0 automatic, 1 tile tasks, 2 subdomain tasks");
+    pb->factor_sched = value;
+  }
   else if (what == ASDG_TUNE_COARSE_PACKED) {
     if (value > 2) FAIL(pb, ASDG_EINVAL, "coarse inverse storage: 0 automatic, 1 packed, 2 dense");
     pb->coarse_packed_mode = value;
@@ -1486,6 +1543,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     if (hit) {
       // the shapes found before for this size class, no timing
       if (what & ASDG_AUTOTUNE_FACTOR) {
+        pb->factor_sched = C.factor_schedule;
         pb->chol_per_cu = C.chol_wg_per_cu;
         pb->inv_per_cu = C.inv_wg_per_cu;
         if (C.task_chunk != pb->task_chunk && !pb->small) {
@@ -1557,7 +1615,10 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   };
   if ((what & ASDG_AUTOTUNE_FACTOR) && !pb->small) {
     double ms = 0.0;
-    asdg_status e = tune(&pb->chol_per_cu, {1, 2}, time_factor, ms);
+    // the schedule first (tile tasks, or one work-group per subdomain / column)
+    asdg_status e = tune(&pb->factor_sched, {1, 2}, time_factor, ms);
+    if (e != ASDG_OK) return e;
+    e = tune(&pb->chol_per_cu, {1, 2}, time_factor, ms);
     if (e != ASDG_OK) return e;
     {
       // task order: all subdomains interleaved, or in groups (smaller working set)
@@ -1569,7 +1630,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
         return time_factor(ms1);
       };
       std::vector<int> cand{0};
-      if (pb->A.n_sub > 64) cand.push_back(64);
+      if (pb->A.n_sub > 64 && pb->factor_sched == 1) cand.push_back(64);  // (the tile-task order only)
       e = tune(&chunk, cand, reorder, ms);
       if (e != ASDG_OK) return e;
       pb->task_chunk = chunk;
@@ -1618,6 +1679,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   R.trsv_wg_per_cu = pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2;
   R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
   R.task_chunk = pb->task_chunk;
+  R.factor_schedule = pb->small ? 0 : factor_schedule(pb);
   pb->drop_graph();
   if ((what & (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL)) == (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL) && !pb->small) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1634,8 +1696,8 @@ asdg_status asdg_tune_cache_save(const char* path) {
   if (!f) return ASDG_EINVAL;
   for (const auto& kv : g_tune_cache) {
     const asdg_tune_report& R = kv.second;
-    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
-                 R.trsv_wg_per_cu, R.symv_waves, R.task_chunk, R.factor_ms, R.local_ms);
+    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f %d\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
+                 R.trsv_wg_per_cu, R.symv_waves, R.task_chunk, R.factor_ms, R.local_ms, R.factor_schedule);
   }
   return std::fclose(f) == 0 ? ASDG_OK : ASDG_EINVAL;
 }
@@ -1646,16 +1708,21 @@ asdg_status asdg_tune_cache_load(const char* path, int32_t* n_entries) {
   if (!f) return ASDG_EINVAL;
   std::map<std::string, asdg_tune_report> add;
   char key[256];
+  char line[512];
   asdg_tune_report R;
   bool ok = true;
-  for (;;) {
+  // one entry per line; the factorisation schedule (last field) may be
+  // missing in files written before it existed (then: automatic)
+  while (std::fgets(line, sizeof(line), f)) {
     std::memset(&R, 0, sizeof(R));
-    const int got = std::fscanf(f, "%255s %d %d %d %d %d %lf %lf", key, &R.chol_wg_per_cu, &R.inv_wg_per_cu,
-                                &R.trsv_wg_per_cu, &R.symv_waves, &R.task_chunk, &R.factor_ms, &R.local_ms);
-    if (got == EOF) break;
+    const int got = std::sscanf(line, "%255s %d %d %d %d %d %lf %lf %d", key, &R.chol_wg_per_cu, &R.inv_wg_per_cu,
+                                &R.trsv_wg_per_cu, &R.symv_waves, &R.task_chunk, &R.factor_ms, &R.local_ms,
+                                &R.factor_schedule);
+    if (got <= 0) continue;  // blank line
     const bool waves_ok = R.symv_waves == 1 || R.symv_waves == 2 || R.symv_waves == 4 || R.symv_waves == 8;
-    if (got != 8 || !waves_ok || R.chol_wg_per_cu < 1 || R.chol_wg_per_cu > 64 || R.inv_wg_per_cu < 1 ||
-        R.inv_wg_per_cu > 64 || R.trsv_wg_per_cu < 1 || R.trsv_wg_per_cu > 64 || R.task_chunk < 0) {
+    if ((got != 8 && got != 9) || !waves_ok || R.chol_wg_per_cu < 1 || R.chol_wg_per_cu > 64 ||
+        R.inv_wg_per_cu < 1 || R.inv_wg_per_cu > 64 || R.trsv_wg_per_cu < 1 || R.trsv_wg_per_cu > 64 ||
+        R.task_chunk < 0 || R.factor_schedule < 0 || R.factor_schedule > 2) {
       ok = false;
       break;
     }

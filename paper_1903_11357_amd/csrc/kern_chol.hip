@@ -27,6 +27,144 @@ namespace {
 
 using namespace mfma;
 
+// One task (b, j) of subdomain `sub` (tiles at `base`, flags at `fl`).
+// OWN = false: the tile-task schedule, where the tiles it reads were written
+// by other work-groups of the launch (flag waits, device-coherent loads and
+// stores, the tile's flag raised at the end). OWN = true: the subdomain
+// schedule, where one work-group runs all tasks of its subdomain in column
+// order, so every tile it reads it wrote itself earlier (plain loads and
+// stores, ordered by the barrier that ends each task). The arithmetic is the
+// same in both.
+template <typename T, bool OWN>
+__device__ __forceinline__ void chol_tile(int sub, int j, int b, T* base, int32_t* fl, DevState* st, T* As, T* Bs,
+                                          int& s_fail) {
+  constexpr size_t TT = (size_t)TILE * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R0 = 32 * (wave >> 1), C0 = 32 * (wave & 1);
+  T* Cg = base + (size_t)(b * (b + 1) / 2 + j) * TT;
+  const int rb = b * (b + 1) / 2, rj = j * (j + 1) / 2;  // first tiles of block rows b and j
+
+  Quad<T> acc;
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    acc.set(e, Cg[(R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane)]);
+
+  TileRegs<T> ga, gb;
+  if (j > 0) {
+    if (OWN) {
+      ga.load(base + (size_t)rb * TT);
+      gb.load(base + (size_t)rj * TT);
+    } else {
+      wait_flags(fl + rb, fl + rj, st);
+      ga.load_coherent(base + (size_t)rb * TT);
+      gb.load_coherent(base + (size_t)rj * TT);
+    }
+  }
+  for (int k = 0; k < j; ++k) {
+    ga.put(As);
+    gb.put(Bs);
+    // the barrier (of the wait) also makes the tiles just written visible to all waves
+    if (k + 1 < j) {
+      if (OWN) {
+        __syncthreads();
+        ga.load(base + (size_t)(rb + k + 1) * TT);
+        gb.load(base + (size_t)(rj + k + 1) * TT);
+      } else {
+        wait_flags(fl + rb + k + 1, fl + rj + k + 1, st);
+        ga.load_coherent(base + (size_t)(rb + k + 1) * TT);
+        gb.load_coherent(base + (size_t)(rj + k + 1) * TT);
+      }
+    } else {
+      __syncthreads();
+    }
+    acc.mma(As, Bs, R0, C0, lane, T(-1));
+    __syncthreads();
+  }
+
+  if (b == j) {
+    // S -> LDS, unblocked Cholesky of the lower triangle
+#pragma unroll
+    for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    for (int kk = 0; kk < TILE; ++kk) {
+      if (tid == 0) {
+        T d = As[kk * LDA + kk];
+        if (!(d > T(0))) {
+          s_fail = 1;
+          d = T(1);
+        }
+        As[kk * LDA + kk] = sqrt(d);
+      }
+      __syncthreads();
+      if (tid > kk && tid < TILE) As[tid * LDA + kk] /= As[kk * LDA + kk];
+      __syncthreads();
+      // trailing update of the lower triangle: thread (ii, jj) pairs with jj <= ii
+      const int m = TILE - kk - 1;
+      for (int e = tid; e < m * m; e += blockDim.x) {
+        const int ii = kk + 1 + e / m, jj = kk + 1 + e % m;
+        if (jj <= ii) As[ii * LDA + jj] -= As[ii * LDA + kk] * As[jj * LDA + kk];
+      }
+      __syncthreads();
+    }
+    if (s_fail && tid == 0) atomicMin(&st->chol_fail, sub);
+    // inverse of the lower-triangular L_jj, one column per thread
+    if (tid < TILE) {
+      const int c = tid;
+      for (int ii = 0; ii < TILE; ++ii) {
+        T v;
+        if (ii < c) {
+          v = T(0);
+        } else if (ii == c) {
+          v = T(1) / As[c * LDA + c];
+        } else {
+          T s = T(0);
+          for (int m2 = c; m2 < ii; ++m2) s += As[ii * LDA + m2] * Bs[m2 * LDA + c];
+          v = -s / As[ii * LDA + ii];
+        }
+        Bs[ii * LDA + c] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < TILE * TILE; e += blockDim.x) {
+      if (OWN)
+        Cg[e] = Bs[(e / TILE) * LDA + (e % TILE)];
+      else
+        store_agent(Cg + e, Bs[(e / TILE) * LDA + (e % TILE)]);
+    }
+  } else {
+    // L_bj = S inv(L_jj)^T
+    if (OWN) {
+      gb.load(base + (size_t)(rj + j) * TT);
+    } else {
+      wait_flag(fl + rj + j, st);
+      gb.load_coherent(base + (size_t)(rj + j) * TT);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
+    gb.put(Bs);
+    __syncthreads();
+    acc.zero();
+    acc.mma(As, Bs, R0, C0, lane, T(1));
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      T* o = Cg + (R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane);
+      if (OWN)
+        *o = acc.get(e);
+      else
+        store_agent(o, acc.get(e));
+    }
+  }
+  if (!OWN) {
+    wait_own_stores();
+    __syncthreads();
+    if (tid == 0) store_agent(fl + rb + j, 1);
+  }
+  __syncthreads();
+}
+
+// Tile-task schedule: one task per tile of every subdomain, from a queue
+// ordered by longest remaining path (see the file comment).
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_cholesky(int32_t n_tasks, const int4* __restrict__ tasks,
                                                   const SubDesc* __restrict__ subs, T* tiles, int32_t* flags,
@@ -37,9 +175,7 @@ __global__ __launch_bounds__(256, 2) void k_cholesky(int32_t n_tasks, const int4
   __shared__ int s_task;
   __shared__ int s_fail;
   constexpr size_t TT = (size_t)TILE * TILE;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int R0 = 32 * (wave >> 1), C0 = 32 * (wave & 1);
-
+  const int tid = threadIdx.x;
   for (;;) {
     // after a failed wait every work-group stops taking tasks
     if (tid == 0) s_task = load_agent(&st->abort) ? n_tasks : atomicAdd(queue, 1);
@@ -49,102 +185,37 @@ __global__ __launch_bounds__(256, 2) void k_cholesky(int32_t n_tasks, const int4
     if (t >= n_tasks) break;
     const int4 td = tasks[t];  // x: subdomain, y: column j, z: row b
     const SubDesc sd = subs[td.x];
-    const int j = td.y, b = td.z;
+    chol_tile<T, false>(td.x, td.y, td.z, tiles + (size_t)sd.tile0 * TT, flags + sd.tile0, st, As, Bs, s_fail);
+  }
+}
+
+// Subdomain schedule: one work-group factorises a whole subdomain, column by
+// column (tasks (j, j), (j, j+1), ..., (j, nb-1), then column j + 1); the
+// subdomains come from a queue ordered largest first. No flags and no waits:
+// for many subdomains of similar size (as many as the work-groups that fit
+// on the device, or more), every work-group stays busy on its own data.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_cholesky_subs(int32_t n_tasks, const int4* __restrict__ tasks,
+                                                       const SubDesc* __restrict__ subs, T* tiles, DevState* st,
+                                                       int32_t* queue) {
+  extern __shared__ unsigned char smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  T* Bs = As + TILE * LDA;
+  __shared__ int s_task;
+  __shared__ int s_fail;
+  constexpr size_t TT = (size_t)TILE * TILE;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= n_tasks) break;
+    const int i = tasks[t].x;
+    const SubDesc sd = subs[i];
     T* base = tiles + (size_t)sd.tile0 * TT;
-    int32_t* fl = flags + sd.tile0;
-    T* Cg = base + (size_t)(b * (b + 1) / 2 + j) * TT;
-    const int rb = b * (b + 1) / 2, rj = j * (j + 1) / 2;  // first tiles of block rows b and j
-
-    Quad<T> acc;
-#pragma unroll
-    for (int e = 0; e < 16; ++e)
-      acc.set(e, Cg[(R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane)]);
-
-    TileRegs<T> ga, gb;
-    if (j > 0) {
-      wait_flags(fl + rb, fl + rj, st);
-      ga.load_coherent(base + (size_t)rb * TT);
-      gb.load_coherent(base + (size_t)rj * TT);
-    }
-    for (int k = 0; k < j; ++k) {
-      ga.put(As);
-      gb.put(Bs);
-      // the barrier of the wait also makes the tiles just written visible to all waves
-      if (k + 1 < j) {
-        wait_flags(fl + rb + k + 1, fl + rj + k + 1, st);
-        ga.load_coherent(base + (size_t)(rb + k + 1) * TT);
-        gb.load_coherent(base + (size_t)(rj + k + 1) * TT);
-      } else {
-        __syncthreads();
-      }
-      acc.mma(As, Bs, R0, C0, lane, T(-1));
-      __syncthreads();
-    }
-
-    if (b == j) {
-      // S -> LDS, unblocked Cholesky of the lower triangle
-#pragma unroll
-      for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
-      if (tid == 0) s_fail = 0;
-      __syncthreads();
-      for (int kk = 0; kk < TILE; ++kk) {
-        if (tid == 0) {
-          T d = As[kk * LDA + kk];
-          if (!(d > T(0))) {
-            s_fail = 1;
-            d = T(1);
-          }
-          As[kk * LDA + kk] = sqrt(d);
-        }
-        __syncthreads();
-        if (tid > kk && tid < TILE) As[tid * LDA + kk] /= As[kk * LDA + kk];
-        __syncthreads();
-        // trailing update of the lower triangle: thread (ii, jj) pairs with jj <= ii
-        const int m = TILE - kk - 1;
-        for (int e = tid; e < m * m; e += blockDim.x) {
-          const int ii = kk + 1 + e / m, jj = kk + 1 + e % m;
-          if (jj <= ii) As[ii * LDA + jj] -= As[ii * LDA + kk] * As[jj * LDA + kk];
-        }
-        __syncthreads();
-      }
-      if (s_fail && tid == 0) atomicMin(&st->chol_fail, td.x);
-      // inverse of the lower-triangular L_jj, one column per thread
-      if (tid < TILE) {
-        const int c = tid;
-        for (int ii = 0; ii < TILE; ++ii) {
-          T v;
-          if (ii < c) {
-            v = T(0);
-          } else if (ii == c) {
-            v = T(1) / As[c * LDA + c];
-          } else {
-            T s = T(0);
-            for (int m2 = c; m2 < ii; ++m2) s += As[ii * LDA + m2] * Bs[m2 * LDA + c];
-            v = -s / As[ii * LDA + ii];
-          }
-          Bs[ii * LDA + c] = v;
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < TILE * TILE; e += blockDim.x) store_agent(Cg + e, Bs[(e / TILE) * LDA + (e % TILE)]);
-    } else {
-      // L_bj = S inv(L_jj)^T
-      wait_flag(fl + rj + j, st);
-      gb.load_coherent(base + (size_t)(rj + j) * TT);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) As[(R0 + Quad<T>::row(e, lane)) * LDA + C0 + Quad<T>::col(e, lane)] = acc.get(e);
-      gb.put(Bs);
-      __syncthreads();
-      acc.zero();
-      acc.mma(As, Bs, R0, C0, lane, T(1));
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-        store_agent(Cg + (R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane), acc.get(e));
-    }
-    wait_own_stores();
-    __syncthreads();
-    if (tid == 0) store_agent(fl + rb + j, 1);
-    __syncthreads();
+    for (int j = 0; j < sd.nb; ++j)
+      for (int b = j; b < sd.nb; ++b) chol_tile<T, true>(i, j, b, base, nullptr, st, As, Bs, s_fail);
   }
 }
 
@@ -195,22 +266,33 @@ hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* meta, const 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
+hipError_t launch_cholesky(int f32, int per_sub, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
                            int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
   if (f32) {
     const size_t sh = 2 * TILE * LDA * sizeof(float);
-    hipLaunchKernelGGL(k_cholesky<float>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (float*)tiles, flags,
-                       st, queue);
+    if (per_sub)
+      hipLaunchKernelGGL(k_cholesky_subs<float>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (float*)tiles, st,
+                         queue);
+    else
+      hipLaunchKernelGGL(k_cholesky<float>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (float*)tiles, flags,
+                         st, queue);
   } else {
     const size_t sh = 2 * TILE * LDA * sizeof(double);
-    // set once per process (a function-local static: initialised once even
+    // set once per process (function-local statics: initialised once even
     // when several host threads factorise at the same time)
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_cholesky<double>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    static const hipError_t attr_s = hipFuncSetAttribute((const void*)k_cholesky_subs<double>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k_cholesky<double>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (double*)tiles, flags,
-                       st, queue);
+    if (attr_s != hipSuccess) return attr_s;
+    if (per_sub)
+      hipLaunchKernelGGL(k_cholesky_subs<double>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (double*)tiles,
+                         st, queue);
+    else
+      hipLaunchKernelGGL(k_cholesky<double>, dim3(grid), dim3(256), sh, s, n_tasks, tasks, subs, (double*)tiles,
+                         flags, st, queue);
   }
   return hipGetLastError();
 }

@@ -88,6 +88,85 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_inv_lower(int32
   }
 }
 
+// ---------------------------------------------------------------- X = L^{-1}, column tasks
+// The same products in the same order as k_inv_lower, scheduled by block
+// column: task (i, j) computes column j of X_i top to bottom in one
+// work-group, X_jj = D_j, then for b = j+1 .. nb-1
+//   acc = sum_{k=j}^{b-1} L_bk X_kj,   X_bj = -D_b acc.
+// Every X_kj a task reads was written by the same work-group earlier in the
+// task (visible after the barrier that ends its row), so there are no flags,
+// no waits and no device-coherent loads; columns are independent and queued
+// longest first. The operands of the next product (and D_b) are loaded into
+// registers during the current MFMA work, across row boundaries.
+// Results are bitwise those of k_inv_lower.
+template <typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_inv_cols(int32_t n_tasks, const int4* __restrict__ tasks,
+                                                  const SubDesc* __restrict__ subs, const T* __restrict__ L, T* X,
+                                                  DevState* st, int32_t* queue) {
+  extern __shared__ unsigned char smem_raw[];
+  T* As = reinterpret_cast<T*>(smem_raw);
+  T* Bs = As + TILE * LDA;
+  __shared__ int s_task;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R0 = 32 * (wave >> 1), C0 = 32 * (wave & 1);
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= n_tasks) break;
+    const int4 td = tasks[t];  // x: subdomain, y: column j
+    const SubDesc sd = subs[td.x];
+    const int j = td.y, nb = sd.nb;
+    const T* Lb = L + (size_t)sd.tile0 * TT;
+    T* Xb = X + (size_t)sd.tile0 * TT;
+    const T* Dj = Lb + (size_t)(j * (j + 1) / 2 + j) * TT;
+    TileRegs<T> gl, gx;
+    gx.load(Dj);  // X_jj = D_j: the operand of every row's first product
+    gx.store(Xb + (size_t)(j * (j + 1) / 2 + j) * TT);
+    if (j + 1 >= nb) {
+      __syncthreads();
+      continue;
+    }
+    gl.load(Lb + (size_t)((j + 1) * (j + 2) / 2 + j) * TT);
+    for (int b = j + 1; b < nb; ++b) {
+      const size_t rb = (size_t)b * (b + 1) / 2;
+      Quad<T> acc;
+      acc.zero();
+      for (int k = j; k < b; ++k) {
+        gl.put(As);    // L_bk
+        gx.put_t(Bs);  // Bs[c][m] = X_kj[m][c]
+        __syncthreads();
+        // operands of the next product (b, k + 1); after the row's last one,
+        // D_b for the row end and the next row's first L tile (b + 1, j)
+        if (k + 1 < b) {
+          gl.load(Lb + (rb + k + 1) * TT);
+          gx.load(Xb + (size_t)((k + 1) * (k + 2) / 2 + j) * TT);
+        } else {
+          if (b + 1 < nb) gl.load(Lb + ((size_t)(b + 1) * (b + 2) / 2 + j) * TT);
+          gx.load(Lb + (rb + b) * TT);
+        }
+        acc.mma(As, Bs, R0, C0, lane, T(1));
+        __syncthreads();
+      }
+      // X_bj = -D_b acc: Bs[c][m] = acc[m][c], As = D_b
+#pragma unroll
+      for (int e = 0; e < 16; ++e) Bs[(C0 + Quad<T>::col(e, lane)) * LDA + R0 + Quad<T>::row(e, lane)] = acc.get(e);
+      gx.put(As);
+      __syncthreads();
+      if (b + 1 < nb) gx.load(Dj);  // the next row's first X operand
+      acc.zero();
+      acc.mma(As, Bs, R0, C0, lane, T(-1));
+      T* out = Xb + (rb + j) * TT;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[(R0 + Quad<T>::row(e, lane)) * TILE + C0 + Quad<T>::col(e, lane)] = acc.get(e);
+      // the row's tile is complete and visible to the whole work-group
+      // before a later row loads it (and before As/Bs are overwritten)
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- S = X^T X
 template <typename T>
 __global__ __launch_bounds__(256) void k_inv_gram(int32_t n_tiles, const int4* __restrict__ meta,
@@ -256,24 +335,33 @@ hipError_t big_lds(K kernel, size_t sh) {
 
 }  // namespace
 
-hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
+hipError_t launch_inverse(int f32, int cols, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
                           const SubDesc* subs, void* L, void* X, int32_t* flags, DevState* st, int32_t* queue,
                           int grid_lower, int grid_gram, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
   hipError_t e;
   if (f32) {
     const size_t sh = 2 * TILE * LDA * sizeof(float);
-    hipLaunchKernelGGL(k_inv_lower<float>, dim3(grid_lower), dim3(256), sh, s, n_tasks, tasks, subs,
-                       (const float*)L, (float*)X, flags, st, queue);
+    if (cols)
+      hipLaunchKernelGGL(k_inv_cols<float>, dim3(grid_lower), dim3(256), sh, s, n_tasks, tasks, subs, (const float*)L,
+                         (float*)X, st, queue);
+    else
+      hipLaunchKernelGGL(k_inv_lower<float>, dim3(grid_lower), dim3(256), sh, s, n_tasks, tasks, subs,
+                         (const float*)L, (float*)X, flags, st, queue);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_inv_gram<float>, dim3(grid_gram), dim3(256), sh, s, n_tiles, meta, subs, (const float*)X,
                        (float*)L);
   } else {
     const size_t sh = 2 * TILE * LDA * sizeof(double);
     if ((e = big_lds(k_inv_lower<double>, sh)) != hipSuccess) return e;
+    if ((e = big_lds(k_inv_cols<double>, sh)) != hipSuccess) return e;
     if ((e = big_lds(k_inv_gram<double>, sh)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_inv_lower<double>, dim3(grid_lower), dim3(256), sh, s, n_tasks, tasks, subs,
-                       (const double*)L, (double*)X, flags, st, queue);
+    if (cols)
+      hipLaunchKernelGGL(k_inv_cols<double>, dim3(grid_lower), dim3(256), sh, s, n_tasks, tasks, subs,
+                         (const double*)L, (double*)X, st, queue);
+    else
+      hipLaunchKernelGGL(k_inv_lower<double>, dim3(grid_lower), dim3(256), sh, s, n_tasks, tasks, subs,
+                         (const double*)L, (double*)X, flags, st, queue);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_inv_gram<double>, dim3(grid_gram), dim3(256), sh, s, n_tiles, meta, subs,
                        (const double*)X, (double*)L);

@@ -112,6 +112,10 @@ struct TileRegs {
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = load_agent(g + threadIdx.x + 256 * i);
   }
+  __device__ void store(T* g) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) g[threadIdx.x + 256 * i] = v[i];
+  }
   __device__ void store_coherent(T* g) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) store_agent(g + threadIdx.x + 256 * i, v[i]);

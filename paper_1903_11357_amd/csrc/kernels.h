@@ -102,12 +102,16 @@ hipError_t launch_reset_queues(DevState* st, hipStream_t s);
 hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* tile_meta, const SubDesc* subs,
                                const int32_t* row_ptr, const int32_t* col, const double* blocks,
                                void* tiles, int f32, hipStream_t s);
-hipError_t launch_cholesky(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
+// per_sub = 0: tasks (subdomain, j, b, -) of every tile, dependency-ordered;
+// per_sub = 1: tasks (subdomain, -, -, -), one work-group per subdomain.
+hipError_t launch_cholesky(int f32, int per_sub, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
                            int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
 
 // Explicit local inverses (kern_inv.hip) and their packed symmetric apply
 // (kern_symv.hip).
-hipError_t launch_inverse(int f32, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
+// cols = 0: tasks (subdomain, j, b, -) of every tile of X = L^{-1}, dependency-
+// ordered; cols = 1: tasks (subdomain, j, -, -), one block column each.
+hipError_t launch_inverse(int f32, int cols, int32_t n_tasks, const int4* tasks, int32_t n_tiles, const int4* meta,
                           const SubDesc* subs, void* L, void* X, int32_t* flags, DevState* st, int32_t* queue,
                           int grid_lower, int grid_gram, hipStream_t s);
 // Phase 1 of the packed symmetric apply: per stored tile (b, j), the row

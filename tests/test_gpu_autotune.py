@@ -39,11 +39,13 @@ def test_autotune_keeps_results_bitwise(precision, inverse):
     if inverse:
         assert rep["inv_wg_per_cu"] in ((1, 2, 3, 4) if precision == "fp32" else (1, 2))
         assert rep["symv_waves"] in (1, 2, 4, 8)
-        # Cholesky shapes 2, task orders 1 (4 subdomains: no grouping below that), inverse formation, packed apply 4
-        assert rep["candidates"] == 2 + 1 + (4 if precision == "fp32" else 2) + 4
+        # schedules 2, Cholesky shapes 2, task orders 1 (4 subdomains: no grouping below that), inverse
+        # formation, packed apply 4
+        assert rep["candidates"] == 2 + 2 + 1 + (4 if precision == "fp32" else 2) + 4
     else:
         assert rep["trsv_wg_per_cu"] in (1, 2, 3, 4)
-        assert rep["candidates"] == 2 + 1 + 4
+        assert rep["candidates"] == 2 + 2 + 1 + 4
+    assert rep["factor_schedule"] in (1, 2)
     assert rep["task_chunk"] == 0
     pr.setup_coarse()
     x1, st1 = pr.solve(rtol=1e-8)
@@ -109,3 +111,47 @@ def test_autotune_cache_reuse_same_size_class(tmp_path):
     assert asdg.tune_cache_load(str(path)) >= 1
     text = path.read_text()
     assert "|fp32|inverse|" in text
+
+
+def _tiles(pr, sub, word):
+    """Raw factor tiles of subdomain `sub` (packed lower, row-major 64x64)."""
+    import ctypes
+
+    from paper_1903_11357_amd import asdg
+
+    nb = (int(pr._sub_sizes()[sub]) + 63) // 64
+    buf = np.empty(nb * (nb + 1) // 2 * 64 * 64, dtype=np.float32 if word == 4 else np.float64)
+    st = asdg.lib().asdg_export_factor_tiles(pr.h, sub, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes)
+    assert st == asdg.OK
+    return buf
+
+
+@pytest.mark.parametrize("case", ["4x1800", "128x200"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("inverse", [True, False], ids=["inverse", "sweeps"])
+def test_factor_schedules_bitwise_equal(case, precision, inverse):
+    """The tile-task schedule and the subdomain/column schedule of the
+    factorisation (ASDG_TUNE_FACTOR_SCHEDULE 1 and 2) run the same products in
+    the same order: bitwise equal factors (or inverses) and solves."""
+    from paper_1903_11357_amd import asdg
+
+    P = _problem() if case == "4x1800" else I.voronoi_problem(4096, 31, p=2, bx=16, by=8, q=1, nonnested_coarse=16,
+                                                                 log10_rho_range=4.0, f=I.f_one)
+    prec = asdg.FP32_LOCAL if precision == "fp32" else asdg.FP64
+    word = 4 if precision == "fp32" else 8
+    out = []
+    for sched in (1, 2):
+        print(f"[schedule] {case} {precision} inverse={inverse} schedule={sched}", flush=True)
+        pr = asdg.setup_problem(P, prec, device="cuda:0", local_inverse=inverse, factor=False)
+        pr.set_tuning(asdg.TUNE_FACTOR_SCHEDULE, sched)
+        pr.factor()
+        pr.setup_coarse()
+        subs = sorted({0, P.n_sub // 2, P.n_sub - 1})
+        tiles = [_tiles(pr, i, word) for i in subs]
+        x, st = pr.solve(rtol=1e-8)
+        out.append((tiles, x.cpu().numpy(), st["iterations"]))
+        del pr
+    (t1, x1, k1), (t2, x2, k2) = out
+    for a, b in zip(t1, t2):
+        assert np.array_equal(a, b)
+    assert k1 == k2 and np.array_equal(x1, x2)
