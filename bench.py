@@ -237,13 +237,13 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
     return res
 
 
-def cpu_baseline(P, n_iter):
-    """The FP64 oracle (NumPy/SciPy) timed on the host: setup untimed, then
-    n_iter PCG iterations of the same workload, as DoF-iterations/s. Timed
-    with BLAS limited to one thread, the threads it actually uses (its
-    sparse products and per-subdomain triangular solves run on one core; one
-    iteration with all BLAS threads is reported beside it and is no faster)."""
+def _cpu_baseline_child(workload, n_iter, conn):
+    """Process of the CPU baseline: builds the oracle for the workload
+    (untimed), reports ready, waits for the go (sent once the GPU work is
+    done, so the timing does not compete with it), then times the oracle's
+    PCG and sends the result."""
     from oracle import OracleSolver
+    from paper_1903_11357_amd import inputs
 
     try:
         from threadpoolctl import threadpool_info, threadpool_limits
@@ -256,7 +256,10 @@ def cpu_baseline(P, n_iter):
         def threadpool_info():
             return []
 
-    orc = OracleSolver(P)
+    t0 = time.perf_counter()
+    orc = OracleSolver(inputs.make_config(workload))
+    conn.send(("ready", time.perf_counter() - t0))
+    conn.recv()
     A, M = orc.A, orc.M
     with threadpool_limits(1):
         t = time.perf_counter()
@@ -267,11 +270,39 @@ def cpu_baseline(P, n_iter):
     orc.solve(fixed_iters=1)
     dt1 = time.perf_counter() - t1
     sfb = sparse_factor_bound(A, M)
-    return {"value": A.shape[0] * n_iter / dt, "unit": "DoF-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_iter} PCG iterations of the full workload (oracle setup untimed), {dt:.1f} s, BLAS "
-                      f"limited to 1 thread ({os.cpu_count()} host CPUs visible)",
-            "all_blas_threads": {"value": A.shape[0] / dt1, "threads": int(blas_threads),
-                                 "sample": f"1 PCG iteration, {dt1:.2f} s"}}, sfb
+    conn.send(({"value": A.shape[0] * n_iter / dt, "unit": "DoF-iters/s", "cores": 1, "kind": "oracle",
+                "sample": f"{n_iter} PCG iterations of the full workload (oracle setup untimed, built in a "
+                          f"process of its own beside the GPU work), {dt:.1f} s, BLAS limited to 1 thread "
+                          f"({os.cpu_count()} host CPUs visible)",
+                "all_blas_threads": {"value": A.shape[0] / dt1, "threads": int(blas_threads),
+                                     "sample": f"1 PCG iteration, {dt1:.2f} s"}}, sfb))
+
+
+def start_cpu_baseline(workload, n_iter):
+    """The FP64 oracle (NumPy/SciPy) timed on the host, in a process of its
+    own: its setup runs beside the GPU work; finish_cpu_baseline() starts the
+    timed part (n_iter PCG iterations, BLAS limited to one thread, the
+    threads it actually uses: its sparse products and per-subdomain
+    triangular solves run on one core; one iteration with all BLAS threads is
+    reported beside it and is no faster)."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("spawn")
+    parent, child = ctx.Pipe()
+    proc = ctx.Process(target=_cpu_baseline_child, args=(workload, n_iter, child), daemon=True)
+    proc.start()
+    return proc, parent
+
+
+def finish_cpu_baseline(handle):
+    proc, conn = handle
+    msg, setup_s = conn.recv()
+    assert msg == "ready"
+    conn.send("go")
+    res, sfb = conn.recv()
+    proc.join(timeout=60)
+    res["oracle_setup_s"] = setup_s
+    return res, sfb
 
 
 def sparse_factor_bound(A, M, sample=32, seed=0):
@@ -299,55 +330,75 @@ def sparse_factor_bound(A, M, sample=32, seed=0):
             "ordering": "SuperLU MMD_AT_PLUS_A, symmetric mode"}
 
 
-def serving_bench(n_requests, seed=5, workers=16, local_inverse=False, loads=(0.8,)):
-    """Continuous batching (C5 shape): requests with log-uniform 4096..65536
-    Voronoi cells, p in {1,2,3}, ~64 cells per subdomain, rho = 10^U[-2,2]
-    per subdomain, random sine-series RHS, nested coarse q=1, FP32-local.
-    First all requests at once (capacity), then Poisson streams at the given
-    fractions of that capacity; latency = arrival to completion. The top
-    level reports the first load, `sweep` all of them."""
+def start_serving_inputs(n_meshes, seed=5, workers=12):
+    """Starts generating the serving workload's mesh pool in worker
+    processes (the requests' input data, not part of the served work)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
 
-    import numpy as np
+    from paper_1903_11357_amd import inputs
 
+    specs = inputs.serving_mesh_specs(n_meshes, seed=seed)
+    ex = ProcessPoolExecutor(max_workers=max(1, min(workers, os.cpu_count() or 1)),
+                             mp_context=mp.get_context("spawn"))
+    # largest meshes first: the pool finishes sooner
+    futs = {sp["mesh_id"]: ex.submit(inputs.serving_mesh, sp)
+            for sp in sorted(specs, key=lambda d: -d["n_cells"])}
+    return ex, futs, time.perf_counter()
+
+
+def serving_bench(n_requests, gen, seed=5, local_inverse=False, loads=(0.8,), capacity_requests=400,
+                  max_active=4):
+    """Continuous batching (C5): requests with log-uniform 4096..65536-cell
+    Voronoi meshes (a pool of relaxed Voronoi meshes, one per stratum of
+    log n, each request picking one uniformly), p uniform in {1,2,3}, about
+    64 cells per subdomain, rho = 10^U[-2,2] per subdomain and a random
+    sine-series load from the request's own seed, nested coarse q=1,
+    FP32-local. First a burst of `capacity_requests` requests at once
+    (capacity), then all n_requests as Poisson streams at the given fractions
+    of that capacity; latency = arrival to completion. The top level reports
+    the first load, `sweep` all of them."""
     from paper_1903_11357_amd import asdg, inputs
     from paper_1903_11357_amd.serve import Request, Server, latency_stats
 
-    descs = inputs.serving_requests(n_requests, seed=seed)
-    t = time.perf_counter()
-    problems = []
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        for P in ex.map(inputs.serving_problem, descs, chunksize=4):
-            problems.append(P)
-            if len(problems) % 256 == 0:
-                print(f"[bench] serving: {len(problems)} of {n_requests} requests generated", file=sys.stderr,
-                      flush=True)
-    t_gen = time.perf_counter() - t
-    print(f"[bench] serving: {n_requests} requests generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
-    srv = Server(precision=asdg.FP32_LOCAL, max_active=16, check_every=16, setup_workers=8,
+    import numpy as np
+
+    ex, futs, t_start = gen
+    pool = {k: f.result() for k, f in futs.items()}
+    ex.shutdown(wait=True)
+    t_gen = time.perf_counter() - t_start
+    descs = inputs.serving_pool_requests(n_requests, len(pool), seed=seed + 1)
+    problems = [inputs.serving_pool_problem(d, pool) for d in descs]
+    print(f"[bench] serving: {len(pool)} pool meshes ready {t_gen:.1f} s after the start; {n_requests} requests",
+          file=sys.stderr, flush=True)
+    srv = Server(precision=asdg.FP32_LOCAL, max_active=max_active, check_every=16, setup_workers=8,
                  local_inverse=local_inverse)
-    burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems)])
+    ncap = min(capacity_requests, n_requests)
+    burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems[:ncap])])
     cap = latency_stats(burst)
-    print(f"[bench] serving: capacity {cap['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    print(f"[bench] serving: capacity {cap['solves_per_s']:.2f} solves/s ({ncap} requests at once)",
+          file=sys.stderr, flush=True)
     sweep = []
     for k, load in enumerate(loads):
         rate = load * cap["solves_per_s"]
-        rng = np.random.default_rng(seed + 1 + k)
+        rng = np.random.default_rng(seed + 10 + k)
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+        t0 = time.perf_counter()
         st = latency_stats(srv.run([Request(i, P, float(a)) for i, (P, a) in enumerate(zip(problems, arrivals))]))
-        st.update({"load": load, "arrival_rate_per_s": rate})
+        st.update({"load": load, "arrival_rate_per_s": rate, "wall_s": time.perf_counter() - t0})
         sweep.append(st)
         print(f"[bench] serving: load {load}: p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms",
               file=sys.stderr, flush=True)
     st = sweep[0]
     dofs = [P.n_dofs for P in problems]
-    return {"requests": n_requests, "dofs_min": int(min(dofs)), "dofs_max": int(max(dofs)),
-            "capacity_solves_per_s": cap["solves_per_s"], "arrival_rate_per_s": st["arrival_rate_per_s"],
+    return {"requests": n_requests, "mesh_pool": len(pool), "dofs_min": int(min(dofs)), "dofs_max": int(max(dofs)),
+            "capacity_solves_per_s": cap["solves_per_s"], "capacity_requests": ncap,
+            "arrival_rate_per_s": st["arrival_rate_per_s"],
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
             "solves_per_s": st["solves_per_s"], "iterations_mean": st["iterations_mean"],
             "all_converged": all(x["all_converged"] for x in sweep) and cap["all_converged"],
-            "peak_active": srv.peak_active, "input_generation_s": t_gen, "precision": "fp32-local",
+            "peak_active": srv.peak_active, "max_active": max_active, "input_generation_s": t_gen,
+            "precision": "fp32-local",
             "local_solves": "explicit inverses" if local_inverse else "triangular sweeps",
             "capacity_run": cap, "sweep": sweep}
 
@@ -369,8 +420,15 @@ def main():
                     help="keep the default launch shapes (no asdg_autotune after the factorisation)")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap PCG iterations (profiling runs; 0 = the workload's own limit)")
-    ap.add_argument("--serving-requests", type=int, default=64,
+    ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the continuous-batching run (0 = skip)")
+    ap.add_argument("--serving-meshes", type=int, default=128,
+                    help="meshes in the serving workload's mesh pool (log-uniform strata of 4096..65536 cells)")
+    ap.add_argument("--serving-capacity-requests", type=int, default=400,
+                    help="requests of the burst run that measures the serving capacity")
+    ap.add_argument("--serving-max-active", type=int, default=int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4),
+                    help="requests on the GPU at once, each with its own stream (default: the HIP runtime's "
+                         "hardware queues, GPU_MAX_HW_QUEUES, 4 unless set)")
     ap.add_argument("--only-serving", action="store_true")
     ap.add_argument("--serving-local", default="sweeps", choices=("sweeps", "inverse"),
                     help="local solvers of the served requests (short solves: setup dominates)")
@@ -384,6 +442,11 @@ def main():
               f"note, not built", file=sys.stderr)
         sys.exit(2)
 
+    # host-side inputs and the CPU baseline's oracle setup start first, in
+    # processes of their own, and run beside the GPU work
+    gen = start_serving_inputs(a.serving_meshes) if a.serving_requests > 0 else None
+    baseline = start_cpu_baseline(a.workload, a.cpu_iters) if not (a.no_cpu_baseline or a.only_serving) else None
+
     import torch
 
     from paper_1903_11357_amd import asdg, inputs
@@ -396,10 +459,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    serve_kw = dict(local_inverse=a.serving_local == "inverse", loads=tuple(float(v) for v in a.serving_loads.split(",")),
+                    capacity_requests=a.serving_capacity_requests, max_active=a.serving_max_active)
     if a.only_serving:
-        print(json.dumps({"serving": serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse",
-                                        loads=tuple(float(v) for v in a.serving_loads.split(",")))}),
-              flush=True)
+        print(json.dumps({"serving": serving_bench(a.serving_requests, gen, **serve_kw)}), flush=True)
         return
     P = inputs.make_config(a.workload)
     if a.max_iter:
@@ -454,11 +517,10 @@ def main():
         out["fp32_local_speedup_per_solve"] = f64["ms_per_step"] / f32["ms_per_step"]
     if a.serving_requests > 0:
         print("[bench] serving", file=sys.stderr, flush=True)
-        out["serving"] = serving_bench(a.serving_requests, local_inverse=a.serving_local == "inverse",
-                                        loads=tuple(float(v) for v in a.serving_loads.split(",")))
-    if not a.no_cpu_baseline:
+        out["serving"] = serving_bench(a.serving_requests, gen, **serve_kw)
+    if baseline is not None:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"], out["sparse_factor_bound"] = cpu_baseline(P, a.cpu_iters)
+        out["cpu_baseline"], out["sparse_factor_bound"] = finish_cpu_baseline(baseline)
     print(json.dumps(out), flush=True)
 
 

@@ -519,6 +519,50 @@ def serving_requests(n_requests: int = 2000, seed: int = 5, n_min: int = 4096,
     return reqs
 
 
+def serving_mesh_specs(n_meshes: int = 128, seed: int = 5, n_min: int = 4096, n_max: int = 65536):
+    """Meshes of the serving workload's mesh pool: one per stratum of
+    log(n_cells) (n_meshes equal strata of [log n_min, log n_max], a
+    log-uniform draw inside each), each with its own seed. Requests that pick
+    a mesh of the pool uniformly have log-uniform mesh sizes."""
+    rng = np.random.default_rng(seed)
+    edges = np.linspace(math.log(n_min), math.log(n_max), n_meshes + 1)
+    return [{"mesh_id": k, "n_cells": int(round(math.exp(rng.uniform(edges[k], edges[k + 1])))),
+             "seed": int(rng.integers(1 << 31))} for k in range(n_meshes)]
+
+
+def serving_mesh(spec: dict):
+    """(mesh, subdomain labels) of one pool mesh: relaxed Voronoi of
+    spec['n_cells'] seeds, subdomains = bins of about 64 cells."""
+    rng = np.random.default_rng(spec["seed"])
+    n = spec["n_cells"]
+    mesh = relaxed_voronoi_mesh(rng.random((n, 2)))
+    b = max(1, int(round(math.sqrt(n) / 8)))
+    return mesh, compact_labels(bins_partition(mesh.vertex_mean(), b, b))
+
+
+def serving_pool_requests(n_requests: int, n_meshes: int, seed: int = 6):
+    """Request descriptors over a mesh pool: mesh uniform over the pool, p
+    uniform in {1, 2, 3}, and a seed for the request's own coefficients and
+    right-hand side."""
+    rng = np.random.default_rng(seed)
+    return [{"id": k, "mesh_id": int(rng.integers(n_meshes)), "p": int(rng.integers(1, 4)),
+             "seed": int(rng.integers(1 << 31))} for k in range(n_requests)]
+
+
+def serving_pool_problem(req: dict, pool) -> Problem:
+    """The request's problem on its pool mesh: rho = 10^U[-2,2] per
+    subdomain and a random sine-series load, both from the request's seed;
+    nested coarse space = the subdomains, q = 1."""
+    mesh, sub = pool[req["mesh_id"]]
+    rng = np.random.default_rng(req["seed"])
+    n_sub = int(sub.max()) + 1
+    rho = (10.0 ** rng.uniform(-2.0, 2.0, size=n_sub))[sub]
+    coef = rng.standard_normal((4, 4))
+    return Problem(name=f"req{req['id']}", mesh=mesh, p=req["p"], c_sigma=10.0, rho=rho,
+                   subdomain=sub, q=1, coarse_of_cell=sub.copy(), coarse_mesh=None,
+                   f=make_f_series(coef))
+
+
 def serving_problem(req: dict) -> Problem:
     rng = np.random.default_rng(req["seed"])
     n = req["n_cells"]

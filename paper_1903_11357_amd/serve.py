@@ -85,7 +85,7 @@ def _device_setup(pr, device):
 
 class Server:
     def __init__(self, device="cuda:0", precision=asdg.FP32_LOCAL, hbm_budget: Optional[int] = None,
-                 max_active: int = 16, check_every: int = 16, setup_workers: int = 4,
+                 max_active: Optional[int] = None, check_every: int = 16, setup_workers: int = 4,
                  keep_solutions: bool = False, rtol: float = 1e-8, max_iter: int = 20000,
                  local_inverse: bool = False, host_threads: Optional[int] = None):
         import torch
@@ -96,6 +96,11 @@ class Server:
             free, total = torch.cuda.mem_get_info(self.device)
             hbm_budget = int(0.5 * free)
         self.hbm_budget = hbm_budget
+        # requests on the device at once: by default one per hardware queue
+        # the HIP runtime gives the process (GPU_MAX_HW_QUEUES, 4 unless set);
+        # more streams than queues only time-slice the queues
+        if max_active is None:
+            max_active = int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4)
         self.max_active = max_active
         self.check_every = check_every
         self.setup_workers = setup_workers
