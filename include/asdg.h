@@ -294,9 +294,10 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * of the explicit inverses. SYMV_WAVES: tiles (waves) per work-group of
  * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL; default 1 in
  * FP32-local mode, 4 in FP64 mode). TASK_CHUNK:
- * queue order of the factorisation and inverse-formation tasks, 0 = all
- * subdomains interleaved (longest remaining path first), c > 0 = groups of
- * c consecutive subdomains one after the other (a smaller working set);
+ * queue order of the factorisation and inverse-formation tasks (tile tasks,
+ * and the block-column tasks of schedule 2), 0 = all subdomains interleaved
+ * (longest remaining path first), c > 0 = groups of c consecutive
+ * subdomains one after the other (a smaller working set);
  * after asdg_bind it takes effect at the next asdg_factor. HOST_THREADS:
  * at most this many host threads for asdg_assemble / asdg_assemble_tet /
  * asdg_plan on this handle (0 = hardware threads, at most 16), for callers

@@ -377,6 +377,24 @@ static std::vector<int4> order_tasks(const std::vector<SubDesc>& subs, std::vect
   return out;
 }
 
+// Block-column tasks (i, j) of X = L^{-1} (schedule 2), largest work first
+// (the column's tile products, about (nb - j)^2 / 2; ties by subdomain,
+// column). chunk > 0: subdomains in groups of chunk consecutive ones, group
+// by group, so the columns running together share their subdomain's L tiles
+// in the caches.
+static std::vector<int4> order_col_tasks(const std::vector<SubDesc>& subs, int chunk) {
+  struct C { int32_t g; int64_t w; int32_t i, j; };
+  std::vector<C> cs;
+  for (int32_t i = 0; i < (int32_t)subs.size(); ++i) {
+    const int64_t nb = subs[i].nb;
+    for (int j = 0; j < nb; ++j) cs.push_back({chunk > 0 ? i / chunk : 0, (nb - j) * (nb - j + 1) / 2, i, j});
+  }
+  std::stable_sort(cs.begin(), cs.end(), [](const C& a, const C& b) { return a.g != b.g ? a.g < b.g : a.w > b.w; });
+  std::vector<int4> out(cs.size());
+  for (size_t k = 0; k < cs.size(); ++k) out[k] = make_int4(cs[k].i, cs[k].j, 0, 0);
+  return out;
+}
+
 void plan_local(asdg_problem* pb) {
   const Assembled& A = pb->A;
   const int np = A.np;
@@ -422,23 +440,15 @@ void plan_local(asdg_problem* pb) {
   // subdomain, column, row); every dependency has a strictly longer path, so
   // it precedes its consumers in the queue
   pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, pb->task_chunk);
-  // schedule 2: whole subdomains (Cholesky) and block columns (X = L^{-1}),
-  // largest work first (ties by index)
+  // schedule 2: whole subdomains (Cholesky), largest first (ties by index),
+  // and block columns (X = L^{-1})
   {
     std::vector<int32_t> ord(ns);
     for (int32_t i = 0; i < ns; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return pb->subs[a].nb > pb->subs[b].nb; });
     pb->sub_tasks.resize(ns);
     for (int32_t k = 0; k < ns; ++k) pb->sub_tasks[k] = make_int4(ord[k], 0, 0, 0);
-    struct C { int64_t w; int32_t i, j; };
-    std::vector<C> cs;
-    for (int32_t i = 0; i < ns; ++i) {
-      const int64_t nb = pb->subs[i].nb;
-      for (int j = 0; j < nb; ++j) cs.push_back({(nb - j) * (nb - j + 1) / 2, i, j});
-    }
-    std::stable_sort(cs.begin(), cs.end(), [](const C& a, const C& b) { return a.w > b.w; });
-    pb->col_tasks.resize(cs.size());
-    for (size_t k = 0; k < cs.size(); ++k) pb->col_tasks[k] = make_int4(cs[k].i, cs[k].j, 0, 0);
+    pb->col_tasks = order_col_tasks(pb->subs, pb->task_chunk);
   }
   struct K { int64_t key; int4 t; };
   std::vector<K> ks;
@@ -1122,9 +1132,12 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
     // reordered task lists (same size); the status read below completes the copies
     HIPCHK(pb, hipMemcpyAsync(pb->buf[1] + pb->o1.chol, pb->chol_tasks.data(), sizeof(int4) * pb->chol_tasks.size(),
                               hipMemcpyHostToDevice, s));
-    if (pb->inv_planned)
+    if (pb->inv_planned) {
       HIPCHK(pb, hipMemcpyAsync(pb->buf[1] + pb->o1.inv, pb->inv_tasks.data(), sizeof(int4) * pb->inv_tasks.size(),
                                 hipMemcpyHostToDevice, s));
+      HIPCHK(pb, hipMemcpyAsync(pb->buf[1] + pb->o1.colt, pb->col_tasks.data(), sizeof(int4) * pb->col_tasks.size(),
+                                hipMemcpyHostToDevice, s));
+    }
     pb->tasks_dirty = false;
   }
   HIPCHK(pb, launch_gather_tiles(pb->A.np, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
@@ -1475,6 +1488,7 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
     if (pb->stage >= 2 && !pb->small) {
       pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, value);
       if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, value);
+      pb->col_tasks = order_col_tasks(pb->subs, value);
       if (pb->stage >= 3) pb->tasks_dirty = true;  // uploaded by the next asdg_factor
     }
   }
@@ -1550,6 +1564,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
           pb->task_chunk = C.task_chunk;
           pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, C.task_chunk);
           if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, C.task_chunk);
+          pb->col_tasks = order_col_tasks(pb->subs, C.task_chunk);
           pb->tasks_dirty = true;
         }
         asdg_status e = asdg_factor(pb, stream);
@@ -1626,16 +1641,18 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
       auto reorder = [&](float& ms1) -> asdg_status {
         pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, chunk);
         if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, chunk);
+        pb->col_tasks = order_col_tasks(pb->subs, chunk);
         pb->tasks_dirty = true;
         return time_factor(ms1);
       };
       std::vector<int> cand{0};
-      if (pb->A.n_sub > 64 && pb->factor_sched == 1) cand.push_back(64);  // (the tile-task order only)
+      if (pb->A.n_sub > 64) cand.push_back(64);
       e = tune(&chunk, cand, reorder, ms);
       if (e != ASDG_OK) return e;
       pb->task_chunk = chunk;
       pb->chol_tasks = order_tasks(pb->subs, cholesky_levels, chunk);
       if (pb->inv_planned) pb->inv_tasks = order_tasks(pb->subs, inverse_levels, chunk);
+      pb->col_tasks = order_col_tasks(pb->subs, chunk);
       pb->tasks_dirty = true;
     }
     if (pb->inv_planned) {

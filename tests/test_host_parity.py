@@ -218,16 +218,24 @@ def test_tune_cache_file_roundtrip_and_malformed(tmp_path):
     """The tuning cache text format: a written file loads back; a malformed
     line rejects the whole file (no device needed)."""
     good = tmp_path / "tune.txt"
-    good.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 38.5 0.43\n"
+    # the factorisation schedule (last field) may be absent: then automatic
+    good.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 38.5 0.43 2\n"
                     "gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 101.5 0.91\n")
     assert asdg.tune_cache_load(str(good)) == 2
     out = tmp_path / "saved.txt"
     asdg.tune_cache_save(str(out))
     lines = out.read_text().splitlines()
-    assert any(l.startswith("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 ") for l in lines)
+    assert any(l.startswith("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 ") and l.endswith(" 2")
+               for l in lines)
+    assert any(l.startswith("gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 ") and l.endswith(" 0")
+               for l in lines)
     bad = tmp_path / "bad.txt"
     bad.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 3 0 38.5 0.43\n")  # 3 waves: invalid
     with pytest.raises(asdg.AsdgError):
         asdg.tune_cache_load(str(bad))
     with pytest.raises(asdg.AsdgError):
         asdg.tune_cache_load(str(tmp_path / "missing.txt"))
+    bad2 = tmp_path / "bad2.txt"
+    bad2.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 8 0 38.5 0.43 5\n")  # schedule 5: invalid
+    with pytest.raises(asdg.AsdgError):
+        asdg.tune_cache_load(str(bad2))
