@@ -442,10 +442,11 @@ def main():
               f"note, not built", file=sys.stderr)
         sys.exit(2)
 
-    # host-side inputs and the CPU baseline's oracle setup start first, in
-    # processes of their own, and run beside the GPU work
-    gen = start_serving_inputs(a.serving_meshes) if a.serving_requests > 0 else None
-    baseline = start_cpu_baseline(a.workload, a.cpu_iters) if not (a.no_cpu_baseline or a.only_serving) else None
+    # host-side inputs (the serving mesh pool) and the CPU baseline's oracle
+    # setup run in processes of their own, started after the timed solves so
+    # that nothing competes with them for the host
+    gen = start_serving_inputs(a.serving_meshes) if a.serving_requests > 0 and a.only_serving else None
+    baseline = None
 
     import torch
 
@@ -477,6 +478,10 @@ def main():
             modes[key] = run_mode(P, prec, a.steps, a.warmup, a.check_every, inverse=(loc == "inverse"),
                                   autotune=not a.no_autotune, ref=ref)
             print(f"[bench] {key}: {json.dumps(modes[key])}", file=sys.stderr, flush=True)
+    if a.serving_requests > 0:
+        gen = start_serving_inputs(a.serving_meshes)
+    if not a.no_cpu_baseline:
+        baseline = start_cpu_baseline(a.workload, a.cpu_iters)
     first = a.local.split(",")[0]
     hk = lambda m: m if first == "inverse" else f"{m}-sweeps"  # noqa: E731
     head = modes.get(hk("fp32")) or modes.get(hk("fp64"))

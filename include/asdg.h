@@ -312,7 +312,7 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * 2 = one work-group per subdomain for the Cholesky factorisation and per
  * block column for X = L^{-1} (no waits; for many subdomains of similar
  * size); 0 = automatic (2 when the largest subdomain's factorisation is at
- * most 1.5 times an even share of the whole over the device's work-groups).
+ * most twice an even share of the whole over the device's work-groups).
  * No launch shape or schedule changes the arithmetic: results are
  * identical for every setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,

@@ -35,6 +35,7 @@ class PCGInfo:
     alphas: list
     betas: list
     history: list
+    history_after: list = dataclasses.field(default_factory=list)  # residuals past the stop (extra)
 
     def lanczos(self):
         k = len(self.alphas)
@@ -53,9 +54,12 @@ class PCGInfo:
         return hi / lo
 
 
-def pcg(A, b, apply_Minv, rtol=1e-8, max_iter=10000, fixed_iters=None):
+def pcg(A, b, apply_Minv, rtol=1e-8, max_iter=10000, fixed_iters=None, extra=0):
     """Returns (x, PCGInfo). With ``fixed_iters`` the loop runs exactly that
-    many iterations regardless of the tolerance."""
+    many iterations regardless of the tolerance. With ``extra`` > 0 the same
+    iteration continues that many steps past the stop and only their
+    residual norms are kept (PCGInfo.history_after); x, the coefficients and
+    the statistics are those of the stop."""
     n = b.shape[0]
     x = np.zeros(n)
     r = b.copy()
@@ -67,26 +71,39 @@ def pcg(A, b, apply_Minv, rtol=1e-8, max_iter=10000, fixed_iters=None):
     it = 0
     converged = False
     limit = fixed_iters if fixed_iters is not None else max_iter
-    for k in range(limit):
+    after = []
+    stopped = None  # (iterate, iteration count) at the stop while extra steps run
+    k = 0
+    while limit > 0:
         q = A @ p
         pq = float(p @ q)
         alpha = rz / pq
         x += alpha * p
         r -= alpha * q
-        alphas.append(alpha)
         res = float(np.linalg.norm(r))
-        hist.append(res / bnorm)
-        it = k + 1
-        if fixed_iters is None and res <= rtol * bnorm:
-            converged = True
-            break
-        if it == limit:
-            break
+        k += 1
+        if stopped is None:
+            alphas.append(alpha)
+            hist.append(res / bnorm)
+            it = k
+            if fixed_iters is None and res <= rtol * bnorm:
+                converged = True
+            if converged or it == limit:
+                if extra <= 0:
+                    break
+                stopped = (x.copy(), it)
+        else:
+            after.append(res / bnorm)
+            if len(after) == extra:
+                break
         z = apply_Minv(r)
         rz_new = float(r @ z)
         beta = rz_new / rz
-        betas.append(beta)
+        if stopped is None:
+            betas.append(beta)
         p = z + beta * p
         rz = rz_new
+    if stopped is not None:
+        x = stopped[0]
     true_res = float(np.linalg.norm(b - A @ x)) / bnorm
-    return x, PCGInfo(it, converged, hist[-1] if hist else 0.0, true_res, alphas, betas, hist)
+    return x, PCGInfo(it, converged, hist[-1] if hist else 0.0, true_res, alphas, betas, hist, after)

@@ -13,6 +13,9 @@ arithmetic): SIPG assembly (Sec. 2), the two-level Schwarz preconditioner
   rel_res       recursive residual ||r_k|| / ||b|| at the stop
   true_rel_res  ||b - A x_k|| / ||b|| at the stop
   history       recursive residual after every iteration
+  history_after recursive residual of 60 further iterations past the stop
+                (the same iteration continued; for comparing with a solve
+                that stops later)
   alphas, betas CG coefficients (Lanczos condition estimate)
   lambda_min, lambda_max  Lanczos extreme eigenvalue estimates
 
@@ -37,6 +40,7 @@ if ROOT not in sys.path:
 
 
 KEEP_X = {"C4"}
+EXTRA = 60
 
 
 def main(name: str) -> None:
@@ -58,14 +62,15 @@ def main(name: str) -> None:
             print(f"[{name}] iteration {calls[0]}  {time.time() - t1:.0f} s", flush=True)
         return orc.M.apply(r)
 
-    x, info = pcg(orc.A, orc.b, precond, rtol=P.rtol, max_iter=P.max_iter)
+    x, info = pcg(orc.A, orc.b, precond, rtol=P.rtol, max_iter=P.max_iter, extra=EXTRA)
     t_pcg = time.time() - t1
     lo, hi = info.lanczos()
     out = os.path.join(HERE, f"{name}_oracle_fp64.npz")
     keep_x = {"x": x} if name in KEEP_X else {}
     np.savez_compressed(out, **keep_x, iterations=info.iterations, converged=info.converged,
                         rel_res=info.rel_res, true_rel_res=info.true_rel_res,
-                        history=np.asarray(info.history), alphas=np.asarray(info.alphas),
+                        history=np.asarray(info.history), history_after=np.asarray(info.history_after),
+                        alphas=np.asarray(info.alphas),
                         betas=np.asarray(info.betas), lambda_min=lo, lambda_max=hi,
                         n=P.n_dofs)
     with open(os.path.join(HERE, f"{name}_oracle_fp64.txt"), "w") as fh:

@@ -150,14 +150,16 @@ def test_pcg_fp64_matches_oracle(name):
     assert st["t_assemble_ms"] > 0.0 and st["t_factor_ms"] > 0.0 and st["t_coarse_ms"] > 0.0, st
 
 
-# Relative noise of the recursive residual late in a solve: two FP64
-# oracle runs that are equal in exact arithmetic (Cholesky vs explicit
-# local inverses, reversed DoF order in the local factors, transposed
-# operator storage) differ by up to 41% in ||r_k|| / ||b|| once it is below
-# 1e-6, and stop one iteration apart on four of the six parity cases
-# (tests/test_oracle_spread.py measures this on the CPU). The GPU is one
-# more such rounding variant.
-RES_NOISE = 0.5
+# Rounding noise of the recursive residual late in a solve, as a factor:
+# two FP64 oracle runs that are equal in exact arithmetic (Cholesky vs
+# explicit local inverses, reversed DoF order in the local factors,
+# transposed operator storage) have ||r_k|| / ||b|| up to 1.6 times apart
+# once it is below 1e-6 on the parity cases, and stop one iteration apart on
+# four of the six (tests/test_oracle_spread.py); at full size (the 786k-DoF
+# jump workload, 2404 iterations) up to 1.98 times apart once below 1e-7
+# (tests/golden/full_rounding_spread.py). The GPU is one more such rounding
+# variant: its residuals must lie within this factor of the oracle's.
+RES_FACTOR = 2.0
 # Relative noise of the Lanczos condition estimate between such variants:
 # up to 1.6e-4 on C1 (22 iterations, lambda_min not yet converged), at most
 # 1e-7 on the other cases.
@@ -169,19 +171,19 @@ def _check_pcg_parity(name, orc, st, xg, b=None):
 
     1. Iterate: after the GPU's iteration count k, the GPU iterate is within
        1e-10 (relative 2-norm) of the oracle's iterate after k iterations.
-    2. Residual: the GPU's final recursive residual equals the oracle's at
-       iteration k up to the relative noise RES_NOISE (relative to the
-       tolerance once below it: a solve that ends far below tol, as with one
-       subdomain and the coarse space, ends at rounding level); the true residual the
-       library reports equals ||b - A x|| / ||b|| of the returned x computed
-       here, up to the rounding of that difference, 64 u (||A||_inf ||x||_inf
-       + ||b||_inf) / ||b||_2 * sqrt(n).
+    2. Residual: the GPU's final recursive residual and the oracle's at
+       iteration k differ by at most (RES_FACTOR - 1) times the larger of the
+       oracle's and the tolerance (a solve that ends far below tol, as with
+       one subdomain and the coarse space, ends at rounding level); the true
+       residual the library reports equals ||b - A x|| / ||b|| of the
+       returned x computed here, up to the rounding of that difference,
+       64 u (||A||_inf ||x||_inf + ||b||_inf) / ||b||_2 * sqrt(n).
     3. Stopping: the GPU's stopping decision is the oracle's up to the same
-       noise: at the GPU's stop iteration the oracle's residual is at most
-       tol (1 + RES_NOISE), and at every earlier iteration at least
-       tol (1 - RES_NOISE). Equal stop iterations satisfy this; different
-       ones only where the oracle's residual stays within the noise band of
-       the tolerance."""
+       factor: at the GPU's stop the oracle's residual is at most
+       RES_FACTOR tol, and at every earlier iteration at least
+       tol / RES_FACTOR. Equal stop iterations satisfy this; different ones
+       only where the oracle's residual stays within that band of the
+       tolerance."""
     tol = 1e-8
     if b is None:
         xo, info = _oracle_run(orc, rtol=tol)
@@ -201,10 +203,10 @@ def _check_pcg_parity(name, orc, st, xg, b=None):
     print(f"{name}: iterations gpu={kg} oracle={ko} rel_err={_rel(xg, xk):.2e} "
           f"res gpu={st['rel_res']:.4e} oracle@k={hk[-1]:.4e} true gpu={st['true_rel_res']:.4e} host={tres:.4e}")
     assert _rel(xg, xk) <= 1e-10, _rel(xg, xk)
-    assert abs(st["rel_res"] - hk[-1]) <= RES_NOISE * max(hk[-1], tol), (st["rel_res"], hk[-1])
+    assert abs(st["rel_res"] - hk[-1]) <= (RES_FACTOR - 1) * max(hk[-1], tol), (st["rel_res"], hk[-1])
     assert abs(st["true_rel_res"] - tres) <= rb, (st["true_rel_res"], tres, rb)
-    assert hk[-1] <= tol * (1 + RES_NOISE), hk[-1]
-    assert all(h >= tol * (1 - RES_NOISE) for h in hk[:-1]), min(hk[:-1])
+    assert hk[-1] <= tol * RES_FACTOR, hk[-1]
+    assert all(h >= tol / RES_FACTOR for h in hk[:-1]), min(hk[:-1])
     return infk
 
 

@@ -397,6 +397,24 @@ def test_one_subdomain_plus_coarse_spectrum_is_one_and_two():
     assert info.iterations == 1
 
 
+def test_pcg_extra_steps_continue_the_same_iteration():
+    """extra > 0 records the residuals of further steps of the same
+    iteration (equal to a longer fixed-length run) and leaves the iterate,
+    coefficients and statistics of the stop unchanged."""
+    import scipy.sparse as sp
+
+    from oracle.pcg import pcg
+
+    A = sp.diags(np.linspace(1.0, 40.0, 60)).tocsr()
+    b = np.cos(np.arange(60.0))
+    x1, i1 = pcg(A, b, lambda r: r / A.diagonal() ** 0.5, rtol=1e-10)
+    x2, i2 = pcg(A, b, lambda r: r / A.diagonal() ** 0.5, rtol=1e-10, extra=4)
+    _, i3 = pcg(A, b, lambda r: r / A.diagonal() ** 0.5, fixed_iters=i1.iterations + 4)
+    assert np.array_equal(x1, x2) and i1.history == i2.history and i1.alphas == i2.alphas
+    assert i1.betas == i2.betas and i1.true_rel_res == i2.true_rel_res and i1.iterations == i2.iterations
+    assert i2.history_after == i3.history[i1.iterations:] and len(i2.history_after) == 4
+
+
 def test_pcg_matches_direct_solve_and_lanczos_matches_dense():
     mesh, sub, A, b, geo, M = _schwarz_problem()
     x, info = pcg(A, b, M.apply, rtol=1e-12)

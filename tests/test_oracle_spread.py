@@ -9,15 +9,16 @@ protocol) that are equal in exact arithmetic but round differently:
             instead of two triangular solves each;
   reversed  local Cholesky factors of the DoF-reversed A_i.
 Measured on the parity cases: the iterates after the same number of
-iterations agree to ~1e-12, while the recursive residual ||r_k|| / ||b||
-differs by up to 41% once it is below 1e-6, the stop iteration at rtol 1e-8
+iterations agree to ~1e-12, while the recursive residuals ||r_k|| / ||b||
+are up to 1.6 times apart once below 1e-6, the stop iteration at rtol 1e-8
 moves by one on four of six cases, and the Lanczos condition estimate of C1
 moves by 1.6e-4 (C1 stops after 22 iterations, before the smallest Ritz
 value has settled; 1e-7 at most on the other cases). A rule that demands
 the same stop iteration unless the residual is within 1e-3 of the
 tolerance, or condition estimates equal to 1e-6, fails between two correct
-FP64 solvers; the GPU rule (iterate 1e-10, residual noise 50%, stopping
-decision consistent up to that noise, K to 1e-3) holds between them.
+FP64 solvers; the GPU rule (iterate 1e-10, residuals within a factor 2,
+stopping decision consistent up to that factor, K to 1e-3) holds between
+them.
 """
 import numpy as np
 import pytest
@@ -27,7 +28,7 @@ from oracle import OracleSolver
 from oracle.pcg import pcg
 from paper_1903_11357_amd import inputs as I
 
-from test_gpu_parity import K_NOISE, RES_NOISE, _check_pcg_parity
+from test_gpu_parity import K_NOISE, RES_FACTOR, _check_pcg_parity
 
 CASES = {
     "C1": lambda: I.make_config("C1"),
@@ -98,9 +99,10 @@ def test_rounding_variant_passes_the_gpu_fp64_rule(name, kind):
 def test_rounding_spread_exceeds_the_strict_reading():
     """On the parity cases at least one variant breaks the stricter rule
     (same stop iteration unless the residual is within 1e-3 of tol; K to
-    1e-6), while the late residual noise stays inside RES_NOISE."""
+    1e-6), while the late residual histories stay within RES_FACTOR of each
+    other."""
     broken = []
-    worst_noise = 0.0
+    worst_noise = 1.0
     for name in sorted(CASES):
         orc = _oracle(name)
         xr, ir = orc.solve(rtol=1e-8)
@@ -110,9 +112,9 @@ def test_rounding_spread_exceeds_the_strict_reading():
             hv = np.asarray(iv.history)
             m = min(len(hr), len(hv))
             late = hr[:m] < 1e-6
-            worst_noise = max(worst_noise, float((np.abs(hv[:m] - hr[:m]) / hr[:m])[late].max()))
+            worst_noise = max(worst_noise, float(np.maximum(hv[:m] / hr[:m], hr[:m] / hv[:m])[late].max()))
             if not _a16_holds(ir, iv, ir.condition_estimate(), iv.condition_estimate()):
                 broken.append((name, kind, ir.iterations, iv.iterations))
     print("variants breaking the strict reading:", broken, "late residual noise:", worst_noise)
     assert broken
-    assert 1e-3 < worst_noise <= RES_NOISE
+    assert 1.001 < worst_noise <= RES_FACTOR
