@@ -169,7 +169,7 @@ template <typename T>
 __global__ __launch_bounds__(256, 2) void k_cholesky(int32_t n_tasks, const int4* __restrict__ tasks,
                                                   const SubDesc* __restrict__ subs, T* tiles, int32_t* flags,
                                                   DevState* st, int32_t* queue) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
   T* Bs = As + TILE * LDA;
   __shared__ int s_task;
@@ -198,7 +198,7 @@ template <typename T>
 __global__ __launch_bounds__(256, 2) void k_cholesky_subs(int32_t n_tasks, const int4* __restrict__ tasks,
                                                        const SubDesc* __restrict__ subs, T* tiles, DevState* st,
                                                        int32_t* queue) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
   T* Bs = As + TILE * LDA;
   __shared__ int s_task;

@@ -23,7 +23,7 @@ template <typename T>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void k_inv_lower(int32_t n_tasks, const int4* __restrict__ tasks,
                                                    const SubDesc* __restrict__ subs, const T* __restrict__ L,
                                                    T* X, int32_t* flags, DevState* st, int32_t* queue) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
   T* Bs = As + TILE * LDA;
   __shared__ int s_task;
@@ -103,7 +103,7 @@ template <typename T>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_inv_cols(int32_t n_tasks, const int4* __restrict__ tasks,
                                                   const SubDesc* __restrict__ subs, const T* __restrict__ L, T* X,
                                                   DevState* st, int32_t* queue) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
   T* Bs = As + TILE * LDA;
   __shared__ int s_task;
@@ -172,7 +172,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_inv_gram(int32_t n_tiles, const int4* __restrict__ meta,
                                                   const SubDesc* __restrict__ subs, const T* __restrict__ X,
                                                   T* __restrict__ S) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* As = reinterpret_cast<T*>(smem_raw);
   T* Bs = As + TILE * LDA;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
