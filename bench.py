@@ -117,7 +117,7 @@ def oracle_reference(workload):
         return {k: z[k] for k in z.files}
 
 
-def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=True, ref=None):
+def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=True, ref=None, schedules=(0, 0)):
     import torch
 
     from paper_1903_11357_amd import asdg
@@ -127,6 +127,8 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
     if inverse:
         pr.set_tuning(asdg.TUNE_LOCAL_INVERSE, 1)
+    pr.set_tuning(asdg.TUNE_FACTOR_SCHEDULE, schedules[0])
+    pr.set_tuning(asdg.TUNE_INVERSE_SCHEDULE, schedules[1])
     pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
             coarse_mesh=P.coarse_mesh)
     t1 = time.perf_counter()
@@ -418,6 +420,9 @@ def main():
                          "A_i^{-1}, one pass) and/or sweeps (Cholesky forward/backward sweeps)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (no asdg_autotune after the factorisation)")
+    ap.add_argument("--schedules", default="0,0",
+                    help="Cholesky and X = L^-1 schedules before any autotuning (0 automatic, 1 tile tasks, "
+                         "2 subdomain / block-column tasks); profiling runs of each kernel")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap PCG iterations (profiling runs; 0 = the workload's own limit)")
     ap.add_argument("--serving-requests", type=int, default=2000,
@@ -476,7 +481,8 @@ def main():
             prec = asdg.FP32_LOCAL if m == "fp32" else asdg.FP64
             key = m if loc == "inverse" else f"{m}-sweeps"
             modes[key] = run_mode(P, prec, a.steps, a.warmup, a.check_every, inverse=(loc == "inverse"),
-                                  autotune=not a.no_autotune, ref=ref)
+                                  autotune=not a.no_autotune, ref=ref,
+                                  schedules=tuple(int(v) for v in a.schedules.split(",")))
             print(f"[bench] {key}: {json.dumps(modes[key])}", file=sys.stderr, flush=True)
     if a.serving_requests > 0:
         gen = start_serving_inputs(a.serving_meshes)

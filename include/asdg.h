@@ -295,7 +295,7 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL; default 1 in
  * FP32-local mode, 4 in FP64 mode). TASK_CHUNK:
  * queue order of the factorisation and inverse-formation tasks (tile tasks,
- * and the block-column tasks of schedule 2), 0 = all subdomains interleaved
+ * and the block-column tasks of INVERSE_SCHEDULE 2), 0 = all subdomains interleaved
  * (longest remaining path first), c > 0 = groups of c consecutive
  * subdomains one after the other (a smaller working set);
  * after asdg_bind it takes effect at the next asdg_factor. HOST_THREADS:
@@ -306,19 +306,22 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * for n0 <= 8192): 0 = packed lower tiles from n0 >= 4096 on, dense below
  * (default); 1 = always packed; 2 = always dense. The packed form is
  * applied by tiles (half the bytes), the dense one by one product.
- * FACTOR_SCHEDULE: how the local factorisation and inverse formation are
- * spread over work-groups: 1 = one task per tile (a dependency-ordered
- * queue with flag waits: one subdomain can occupy many work-groups);
- * 2 = one work-group per subdomain for the Cholesky factorisation and per
- * block column for X = L^{-1} (no waits; for many subdomains of similar
- * size); 0 = automatic (2 when the largest subdomain's factorisation is at
- * most twice an even share of the whole over the device's work-groups).
- * No launch shape or schedule changes the arithmetic: results are
- * identical for every setting. */
+ * FACTOR_SCHEDULE: how the local Cholesky factorisation is spread over
+ * work-groups: 1 = one task per tile (a dependency-ordered queue with flag
+ * waits: one subdomain can occupy many work-groups); 2 = one work-group per
+ * subdomain (no waits; for many subdomains of similar size); 0 = automatic
+ * (2 when the largest subdomain's factorisation is at most one and a half
+ * times an even share of the whole over the device's work-groups).
+ * INVERSE_SCHEDULE: the same choice for the formation of X = L^{-1}:
+ * 1 = one task per tile, 2 = one work-group per block column of X (no
+ * waits); 0 = automatic (2 when the largest column's products are at most
+ * twice an even share). No launch shape or schedule changes the
+ * arithmetic: results are identical for every setting. */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
        ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
        ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9,
-       ASDG_TUNE_HOST_THREADS = 10, ASDG_TUNE_COARSE_PACKED = 11, ASDG_TUNE_FACTOR_SCHEDULE = 12 };
+       ASDG_TUNE_HOST_THREADS = 10, ASDG_TUNE_COARSE_PACKED = 11, ASDG_TUNE_FACTOR_SCHEDULE = 12,
+       ASDG_TUNE_INVERSE_SCHEDULE = 13 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Launch shapes chosen by asdg_autotune and the best times measured. */
@@ -329,6 +332,7 @@ typedef struct {
   int32_t candidates; /* configurations timed */
   int32_t from_cache; /* 1: shapes taken from the process's tuning cache, nothing timed */
   int32_t factor_schedule; /* ASDG_TUNE_FACTOR_SCHEDULE in effect (1 or 2; 0 with whole small inverses) */
+  int32_t inverse_schedule; /* ASDG_TUNE_INVERSE_SCHEDULE in effect (1 or 2; 0 without tiled explicit inverses) */
 } asdg_tune_report;
 
 /* Own launch-shape autotuner (the batched factorisation and local-solve
@@ -336,9 +340,10 @@ typedef struct {
  * problem with HIP events on `stream` (median of three runs, or one run
  * when it takes more than 20 ms) and keeps the fastest, through the same
  * settings as asdg_set_tuning.
- * ASDG_AUTOTUNE_FACTOR (after asdg_bind): the factorisation schedule
- * (FACTOR_SCHEDULE 1, 2), work-groups per compute unit of
- * the Cholesky launch (1, 2), the task order of the tile schedule
+ * ASDG_AUTOTUNE_FACTOR (after asdg_bind): the Cholesky schedule
+ * (FACTOR_SCHEDULE 1, 2), with explicit inverses the schedule of
+ * X = L^{-1} (INVERSE_SCHEDULE 1, 2), work-groups per compute unit of
+ * the Cholesky launch (1, 2), the task order
  * (TASK_CHUNK 0, and 64 when there are more than 64 subdomains) and, with explicit inverses,
  * work-groups per compute unit of the inverse formation (1-4 FP32, 1-2
  * FP64); runs asdg_factor up to 3 times per candidate and leaves the
@@ -362,7 +367,9 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
 
 /* The tuning cache as text, one line per size class (key, then Cholesky,
  * inverse-formation and sweep work-groups per CU, packed-apply waves,
- * task-order chunk, best factorisation and local-solve ms). save writes
+ * task-order chunk, best factorisation and local-solve ms, Cholesky and
+ * inverse-formation schedules; lines of older files without the last one
+ * or two fields load with those automatic). save writes
  * the whole cache (EINVAL if the file cannot be written); load adds the
  * entries of a file written by save (n_entries: how many; EINVAL and
  * nothing added if it cannot be read or a line is malformed). Both are

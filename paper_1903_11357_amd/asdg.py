@@ -51,7 +51,8 @@ class TuneReport(C.Structure):
     _fields_ = [("chol_wg_per_cu", C.c_int32), ("inv_wg_per_cu", C.c_int32), ("trsv_wg_per_cu", C.c_int32),
                 ("symv_waves", C.c_int32), ("task_chunk", C.c_int32), ("factor_ms", C.c_double),
                 ("local_ms", C.c_double),
-                ("candidates", C.c_int32), ("from_cache", C.c_int32), ("factor_schedule", C.c_int32)]
+                ("candidates", C.c_int32), ("from_cache", C.c_int32), ("factor_schedule", C.c_int32),
+                ("inverse_schedule", C.c_int32)]
 
 
 class TetMesh_(C.Structure):
@@ -102,7 +103,7 @@ _SIGS = {
 }
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
     TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES, TUNE_TASK_CHUNK, TUNE_HOST_THREADS, TUNE_COARSE_PACKED, \
-    TUNE_FACTOR_SCHEDULE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
+    TUNE_FACTOR_SCHEDULE, TUNE_INVERSE_SCHEDULE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13
 AUTOTUNE_FACTOR, AUTOTUNE_LOCAL, AUTOTUNE_REUSE = 1, 2, 4
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 

@@ -171,7 +171,7 @@ struct asdg_problem {
   int task_chunk = 0;        // subdomains per group of the factorisation task order (0: all at once)
   // factorisation schedule: 0 automatic, 1 tile tasks (Cholesky and X = L^{-1}), 2 one work-group per
   // subdomain (Cholesky) and per block column (X = L^{-1})
-  int factor_sched = 0;
+  int factor_sched = 0, inv_sched = 0;
   std::vector<int4> sub_tasks, col_tasks;  // the schedule-2 queues, largest work first
   int host_threads = 0;      // cap on host threads of assembly and planning (0: default)
   std::string arch;          // device architecture name (set by asdg_bind)
@@ -1063,15 +1063,16 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   return ASDG_OK;
 }
 
-// Factorisation schedule of the local matrices (1 tile tasks, 2 subdomain
-// and column tasks). Automatic: the subdomain schedule when the largest
-// subdomain's Cholesky (about nb^3/6 tile products) is no more than twice
-// an even share of all of them over the work-groups that fit on the device,
-// i.e. when one work-group per subdomain keeps the device busy to nearly the
-// end (the schedule without waits runs its products faster, which makes up
-// for some imbalance: measured on 512 subdomains whose largest is 1.65 times
-// the mean); otherwise the tile tasks, which spread one subdomain over many
-// work-groups.
+// Schedules of the local factorisation (1 tile tasks, 2 one work-group per
+// subdomain) and of the formation of X = L^{-1} (1 tile tasks, 2 one
+// work-group per block column). The schedules without waits run their
+// products faster, the tile tasks spread a large subdomain over many
+// work-groups; the automatic choice compares the largest task of the
+// coarse-grained schedule with an even share of all products over the
+// work-groups that fit on the device.
+// Cholesky: subdomain tasks when the largest subdomain (about nb^3/6 tile
+// products) is at most 1.5 times that share (measured on 512 subdomains
+// whose largest is 1.65 times the mean: the tile tasks are 6% faster).
 static int factor_schedule(const asdg_problem* pb) {
   if (pb->factor_sched == 1 || pb->factor_sched == 2) return pb->factor_sched;
   double total = 0.0, largest = 0.0;
@@ -1081,6 +1082,23 @@ static int factor_schedule(const asdg_problem* pb) {
     largest = std::max(largest, w);
   }
   const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
+  const double slots = (double)pb->n_cu * per_cu;
+  return largest <= 1.5 * total / slots ? 2 : 1;
+}
+
+// X = L^{-1}: column tasks when the largest column (m(m+3)/2 tile products
+// for the m block rows below its diagonal) is at most twice the share (at
+// that size the column tasks are 20-35% faster than the tile tasks).
+static int inverse_schedule(const asdg_problem* pb) {
+  if (pb->inv_sched == 1 || pb->inv_sched == 2) return pb->inv_sched;
+  double total = 0.0, largest = 0.0;
+  for (const SubDesc& d : pb->subs)
+    for (int m = 0; m < d.nb; ++m) {
+      const double w = 0.5 * m * (m + 3);
+      total += w;
+      largest = std::max(largest, w);
+    }
+  const int per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);
   const double slots = (double)pb->n_cu * per_cu;
   return largest <= 2.0 * total / slots ? 2 : 1;
 }
@@ -1147,8 +1165,7 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.row_ptr),
                                  pb->ptr<int32_t>(0, pb->o0.col), pb->ptr<double>(0, pb->o0.blocks),
                                  pb->ptr<void>(1, pb->o1.tiles), pb->f32, s));
-  const int sched = factor_schedule(pb);
-  const bool per_sub = sched == 2;
+  const bool per_sub = factor_schedule(pb) == 2;
   asdg_status e = per_sub ? run_cholesky(pb, s, pb->f32, 1, (int32_t)pb->sub_tasks.size(), pb->ptr<int4>(1, pb->o1.subt),
                                          pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0)
                           : run_cholesky(pb, s, pb->f32, 0, (int32_t)pb->chol_tasks.size(), pb->ptr<int4>(1, pb->o1.chol),
@@ -1156,14 +1173,15 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
   if (e != ASDG_OK) return e;
   if (pb->inv_planned) {
     DevState* st = pb->ptr<DevState>(3, pb->o3.st);
-    if (!per_sub) HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_tiles, 0, s));
+    const bool cols = inverse_schedule(pb) == 2;
+    if (!cols) HIPCHK(pb, launch_fill_i32(pb->ptr<int32_t>(3, pb->o3.flags), pb->n_tiles, 0, s));
     HIPCHK(pb, launch_reset_queues(st, s));
     const int per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);  // default: the occupancy
-    const int64_t nt = per_sub ? (int64_t)pb->col_tasks.size() : (int64_t)pb->inv_tasks.size();
+    const int64_t nt = cols ? (int64_t)pb->col_tasks.size() : (int64_t)pb->inv_tasks.size();
     const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t)pb->n_cu * per_cu));
     const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>(pb->n_tiles, (int64_t)pb->n_cu * per_cu * 4));
-    HIPCHK(pb, launch_inverse(pb->f32, per_sub ? 1 : 0, (int32_t)nt,
-                              per_sub ? pb->ptr<int4>(1, pb->o1.colt) : pb->ptr<int4>(1, pb->o1.inv),
+    HIPCHK(pb, launch_inverse(pb->f32, cols ? 1 : 0, (int32_t)nt,
+                              cols ? pb->ptr<int4>(1, pb->o1.colt) : pb->ptr<int4>(1, pb->o1.inv),
                               (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta), pb->ptr<SubDesc>(1, pb->o1.subs),
                               pb->ptr<void>(1, pb->o1.tiles), pb->ptr<void>(1, pb->o1.xtiles),
                               pb->ptr<int32_t>(3, pb->o3.flags), st, &st->q_chol, g1, g2, s));
@@ -1482,6 +1500,10 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
     if (value > 2) FAIL(pb, ASDG_EINVAL, "factorisation schedule: 0 automatic, 1 tile tasks, 2 subdomain tasks");
     pb->factor_sched = value;
   }
+  else if (what == ASDG_TUNE_INVERSE_SCHEDULE) {
+    if (value > 2) FAIL(pb, ASDG_EINVAL, "inverse-formation schedule: 0 automatic, 1 tile tasks, 2 column tasks");
+    pb->inv_sched = value;
+  }
   else if (what == ASDG_TUNE_COARSE_PACKED) {
     if (value > 2) FAIL(pb, ASDG_EINVAL, "coarse inverse storage: 0 automatic, 1 packed, 2 dense");
     pb->coarse_packed_mode = value;
@@ -1561,6 +1583,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
       // the shapes found before for this size class, no timing
       if (what & ASDG_AUTOTUNE_FACTOR) {
         pb->factor_sched = C.factor_schedule;
+        pb->inv_sched = C.inverse_schedule;
         pb->chol_per_cu = C.chol_wg_per_cu;
         pb->inv_per_cu = C.inv_wg_per_cu;
         if (C.task_chunk != pb->task_chunk && !pb->small) {
@@ -1633,9 +1656,13 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   };
   if ((what & ASDG_AUTOTUNE_FACTOR) && !pb->small) {
     double ms = 0.0;
-    // the schedule first (tile tasks, or one work-group per subdomain / column)
+    // the schedules first (tile tasks, or one work-group per subdomain / column)
     asdg_status e = tune(&pb->factor_sched, {1, 2}, time_factor, ms);
     if (e != ASDG_OK) return e;
+    if (pb->inv_planned) {
+      e = tune(&pb->inv_sched, {1, 2}, time_factor, ms);
+      if (e != ASDG_OK) return e;
+    }
     e = tune(&pb->chol_per_cu, {1, 2}, time_factor, ms);
     if (e != ASDG_OK) return e;
     {
@@ -1700,6 +1727,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
   R.task_chunk = pb->task_chunk;
   R.factor_schedule = pb->small ? 0 : factor_schedule(pb);
+  R.inverse_schedule = pb->small || !pb->inv_planned ? 0 : inverse_schedule(pb);
   pb->drop_graph();
   if ((what & (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL)) == (ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL) && !pb->small) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1716,8 +1744,9 @@ asdg_status asdg_tune_cache_save(const char* path) {
   if (!f) return ASDG_EINVAL;
   for (const auto& kv : g_tune_cache) {
     const asdg_tune_report& R = kv.second;
-    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f %d\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
-                 R.trsv_wg_per_cu, R.symv_waves, R.task_chunk, R.factor_ms, R.local_ms, R.factor_schedule);
+    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f %d %d\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
+                 R.trsv_wg_per_cu, R.symv_waves, R.task_chunk, R.factor_ms, R.local_ms, R.factor_schedule,
+                 R.inverse_schedule);
   }
   return std::fclose(f) == 0 ? ASDG_OK : ASDG_EINVAL;
 }
@@ -1731,18 +1760,18 @@ asdg_status asdg_tune_cache_load(const char* path, int32_t* n_entries) {
   char line[512];
   asdg_tune_report R;
   bool ok = true;
-  // one entry per line; the factorisation schedule (last field) may be
-  // missing in files written before it existed (then: automatic)
+  // one entry per line; the two schedules (last fields) may be missing in
+  // files written before they existed (then: automatic)
   while (std::fgets(line, sizeof(line), f)) {
     std::memset(&R, 0, sizeof(R));
-    const int got = std::sscanf(line, "%255s %d %d %d %d %d %lf %lf %d", key, &R.chol_wg_per_cu, &R.inv_wg_per_cu,
-                                &R.trsv_wg_per_cu, &R.symv_waves, &R.task_chunk, &R.factor_ms, &R.local_ms,
-                                &R.factor_schedule);
+    const int got = std::sscanf(line, "%255s %d %d %d %d %d %lf %lf %d %d", key, &R.chol_wg_per_cu,
+                                &R.inv_wg_per_cu, &R.trsv_wg_per_cu, &R.symv_waves, &R.task_chunk, &R.factor_ms,
+                                &R.local_ms, &R.factor_schedule, &R.inverse_schedule);
     if (got <= 0) continue;  // blank line
     const bool waves_ok = R.symv_waves == 1 || R.symv_waves == 2 || R.symv_waves == 4 || R.symv_waves == 8;
-    if ((got != 8 && got != 9) || !waves_ok || R.chol_wg_per_cu < 1 || R.chol_wg_per_cu > 64 ||
-        R.inv_wg_per_cu < 1 || R.inv_wg_per_cu > 64 || R.trsv_wg_per_cu < 1 || R.trsv_wg_per_cu > 64 ||
-        R.task_chunk < 0 || R.factor_schedule < 0 || R.factor_schedule > 2) {
+    if (got < 8 || !waves_ok || R.chol_wg_per_cu < 1 || R.chol_wg_per_cu > 64 || R.inv_wg_per_cu < 1 ||
+        R.inv_wg_per_cu > 64 || R.trsv_wg_per_cu < 1 || R.trsv_wg_per_cu > 64 || R.task_chunk < 0 ||
+        R.factor_schedule < 0 || R.factor_schedule > 2 || R.inverse_schedule < 0 || R.inverse_schedule > 2) {
       ok = false;
       break;
     }

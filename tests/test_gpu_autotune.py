@@ -39,12 +39,14 @@ def test_autotune_keeps_results_bitwise(precision, inverse):
     if inverse:
         assert rep["inv_wg_per_cu"] in ((1, 2, 3, 4) if precision == "fp32" else (1, 2))
         assert rep["symv_waves"] in (1, 2, 4, 8)
-        # schedules 2, Cholesky shapes 2, task orders 1 (4 subdomains: no grouping below that), inverse
-        # formation, packed apply 4
-        assert rep["candidates"] == 2 + 2 + 1 + (4 if precision == "fp32" else 2) + 4
+        # Cholesky schedules 2, inverse-formation schedules 2, Cholesky shapes 2, task orders 1 (4 subdomains:
+        # no grouping below that), inverse formation, packed apply 4
+        assert rep["candidates"] == 2 + 2 + 2 + 1 + (4 if precision == "fp32" else 2) + 4
+        assert rep["inverse_schedule"] in (1, 2)
     else:
         assert rep["trsv_wg_per_cu"] in (1, 2, 3, 4)
         assert rep["candidates"] == 2 + 2 + 1 + 4
+        assert rep["inverse_schedule"] == 0
     assert rep["factor_schedule"] in (1, 2)
     assert rep["task_chunk"] == 0
     pr.setup_coarse()
@@ -99,7 +101,7 @@ def test_autotune_cache_reuse_same_size_class(tmp_path):
     second = asdg.setup_problem(P, asdg.FP32_LOCAL, device="cuda:0", local_inverse=True, factor=False)
     rep2 = second.autotune(asdg.AUTOTUNE_FACTOR | asdg.AUTOTUNE_LOCAL | asdg.AUTOTUNE_REUSE)
     assert rep2["from_cache"] == 1 and rep2["candidates"] == 0
-    for k in ("chol_wg_per_cu", "inv_wg_per_cu", "symv_waves", "task_chunk"):
+    for k in ("chol_wg_per_cu", "inv_wg_per_cu", "symv_waves", "task_chunk", "factor_schedule", "inverse_schedule"):
         assert rep2[k] == rep1[k], k
     second.setup_coarse()
     x2, st2 = second.solve(rtol=1e-8)
@@ -130,9 +132,11 @@ def _tiles(pr, sub, word):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("inverse", [True, False], ids=["inverse", "sweeps"])
 def test_factor_schedules_bitwise_equal(case, precision, inverse):
-    """The tile-task schedule and the subdomain/column schedule of the
-    factorisation (ASDG_TUNE_FACTOR_SCHEDULE 1 and 2) run the same products in
-    the same order: bitwise equal factors (or inverses) and solves."""
+    """The tile-task schedules and the subdomain (Cholesky) / block-column
+    (X = L^-1) schedules (ASDG_TUNE_FACTOR_SCHEDULE and
+    ASDG_TUNE_INVERSE_SCHEDULE 1 and 2, in every combination) run the same
+    products in the same order: bitwise equal factors (or inverses) and
+    solves."""
     from paper_1903_11357_amd import asdg
 
     P = _problem() if case == "4x1800" else I.voronoi_problem(4096, 31, p=2, bx=16, by=8, q=1, nonnested_coarse=16,
@@ -140,10 +144,12 @@ def test_factor_schedules_bitwise_equal(case, precision, inverse):
     prec = asdg.FP32_LOCAL if precision == "fp32" else asdg.FP64
     word = 4 if precision == "fp32" else 8
     out = []
-    for sched in (1, 2):
-        print(f"[schedule] {case} {precision} inverse={inverse} schedule={sched}", flush=True)
+    combos = [(1, 1), (2, 2), (1, 2), (2, 1)] if inverse else [(1, 0), (2, 0)]
+    for sched, isched in combos:
+        print(f"[schedule] {case} {precision} inverse={inverse} schedules={sched},{isched}", flush=True)
         pr = asdg.setup_problem(P, prec, device="cuda:0", local_inverse=inverse, factor=False)
         pr.set_tuning(asdg.TUNE_FACTOR_SCHEDULE, sched)
+        pr.set_tuning(asdg.TUNE_INVERSE_SCHEDULE, isched)
         pr.factor()
         pr.setup_coarse()
         subs = sorted({0, P.n_sub // 2, P.n_sub - 1})
@@ -151,7 +157,8 @@ def test_factor_schedules_bitwise_equal(case, precision, inverse):
         x, st = pr.solve(rtol=1e-8)
         out.append((tiles, x.cpu().numpy(), st["iterations"]))
         del pr
-    (t1, x1, k1), (t2, x2, k2) = out
-    for a, b in zip(t1, t2):
-        assert np.array_equal(a, b)
-    assert k1 == k2 and np.array_equal(x1, x2)
+    t1, x1, k1 = out[0]
+    for t2, x2, k2 in out[1:]:
+        for a, b in zip(t1, t2):
+            assert np.array_equal(a, b)
+        assert k1 == k2 and np.array_equal(x1, x2)

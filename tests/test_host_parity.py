@@ -206,6 +206,11 @@ def test_tuning_and_autotune_argument_errors():
         pr.set_tuning(asdg.TUNE_HOST_THREADS, -1)
     for w in (0, 1, 2, 4, 8):
         pr.set_tuning(asdg.TUNE_SYMV_WAVES, w)
+    for knob in (asdg.TUNE_FACTOR_SCHEDULE, asdg.TUNE_INVERSE_SCHEDULE):
+        for v in (0, 1, 2):
+            pr.set_tuning(knob, v)
+        with pytest.raises(asdg.AsdgError):
+            pr.set_tuning(knob, 3)
     L = asdg.lib()
     rep = asdg.TuneReport()
     assert L.asdg_autotune(pr.h, asdg.AUTOTUNE_FACTOR, None, ctypes.byref(rep)) == asdg.ESTATE  # not bound
@@ -218,16 +223,19 @@ def test_tune_cache_file_roundtrip_and_malformed(tmp_path):
     """The tuning cache text format: a written file loads back; a malformed
     line rejects the whole file (no device needed)."""
     good = tmp_path / "tune.txt"
-    # the factorisation schedule (last field) may be absent: then automatic
-    good.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 38.5 0.43 2\n"
-                    "gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 101.5 0.91\n")
-    assert asdg.tune_cache_load(str(good)) == 2
+    # the two schedules (last fields) may be absent (files written before they existed): then automatic
+    good.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 38.5 0.43 1 2\n"
+                    "gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 101.5 0.91\n"
+                    "gfx950|fp64|sweeps|ns2^9|nbmax24|nbmean24 2 2 2 4 64 90.0 1.5 2\n")
+    assert asdg.tune_cache_load(str(good)) == 3
     out = tmp_path / "saved.txt"
     asdg.tune_cache_save(str(out))
     lines = out.read_text().splitlines()
-    assert any(l.startswith("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 ") and l.endswith(" 2")
+    assert any(l.startswith("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 ") and l.endswith(" 1 2")
                for l in lines)
-    assert any(l.startswith("gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 ") and l.endswith(" 0")
+    assert any(l.startswith("gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 ") and l.endswith(" 0 0")
+               for l in lines)
+    assert any(l.startswith("gfx950|fp64|sweeps|ns2^9|nbmax24|nbmean24 2 2 2 4 64 ") and l.endswith(" 2 0")
                for l in lines)
     bad = tmp_path / "bad.txt"
     bad.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 3 0 38.5 0.43\n")  # 3 waves: invalid
@@ -239,3 +247,7 @@ def test_tune_cache_file_roundtrip_and_malformed(tmp_path):
     bad2.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 8 0 38.5 0.43 5\n")  # schedule 5: invalid
     with pytest.raises(asdg.AsdgError):
         asdg.tune_cache_load(str(bad2))
+    bad3 = tmp_path / "bad3.txt"
+    bad3.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 8 0 38.5 0.43 1 3\n")  # inverse schedule 3
+    with pytest.raises(asdg.AsdgError):
+        asdg.tune_cache_load(str(bad3))
