@@ -292,8 +292,8 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * is K(A_h) rather than K(P_ad); asdg_apply is unaffected.
  * INV_WG_PER_CU: persistent work-groups per compute unit of the formation
  * of the explicit inverses. SYMV_WAVES: tiles (waves) per work-group of
- * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL; default 1 in
- * FP32-local mode, 4 in FP64 mode). TASK_CHUNK:
+ * the packed-inverse apply, 1, 2, 4 or 8 (others: EINVAL; default 4).
+ * TASK_CHUNK:
  * queue order of the factorisation and inverse-formation tasks (tile tasks,
  * and the block-column tasks of INVERSE_SCHEDULE 2), 0 = all subdomains interleaved
  * (longest remaining path first), c > 0 = groups of c consecutive
@@ -337,8 +337,9 @@ typedef struct {
 
 /* Own launch-shape autotuner (the batched factorisation and local-solve
  * launches of Sec. 3's local solvers): times every candidate on this
- * problem with HIP events on `stream` (median of three runs, or one run
- * when it takes more than 20 ms) and keeps the fastest, through the same
+ * problem with HIP events on `stream` (one run when it takes more than
+ * 20 ms, else the median of 3 to 15 runs filling about 20 ms) and keeps the
+ * fastest, through the same
  * settings as asdg_set_tuning.
  * ASDG_AUTOTUNE_FACTOR (after asdg_bind): the Cholesky schedule
  * (FACTOR_SCHEDULE 1, 2), with explicit inverses the schedule of
@@ -346,7 +347,7 @@ typedef struct {
  * the Cholesky launch (1, 2), the task order
  * (TASK_CHUNK 0, and 64 when there are more than 64 subdomains) and, with explicit inverses,
  * work-groups per compute unit of the inverse formation (1-4 FP32, 1-2
- * FP64); runs asdg_factor up to 3 times per candidate and leaves the
+ * FP64); runs asdg_factor up to 15 times per candidate and leaves the
  * problem factorised. ASDG_AUTOTUNE_LOCAL (after
  * asdg_factor, or together with FACTOR): waves per work-group of the packed
  * apply (1, 2, 4, 8) or work-groups per compute unit of the triangular

@@ -563,7 +563,7 @@ asdg_status enqueue_local(asdg_problem* pb, hipStream_t s, const DevState* st_do
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   const double* r = pb->ptr<double>(3, pb->o3.r);
   if (pb->inv_planned) {
-    const int waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
+    const int waves = pb->symv_waves > 0 ? pb->symv_waves : 4;
     HIPCHK(pb, launch_symv_tiles(pb->f32, waves, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
                                  pb->ptr<void>(3, pb->o3.part), st_done, s));
@@ -1620,7 +1620,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
       (void)hipEventDestroy(b);
     }
   } guard{e0, e1};
-  auto median3 = [](float x, float y, float z) { return std::max(std::min(x, y), std::min(std::max(x, y), z)); };
+
   // one timed factorisation (gather, Cholesky, inverse formation)
   auto time_factor = [&](float& ms) -> asdg_status {
     HIPCHK(pb, hipEventRecord(e0, s));
@@ -1636,14 +1636,21 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     best_ms = 1e300;
     for (int c : cand) {
       *knob = c;
-      float t[3];
-      asdg_status e = run(t[0]);
+      float t0 = 0.0f;
+      asdg_status e = run(t0);
       if (e != ASDG_OK) return e;
-      float m = t[0];
-      if (t[0] < 20.0f) {  // short runs: median of three
-        for (int k = 1; k < 3; ++k)
+      float m = t0;
+      if (t0 < 20.0f) {
+        // short runs: the median of an odd number of runs (3 to 15) filling
+        // about 20 ms, so that candidates a few percent apart are told apart
+        int n = std::max(3, std::min(15, (int)(20.0f / std::max(t0, 1e-3f))));
+        if (n % 2 == 0) --n;
+        std::vector<float> t(n);
+        t[0] = t0;
+        for (int k = 1; k < n; ++k)
           if ((e = run(t[k])) != ASDG_OK) return e;
-        m = median3(t[0], t[1], t[2]);
+        std::nth_element(t.begin(), t.begin() + n / 2, t.end());
+        m = t[n / 2];
       }
       ++R.candidates;
       if (m < best_ms) {
@@ -1724,7 +1731,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
   R.chol_wg_per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
   R.inv_wg_per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);
   R.trsv_wg_per_cu = pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2;
-  R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : (pb->f32 ? 1 : 4);
+  R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : 4;
   R.task_chunk = pb->task_chunk;
   R.factor_schedule = pb->small ? 0 : factor_schedule(pb);
   R.inverse_schedule = pb->small || !pb->inv_planned ? 0 : inverse_schedule(pb);
