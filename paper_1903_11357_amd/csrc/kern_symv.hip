@@ -66,40 +66,72 @@ struct TileRow<double> {
 // of a ragged last tile row (zero, and identity on the diagonal, with r zero
 // there) contribute nothing to the sums that are read and are not loaded.
 // WPB waves (tiles) per work-group, a launch-shape choice of the autotuner.
+//
+// The two precisions take the load forms measured fastest for them. FP32:
+// the tile index is made wave-uniform, so its meta data and subdomain
+// descriptor come through scalar loads; the 16 row pieces are loaded without
+// branches and the loads of r are issued right behind them, so no wave
+// waits for its tile before fetching r. A piece that is not read (see below)
+// is loaded from the tile's first piece instead, which lane 0 reads in the
+// same instruction: no extra memory traffic. FP64 (twice the registers per
+// piece): one branch per row piece, and r after the tile.
 template <typename T, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
                                                          const SubDesc* __restrict__ subs, const T* __restrict__ S,
                                                          const double* __restrict__ r, T* __restrict__ part,
                                                          const DevState* st) {
+  constexpr bool F32 = sizeof(T) == 4;
   __shared__ __align__(16) T s_r[WPB][2 * TILE];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int t = blockIdx.x * WPB + w;
+  const int t = F32 ? __builtin_amdgcn_readfirstlane(blockIdx.x * WPB + w) : blockIdx.x * WPB + w;
   if ((st && st->done) || t >= n_tiles) return;
   const int c4 = lane & 15, r0 = lane >> 4;
   const int4 m = meta[t];
   const int b = m.y, j = m.z;
   const bool diag = j == b;
   // diagonal tiles: rows r0 + 4k are read only in the 16-byte pieces that
-  // reach the diagonal (column offset 4 c4 - 4k <= r0)
+  // reach the diagonal (column offset 4 c4 - 4k <= r0); nor are rows beyond
+  // the subdomain. Where such a piece holds other values (FP32), they never
+  // reach a sum that is read: the masks below drop the diagonal tiles' upper
+  // pieces, r is zero beyond the subdomain, and the row sums of padding rows
+  // are not read.
   const int cut = diag ? 4 * c4 - r0 : -64;
   const int rows = m.w - r0;  // row r0 + 4k is inside the subdomain when 4k < rows
   T a[16][4];
-  const T* base = S + (size_t)t * TT + r0 * TILE + 4 * c4;
+  const T* tile = S + (size_t)t * TT;
+  const int off = r0 * TILE + 4 * c4;
+  if (F32) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (cut <= 4 * k && 4 * k < rows) {
-      TileRow<T>::load(base + 4 * TILE * k, a[k]);
-    } else {
+    for (int k = 0; k < 16; ++k)
+      TileRow<T>::load(tile + (cut <= 4 * k && 4 * k < rows ? off + 4 * TILE * k : 0), a[k]);
+    __builtin_amdgcn_sched_barrier(0);  // all tile loads issue before the loads of r wait for the descriptor
+  } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[k][e] = T(0);
+    for (int k = 0; k < 16; ++k) {
+      if (cut <= 4 * k && 4 * k < rows) {
+        TileRow<T>::load(tile + off + 4 * TILE * k, a[k]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[k][e] = T(0);
+      }
     }
   }
   const SubDesc sd = subs[m.x];
   const int gj = j * TILE + lane, gb = b * TILE + lane;
   T* sr = s_r[w];
-  sr[lane] = gj < sd.n ? (T)r[sd.dof0 + gj] : T(0);
+  T vj, vb;
+  if (F32) {
+    // indices clamped into the subdomain: no branch around the loads
+    const double rjv = r[sd.dof0 + min(gj, sd.n - 1)], rbv = r[sd.dof0 + min(gb, sd.n - 1)];
+    vj = gj < sd.n ? (T)rjv : T(0);
+    vb = gb < sd.n ? (T)rbv : T(0);
+  } else {
+    vj = gj < sd.n ? (T)r[sd.dof0 + gj] : T(0);
+    vb = gb < sd.n ? (T)r[sd.dof0 + gb] : T(0);
+  }
+  sr[lane] = vj;
   // r_b stored so that rows r0 + 4k (k = 0..15) are contiguous at 16 r0
-  sr[TILE + (lane & 3) * 16 + (lane >> 2)] = gb < sd.n ? (T)r[sd.dof0 + gb] : T(0);
+  sr[TILE + (lane & 3) * 16 + (lane >> 2)] = vb;
   wave_sync();
   T rj[4], rb[16];
   TileRow<T>::lds4(sr + 4 * c4, rj);
