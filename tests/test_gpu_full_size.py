@@ -3,8 +3,12 @@ subdomains, nested coarse q=2; C4: 786k DoFs, 512 subdomains, 10^+-4
 coefficient jumps, non-nested coarse), in the launch configuration bench.py
 times. The oracle assembles the full operator and load vector; local solves
 are compared on sampled subdomains, the non-nested coarse correction through
-properties that hold at any size, the solution through its true residual
-measured with the oracle's own A and b."""
+properties that hold at any size, and the solution against the FP64
+oracle's own full solve of the same workload (iterations, residual history,
+true residual and, for C4, the iterate), stored in tests/golden by
+tests/golden/make_full_reference.py."""
+import os
+
 import numpy as np
 import pytest
 
@@ -74,7 +78,9 @@ def test_full_operator_apply(name):
     v = np.random.default_rng(1).standard_normal(pr.n)
     out = pr.apply(asdg.APPLY_OPERATOR, torch.from_numpy(v).cuda()).cpu().numpy()
     ref = A @ v
-    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+    # entry by entry against the rounding scale of that entry's own sum
+    scale = abs(A) @ np.abs(v)
+    assert np.all(np.abs(out - ref) <= 1e-13 * scale), float((np.abs(out - ref) / scale).max())
 
 
 @pytest.mark.parametrize("local", ["sweeps", "inverse"])
@@ -149,32 +155,94 @@ def test_full_coarse_correction_is_A_orthogonal_projection_C4():
     assert abs(lhs - rhs) <= 1e-9 * max(abs(lhs), abs(rhs))
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+# rounding noise of the recursive residual between FP64 runs that are equal
+# in exact arithmetic, as a factor: up to 1.98 at this size once below 1e-7
+# (tests/golden/full_rounding_spread.py on the 786k-DoF jump workload)
+RES_FACTOR = 2.0
+
+
+def _reference(name):
+    path = os.path.join(GOLDEN, f"{name}_oracle_fp64.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _check_full_solve(name, prec, st, xg, A, b, ref):
+    """The benchmark solve (captured graphs, rtol 1e-8) against the oracle's
+    FP64 solve of the same workload:
+      - converged, recursive residual <= 1e-8;
+      - the true residual the library reports equals ||b - A x|| / ||b||
+        computed here with the oracle's A and b (up to the rounding of that
+        difference), and is at most twice the oracle's own true residual at
+        its stop (both carry the drift between the recursive and the true
+        residual that rounding builds up over the iterations);
+      - FP64: the stopping decision is the oracle's up to that factor (at
+        the GPU's stop the oracle's residual is at most RES_FACTOR tol,
+        before it at least tol / RES_FACTOR). FP32-local stops where its own
+        inexact local solves take it (its iteration count is reported)."""
+    tol = 1e-8
+    nb = np.linalg.norm(b)
+    tres = np.linalg.norm(b - A @ xg) / nb
+    rb = 64 * 2.0 ** -53 * (abs(A).sum(axis=1).max() * np.abs(xg).max() + np.abs(b).max()) * np.sqrt(len(b)) / nb
+    kg, ko = st["iterations"], int(ref["iterations"])
+    print(f"{name} {prec}: iterations gpu={kg} oracle={ko} recursive={st['rel_res']:.3e} "
+          f"true gpu={st['true_rel_res']:.3e} host={tres:.3e} oracle={float(ref['true_rel_res']):.3e}")
+    assert st["converged"] == 1
+    assert st["rel_res"] <= tol
+    assert abs(st["true_rel_res"] - tres) <= rb, (st["true_rel_res"], tres, rb)
+    assert tres <= 2.0 * float(ref["true_rel_res"]), (tres, float(ref["true_rel_res"]))
+    if prec == "fp64":
+        # the oracle's residual history, continued past its stop
+        h = np.concatenate([np.asarray(ref["history"]), np.asarray(ref["history_after"])])
+        assert kg <= len(h)
+        assert h[kg - 1] <= tol * RES_FACTOR, h[kg - 1]
+        assert np.all(h[:kg - 1] >= tol / RES_FACTOR), h[:kg - 1].min()
+
+
 @pytest.mark.parametrize("local", ["sweeps", "inverse"])
 @pytest.mark.parametrize("name", ["C3", "C4"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_solve_true_residual_against_oracle_system(name, prec, local):
-    """The solution of the benchmark solve (captured-graph path, 1e-8)
-    satisfies the oracle's own SIPG system. In floating point the true
-    residual b - A x_k and CG's recursive residual r_k drift apart by at most
-    about k u (||A|| ||x|| + ||b||) after k iterations (u = 2^-53), so
-    ||b - A x|| / ||b|| <= 1e-8 + k u (||A||_inf ||x|| + ||b||) / ||b||. For
-    C3 (340 iterations) this is ~1e-8; for C4 (~2400 iterations, 10^8
-    coefficient contrast, ||A|| large) the gap dominates."""
+def test_full_solve_against_oracle_reference(name, prec, local):
     from paper_1903_11357_amd import asdg
 
     P, A, b, _ = _oracle(name)
+    ref = _reference(name)
     pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, local == "inverse")
     x, st = pr.solve(rtol=1e-8, check_every=32)
     xg = x.cpu().numpy()
-    nb = np.linalg.norm(b)
-    true_res = np.linalg.norm(b - A @ xg) / nb
-    a_inf = float(abs(A).sum(axis=1).max())
-    gap = st["iterations"] * 2.0 ** -53 * (a_inf * np.linalg.norm(xg) + nb) / nb
-    print(f"{name} {prec}: iterations={st['iterations']} recursive={st['rel_res']:.3e} true={true_res:.3e} "
-          f"gap bound={gap:.3e}")
-    assert st["converged"] == 1
-    assert st["rel_res"] <= 1e-8
-    assert true_res <= 1e-8 * 1.05 + gap, (true_res, gap)
+    _check_full_solve(name, prec, st, xg, A, b, ref)
+    if "x" in ref:
+        err = _rel(xg, ref["x"])
+        print(f"{name} {prec} {local}: ||x - x_oracle|| / ||x_oracle|| = {err:.3e}")
+
+
+# How far the iterate after the oracle's 2404 iterations moves at C4 under
+# rounding-level changes of the assembly: the oracle's own PCG with every
+# entry of A and b scaled by 1 + 2e-15 xi (xi uniform in [-1, 1]) and the
+# preconditioner formed again from that A ends 9.0e-10 from the stored
+# iterate (tests/golden/full_rounding_spread.py C4 --perturb 2e-15). The
+# library's host assembly and the oracle's differ entry by entry by about
+# 1e-16 (median) to a few 1e-15 (99th percentile).
+C4_ITERATE_SPREAD = 1e-9
+
+
+@pytest.mark.parametrize("local", ["sweeps", "inverse"])
+def test_full_fp64_iterate_after_oracle_iterations_C4(local):
+    """FP64 mode run for exactly the oracle's iteration count: the iterate
+    against the oracle's iterate after that count (x_0 = 0, Sec. 7), within
+    the rounding spread of the iterate at this size (C4_ITERATE_SPREAD,
+    relative 2-norm)."""
+    from paper_1903_11357_amd import asdg
+
+    ref = _reference("C4")
+    pr = _gpu("C4", asdg.FP64, local == "inverse")
+    k = int(ref["iterations"])
+    x, st = pr.solve(rtol=0.0, max_iter=k, check_every=32, raise_on_noconv=False)
+    assert st["iterations"] == k and st["status"] == "ENOCONV"
+    err = _rel(x.cpu().numpy(), ref["x"])
+    print(f"C4 fp64 {local}: {k} iterations, ||x - x_oracle|| / ||x_oracle|| = {err:.3e}")
+    assert err <= C4_ITERATE_SPREAD, err
 
 
 # ---------------------------------------------------------------- one element per subdomain (C4h)
@@ -202,23 +270,14 @@ def test_full_small_local_solves_sampled_C4h(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_small_solve_true_residual_C4h(prec):
-    """The benchmark solve of C4h satisfies the oracle's SIPG system to the
-    tolerance plus the recursive/true residual gap bound (see above)."""
+def test_full_small_solve_against_oracle_reference_C4h(prec):
+    """The benchmark solve of C4h against the oracle's FP64 solve of C4h."""
     from paper_1903_11357_amd import asdg
 
     P, A, b, _ = _oracle("C4h")
     pr = _gpu("C4h", asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL)
     x, st = pr.solve(rtol=1e-8, check_every=32)
-    xg = x.cpu().numpy()
-    nb = np.linalg.norm(b)
-    true_res = np.linalg.norm(b - A @ xg) / nb
-    a_inf = float(abs(A).sum(axis=1).max())
-    gap = st["iterations"] * 2.0 ** -53 * (a_inf * np.linalg.norm(xg) + nb) / nb
-    print(f"C4h {prec}: iterations={st['iterations']} recursive={st['rel_res']:.3e} true={true_res:.3e} "
-          f"gap bound={gap:.3e}")
-    assert st["converged"] == 1
-    assert true_res <= 1e-8 * 1.05 + gap, (true_res, gap)
+    _check_full_solve("C4h", prec, st, x.cpu().numpy(), A, b, _reference("C4h"))
 
 
 # ---------------------------------------------------------------- tetrahedra (T1, T1b, T3)
@@ -233,7 +292,9 @@ def test_full_tet_operator_apply(name):
     v = np.random.default_rng(7).standard_normal(pr.n)
     out = pr.apply(asdg.APPLY_OPERATOR, torch.from_numpy(v).cuda()).cpu().numpy()
     ref = A @ v
-    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+    # entry by entry against the rounding scale of that entry's own sum
+    scale = abs(A) @ np.abs(v)
+    assert np.all(np.abs(out - ref) <= 1e-13 * scale), float((np.abs(out - ref) / scale).max())
 
 
 @pytest.mark.parametrize("name", ["T1", "T3", "T1b"])
@@ -266,18 +327,10 @@ def test_full_tet_local_solves_sampled(name, prec):
 
 @pytest.mark.parametrize("name", ["T1", "T3", "T1b"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_tet_solve_true_residual(name, prec):
+def test_full_tet_solve_against_oracle_reference(name, prec):
     from paper_1903_11357_amd import asdg
 
     P, A, b, _ = _oracle(name)
     pr = _gpu(name, asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, inverse=(name == "T1b"))
     x, st = pr.solve(rtol=1e-8, check_every=32)
-    xg = x.cpu().numpy()
-    nb = np.linalg.norm(b)
-    true_res = np.linalg.norm(b - A @ xg) / nb
-    a_inf = float(abs(A).sum(axis=1).max())
-    gap = st["iterations"] * 2.0 ** -53 * (a_inf * np.linalg.norm(xg) + nb) / nb
-    print(f"{name} {prec}: iterations={st['iterations']} recursive={st['rel_res']:.3e} true={true_res:.3e} "
-          f"gap bound={gap:.3e}")
-    assert st["converged"] == 1
-    assert true_res <= 1e-8 * 1.05 + gap, (true_res, gap)
+    _check_full_solve(name, prec, st, x.cpu().numpy(), A, b, _reference(name))
