@@ -73,10 +73,11 @@ struct TileRow<double> {
 // branches and the loads of r are issued right behind them, so no wave
 // waits for its tile before fetching r. A piece that is not read (see below)
 // is loaded from the tile's first piece instead, which lane 0 reads in the
-// same instruction: no extra memory traffic. FP64 (twice the registers per
-// piece): one branch per row piece, and r after the tile.
+// same instruction: no extra memory traffic; at most 96 registers, so five
+// waves fit per SIMD. FP64 (twice the registers per piece): one branch per
+// row piece, and r after the tile (a third wave per SIMD would spill).
 template <typename T, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_symv_tiles(int32_t n_tiles, const int4* __restrict__ meta,
                                                          const SubDesc* __restrict__ subs, const T* __restrict__ S,
                                                          const double* __restrict__ r, T* __restrict__ part,
                                                          const DevState* st) {
