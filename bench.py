@@ -241,9 +241,9 @@ def run_mode(P, precision, steps, warmup, check_every, inverse=False, autotune=T
 
 def _cpu_baseline_child(workload, n_iter, conn):
     """Process of the CPU baseline: builds the oracle for the workload
-    (untimed), reports ready, waits for the go (sent once the GPU work is
-    done, so the timing does not compete with it), then times the oracle's
-    PCG and sends the result."""
+    (untimed, on one host thread), reports ready, waits for the go (sent once
+    the GPU work is done, so the timing does not compete with it), then times
+    the oracle's PCG and sends the result."""
     from oracle import OracleSolver
     from paper_1903_11357_amd import inputs
 
@@ -259,7 +259,10 @@ def _cpu_baseline_child(workload, n_iter, conn):
             return []
 
     t0 = time.perf_counter()
-    orc = OracleSolver(inputs.make_config(workload))
+    # one host thread while it overlaps the serving run (whose host assembly
+    # workers take the rest of the host's CPUs)
+    with threadpool_limits(1):
+        orc = OracleSolver(inputs.make_config(workload))
     conn.send(("ready", time.perf_counter() - t0))
     conn.recv()
     A, M = orc.A, orc.M
@@ -376,7 +379,9 @@ def serving_bench(n_requests, gen, seed=5, local_inverse=False, loads=(0.8,), ca
     srv = Server(precision=asdg.FP32_LOCAL, max_active=max_active, check_every=16, setup_workers=8,
                  local_inverse=local_inverse)
     ncap = min(capacity_requests, n_requests)
-    burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems[:ncap])])
+    burst = srv.run([Request(i, P, 0.0) for i, P in enumerate(problems[:ncap])],
+                    on_done=lambda n, tot, t: n % 100 == 0 and print(
+                        f"[bench] serving: burst {n}/{tot} requests done at {t:.1f} s", file=sys.stderr, flush=True))
     cap = latency_stats(burst)
     print(f"[bench] serving: capacity {cap['solves_per_s']:.2f} solves/s ({ncap} requests at once)",
           file=sys.stderr, flush=True)
@@ -386,7 +391,14 @@ def serving_bench(n_requests, gen, seed=5, local_inverse=False, loads=(0.8,), ca
         rng = np.random.default_rng(seed + 10 + k)
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
         t0 = time.perf_counter()
-        st = latency_stats(srv.run([Request(i, P, float(a)) for i, (P, a) in enumerate(zip(problems, arrivals))]))
+
+        def report(n_done, n_total, t, load=load):
+            if n_done % 200 == 0 or n_done == n_total:
+                print(f"[bench] serving: load {load}: {n_done}/{n_total} requests done at {t:.1f} s",
+                      file=sys.stderr, flush=True)
+
+        st = latency_stats(srv.run([Request(i, P, float(a)) for i, (P, a) in enumerate(zip(problems, arrivals))],
+                                   on_done=report))
         st.update({"load": load, "arrival_rate_per_s": rate, "wall_s": time.perf_counter() - t0})
         sweep.append(st)
         print(f"[bench] serving: load {load}: p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms",

@@ -25,7 +25,7 @@ import concurrent.futures as cf
 import dataclasses
 import os
 import time
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 
@@ -120,7 +120,11 @@ class Server:
         self.peak_active = 0
         self.peak_bytes = 0
 
-    def run(self, requests: List[Request]) -> List[Request]:
+    def run(self, requests: List[Request], on_done: Optional[Callable[[int, int, float], None]] = None
+            ) -> List[Request]:
+        """Serves `requests` (each admitted at its arrival time, seconds from
+        the start) to completion; returns them in completion order.
+        on_done(n_done, n_total, t) is called after each request completes."""
         # the host workers already run in parallel: BLAS inside user load
         # callbacks stays single-threaded meanwhile (no oversubscription)
         try:
@@ -131,9 +135,9 @@ class Server:
             def threadpool_limits(limits):
                 return contextlib.nullcontext()
         with threadpool_limits(limits=1):
-            return self._run(requests)
+            return self._run(requests, on_done)
 
-    def _run(self, requests: List[Request]) -> List[Request]:
+    def _run(self, requests: List[Request], on_done=None) -> List[Request]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         pool = cf.ThreadPoolExecutor(max_workers=self.setup_workers)
         t0 = time.perf_counter()
@@ -194,6 +198,8 @@ class Server:
                         active.remove(a)
                         del a.pr
                         done.append(r)
+                        if on_done is not None:
+                            on_done(len(done), len(reqs), r.t_done)
                     else:
                         a.pr.step(stream=a.stream)
                 if not progressed and not (preparing and preparing[0][1].done()):

@@ -21,7 +21,13 @@ def _run(problems, arrivals, **kw):
     from paper_1903_11357_amd.serve import Request, Server
 
     srv = Server(keep_solutions=True, check_every=8, **kw)
-    done = srv.run([Request(i, P, a) for i, (P, a) in enumerate(zip(problems, arrivals))])
+    calls = []
+    done = srv.run([Request(i, P, a) for i, (P, a) in enumerate(zip(problems, arrivals))],
+                   on_done=lambda n, tot, t: calls.append((n, tot, t)))
+    # one completion report per request, in completion order
+    assert [c[0] for c in calls] == list(range(1, len(problems) + 1))
+    assert all(c[1] == len(problems) for c in calls)
+    assert [c[2] for c in calls] == [r.t_done for r in done]
     return {r.rid: r for r in done}, srv
 
 
