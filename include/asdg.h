@@ -251,7 +251,8 @@ asdg_status asdg_apply_operator_static(asdg_problem* pb, const double* d_in, dou
 
 /* Problem sizes: info[0] = n_cells, [1] = n_p, [2] = n (DoFs), [3] = n_sub,
  * [4] = n0 (coarse DoFs), [5] = nnz blocks of A, [6] = max subdomain DoFs,
- * [7] = tile size of the local factors. */
+ * [7] = tile edge of the local factors (64 or 32, ASDG_TUNE_TILE; the
+ * coarse factor's tiles are always 64). */
 asdg_status asdg_info(const asdg_problem* pb, int64_t info[8]);
 
 /* Host copies for verification, caller layout:
@@ -316,12 +317,22 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
  * 1 = one task per tile, 2 = one work-group per block column of X (no
  * waits); 0 = automatic (2 when the largest column's products are at most
  * twice an even share). No launch shape or schedule changes the
- * arithmetic: results are identical for every setting. */
+ * arithmetic: results are identical for every setting.
+ * TILE (set before asdg_plan): edge of the packed tiles of the local
+ * Cholesky factors with the triangular sweeps (Sec. 3 local solvers):
+ * 64 or 32 rows; 0 = automatic: 64, with the factor, scratch and task
+ * buffers planned large enough for both edges, so that asdg_autotune
+ * (FACTOR | LOCAL) can time both and keep the faster. 32-row tiles pad
+ * each subdomain's ragged last tile row less, at the cost of four times
+ * the tiles and twice the sweep steps. The edge changes the blocking of
+ * the factorisation, so results of the two edges agree to rounding, not
+ * bitwise. Explicit local inverses and the coarse factor always use 64
+ * (LOCAL_INVERSE with TILE 32: EINVAL at asdg_plan). */
 enum { ASDG_TUNE_CHOL_WG_PER_CU = 0, ASDG_TUNE_TRSV_WG_PER_CU = 1, ASDG_TUNE_CHOL_GRID = 2,
        ASDG_TUNE_TRACE = 3, ASDG_TUNE_LOCAL_INVERSE = 4, ASDG_TUNE_SMALL_OFF = 5, ASDG_TUNE_NO_PRECOND = 6,
        ASDG_TUNE_INV_WG_PER_CU = 7, ASDG_TUNE_SYMV_WAVES = 8, ASDG_TUNE_TASK_CHUNK = 9,
        ASDG_TUNE_HOST_THREADS = 10, ASDG_TUNE_COARSE_PACKED = 11, ASDG_TUNE_FACTOR_SCHEDULE = 12,
-       ASDG_TUNE_INVERSE_SCHEDULE = 13 };
+       ASDG_TUNE_INVERSE_SCHEDULE = 13, ASDG_TUNE_TILE = 14 };
 asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value);
 
 /* Launch shapes chosen by asdg_autotune and the best times measured. */
@@ -333,6 +344,7 @@ typedef struct {
   int32_t from_cache; /* 1: shapes taken from the process's tuning cache, nothing timed */
   int32_t factor_schedule; /* ASDG_TUNE_FACTOR_SCHEDULE in effect (1 or 2; 0 with whole small inverses) */
   int32_t inverse_schedule; /* ASDG_TUNE_INVERSE_SCHEDULE in effect (1 or 2; 0 without tiled explicit inverses) */
+  int32_t tile; /* tile edge of the local factors in effect (64 or 32) */
 } asdg_tune_report;
 
 /* Own launch-shape autotuner (the batched factorisation and local-solve
@@ -341,10 +353,14 @@ typedef struct {
  * 20 ms, else the median of 3 to 15 runs filling about 20 ms) and keeps the
  * fastest, through the same
  * settings as asdg_set_tuning.
+ * FACTOR | LOCAL with the automatic tile edge (ASDG_TUNE_TILE 0, triangular
+ * sweeps): first the tile edge of the local factors, 64 or 32, by the time
+ * of one batched local solve (the step repeated every iteration; each edge
+ * factorised once with default shapes); then the shapes below for that edge.
  * ASDG_AUTOTUNE_FACTOR (after asdg_bind): the Cholesky schedule
  * (FACTOR_SCHEDULE 1, 2), with explicit inverses the schedule of
  * X = L^{-1} (INVERSE_SCHEDULE 1, 2), work-groups per compute unit of
- * the Cholesky launch (1, 2), the task order
+ * the Cholesky launch (1, 2 with 64-row tiles; 4, 8 with 32-row tiles), the task order
  * (TASK_CHUNK 0, and 64 when there are more than 64 subdomains) and, with explicit inverses,
  * work-groups per compute unit of the inverse formation (1-4 FP32, 1-2
  * FP64); runs asdg_factor up to 15 times per candidate and leaves the
@@ -358,9 +374,10 @@ typedef struct {
  * Results of a FACTOR | LOCAL run are kept in a process-wide cache keyed
  * by device architecture, precision, local-solve representation and size
  * class (subdomain count to a power of two, largest and mean tile rows per
- * subdomain). With ASDG_AUTOTUNE_REUSE and a cache hit nothing is timed:
- * the cached shapes are applied (and asdg_factor run once for FACTOR) and
- * rep->from_cache is 1.
+ * subdomain, in 64-row units). With ASDG_AUTOTUNE_REUSE and a cache hit
+ * nothing is timed: the cached shapes are applied (with FACTOR also the
+ * cached tile edge, when the plan has room for both, and asdg_factor run
+ * once) and rep->from_cache is 1.
  * Errors: EINVAL (flags), ESTATE (stage, or a solve in progress), EHIP,
  * and those of asdg_factor. */
 enum { ASDG_AUTOTUNE_FACTOR = 1, ASDG_AUTOTUNE_LOCAL = 2, ASDG_AUTOTUNE_REUSE = 4 };
@@ -369,8 +386,9 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
 /* The tuning cache as text, one line per size class (key, then Cholesky,
  * inverse-formation and sweep work-groups per CU, packed-apply waves,
  * task-order chunk, best factorisation and local-solve ms, Cholesky and
- * inverse-formation schedules; lines of older files without the last one
- * or two fields load with those automatic). save writes
+ * inverse-formation schedules, tile edge; lines of older files without the
+ * last one to three fields load with automatic schedules and 64-row
+ * tiles). save writes
  * the whole cache (EINVAL if the file cannot be written); load adds the
  * entries of a file written by save (n_entries: how many; EINVAL and
  * nothing added if it cannot be read or a line is malformed). Both are

@@ -52,7 +52,7 @@ class TuneReport(C.Structure):
                 ("symv_waves", C.c_int32), ("task_chunk", C.c_int32), ("factor_ms", C.c_double),
                 ("local_ms", C.c_double),
                 ("candidates", C.c_int32), ("from_cache", C.c_int32), ("factor_schedule", C.c_int32),
-                ("inverse_schedule", C.c_int32)]
+                ("inverse_schedule", C.c_int32), ("tile", C.c_int32)]
 
 
 class TetMesh_(C.Structure):
@@ -103,7 +103,7 @@ _SIGS = {
 }
 TUNE_CHOL_WG_PER_CU, TUNE_TRSV_WG_PER_CU, TUNE_CHOL_GRID, TUNE_TRACE, TUNE_LOCAL_INVERSE, TUNE_SMALL_OFF, \
     TUNE_NO_PRECOND, TUNE_INV_WG_PER_CU, TUNE_SYMV_WAVES, TUNE_TASK_CHUNK, TUNE_HOST_THREADS, TUNE_COARSE_PACKED, \
-    TUNE_FACTOR_SCHEDULE, TUNE_INVERSE_SCHEDULE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13
+    TUNE_FACTOR_SCHEDULE, TUNE_INVERSE_SCHEDULE, TUNE_TILE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14
 AUTOTUNE_FACTOR, AUTOTUNE_LOCAL, AUTOTUNE_REUSE = 1, 2, 4
 LOCAL_SWEEPS, LOCAL_INVERSE, LOCAL_SMALL = 0, 1, 2
 
@@ -392,16 +392,19 @@ def tune_cache_load(path: str) -> int:
     return int(n.value)
 
 
-def setup_problem(P, precision=FP64, device="cuda", factor=True, local_inverse=False, small=True):
+def setup_problem(P, precision=FP64, device="cuda", factor=True, local_inverse=False, small=True, tile=0):
     """Assemble + plan (+ bind/factor/coarse if a device is given) for an
     ``inputs.Problem``. small=False keeps subdomains of <= 64 DoFs on the
-    tile path."""
+    tile path; tile: edge of the local factor tiles with the sweeps (0
+    automatic, 32 or 64)."""
     pr = Problem()
     pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
     if local_inverse:
         pr.set_tuning(TUNE_LOCAL_INVERSE, 1)
     if not small:
         pr.set_tuning(TUNE_SMALL_OFF, 1)
+    if tile:
+        pr.set_tuning(TUNE_TILE, tile)
     pr.plan(precision, P.q, coarse_of_cell=P.coarse_of_cell if P.coarse_mesh is None else None,
             coarse_mesh=P.coarse_mesh)
     if device is not None:

@@ -140,6 +140,9 @@ struct asdg_problem {
   int32_t n0 = 0;
   std::vector<double> rhs_caller;
   // local factor planning
+  int tile = TILE;        // tile edge of the local factors (64 or 32; the coarse factor always TILE)
+  int tile_req = 0;       // ASDG_TUNE_TILE: 0 automatic (64, the autotuner may switch), 32 or 64 fixed
+  bool tile_search = false;  // buffers planned for both edges (the autotuner may switch the layout)
   std::vector<SubDesc> subs;
   std::vector<int4> tile_meta, chol_tasks, trsv_tasks;
   int64_t n_tiles = 0;
@@ -395,6 +398,18 @@ static std::vector<int4> order_col_tasks(const std::vector<SubDesc>& subs, int c
   return out;
 }
 
+// Stored tiles and sweep tasks of the local tile layout with edge t.
+void local_counts(const asdg_problem* pb, int t, int64_t& tiles, int64_t& sweeps) {
+  tiles = 0;
+  sweeps = 0;
+  for (int32_t i = 0; i < pb->A.n_sub; ++i) {
+    const int64_t n = (int64_t)(pb->A.sub_ptr[i + 1] - pb->A.sub_ptr[i]) * pb->A.np;
+    const int64_t nb = (n + t - 1) / t;
+    tiles += nb * (nb + 1) / 2;
+    sweeps += 2 * nb;
+  }
+}
+
 void plan_local(asdg_problem* pb) {
   const Assembled& A = pb->A;
   const int np = A.np;
@@ -407,7 +422,7 @@ void plan_local(asdg_problem* pb) {
     SubDesc& s = pb->subs[i];
     s.dof0 = A.sub_ptr[i] * np;
     s.n = (A.sub_ptr[i + 1] - A.sub_ptr[i]) * np;
-    s.nb = (s.n + TILE - 1) / TILE;
+    s.nb = (s.n + pb->tile - 1) / pb->tile;
     s.tile0 = (int32_t)tiles;
     tiles += (int64_t)s.nb * (s.nb + 1) / 2;
     nbmax = std::max(nbmax, s.nb);
@@ -435,7 +450,7 @@ void plan_local(asdg_problem* pb) {
   for (int32_t i = 0; i < ns; ++i)
     for (int b = 0; b < pb->subs[i].nb; ++b)
       for (int j = 0; j <= b; ++j)  // w: rows of tile row b inside the subdomain
-        pb->tile_meta.push_back(make_int4(i, b, j, std::min(TILE, pb->subs[i].n - TILE * b)));
+        pb->tile_meta.push_back(make_int4(i, b, j, std::min(pb->tile, pb->subs[i].n - pb->tile * b)));
   // factorisation tasks (i, j, b): longest path to the end first (ties by
   // subdomain, column, row); every dependency has a strictly longer path, so
   // it precedes its consumers in the queue
@@ -542,7 +557,7 @@ asdg_status enqueue_coarse_solve(asdg_problem* pb, const DevState* st_done, hipS
   }
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   const int cgrid = (int)std::min<int64_t>((int64_t)pb->ctrsv_tasks.size(), (int64_t)pb->n_cu);
-  HIPCHK(pb, launch_trsv(0, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
+  HIPCHK(pb, launch_trsv(0, TILE, (int32_t)pb->ctrsv_tasks.size(), pb->ptr<int4>(2, pb->o2.ctrsv),
                          pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles),
                          pb->ptr<double>(3, pb->o3.r0), pb->ptr<void>(3, pb->o3.y0), pb->ptr<void>(3, pb->o3.z0), st,
                          &st->q_coarse, cgrid, nullptr, s));
@@ -570,7 +585,7 @@ asdg_status enqueue_local(asdg_problem* pb, hipStream_t s, const DevState* st_do
   } else {
     const int lgrid = (int)std::min<int64_t>((int64_t)pb->trsv_tasks.size(),
                                              (int64_t)pb->n_cu * (pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2));
-    HIPCHK(pb, launch_trsv(pb->f32, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
+    HIPCHK(pb, launch_trsv(pb->f32, pb->tile, (int32_t)pb->trsv_tasks.size(), pb->ptr<int4>(1, pb->o1.trsv),
                            pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), r,
                            pb->ptr<void>(3, pb->o3.yl), pb->ptr<void>(3, pb->o3.zl), st, &st->q_local, lgrid,
                            pb->trace ? pb->ptr<uint64_t>(3, pb->o3.trace) : nullptr, s));
@@ -905,8 +920,26 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
     plan_coarse_factor(pb);
     pb->t_coarse_host_ms = wall_ms() - tc;
   }
+  if (pb->local_inverse && pb->tile_req == 32)
+    FAIL(pb, ASDG_EINVAL, "explicit local inverses are stored in 64-row tiles (ASDG_TUNE_TILE 32 needs the sweeps)");
+  pb->tile = pb->tile_req ? pb->tile_req : TILE;
   plan_local(pb);
   pb->inv_planned = pb->local_inverse && !pb->small;
+  // with the automatic edge, room for the layouts of both edges (the 32-row
+  // layout never stores more tile words, it has more tiles and tasks), so
+  // that the autotuner can switch between them in the bound buffers
+  pb->tile_search = pb->tile_req == 0 && !pb->inv_planned && !pb->small;
+  int64_t res_tiles = pb->n_tiles, res_sweeps = (int64_t)pb->trsv_tasks.size();
+  int64_t res_words = pb->n_tiles * pb->tile * pb->tile;
+  if (pb->tile_search) {
+    for (int t : {32, 64}) {
+      int64_t nt = 0, ns = 0;
+      local_counts(pb, t, nt, ns);
+      res_tiles = std::max(res_tiles, nt);
+      res_sweeps = std::max(res_sweeps, ns);
+      res_words = std::max(res_words, nt * t * t);
+    }
+  }
   pb->inv_tasks.clear();
   if (pb->inv_planned) {
     // X = L^{-1} tasks (i, j, b), j <= b: longest path to the end first, so
@@ -927,11 +960,11 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o0.rhs = L0.add(8 * n);
   pb->o0.perm = L0.add(4 * N);
   pb->o0.cell_sub = L0.add(4 * N);
-  pb->o1.tiles = L1.add(pb->small ? (size_t)pb->small_words * w : (size_t)pb->n_tiles * TILE * TILE * w);
+  pb->o1.tiles = L1.add(pb->small ? (size_t)pb->small_words * w : (size_t)res_words * w);
   pb->o1.subs = L1.add(sizeof(SubDesc) * pb->subs.size());
-  pb->o1.chol = L1.add(sizeof(int4) * pb->chol_tasks.size());
-  pb->o1.trsv = L1.add(sizeof(int4) * pb->trsv_tasks.size());
-  pb->o1.meta = L1.add(sizeof(int4) * pb->tile_meta.size());
+  pb->o1.chol = L1.add(sizeof(int4) * (size_t)res_tiles);
+  pb->o1.trsv = L1.add(sizeof(int4) * (size_t)res_sweeps);
+  pb->o1.meta = L1.add(sizeof(int4) * (size_t)res_tiles);
   if (pb->inv_planned) {
     pb->o1.xtiles = L1.add((size_t)pb->n_tiles * TILE * TILE * w);
     pb->o1.inv = L1.add(sizeof(int4) * pb->inv_tasks.size());
@@ -977,8 +1010,8 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   pb->o3.rz2 = L3.add(16);
   pb->o3.ah = L3.add(8 * (size_t)HIST);
   pb->o3.bh = L3.add(8 * (size_t)HIST);
-  pb->o3.flags = L3.add(4 * (size_t)std::max<int64_t>(pb->n_tiles, pb->n_ctiles));
-  pb->o3.trace = L3.add(3 * 8 * pb->trsv_tasks.size());
+  pb->o3.flags = L3.add(4 * (size_t)std::max<int64_t>(res_tiles, pb->n_ctiles));
+  pb->o3.trace = L3.add(3 * 8 * (size_t)res_sweeps);
   pb->o3.part = L3.add(pb->inv_planned ? (size_t)pb->n_tiles * 2 * TILE * w : 0);
   pb->bytes[0] = L0.size;
   pb->bytes[1] = L1.size;
@@ -1073,6 +1106,11 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
 // Cholesky: subdomain tasks when the largest subdomain (about nb^3/6 tile
 // products) is at most 1.5 times that share (measured on 512 subdomains
 // whose largest is 1.65 times the mean: the tile tasks are 6% faster).
+// Work-groups per compute unit of the Cholesky launch by default: the
+// kernel's occupancy (eight waves per CU: two work-groups of four waves for
+// 64-row tiles, eight of one wave for 32-row tiles).
+static int chol_occupancy(int tile) { return tile == 32 ? 8 : 2; }
+
 static int factor_schedule(const asdg_problem* pb) {
   if (pb->factor_sched == 1 || pb->factor_sched == 2) return pb->factor_sched;
   double total = 0.0, largest = 0.0;
@@ -1081,7 +1119,7 @@ static int factor_schedule(const asdg_problem* pb) {
     total += w;
     largest = std::max(largest, w);
   }
-  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
+  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : chol_occupancy(pb->tile);
   const double slots = (double)pb->n_cu * per_cu;
   return largest <= 1.5 * total / slots ? 2 : 1;
 }
@@ -1103,16 +1141,16 @@ static int inverse_schedule(const asdg_problem* pb) {
   return largest <= 2.0 * total / slots ? 2 : 1;
 }
 
-static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int per_sub, int32_t n_tasks,
+static asdg_status run_cholesky(asdg_problem* pb, hipStream_t s, int f32, int tile, int per_sub, int32_t n_tasks,
                                 const int4* tasks, const SubDesc* subs, void* tiles, int64_t n_tiles, int coarse) {
   DevState* st = pb->ptr<DevState>(3, pb->o3.st);
   int32_t* flags = pb->ptr<int32_t>(3, pb->o3.flags);
   if (!per_sub) HIPCHK(pb, launch_fill_i32(flags, n_tiles, 0, s));
   HIPCHK(pb, launch_reset_queues(st, s));
-  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;  // the kernel's occupancy (registers)
+  const int per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : chol_occupancy(tile);
   int64_t gmax = pb->chol_grid > 0 ? pb->chol_grid : (int64_t)pb->n_cu * per_cu;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_tasks, gmax));
-  HIPCHK(pb, launch_cholesky(f32, per_sub, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
+  HIPCHK(pb, launch_cholesky(f32, tile, per_sub, n_tasks, tasks, subs, tiles, flags, st, &st->q_chol, grid, s));
   DevState h;
   asdg_status e = read_state(pb, s, h);
   if (e != ASDG_OK) return e;
@@ -1161,15 +1199,17 @@ asdg_status asdg_factor(asdg_problem* pb, void* stream) {
     }
     pb->tasks_dirty = false;
   }
-  HIPCHK(pb, launch_gather_tiles(pb->A.np, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
+  HIPCHK(pb, launch_gather_tiles(pb->A.np, pb->tile, (int32_t)pb->n_tiles, pb->ptr<int4>(1, pb->o1.meta),
                                  pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<int32_t>(0, pb->o0.row_ptr),
                                  pb->ptr<int32_t>(0, pb->o0.col), pb->ptr<double>(0, pb->o0.blocks),
                                  pb->ptr<void>(1, pb->o1.tiles), pb->f32, s));
   const bool per_sub = factor_schedule(pb) == 2;
-  asdg_status e = per_sub ? run_cholesky(pb, s, pb->f32, 1, (int32_t)pb->sub_tasks.size(), pb->ptr<int4>(1, pb->o1.subt),
-                                         pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0)
-                          : run_cholesky(pb, s, pb->f32, 0, (int32_t)pb->chol_tasks.size(), pb->ptr<int4>(1, pb->o1.chol),
-                                         pb->ptr<SubDesc>(1, pb->o1.subs), pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0);
+  asdg_status e = per_sub ? run_cholesky(pb, s, pb->f32, pb->tile, 1, (int32_t)pb->sub_tasks.size(),
+                                         pb->ptr<int4>(1, pb->o1.subt), pb->ptr<SubDesc>(1, pb->o1.subs),
+                                         pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0)
+                          : run_cholesky(pb, s, pb->f32, pb->tile, 0, (int32_t)pb->chol_tasks.size(),
+                                         pb->ptr<int4>(1, pb->o1.chol), pb->ptr<SubDesc>(1, pb->o1.subs),
+                                         pb->ptr<void>(1, pb->o1.tiles), pb->n_tiles, 0);
   if (e != ASDG_OK) return e;
   if (pb->inv_planned) {
     DevState* st = pb->ptr<DevState>(3, pb->o3.st);
@@ -1206,7 +1246,7 @@ asdg_status asdg_setup_coarse(asdg_problem* pb, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(pb, hipMemcpyAsync(pb->buf[2] + pb->o2.ctiles, pb->ctiles_host.data(), 8 * pb->ctiles_host.size(),
                             hipMemcpyHostToDevice, s));
-  asdg_status e = run_cholesky(pb, s, 0, 0, (int32_t)pb->cchol_tasks.size(), pb->ptr<int4>(2, pb->o2.cchol),
+  asdg_status e = run_cholesky(pb, s, 0, TILE, 0, (int32_t)pb->cchol_tasks.size(), pb->ptr<int4>(2, pb->o2.cchol),
                                pb->ptr<SubDesc>(2, pb->o2.csub), pb->ptr<void>(2, pb->o2.ctiles), pb->n_ctiles, 1);
   if (e != ASDG_OK) return e;
   if (pb->coarse_dense) {
@@ -1392,7 +1432,7 @@ asdg_status asdg_info(const asdg_problem* pb, int64_t info[8]) {
   info[4] = pb->n0;
   info[5] = pb->A.row_ptr.empty() ? 0 : pb->A.row_ptr.back();
   info[6] = pb->max_n;
-  info[7] = TILE;
+  info[7] = pb->tile;
   return ASDG_OK;
 }
 
@@ -1449,8 +1489,8 @@ asdg_status asdg_export_factor_tiles(asdg_problem* pb, int32_t sub, void* out, s
       src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * w;
       nbytes = (size_t)d.n * d.n * w;
     } else {
-      src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * TILE * TILE * w;
-      nbytes = (size_t)d.nb * (d.nb + 1) / 2 * TILE * TILE * w;
+      src = pb->buf[1] + pb->o1.tiles + (size_t)d.tile0 * pb->tile * pb->tile * w;
+      nbytes = (size_t)d.nb * (d.nb + 1) / 2 * pb->tile * pb->tile * w;
     }
   }
   if (out_bytes < nbytes) FAIL(pb, ASDG_ENOMEM, "output too small");
@@ -1517,6 +1557,10 @@ asdg_status asdg_set_tuning(asdg_problem* pb, int32_t what, int32_t value) {
       if (pb->stage >= 3) pb->tasks_dirty = true;  // uploaded by the next asdg_factor
     }
   }
+  else if (what == ASDG_TUNE_TILE) {
+    if (value != 0 && value != 32 && value != 64) FAIL(pb, ASDG_EINVAL, "tile edge: 0 automatic, 32 or 64");
+    pb->tile_req = value;  // takes effect at the next asdg_plan
+  }
   else if (what == ASDG_TUNE_SYMV_WAVES) {
     if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
       FAIL(pb, ASDG_EINVAL, "waves per work-group of the packed apply must be 1, 2, 4 or 8");
@@ -1534,11 +1578,13 @@ std::mutex g_tune_mu;
 std::map<std::string, asdg_tune_report> g_tune_cache;
 
 std::string tune_key(const asdg_problem* pb) {
+  // tile rows counted in 64-row units whatever the current layout's edge
   double nb_sum = 0.0;
   int nb_max = 0;
   for (const SubDesc& d : pb->subs) {
-    nb_sum += d.nb;
-    nb_max = std::max(nb_max, d.nb);
+    const int nb = (d.n + TILE - 1) / TILE;
+    nb_sum += nb;
+    nb_max = std::max(nb_max, nb);
   }
   const int ns = (int)pb->subs.size();
   int ns_log2 = 0;
@@ -1548,6 +1594,29 @@ std::string tune_key(const asdg_problem* pb) {
                 pb->f32 ? "fp32" : "fp64", pb->inv_planned ? "inverse" : "sweeps", ns_log2, nb_max,
                 (int)std::lround(nb_sum / std::max(ns, 1)));
   return k;
+}
+// Switches the local factors to tiles of edge `tile` inside the bound
+// buffers (planned for both edges: tile_search): new task lists, tile
+// metadata and subdomain descriptors, uploaded on `s`. The factors must be
+// formed again (stage 3).
+asdg_status relayout_local(asdg_problem* pb, int tile, hipStream_t s) {
+  if (tile == pb->tile) return ASDG_OK;
+  if (!pb->tile_search) FAIL(pb, ASDG_ESTATE, "the plan has room for one tile edge only");
+  pb->tile = tile;
+  plan_local(pb);
+  auto up = [&](size_t off, const void* src, size_t nbytes) {
+    return nbytes ? hipMemcpyAsync(pb->buf[1] + off, src, nbytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  HIPCHK(pb, up(pb->o1.subs, pb->subs.data(), sizeof(SubDesc) * pb->subs.size()));
+  HIPCHK(pb, up(pb->o1.chol, pb->chol_tasks.data(), sizeof(int4) * pb->chol_tasks.size()));
+  HIPCHK(pb, up(pb->o1.trsv, pb->trsv_tasks.data(), sizeof(int4) * pb->trsv_tasks.size()));
+  HIPCHK(pb, up(pb->o1.meta, pb->tile_meta.data(), sizeof(int4) * pb->tile_meta.size()));
+  HIPCHK(pb, up(pb->o1.subt, pb->sub_tasks.data(), sizeof(int4) * pb->sub_tasks.size()));
+  HIPCHK(pb, hipStreamSynchronize(s));  // the host lists may change again before the copies complete
+  pb->tasks_dirty = false;
+  pb->drop_graph();
+  if (pb->stage > 3) pb->stage = 3;
+  return ASDG_OK;
 }
 }  // namespace
 
@@ -1581,6 +1650,10 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     }
     if (hit) {
       // the shapes found before for this size class, no timing
+      if ((what & ASDG_AUTOTUNE_FACTOR) && pb->tile_search && C.tile != pb->tile) {
+        asdg_status e = relayout_local(pb, C.tile, s);
+        if (e != ASDG_OK) return e;
+      }
       if (what & ASDG_AUTOTUNE_FACTOR) {
         pb->factor_sched = C.factor_schedule;
         pb->inv_sched = C.inverse_schedule;
@@ -1603,6 +1676,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
       pb->drop_graph();
       C.candidates = 0;
       C.from_cache = 1;
+      C.tile = pb->tile;
       if (rep) *rep = C;
       return ASDG_OK;
     }
@@ -1661,6 +1735,44 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     *knob = best;
     return ASDG_OK;
   };
+  // one timed batched local solve (input: zeros permuted into r, which also
+  // sets the sweeps' not-yet-written markers)
+  double* qz = pb->ptr<double>(3, pb->o3.q);
+  DevState* stl = pb->ptr<DevState>(3, pb->o3.st);
+  auto time_local = [&](float& ms) -> asdg_status {
+    HIPCHK(pb, launch_permute_in(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm), qz,
+                                 pb->ptr<double>(3, pb->o3.r), nullptr, pb->ptr<void>(3, pb->o3.yl),
+                                 pb->ptr<void>(3, pb->o3.zl), pb->f32, nullptr, nullptr, 0.0, 0, s));
+    HIPCHK(pb, launch_reset_queues(stl, s));
+    HIPCHK(pb, hipEventRecord(e0, s));
+    asdg_status e = enqueue_local(pb, s, nullptr);
+    if (e != ASDG_OK) return e;
+    HIPCHK(pb, hipEventRecord(e1, s));
+    HIPCHK(pb, hipEventSynchronize(e1));
+    HIPCHK(pb, hipEventElapsedTime(&ms, e0, e1));
+    return ASDG_OK;
+  };
+  if ((what & ASDG_AUTOTUNE_LOCAL) && !pb->small) HIPCHK(pb, hipMemsetAsync(qz, 0, sizeof(double) * pb->n(), s));
+  if ((what & ASDG_AUTOTUNE_FACTOR) && (what & ASDG_AUTOTUNE_LOCAL) && pb->tile_search) {
+    // the tile edge first (64 or 32 rows; the padding of each subdomain's
+    // last tile row against the number of tiles and sweep steps), by the
+    // time of one batched local solve, the step repeated every iteration;
+    // each edge is factorised once with the default launch shapes
+    int tile = pb->tile;
+    auto time_tile = [&](float& ms) -> asdg_status {
+      if (tile != pb->tile || pb->stage < 4) {
+        asdg_status e = relayout_local(pb, tile, s);
+        if (e == ASDG_OK) e = asdg_factor(pb, stream);
+        if (e != ASDG_OK) return e;
+      }
+      return time_local(ms);
+    };
+    double ms = 0.0;
+    asdg_status e = tune(&tile, {TILE, 32}, time_tile, ms);
+    if (e != ASDG_OK) return e;
+    e = relayout_local(pb, tile, s);  // factorised again below with the tuned shapes
+    if (e != ASDG_OK) return e;
+  }
   if ((what & ASDG_AUTOTUNE_FACTOR) && !pb->small) {
     double ms = 0.0;
     // the schedules first (tile tasks, or one work-group per subdomain / column)
@@ -1670,7 +1782,7 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
       e = tune(&pb->inv_sched, {1, 2}, time_factor, ms);
       if (e != ASDG_OK) return e;
     }
-    e = tune(&pb->chol_per_cu, {1, 2}, time_factor, ms);
+    e = tune(&pb->chol_per_cu, pb->tile == 32 ? std::vector<int>{4, 8} : std::vector<int>{1, 2}, time_factor, ms);
     if (e != ASDG_OK) return e;
     {
       // task order: all subdomains interleaved, or in groups (smaller working set)
@@ -1701,23 +1813,6 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     R.factor_ms = ms;
   }
   if ((what & ASDG_AUTOTUNE_LOCAL) && !pb->small) {
-    // input: zeros permuted into r (this also sets the sweeps' not-yet-written markers)
-    double* q = pb->ptr<double>(3, pb->o3.q);
-    DevState* st = pb->ptr<DevState>(3, pb->o3.st);
-    HIPCHK(pb, hipMemsetAsync(q, 0, sizeof(double) * pb->n(), s));
-    auto time_local = [&](float& ms) -> asdg_status {
-      HIPCHK(pb, launch_permute_in(pb->A.np, pb->A.n_cells, pb->ptr<int32_t>(0, pb->o0.perm), q,
-                                   pb->ptr<double>(3, pb->o3.r), nullptr, pb->ptr<void>(3, pb->o3.yl),
-                                   pb->ptr<void>(3, pb->o3.zl), pb->f32, nullptr, nullptr, 0.0, 0, s));
-      HIPCHK(pb, launch_reset_queues(st, s));
-      HIPCHK(pb, hipEventRecord(e0, s));
-      asdg_status e = enqueue_local(pb, s, nullptr);
-      if (e != ASDG_OK) return e;
-      HIPCHK(pb, hipEventRecord(e1, s));
-      HIPCHK(pb, hipEventSynchronize(e1));
-      HIPCHK(pb, hipEventElapsedTime(&ms, e0, e1));
-      return ASDG_OK;
-    };
     double ms = 0.0;
     asdg_status e = pb->inv_planned ? tune(&pb->symv_waves, {1, 2, 4, 8}, time_local, ms)
                                     : tune(&pb->trsv_per_cu, {1, 2, 3, 4}, time_local, ms);
@@ -1728,7 +1823,8 @@ asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tun
     if (h.abort) FAIL(pb, ASDG_EHIP, "local solve wait budget exhausted during autotuning");
     R.local_ms = ms;
   }
-  R.chol_wg_per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : 2;
+  R.chol_wg_per_cu = pb->chol_per_cu > 0 ? pb->chol_per_cu : chol_occupancy(pb->tile);
+  R.tile = pb->tile;
   R.inv_wg_per_cu = pb->inv_per_cu > 0 ? pb->inv_per_cu : (pb->f32 ? 4 : 2);
   R.trsv_wg_per_cu = pb->trsv_per_cu > 0 ? pb->trsv_per_cu : 2;
   R.symv_waves = pb->symv_waves > 0 ? pb->symv_waves : 4;
@@ -1751,9 +1847,9 @@ asdg_status asdg_tune_cache_save(const char* path) {
   if (!f) return ASDG_EINVAL;
   for (const auto& kv : g_tune_cache) {
     const asdg_tune_report& R = kv.second;
-    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f %d %d\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
+    std::fprintf(f, "%s %d %d %d %d %d %.6f %.6f %d %d %d\n", kv.first.c_str(), R.chol_wg_per_cu, R.inv_wg_per_cu,
                  R.trsv_wg_per_cu, R.symv_waves, R.task_chunk, R.factor_ms, R.local_ms, R.factor_schedule,
-                 R.inverse_schedule);
+                 R.inverse_schedule, R.tile);
   }
   return std::fclose(f) == 0 ? ASDG_OK : ASDG_EINVAL;
 }
@@ -1767,18 +1863,21 @@ asdg_status asdg_tune_cache_load(const char* path, int32_t* n_entries) {
   char line[512];
   asdg_tune_report R;
   bool ok = true;
-  // one entry per line; the two schedules (last fields) may be missing in
-  // files written before they existed (then: automatic)
+  // one entry per line; the two schedules and the tile edge (last fields)
+  // may be missing in files written before they existed (then: automatic,
+  // and 64-row tiles)
   while (std::fgets(line, sizeof(line), f)) {
     std::memset(&R, 0, sizeof(R));
-    const int got = std::sscanf(line, "%255s %d %d %d %d %d %lf %lf %d %d", key, &R.chol_wg_per_cu,
+    R.tile = TILE;
+    const int got = std::sscanf(line, "%255s %d %d %d %d %d %lf %lf %d %d %d", key, &R.chol_wg_per_cu,
                                 &R.inv_wg_per_cu, &R.trsv_wg_per_cu, &R.symv_waves, &R.task_chunk, &R.factor_ms,
-                                &R.local_ms, &R.factor_schedule, &R.inverse_schedule);
+                                &R.local_ms, &R.factor_schedule, &R.inverse_schedule, &R.tile);
     if (got <= 0) continue;  // blank line
     const bool waves_ok = R.symv_waves == 1 || R.symv_waves == 2 || R.symv_waves == 4 || R.symv_waves == 8;
     if (got < 8 || !waves_ok || R.chol_wg_per_cu < 1 || R.chol_wg_per_cu > 64 || R.inv_wg_per_cu < 1 ||
         R.inv_wg_per_cu > 64 || R.trsv_wg_per_cu < 1 || R.trsv_wg_per_cu > 64 || R.task_chunk < 0 ||
-        R.factor_schedule < 0 || R.factor_schedule > 2 || R.inverse_schedule < 0 || R.inverse_schedule > 2) {
+        R.factor_schedule < 0 || R.factor_schedule > 2 || R.inverse_schedule < 0 || R.inverse_schedule > 2 ||
+        (R.tile != 32 && R.tile != TILE)) {
       ok = false;
       break;
     }

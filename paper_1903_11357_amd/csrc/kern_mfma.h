@@ -1,6 +1,7 @@
 // MFMA tile helpers shared by the factorisation kernels (gfx950, wave64).
-// A work-group of four waves owns a TILE x TILE tile; wave w owns the 32x32
-// quadrant at rows 32*(w/2), columns 32*(w%2).
+// A work-group owns one TB x TB tile (TB = 64 or 32) with one wave per 32x32
+// quadrant: four waves for TB = 64 (wave w at rows 32*(w/2), columns
+// 32*(w%2)), a single wave for TB = 32.
 #pragma once
 
 #include "kern_common.h"
@@ -9,6 +10,17 @@ namespace asdg {
 namespace mfma {
 
 constexpr int LDA = TILE + 1;  // padded LDS row (bank spread for column reads)
+
+// Work-group shape for a TB x TB tile: one wave per 32x32 quadrant.
+template <int TB>
+struct Shape {
+  static_assert(TB == 32 || TB == 64, "tile edge 32 or 64");
+  static constexpr int LD = TB + 1;                 // padded LDS row
+  static constexpr int QPR = TB / 32;               // quadrants per tile row
+  static constexpr int THREADS = 64 * QPR * QPR;    // one wave per quadrant
+  __device__ static int r0(int wave) { return 32 * (wave / QPR); }
+  __device__ static int c0(int wave) { return 32 * (wave % QPR); }
+};
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -29,12 +41,15 @@ struct Quad<float> {
   __device__ static int col(int e, int lane) { return lane & 31; }
   __device__ float get(int e) const { return c[e]; }
   __device__ void set(int e, float v) { c[e] = v; }
-  // c += sign * A[R0.., :] * B[C0.., :]^T with A, B in LDS (row-major, LDA)
+  // c += sign * A[R0.., :] * B[C0.., :]^T with A, B in LDS (row-major, row
+  // pitch TB + 1, TB columns)
+  template <int TB = TILE>
   __device__ void mma(const float* A, const float* B, int R0, int C0, int lane, float sign) {
-    const float* a = A + (R0 + (lane & 31)) * LDA + (lane >> 5);
-    const float* b = B + (C0 + (lane & 31)) * LDA + (lane >> 5);
+    constexpr int LD = TB + 1;
+    const float* a = A + (R0 + (lane & 31)) * LD + (lane >> 5);
+    const float* b = B + (C0 + (lane & 31)) * LD + (lane >> 5);
 #pragma unroll 8
-    for (int k0 = 0; k0 < TILE; k0 += 2) c = __builtin_amdgcn_mfma_f32_32x32x2f32(sign * a[k0], b[k0], c, 0, 0, 0);
+    for (int k0 = 0; k0 < TB; k0 += 2) c = __builtin_amdgcn_mfma_f32_32x32x2f32(sign * a[k0], b[k0], c, 0, 0, 0);
   }
 };
 
@@ -52,13 +67,15 @@ struct Quad<double> {
   __device__ static int col(int e, int lane) { return 16 * ((e >> 2) & 1) + (lane & 15); }
   __device__ double get(int e) const { return c[e >> 2][e & 3]; }
   __device__ void set(int e, double v) { c[e >> 2][e & 3] = v; }
+  template <int TB = TILE>
   __device__ void mma(const double* A, const double* B, int R0, int C0, int lane, double sign) {
-    const double* a0 = A + (R0 + (lane & 15)) * LDA + (lane >> 4);
-    const double* a1 = a0 + 16 * LDA;
-    const double* b0 = B + (C0 + (lane & 15)) * LDA + (lane >> 4);
-    const double* b1 = b0 + 16 * LDA;
+    constexpr int LD = TB + 1;
+    const double* a0 = A + (R0 + (lane & 15)) * LD + (lane >> 4);
+    const double* a1 = a0 + 16 * LD;
+    const double* b0 = B + (C0 + (lane & 15)) * LD + (lane >> 4);
+    const double* b1 = b0 + 16 * LD;
 #pragma unroll 4
-    for (int k0 = 0; k0 < TILE; k0 += 4) {
+    for (int k0 = 0; k0 < TB; k0 += 4) {
       const double x0 = sign * a0[k0], x1 = sign * a1[k0];
       const double y0 = b0[k0], y1 = b1[k0];
       c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c[0], 0, 0, 0);
@@ -96,44 +113,45 @@ __device__ __forceinline__ void wait_flag(const int32_t* f, DevState* st) {
   __syncthreads();
 }
 
-// A tile (global, row-major TILE x TILE) held in registers by a work-group
-// of 256 threads: thread t keeps elements t + 256 i, i < 16. Loading the
-// next operands into registers before the MFMA work on the current ones
-// overlaps global latency with compute.
-template <typename T>
+// A tile (global, row-major TB x TB) held in registers by the NT threads of
+// a work-group: thread t keeps elements t + NT i, i < TB * TB / NT (16 for
+// both tile shapes). Loading the next operands into registers before the
+// MFMA work on the current ones overlaps global latency with compute.
+template <typename T, int TB = TILE, int NT = Shape<TB>::THREADS>
 struct TileRegs {
-  static constexpr int N = TILE * TILE / 256;
+  static constexpr int N = TB * TB / NT;
+  static constexpr int LD = TB + 1;
   T v[N];
   __device__ void load(const T* g) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = g[threadIdx.x + 256 * i];
+    for (int i = 0; i < N; ++i) v[i] = g[threadIdx.x + NT * i];
   }
   __device__ void load_coherent(const T* g) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = load_agent(g + threadIdx.x + 256 * i);
+    for (int i = 0; i < N; ++i) v[i] = load_agent(g + threadIdx.x + NT * i);
   }
   __device__ void store(T* g) const {
 #pragma unroll
-    for (int i = 0; i < N; ++i) g[threadIdx.x + 256 * i] = v[i];
+    for (int i = 0; i < N; ++i) g[threadIdx.x + NT * i] = v[i];
   }
   __device__ void store_coherent(T* g) const {
 #pragma unroll
-    for (int i = 0; i < N; ++i) store_agent(g + threadIdx.x + 256 * i, v[i]);
+    for (int i = 0; i < N; ++i) store_agent(g + threadIdx.x + NT * i, v[i]);
   }
   // s[r][c] = g[r][c]
   __device__ void put(T* s) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      s[(e / TILE) * LDA + (e % TILE)] = v[i];
+      const int e = threadIdx.x + NT * i;
+      s[(e / TB) * LD + (e % TB)] = v[i];
     }
   }
   // s[c][r] = g[r][c]
   __device__ void put_t(T* s) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      s[(e % TILE) * LDA + (e / TILE)] = v[i];
+      const int e = threadIdx.x + NT * i;
+      s[(e % TB) * LD + (e / TB)] = v[i];
     }
   }
 };

@@ -2,8 +2,8 @@
 // (exact local solvers of Sec. 3 applied in parallel) in one persistent
 // launch.
 //
-// Each factor is stored as packed lower-triangular TILE x TILE tiles,
-// row-major inside a tile; the diagonal tiles hold inv(L_bb) (formed during
+// Each factor is stored as packed lower-triangular TB x TB tiles (TB = 64
+// or 32), row-major inside a tile; the diagonal tiles hold inv(L_bb) (formed during
 // the factorisation), so every step of a sweep is a tile GEMV.
 //
 // Work decomposition: a task is one tile row of one sweep of one subdomain:
@@ -62,7 +62,7 @@ __device__ __forceinline__ void wait_group(const T* p, DevState* st) {
   __syncthreads();
 }
 
-template <typename T, int UNROLL>
+template <typename T, int UNROLL, int TB>
 __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __restrict__ tasks,
                                               const SubDesc* __restrict__ subs, const T* __restrict__ tiles,
                                               const double* __restrict__ r, T* y, T* z, DevState* st,
@@ -70,15 +70,15 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
   using VT = Vec16<T>;
   using V = typename VT::V;
   constexpr int VEC = VT::N;
-  constexpr int LPR = TILE / VEC;     // lanes covering one tile row
+  constexpr int LPR = TB / VEC;     // lanes covering one tile row
   constexpr int RPP = 256 / LPR;      // tile rows per pass of the work-group
-  constexpr int PASSES = TILE / RPP;  // passes per tile
-  constexpr size_t TT = (size_t)TILE * TILE;
+  constexpr int PASSES = TB / RPP;  // passes per tile
+  constexpr size_t TT = (size_t)TB * TB;
   __shared__ int s_task;
-  __shared__ T s_vec[TILE];
-  __shared__ T s_red[4][TILE];
-  __shared__ T s_x[2][UNROLL * TILE];  // staged y (forward) or z (backward) values, double-buffered
-  static_assert(UNROLL * TILE <= 256, "one staged value per thread");
+  __shared__ T s_vec[TB];
+  __shared__ T s_red[4][TB];
+  __shared__ T s_x[2][UNROLL * TB];  // staged y (forward) or z (backward) values, double-buffered
+  static_assert(UNROLL * TB <= 256, "one staged value per thread");
   if (st->done) return;
   const int tid = threadIdx.x;
   const int lc = tid % LPR, r0 = tid / LPR;
@@ -100,11 +100,11 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
     // the diagonal inverse and the right-hand side are needed last: fetch them first
     V dv[PASSES];
 #pragma unroll
-    for (int k = 0; k < PASSES; ++k) dv[k] = *(const V*)(D + (r0 + RPP * k) * TILE + lc * VEC);
+    for (int k = 0; k < PASSES; ++k) dv[k] = *(const V*)(D + (r0 + RPP * k) * TB + lc * VEC);
     T rhs[PASSES];  // forward: r rows of this tile row (lanes lc == 0)
 #pragma unroll
     for (int k = 0; k < PASSES; ++k) {
-      const int gi = b * TILE + r0 + RPP * k;
+      const int gi = b * TB + r0 + RPP * k;
       rhs[k] = (td.y == 0 && lc == 0 && gi < n) ? (T)r[sd.dof0 + gi] : T(0);
     }
 
@@ -123,15 +123,15 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
           const bool ok = j + u < b;
 #pragma unroll
           for (int k = 0; k < PASSES; ++k)
-            tv[u][k] = ok ? *(const V*)(rowbase + (size_t)(j + u) * TT + (r0 + RPP * k) * TILE + lc * VEC) : V{};
+            tv[u][k] = ok ? *(const V*)(rowbase + (size_t)(j + u) * TT + (r0 + RPP * k) * TB + lc * VEC) : V{};
         }
         // the chunk's y values: one poller for the latest tile, then one
         // device-coherent load per thread, shared via LDS
         const int jl = min(j + UNROLL, b) - 1;
-        wait_group(yv0 + jl * TILE + TILE - 1, st);
-        if (tid < UNROLL * TILE) {
-          const int jt = j + tid / TILE;
-          s_x[buf][tid] = jt < b ? wait_value(yv0 + jt * TILE + (tid % TILE), st) : T(0);
+        wait_group(yv0 + jl * TB + TB - 1, st);
+        if (tid < UNROLL * TB) {
+          const int jt = j + tid / TB;
+          s_x[buf][tid] = jt < b ? wait_value(yv0 + jt * TB + (tid % TB), st) : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
 #pragma unroll
           for (int k = 0; k < PASSES; ++k)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[k] += VT::at(tv[u][k], v) * s_x[buf][u * TILE + lc * VEC + v];
+            for (int v = 0; v < VEC; ++v) acc[k] += VT::at(tv[u][k], v) * s_x[buf][u * TB + lc * VEC + v];
       }
       if (trace && tid == 0) trace[3 * (size_t)t + 1] = wall_clock64();
 #pragma unroll
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
       if (lc == 0) {
 #pragma unroll
         for (int k = 0; k < PASSES; ++k) {
-          const int gi = b * TILE + r0 + RPP * k;
+          const int gi = b * TB + r0 + RPP * k;
           if (gi < n) store_agent(y + sd.dof0 + gi, acc[k]);
         }
       }
@@ -193,20 +193,20 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
           const bool ok = jj <= jhi;
           const T* tile = base + (size_t)(jj * (jj + 1) / 2 + b) * TT;
 #pragma unroll
-          for (int k = 0; k < PASSES; ++k) tv[u][k] = ok ? *(const V*)(tile + (r0 + RPP * k) * TILE + lc * VEC) : V{};
+          for (int k = 0; k < PASSES; ++k) tv[u][k] = ok ? *(const V*)(tile + (r0 + RPP * k) * TB + lc * VEC) : V{};
         }
         // tile jlo was finished last among the chunk's tiles
-        wait_group(z + sd.dof0 + jlo * TILE, st);
-        if (tid < UNROLL * TILE) {
-          const int gi = jlo * TILE + tid;
-          s_x[buf][tid] = (gi < (jhi + 1) * TILE && gi < n) ? wait_value(z + sd.dof0 + gi, st) : T(0);
+        wait_group(z + sd.dof0 + jlo * TB, st);
+        if (tid < UNROLL * TB) {
+          const int gi = jlo * TB + tid;
+          s_x[buf][tid] = (gi < (jhi + 1) * TB && gi < n) ? wait_value(z + sd.dof0 + gi, st) : T(0);
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
           for (int k = 0; k < PASSES; ++k) {
-            const T zk = s_x[buf][u * TILE + r0 + RPP * k];
+            const T zk = s_x[buf][u * TB + r0 + RPP * k];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[v] += VT::at(tv[u][k], v) * zk;
           }
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
         for (int v = 0; v < VEC; ++v) s_red[wave][lc * VEC + v] = acc[v];
       }
       __syncthreads();
-      if (tid < TILE) {
+      if (tid < TB) {
         const T u = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-        const int gi = b * TILE + tid;
+        const int gi = b * TB + tid;
         const T yv = gi < n ? wait_value(y + sd.dof0 + gi, st) : T(0);
         s_vec[tid] = yv - u;
       }
@@ -245,9 +245,9 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
         for (int v = 0; v < VEC; ++v) s_red[wave][lc * VEC + v] = acc[v];
       }
       __syncthreads();
-      if (tid < TILE) {
+      if (tid < TB) {
         const T u = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-        const int gi = b * TILE + tid;
+        const int gi = b * TB + tid;
         if (gi < n) store_agent(z + sd.dof0 + gi, u);
       }
       if (trace && tid == 0) trace[3 * (size_t)t + 2] = wall_clock64();
@@ -258,16 +258,26 @@ __global__ __launch_bounds__(256) void k_trsv(int32_t n_tasks, const int4* __res
 
 }  // namespace
 
-hipError_t launch_trsv(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs, const void* tiles,
-                       const double* r, void* y, void* z, DevState* st, int32_t* queue, int grid,
+hipError_t launch_trsv(int f32, int tile, int32_t n_tasks, const int4* tasks, const SubDesc* subs,
+                       const void* tiles, const double* r, void* y, void* z, DevState* st, int32_t* queue, int grid,
                        uint64_t* trace, hipStream_t s) {
+  if (tile != 32 && tile != 64) return hipErrorInvalidValue;
   if (n_tasks <= 0) return hipSuccess;
-  if (f32)
-    hipLaunchKernelGGL((k_trsv<float, 4>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs, (const float*)tiles, r,
-                       (float*)y, (float*)z, st, queue, trace);
-  else
-    hipLaunchKernelGGL((k_trsv<double, 2>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs, (const double*)tiles,
-                       r, (double*)y, (double*)z, st, queue, trace);
+  if (f32) {
+    if (tile == 64)
+      hipLaunchKernelGGL((k_trsv<float, 4, 64>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs,
+                         (const float*)tiles, r, (float*)y, (float*)z, st, queue, trace);
+    else
+      hipLaunchKernelGGL((k_trsv<float, 8, 32>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs,
+                         (const float*)tiles, r, (float*)y, (float*)z, st, queue, trace);
+  } else {
+    if (tile == 64)
+      hipLaunchKernelGGL((k_trsv<double, 2, 64>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs,
+                         (const double*)tiles, r, (double*)y, (double*)z, st, queue, trace);
+    else
+      hipLaunchKernelGGL((k_trsv<double, 4, 32>), dim3(grid), dim3(256), 0, s, n_tasks, tasks, subs,
+                         (const double*)tiles, r, (double*)y, (double*)z, st, queue, trace);
+  }
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 
 namespace asdg {
 
-constexpr int TILE = 64;            // tile edge of the packed local/coarse factors
+constexpr int TILE = 64;            // tile edge of the coarse factor and the explicit inverses (local sweeps: 64 or 32)
 constexpr int MAXG = 8192;          // max work-groups of a kernel that reduces over the grid
 constexpr int HIST = 65536;         // recorded CG coefficients (Lanczos estimate)
 
@@ -46,7 +46,7 @@ struct DevState {
 struct SubDesc {
   int32_t dof0;   // first (internal) DoF of the subdomain
   int32_t n;      // DoFs
-  int32_t nb;     // tile rows = ceil(n / TILE)
+  int32_t nb;     // tile rows = ceil(n / tile edge)
   int32_t tile0;  // index of tile (0,0); tile (b,j) is tile0 + b(b+1)/2 + j
 };
 
@@ -99,13 +99,15 @@ hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_reset_queues(DevState* st, hipStream_t s);
 
 // Local-factor formation and batched Cholesky (kern_chol.hip).
-hipError_t launch_gather_tiles(int np, int32_t n_tiles, const int4* tile_meta, const SubDesc* subs,
+// tile: edge of the packed tiles, 64 or 32 (hipErrorInvalidValue otherwise).
+hipError_t launch_gather_tiles(int np, int tile, int32_t n_tiles, const int4* tile_meta, const SubDesc* subs,
                                const int32_t* row_ptr, const int32_t* col, const double* blocks,
                                void* tiles, int f32, hipStream_t s);
 // per_sub = 0: tasks (subdomain, j, b, -) of every tile, dependency-ordered;
 // per_sub = 1: tasks (subdomain, -, -, -), one work-group per subdomain.
-hipError_t launch_cholesky(int f32, int per_sub, int32_t n_tasks, const int4* tasks, const SubDesc* subs, void* tiles,
-                           int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
+// Work-groups of four waves (tile 64) or one wave (tile 32).
+hipError_t launch_cholesky(int f32, int tile, int per_sub, int32_t n_tasks, const int4* tasks, const SubDesc* subs,
+                           void* tiles, int32_t* flags, DevState* st, int32_t* queue, int grid, hipStream_t s);
 
 // Explicit local inverses (kern_inv.hip) and their packed symmetric apply
 // (kern_symv.hip).
@@ -142,9 +144,10 @@ hipError_t launch_expand_sym(int32_t n0, const double* S, double* D, hipStream_t
 hipError_t launch_dense_mv(int32_t n, int splits, const double* D, const double* xp, double* y, const DevState* st,
                            hipStream_t s);
 
-// Batched forward/backward triangular sweeps (kern_trsv.hip).
+// Batched forward/backward triangular sweeps (kern_trsv.hip) over packed
+// tiles of edge `tile` (64 or 32).
 // trace (optional): per task, wall-clock at dequeue, end of waits, end.
-hipError_t launch_trsv(int f32, int32_t n_tasks, const int4* tasks, const SubDesc* subs,
+hipError_t launch_trsv(int f32, int tile, int32_t n_tasks, const int4* tasks, const SubDesc* subs,
                        const void* tiles, const double* r, void* y, void* z, DevState* st,
                        int32_t* queue, int grid, uint64_t* trace, hipStream_t s);
 

@@ -25,16 +25,21 @@ def test_autotune_keeps_results_bitwise(precision, inverse):
     prec = asdg.FP32_LOCAL if precision == "fp32" else asdg.FP64
     P = _problem()
     print(f"[autotune] {precision} inverse={inverse} n={P.n_dofs}", flush=True)
-    ref = asdg.setup_problem(P, prec, device="cuda:0", local_inverse=inverse)
-    x0, st0 = ref.solve(rtol=1e-8)
-    x0 = x0.cpu().numpy()
-    del ref
-
     pr = asdg.setup_problem(P, prec, device="cuda:0", local_inverse=inverse, factor=False)
     rep = pr.autotune(asdg.AUTOTUNE_FACTOR | asdg.AUTOTUNE_LOCAL)
     torch.cuda.synchronize()
     print(f"[autotune] report {rep}", flush=True)
-    assert rep["chol_wg_per_cu"] in (1, 2)
+    # with the sweeps the tile edge is searched too (64 or 32 rows); the
+    # reference is planned with the edge the autotuner kept and default shapes
+    tile = rep["tile"]
+    assert tile == 64 if inverse else tile in (32, 64)
+    assert pr.info()[7] == tile
+    ref = asdg.setup_problem(P, prec, device="cuda:0", local_inverse=inverse, tile=0 if inverse else tile)
+    x0, st0 = ref.solve(rtol=1e-8)
+    x0 = x0.cpu().numpy()
+    del ref
+
+    assert rep["chol_wg_per_cu"] in ((1, 2) if tile == 64 else (4, 8))
     assert rep["factor_ms"] > 0 and rep["local_ms"] > 0
     if inverse:
         assert rep["inv_wg_per_cu"] in ((1, 2, 3, 4) if precision == "fp32" else (1, 2))
@@ -45,7 +50,8 @@ def test_autotune_keeps_results_bitwise(precision, inverse):
         assert rep["inverse_schedule"] in (1, 2)
     else:
         assert rep["trsv_wg_per_cu"] in (1, 2, 3, 4)
-        assert rep["candidates"] == 2 + 2 + 1 + 4
+        # tile edges 2, Cholesky schedules 2, Cholesky shapes 2, task orders 1, sweeps 4
+        assert rep["candidates"] == 2 + 2 + 2 + 1 + 4
         assert rep["inverse_schedule"] == 0
     assert rep["factor_schedule"] in (1, 2)
     assert rep["task_chunk"] == 0

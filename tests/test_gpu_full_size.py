@@ -112,6 +112,64 @@ def test_full_local_solves_sampled(name, prec, local):
         assert _rel(z[d], zi) <= tol, (i, len(d), _rel(z[d], zi), tol)
 
 
+def _every_subdomain_reference(name, seed=2):
+    """For every subdomain i of the workload: the DoF range in subdomain
+    order, the dense Cholesky solve z_i = A_i^{-1} v_i of the oracle's
+    principal submatrix, and kappa_2(A_i) from its extreme eigenvalues
+    (Lanczos on A_i and on A_i^{-1} through the factor, to 1e-6)."""
+    import scipy.linalg as la
+    import scipy.sparse.linalg as spla
+
+    key = (name, "every_sub", seed)
+    if key not in _cache:
+        P, A, b, _ = _oracle(name)
+        print(f"[full] {name}: dense solves and condition numbers of every subdomain", flush=True)
+        npb = P.n_p
+        cells = np.argsort(P.subdomain, kind="stable")
+        perm = (cells[:, None] * npb + np.arange(npb)[None, :]).ravel()
+        Ap = A[perm][:, perm].tocsr()
+        ptr = np.concatenate([[0], np.cumsum(np.bincount(P.subdomain) * npb)])
+        v = np.random.default_rng(seed).standard_normal(P.n_dofs)
+        vp = v[perm]
+        zs, kappas = [], []
+        for i in range(len(ptr) - 1):
+            s, e = ptr[i], ptr[i + 1]
+            Ai = Ap[s:e, s:e]
+            c = la.cho_factor(Ai.toarray(), lower=True)
+            zs.append(la.cho_solve(c, vp[s:e]))
+            lmax = spla.eigsh(Ai, k=1, which="LA", tol=1e-6, return_eigenvectors=False)[0]
+            inv = spla.LinearOperator(Ai.shape, matvec=lambda x, c=c: la.cho_solve(c, x), dtype=np.float64)
+            lmin = 1.0 / spla.eigsh(inv, k=1, which="LA", tol=1e-6, return_eigenvectors=False)[0]
+            kappas.append(lmax / lmin)
+        _cache[key] = (v, perm, ptr, zs, np.array(kappas))
+    return _cache[key]
+
+
+@pytest.mark.parametrize("local", ["sweeps", "inverse"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_local_solves_every_subdomain_C4(prec, local):
+    """All 512 subdomains of the local solves at full size, each against the
+    dense solve of the oracle's A_i (relative 2-norm per subdomain): FP64
+    within 1e-10, FP32-local within 64 u kappa(A_i) (u = 2^-24) with each
+    subdomain's own condition number."""
+    import torch
+
+    from paper_1903_11357_amd import asdg
+
+    v, perm, ptr, zs, kappas = _every_subdomain_reference("C4")
+    pr = _gpu("C4", asdg.FP64 if prec == "fp64" else asdg.FP32_LOCAL, local == "inverse")
+    z = pr.apply(asdg.APPLY_LOCAL, torch.from_numpy(v).cuda()).cpu().numpy()[perm]
+    worst = 0.0
+    for i in range(len(zs)):
+        zi = z[ptr[i]:ptr[i + 1]]
+        tol = 1e-10 if prec == "fp64" else 64 * 2.0 ** -24 * kappas[i]
+        e = _rel(zi, zs[i])
+        worst = max(worst, e / tol)
+        assert e <= tol, (i, ptr[i + 1] - ptr[i], e, tol)
+    print(f"C4 {prec} {local}: {len(zs)} subdomains, kappa(A_i) in [{kappas.min():.3g}, {kappas.max():.3g}], "
+          f"worst error / bound = {worst:.2e}")
+
+
 def test_full_coarse_apply_nested_C3():
     import scipy.linalg as la
     import torch

@@ -76,6 +76,37 @@ def test_plan_reports_buffer_sizes():
     assert b64[1] >= 4 * 6 * 64 * 64 * 8 and b32[1] < b64[1]
 
 
+def test_plan_tile_edges():
+    """Tile edge of the local factors (ASDG_TUNE_TILE): 32-row tiles of the
+    sweeps store fewer words than 64-row ones on ragged subdomains, the
+    automatic edge plans room for both layouts, explicit inverses take 64
+    only, other edges are rejected."""
+    P = I.voronoi_problem(400, 7, p=2, bx=3, by=3, q=1)  # 9 ragged subdomains of ~270 DoFs
+    sizes = np.bincount(P.subdomain) * P.n_p
+    out = {}
+    for tile in (0, 32, 64):
+        pr = asdg.Problem()
+        pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+        pr.set_tuning(asdg.TUNE_TILE, tile)
+        out[tile] = pr.plan(asdg.FP64, 1, coarse_of_cell=P.coarse_of_cell)
+        assert pr.info()[7] == (tile or 64)
+    words = {t: sum(((n + t - 1) // t) * ((n + t - 1) // t + 1) // 2 * t * t for n in sizes) for t in (32, 64)}
+    assert words[32] < words[64]
+    assert out[64][1] >= 8 * words[64] and out[32][1] >= 8 * words[32]
+    assert out[32][1] < out[64][1]
+    # the automatic edge: the larger tile storage and the larger task lists of both
+    assert out[0][1] >= max(out[32][1], out[64][1]) and out[0][3] >= max(out[32][3], out[64][3])
+    pr = asdg.Problem()
+    with pytest.raises(asdg.AsdgError):
+        pr.set_tuning(asdg.TUNE_TILE, 48)
+    pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    pr.set_tuning(asdg.TUNE_TILE, 32)
+    pr.set_tuning(asdg.TUNE_LOCAL_INVERSE, 1)
+    with pytest.raises(asdg.AsdgError) as e:
+        pr.plan(asdg.FP64, 1, coarse_of_cell=P.coarse_of_cell)
+    assert e.value.status == asdg.EINVAL
+
+
 def test_validation_errors():
     P = I.make_config("C1")
     pr = asdg.Problem()
@@ -223,19 +254,23 @@ def test_tune_cache_file_roundtrip_and_malformed(tmp_path):
     """The tuning cache text format: a written file loads back; a malformed
     line rejects the whole file (no device needed)."""
     good = tmp_path / "tune.txt"
-    # the two schedules (last fields) may be absent (files written before they existed): then automatic
+    # the two schedules and the tile edge (last fields) may be absent (files written before they
+    # existed): then automatic schedules and 64-row tiles
     good.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 38.5 0.43 1 2\n"
                     "gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 101.5 0.91\n"
-                    "gfx950|fp64|sweeps|ns2^9|nbmax24|nbmean24 2 2 2 4 64 90.0 1.5 2\n")
-    assert asdg.tune_cache_load(str(good)) == 3
+                    "gfx950|fp64|sweeps|ns2^9|nbmax24|nbmean24 2 2 2 4 64 90.0 1.5 2\n"
+                    "gfx950|fp32|sweeps|ns2^9|nbmax24|nbmean24 8 2 2 4 0 30.0 0.9 1 0 32\n")
+    assert asdg.tune_cache_load(str(good)) == 4
     out = tmp_path / "saved.txt"
     asdg.tune_cache_save(str(out))
     lines = out.read_text().splitlines()
-    assert any(l.startswith("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 ") and l.endswith(" 1 2")
+    assert any(l.startswith("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 1 0 ") and l.endswith(" 1 2 64")
                for l in lines)
-    assert any(l.startswith("gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 ") and l.endswith(" 0 0")
+    assert any(l.startswith("gfx950|fp64|inverse|ns2^9|nbmax24|nbmean24 2 2 2 8 0 ") and l.endswith(" 0 0 64")
                for l in lines)
-    assert any(l.startswith("gfx950|fp64|sweeps|ns2^9|nbmax24|nbmean24 2 2 2 4 64 ") and l.endswith(" 2 0")
+    assert any(l.startswith("gfx950|fp64|sweeps|ns2^9|nbmax24|nbmean24 2 2 2 4 64 ") and l.endswith(" 2 0 64")
+               for l in lines)
+    assert any(l.startswith("gfx950|fp32|sweeps|ns2^9|nbmax24|nbmean24 8 2 2 4 0 ") and l.endswith(" 1 0 32")
                for l in lines)
     bad = tmp_path / "bad.txt"
     bad.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 3 0 38.5 0.43\n")  # 3 waves: invalid
@@ -247,6 +282,10 @@ def test_tune_cache_file_roundtrip_and_malformed(tmp_path):
     bad2.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 8 0 38.5 0.43 5\n")  # schedule 5: invalid
     with pytest.raises(asdg.AsdgError):
         asdg.tune_cache_load(str(bad2))
+    bad4 = tmp_path / "bad4.txt"
+    bad4.write_text("gfx950|fp32|sweeps|ns2^9|nbmax24|nbmean24 8 2 2 4 0 30.0 0.9 1 0 48\n")  # tile edge 48
+    with pytest.raises(asdg.AsdgError):
+        asdg.tune_cache_load(str(bad4))
     bad3 = tmp_path / "bad3.txt"
     bad3.write_text("gfx950|fp32|inverse|ns2^9|nbmax24|nbmean24 2 3 2 8 0 38.5 0.43 1 3\n")  # inverse schedule 3
     with pytest.raises(asdg.AsdgError):
