@@ -93,6 +93,19 @@ typedef struct {
  * (tetrahedral meshes: f(xyz[3k], xyz[3k+1], xyz[3k+2])). */
 typedef void (*asdg_field_fn)(int64_t n, const double* xy, double* out, void* user);
 
+/* A ready-made asdg_field_fn for a load given as a double sine series on
+ * the unit square (Sec. 2 takes any f in L^2(Omega)):
+ *   f(x, y) = sum_{k=1..kx} sum_{l=1..ky} coef[(k-1) ky + (l-1)] sin(k pi x) sin(l pi y).
+ * Pass asdg_field_sine_series as f and a pointer to an asdg_sine_series as
+ * f_user of asdg_assemble; evaluated natively on the assembly's host
+ * threads. coef is read only during the call. kx < 1, ky < 1 or a NULL
+ * coef give NaN loads (asdg_field_fn has no error channel). */
+typedef struct {
+  int32_t kx, ky;      /* frequencies per direction                          */
+  const double* coef;  /* [kx][ky] row-major                                 */
+} asdg_sine_series;
+void asdg_field_sine_series(int64_t n, const double* xy, double* out, void* user);
+
 typedef struct {
   double rtol;          /* stop when ||r_k||_2 <= rtol * ||b||_2 (Sec. 7: 1e-8) */
   int32_t max_iter;     /* >= 1                                            */

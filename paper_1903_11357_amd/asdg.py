@@ -62,10 +62,15 @@ class TetMesh_(C.Structure):
 
 FIELD_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
 
+
+class SineSeries_(C.Structure):
+    _fields_ = [("kx", C.c_int32), ("ky", C.c_int32), ("coef", C.POINTER(C.c_double))]
+
 _lib = None
 
 # exported symbols and their signatures (restype, argtypes)
 _SIGS = {
+    "asdg_field_sine_series": (None, [C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "asdg_create": (C.c_int, [C.POINTER(C.c_void_p)]),
     "asdg_destroy": (None, [C.c_void_p]),
     "asdg_last_error": (C.c_char_p, [C.c_void_p]),
@@ -175,7 +180,17 @@ class Problem:
             out = np.ctypeslib.as_array(out_p, shape=(n,))
             out[:] = f(xy) if f is not None else 0.0
 
-        self._cb = FIELD_FN(cb)
+        # a load that is a double sine series (it exposes `sine_series_coef`)
+        # goes to the library's native callback, asdg_field_sine_series
+        coef = getattr(f, "sine_series_coef", None) if dim == 2 else None
+        user = None
+        if coef is not None:
+            coef = np.ascontiguousarray(coef, dtype=np.float64)
+            self._cb = FIELD_FN(C.cast(self._L.asdg_field_sine_series, C.c_void_p).value)
+            series = SineSeries_(coef.shape[0], coef.shape[1], _dptr(coef, C.c_double))
+            user = C.cast(C.byref(series), C.c_void_p)
+        else:
+            self._cb = FIELD_FN(cb)
         if dim == 3:
             xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
             tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
@@ -187,7 +202,7 @@ class Problem:
         else:
             m, keep = _mesh_struct(mesh)
             self._check(self._L.asdg_assemble(self.h, C.byref(m), p, c_sigma, _dptr(rho, C.c_double),
-                                              _dptr(sub, C.c_int32), self._cb, None))
+                                              _dptr(sub, C.c_int32), self._cb, user))
             npb = (p + 1) * (p + 2) // 2
         self._subsizes = np.bincount(sub) * npb
         del keep

@@ -23,6 +23,8 @@
 // A_0 = P_0^T A P_0 (eq. (A0)).
 #include "discretize.h"
 
+#include "asdg.h"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -1028,3 +1030,40 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
 }
 
 }  // namespace asdg
+
+// Double sine series load (asdg_field_sine_series): per point one sine and
+// one cosine per direction, the higher frequencies by the recurrence
+// sin((k+1)a) = 2 cos(a) sin(ka) - sin((k-1)a); points split over the
+// host threads of the calling assembly.
+extern "C" void asdg_field_sine_series(int64_t n, const double* xy, double* out, void* user) {
+  const asdg_sine_series* S = static_cast<const asdg_sine_series*>(user);
+  if (!S || !S->coef || S->kx < 1 || S->ky < 1) {
+    for (int64_t i = 0; i < n; ++i) out[i] = std::nan("");
+    return;
+  }
+  const int kx = S->kx, ky = S->ky;
+  const double* c = S->coef;
+  asdg::parallel_for(n, [&](int64_t lo, int64_t hi) {
+    std::vector<double> sx(kx), sy(ky);
+    auto sines = [](double t, int K, double* s) {
+      const double a = M_PI * t;
+      s[0] = std::sin(a);
+      if (K > 1) {
+        const double c2 = 2.0 * std::cos(a);
+        s[1] = c2 * s[0];
+        for (int k = 2; k < K; ++k) s[k] = c2 * s[k - 1] - s[k - 2];
+      }
+    };
+    for (int64_t i = lo; i < hi; ++i) {
+      sines(xy[2 * i], kx, sx.data());
+      sines(xy[2 * i + 1], ky, sy.data());
+      double v = 0.0;
+      for (int k = 0; k < kx; ++k) {
+        double t = 0.0;
+        for (int l = 0; l < ky; ++l) t += c[k * ky + l] * sy[l];
+        v += t * sx[k];
+      }
+      out[i] = v;
+    }
+  });
+}

@@ -265,6 +265,11 @@ class SineSeries:
                 out[k] -= out[k - 2]
         return out
 
+    @property
+    def sine_series_coef(self) -> np.ndarray:
+        """[K, L] coefficients (lets the library evaluate the series natively)."""
+        return self.coef
+
     def __call__(self, xy: np.ndarray) -> np.ndarray:
         sx = self._sines(np.ascontiguousarray(xy[:, 0]), self.coef.shape[0])
         sy = self._sines(np.ascontiguousarray(xy[:, 1]), self.coef.shape[1])

@@ -76,6 +76,33 @@ def test_plan_reports_buffer_sizes():
     assert b64[1] >= 4 * 6 * 64 * 64 * 8 and b32[1] < b64[1]
 
 
+def test_native_sine_series_load():
+    """The library's sine-series load (asdg_field_sine_series) equals the
+    series evaluated term by term with numpy sines, and a problem whose load
+    is such a series assembles the same load vector as through the
+    interpreter callback and as the oracle."""
+    rng = np.random.default_rng(3)
+    coef = rng.standard_normal((4, 3))
+    xy = rng.random((1000, 2))
+    ref = sum(coef[k, l] * np.sin((k + 1) * np.pi * xy[:, 0]) * np.sin((l + 1) * np.pi * xy[:, 1])
+              for k in range(4) for l in range(3))
+    out = np.empty(len(xy))
+    series = asdg.SineSeries_(4, 3, coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    asdg.lib().asdg_field_sine_series(len(xy), xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.cast(ctypes.byref(series), ctypes.c_void_p))
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(coef).sum()
+    P = I.voronoi_problem(300, 5, p=2, bx=2, by=2, q=1, f=I.make_f_series(rng.standard_normal((4, 4))))
+    native = asdg.Problem()
+    native.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+    interp = asdg.Problem()
+    interp.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, lambda xy: P.f(xy))
+    _, b, _, _ = assemble(P.mesh, P.p, P.rho, P.c_sigma, P.f)
+    bn, bi = native.export_rhs(), interp.export_rhs()
+    assert np.abs(bn - bi).max() <= 1e-14 * np.abs(bi).max()
+    assert _rel(bn.reshape(-1, P.n_p), b.reshape(-1, P.n_p)) < 1e-13
+
+
 def test_plan_tile_edges():
     """Tile edge of the local factors (ASDG_TUNE_TILE): 32-row tiles of the
     sweeps store fewer words than 64-row ones on ragged subdomains, the
