@@ -860,49 +860,69 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
 
 namespace {
 
-// Nested coarse transfer of fine cells [lo, hi): the fine mass matrix M and
-// the projection right-hand side B (fine basis against the basis of the
-// cell's coarse element) at the cell's quadrature points, then B := M^{-1} B.
-// The fine basis values of the mass pass are reused for B.
-template <int P, int Q>
-void nested_range(const MeshView& fine, const CellGeom& G, const std::vector<double>& gq, const std::vector<double>& wq,
-                  const int32_t* coarse_of_cell, const std::vector<Box>& cbox, int64_t lo, int64_t hi,
-                  std::vector<std::vector<int32_t>>& bcol, std::vector<std::vector<double>>& bval,
-                  std::atomic<bool>& fail) {
-  constexpr int NP = (P + 1) * (P + 2) / 2, NQ = (Q + 1) * (Q + 2) / 2;
-  std::vector<QuadPoint> qp;
-  std::vector<double> vq, M(NP * NP);
-  double B[NP * NQ], psi[NQ];
-  BasisBox fbb, cbb;
+// Nested coarse transfer of fine cells [lo, hi) without quadrature over the
+// cell. Inside a fine cell the coarse basis function psi_(i,j) of its coarse
+// element (degree q <= p) is a polynomial of the fine space, so its L2
+// projection (M^{-1} B above) is psi itself written in the fine basis
+// (Remark 3.2: the injection). Both bases are products of 1D scaled
+// Legendre polynomials, orthonormal on their boxes, so the coefficients are
+// products of 1D ones: psi_(i,j) = sum_(i',j') Tx[i][i'] Ty[j][j'] phi_(i',j')
+// with Tx[i][i'] = int over the fine box's x-interval of the coarse 1D factor
+// of degree i times the fine 1D factor of degree i' (zero for i' > i), by
+// Gauss-Legendre with p + 1 points (exact for degree i + i' <= 2p).
+void nested_exact_range(int p, int q, const CellGeom& G, const int32_t* coarse_of_cell, const std::vector<Box>& cbox,
+                        int64_t lo, int64_t hi, std::vector<std::vector<int32_t>>& bcol,
+                        std::vector<std::vector<double>>& bval) {
+  const int np = n_basis(p), nq = n_basis(q), m = p + 1;
+  std::vector<double> gx, gw;
+  gauss_legendre01(m, gx, gw);
+  // 1D normalised Legendre factors sqrt((2k+1)/len) L_k(2(t - c)/len), k <= kmax
+  auto leg = [](double t, double c, double len, int kmax, double* out) {
+    const double xi = 2.0 * (t - c) / len;
+    double l0 = 1.0, l1 = xi;
+    out[0] = 1.0;
+    if (kmax >= 1) out[1] = xi;
+    for (int k = 1; k < kmax; ++k) {
+      const double l2 = ((2 * k + 1) * xi * l1 - k * l0) / (k + 1);
+      l0 = l1;
+      l1 = l2;
+      out[k + 1] = l2;
+    }
+    for (int k = 0; k <= kmax; ++k) out[k] *= std::sqrt((2.0 * k + 1.0) / len);
+  };
+  auto transfer = [&](double f0, double f1, double c0, double c1, double* T /* [q+1][p+1] */) {
+    const double lf = f1 - f0, lc = c1 - c0, cf = 0.5 * (f0 + f1), cc = 0.5 * (c0 + c1);
+    std::fill(T, T + (q + 1) * (p + 1), 0.0);
+    double vf[16], vc[16];
+    for (int k = 0; k < m; ++k) {
+      const double t = f0 + lf * gx[k], w = lf * gw[k];
+      leg(t, cf, lf, p, vf);
+      leg(t, cc, lc, q, vc);
+      for (int i = 0; i <= q; ++i)
+        for (int i2 = 0; i2 <= i; ++i2) T[i * (p + 1) + i2] += w * vc[i] * vf[i2];
+    }
+  };
+  std::vector<double> Tx((q + 1) * (p + 1)), Ty((q + 1) * (p + 1)), B(np * nq);
   for (int64_t c = lo; c < hi; ++c) {
-    cell_points(fine, G, (int32_t)c, gq, wq, qp);
-    basis_prepare(P, G.box[c], fbb);
-    vq.resize(qp.size() * NP);
-    std::fill(M.begin(), M.end(), 0.0);
-    for (size_t k = 0; k < qp.size(); ++k) {
-      double* v = &vq[k * NP];
-      basis_val_p<P>(fbb, qp[k].x, qp[k].y, v);
-      const double w = qp[k].w;
-#pragma GCC unroll 15
-      for (int a = 0; a < NP; ++a)
-#pragma GCC unroll 15
-        for (int b = 0; b < NP; ++b) M[a * NP + b] += w * v[a] * v[b];
-    }
     const int32_t j = coarse_of_cell[c];
-    basis_prepare(Q, cbox[j], cbb);
-    std::fill(B, B + NP * NQ, 0.0);
-    for (size_t k = 0; k < qp.size(); ++k) {
-      basis_val_p<Q>(cbb, qp[k].x, qp[k].y, psi);
-      const double* v = &vq[k * NP];
-      const double w = qp[k].w;
-#pragma GCC unroll 15
-      for (int a = 0; a < NP; ++a)
-#pragma GCC unroll 15
-        for (int b = 0; b < NQ; ++b) B[a * NQ + b] += w * v[a] * psi[b];
-    }
-    if (!spd_solve(NP, M, B, NQ)) fail = true;
+    const Box& F = G.box[c];
+    const Box& D = cbox[j];
+    transfer(F.x0, F.x1, D.x0, D.x1, Tx.data());
+    transfer(F.y0, F.y1, D.y0, D.y1, Ty.data());
+    // degree-graded order: for d = 0..deg, for jj = 0..d: (d - jj, jj)
+    int a = 0;
+    for (int d = 0; d <= p; ++d)
+      for (int ja = 0; ja <= d; ++ja, ++a) {
+        const int ia = d - ja;
+        int bb = 0;
+        for (int e = 0; e <= q; ++e)
+          for (int jb = 0; jb <= e; ++jb, ++bb) {
+            const int ib = e - jb;
+            B[a * nq + bb] = (ia <= ib && ja <= jb) ? Tx[ib * (p + 1) + ia] * Ty[jb * (p + 1) + ja] : 0.0;
+          }
+      }
     bcol[c] = {j};
-    bval[c].assign(B, B + NP * NQ);
+    bval[c].assign(B.begin(), B.end());
   }
 }
 
@@ -958,24 +978,9 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
     for (int32_t j = 0; j < nc; ++j)
       if (!used[j]) return "coarse id " + std::to_string(j) + " is unused";
     C.n_coarse = nc;
-    std::atomic<bool> fail{false};
     parallel_for(N, [&](int64_t lo, int64_t hi) {
-#define ASDG_NESTED(P_, Q_) nested_range<P_, Q_>(fine, G, gq, wq, coarse_of_cell, cbox, lo, hi, bcol, bval, fail)
-      switch (A.p * 8 + q) {
-        case 9: ASDG_NESTED(1, 1); break;
-        case 17: ASDG_NESTED(2, 1); break;
-        case 18: ASDG_NESTED(2, 2); break;
-        case 25: ASDG_NESTED(3, 1); break;
-        case 26: ASDG_NESTED(3, 2); break;
-        case 27: ASDG_NESTED(3, 3); break;
-        case 33: ASDG_NESTED(4, 1); break;
-        case 34: ASDG_NESTED(4, 2); break;
-        case 35: ASDG_NESTED(4, 3); break;
-        default: ASDG_NESTED(4, 4); break;
-      }
-#undef ASDG_NESTED
+      nested_exact_range(A.p, q, G, coarse_of_cell, cbox, lo, hi, bcol, bval);
     });
-    if (fail) return "singular fine-cell mass matrix";
   } else {
     CellGeom CG;
     std::string err = geometry(*cmesh, CG, true);
