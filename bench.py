@@ -352,7 +352,7 @@ def start_serving_inputs(n_meshes, seed=5, workers=12):
     return ex, futs, time.perf_counter()
 
 
-def serving_bench(n_requests, gen, seed=5, local_inverse=False, loads=(0.8,), capacity_requests=400,
+def serving_bench(n_requests, gen, seed=5, local_inverse=True, loads=(0.8,), capacity_requests=400,
                   max_active=4):
     """Continuous batching (C5): requests with log-uniform 4096..65536-cell
     Voronoi meshes (a pool of relaxed Voronoi meshes, one per stratum of
@@ -447,8 +447,9 @@ def main():
                     help="requests on the GPU at once, each with its own stream (default: the HIP runtime's "
                          "hardware queues, GPU_MAX_HW_QUEUES, 4 unless set)")
     ap.add_argument("--only-serving", action="store_true")
-    ap.add_argument("--serving-local", default="sweeps", choices=("sweeps", "inverse"),
-                    help="local solvers of the served requests (short solves: setup dominates)")
+    ap.add_argument("--serving-local", default="inverse", choices=("sweeps", "inverse"),
+                    help="local solvers of the served requests (explicit inverses: 1.3-2.3x less GPU time per "
+                         "request than the sweeps, whose dependency chain dominates at these sizes)")
     ap.add_argument("--serving-loads", default="0.8",
                     help="Poisson arrival rates as fractions of the measured capacity, comma-separated")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

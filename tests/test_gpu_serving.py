@@ -31,12 +31,13 @@ def _run(problems, arrivals, **kw):
     return {r.rid: r for r in done}, srv
 
 
-def test_results_identical_alone_and_in_the_mix():
+@pytest.mark.parametrize("local_inverse", [True, False], ids=["inverse", "sweeps"])
+def test_results_identical_alone_and_in_the_mix(local_inverse):
     from paper_1903_11357_amd import asdg
 
     probs = _problems()
-    solo, _ = _run(probs, [0.0] * len(probs), max_active=1)
-    mixed, srv = _run(probs, [0.0] * len(probs), max_active=len(probs))
+    solo, _ = _run(probs, [0.0] * len(probs), max_active=1, local_inverse=local_inverse)
+    mixed, srv = _run(probs, [0.0] * len(probs), max_active=len(probs), local_inverse=local_inverse)
     assert srv.peak_active >= 3
     for i in range(len(probs)):
         a, b = solo[i], mixed[i]
@@ -45,7 +46,7 @@ def test_results_identical_alone_and_in_the_mix():
         assert bool((a.x == b.x).all()), i
     # the same request through the blocking solve entry point
     P = probs[2]
-    pr = asdg.setup_problem(P, asdg.FP32_LOCAL, device="cuda:0")
+    pr = asdg.setup_problem(P, asdg.FP32_LOCAL, device="cuda:0", local_inverse=local_inverse)
     x, st = pr.solve(rtol=1e-8, check_every=8)
     assert st["iterations"] == mixed[2].iterations
     assert bool((x == mixed[2].x).all())
@@ -59,6 +60,7 @@ def test_admission_respects_hbm_budget():
     for P in probs:
         pr = asdg.Problem()
         pr.assemble(P.mesh, P.p, P.c_sigma, P.rho, P.subdomain, P.f)
+        pr.set_tuning(asdg.TUNE_LOCAL_INVERSE, 1)  # the server's default local solvers
         sizes.append(sum(pr.plan(asdg.FP32_LOCAL, P.q, coarse_of_cell=P.coarse_of_cell)))
     budget = int(2.2 * max(sizes))
     arrivals = list(np.arange(len(probs)) * 0.002)
