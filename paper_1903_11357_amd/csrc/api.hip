@@ -1054,10 +1054,15 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   {
     // device blocks are row-major (host assembly keeps them column-major)
     const int np = A.np;
-    std::vector<double> rm(A.blocks.size());
-    for (size_t k = 0; k < A.blocks.size() / (np * np); ++k)
-      for (int r = 0; r < np; ++r)
-        for (int c = 0; c < np; ++c) rm[k * np * np + r * np + c] = A.blocks[k * np * np + c * np + r];
+    std::vector<double, DefaultInit<double>> rm(A.blocks.size());
+    {
+      HostThreadCap cap(pb->host_threads);
+      parallel_for((int64_t)(A.blocks.size() / (np * np)), [&](int64_t lo, int64_t hi) {
+        for (int64_t k = lo; k < hi; ++k)
+          for (int r = 0; r < np; ++r)
+            for (int c = 0; c < np; ++c) rm[k * np * np + r * np + c] = A.blocks[k * np * np + c * np + r];
+      });
+    }
     HIPCHK(pb, up(0, pb->o0.blocks, rm.data(), 8 * rm.size()));
     HIPCHK(pb, hipStreamSynchronize(s));  // rm is released at the end of this scope
   }

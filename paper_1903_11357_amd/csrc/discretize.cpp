@@ -445,12 +445,16 @@ std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::v
 
   // accumulate rows (internal order), deterministic order: volume, then the
   // cell's faces in face-index order
-  A.blocks.assign((size_t)A.row_ptr[N] * np * np, 0.0);
+  // (the blocks are left uninitialised and zeroed row by row in parallel:
+  // a serial fill of the whole array cost as much as the accumulation)
+  A.blocks.clear();
+  A.blocks.resize((size_t)A.row_ptr[N] * np * np);
   A.rhs.assign((size_t)N * np, 0.0);
   parallel_for(N, [&](int64_t lo, int64_t hi) {
     for (int64_t r = lo; r < hi; ++r) {
       int32_t c = A.perm[r];
       int32_t rs = A.row_ptr[r], re = A.row_ptr[r + 1];
+      std::fill(A.blocks.begin() + (size_t)rs * np * np, A.blocks.begin() + (size_t)re * np * np, 0.0);
       auto slot = [&](int32_t col) {
         int32_t k = (int32_t)(std::lower_bound(A.col_idx.begin() + rs, A.col_idx.begin() + re, col) -
                               A.col_idx.begin());

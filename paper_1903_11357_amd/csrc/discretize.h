@@ -3,12 +3,34 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <functional>
 #include <string>
 #include <utility>
 #include <vector>
 
 namespace asdg {
+
+// Allocator whose resize leaves new elements uninitialised (each user
+// writes every element, in parallel, instead of a serial zero fill first).
+template <class T>
+struct DefaultInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = DefaultInit<U>;
+  };
+  DefaultInit() = default;
+  template <class U>
+  DefaultInit(const DefaultInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
 
 struct Box {
   double x0, x1, y0, y1;
@@ -62,7 +84,7 @@ struct Assembled {
   std::vector<int32_t> sub_ptr;  // [n_sub + 1] internal cell offsets
   std::vector<int32_t> row_ptr;  // BSR, internal order
   std::vector<int32_t> col_idx;
-  std::vector<double> blocks;    // per block np*np, element (a,b) at b*np + a
+  std::vector<double, DefaultInit<double>> blocks;  // per block np*np, element (a,b) at b*np + a
   std::vector<double> rhs;       // internal order
   CellGeom geom;                 // caller order (2D)
   std::vector<Face> faces;       // caller cell ids (2D)
