@@ -545,20 +545,14 @@ inline void basis_val_p(const BasisBox& bb, double x, double y, double* val) {
     for (int j = 0; j <= d; ++j, ++a) val[a] = bb.s[a] * Lx[d - j] * Ly[j];
 }
 
-// Volume blocks (rho grad v . grad u) and loads (f v) of cells c0 + [lo, hi).
-// The load uses the cell rule of the load vector, whose points of cell
-// c0 + cc are at [pptr[cc], pptr[cc + 1]) (f evaluated there). The stiffness
-// integrand is a polynomial of degree 2P - 2, so it takes the centroid-fan
-// rule with P points per direction (gqs, wqs: exact to degree 2P - 2), the
-// same integral as any exact rule, at a fraction of the points.
+// Volume blocks (rho grad v . grad u) and loads (f v) of cells c0 + [lo, hi),
+// points of cell c0 + cc at [pptr[cc], pptr[cc + 1]).
 template <int P>
-void volume_range(const MeshView& mesh, const std::vector<double>& gqs, const std::vector<double>& wqs, int64_t c0,
-                  int64_t lo, int64_t hi, const int64_t* pptr, const double* pts, const double* wts,
+void volume_range(int64_t c0, int64_t lo, int64_t hi, const int64_t* pptr, const double* pts, const double* wts,
                   const double* fv, const CellGeom& G, const double* rho, double* vol, double* rhs_c) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   double v[NP], gx[NP], gy[NP];
   BasisBox bb;
-  std::vector<QuadPoint> qs;
   for (int64_t cc = lo; cc < hi; ++cc) {
     const int64_t c = c0 + cc;
     double* K = vol + (size_t)c * NP * NP;
@@ -566,20 +560,16 @@ void volume_range(const MeshView& mesh, const std::vector<double>& gqs, const st
     std::fill(K, K + NP * NP, 0.0);
     std::fill(bl, bl + NP, 0.0);
     basis_prepare(P, G.box[c], bb);
-    cell_points(mesh, G, (int32_t)c, gqs, wqs, qs);
-    const double r = rho[c];
-    for (const QuadPoint& q : qs) {
-      basis_eval_p<P>(bb, q.x, q.y, v, gx, gy);
-      const double wr = q.w * r;
+    for (int64_t k = pptr[cc]; k < pptr[cc + 1]; ++k) {
+      basis_eval_p<P>(bb, pts[2 * k], pts[2 * k + 1], v, gx, gy);
+      const double w = wts[k];
+      const double wr = w * rho[c];
       // the (a, b) and (b, a) terms are the same products: one triangle, mirrored below
 #pragma GCC unroll 15
       for (int b = 0; b < NP; ++b)
 #pragma GCC unroll 15
         for (int a = b; a < NP; ++a) K[b * NP + a] += wr * (gx[a] * gx[b] + gy[a] * gy[b]);
-    }
-    for (int64_t k = pptr[cc]; k < pptr[cc + 1]; ++k) {
-      basis_val_p<P>(bb, pts[2 * k], pts[2 * k + 1], v);
-      const double wf = wts[k] * fv[k];
+      const double wf = w * fv[k];
 #pragma GCC unroll 15
       for (int a = 0; a < NP; ++a) bl[a] += wf * v[a];
     }
@@ -723,15 +713,9 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
       return "non-conforming mesh: unmatched edge inside the domain";
   }
 
-  // load vector: the cell rule with p + 2 points per direction (exact to
-  // degree 2p + 2; f is not a polynomial, and the oracle takes the same
-  // rule); stiffness: p points (exact for its degree 2p - 2); faces: p + 1
-  // Gauss-Legendre points (exact for the degree 2p of their integrands)
   const int m = p + 2;
-  std::vector<double> gq, wq, gqs, wqs, gqf, wqf;
+  std::vector<double> gq, wq;
   gauss_legendre01(m, gq, wq);
-  gauss_legendre01(p, gqs, wqs);
-  gauss_legendre01(p + 1, gqf, wqf);
   const double pp = (double)p * (double)p;
 
   // volume blocks and load vector, caller order (zeroed per cell by volume_range)
@@ -762,10 +746,10 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
       parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
         const int64_t* pp_ = pptr.data();
         switch (p) {
-          case 1: volume_range<1>(mesh, gqs, wqs, c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 2: volume_range<2>(mesh, gqs, wqs, c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 3: volume_range<3>(mesh, gqs, wqs, c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          default: volume_range<4>(mesh, gqs, wqs, c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 1: volume_range<1>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 2: volume_range<2>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 3: volume_range<3>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          default: volume_range<4>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
         }
       });
     }
@@ -777,7 +761,7 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   // not value-initialised: face_range zeroes each face's blocks in its own
   // thread (a serial fill of this buffer cost as much as computing it)
   std::unique_ptr<double[]> fblk(new double[(size_t)NF * 4 * np * np]);
-  const FaceCtx X{&mesh, &G, &A.faces, rho, c_sigma, pp, p + 1, gqf.data(), wqf.data(), fblk.get()};
+  const FaceCtx X{&mesh, &G, &A.faces, rho, c_sigma, pp, m, gq.data(), wq.data(), fblk.get()};
   parallel_for(NF, [&](int64_t lo, int64_t hi) {
     switch (p) {
       case 1: face_range<1>(X, lo, hi); break;
