@@ -517,7 +517,8 @@ def _read_fig6():
     return rows
 
 
-@pytest.mark.parametrize("row", _read_fig6(), ids=lambda r: f"n{r[0]}_p{r[2]}")
+@pytest.mark.parametrize("row", [pytest.param(r, marks=pytest.mark.slow) if r[2] >= 7 else r for r in _read_fig6()],
+                         ids=lambda r: f"n{r[0]}_p{r[2]}")
 def test_example5_printed_condition_numbers(row):
     """Massively parallel setting (subdomain = element), nested square
     coarse mesh with H = 4h, q = p, f = 1: the Lanczos estimate from ASPCG
