@@ -144,7 +144,9 @@ const char* asdg_last_error(const asdg_problem* pb);
 
 /* Host-side SIPG assembly (Sec. 2, eqs. (Ah), (lifting), (Sigma)).
  * fine:      the fine mesh T_h.
- * p:         polynomial degree, 1 <= p <= 4.
+ * p:         polynomial degree, 1 <= p <= 9 (Sec. 7 reaches p = 9 in Example 5;
+ *            operator kernels of one wave per n_p DoFs up to p = 3, one thread per
+ *            DoF above).
  * c_sigma:   penalty constant C_sigma > 0 (the paper's experiments use 10).
  * rho:       [n_cells] cell-wise constant coefficient, > 0 (Remark 2.1).
  * subdomain: [n_cells] subdomain id of each cell in 0..n_sub-1, every id used
@@ -171,7 +173,8 @@ asdg_status asdg_assemble_tet(asdg_problem* pb, const asdg_tet_mesh* fine, int32
 
 /* Coarse space choice and device footprint (Sec. 3, V_0, eqs. (R0T), (A0)).
  * precision:      local factor precision.
- * q:              coarse degree, 1 <= q <= p; q = 0 disables the coarse level
+ * q:              coarse degree, 1 <= q <= p (for p >= 5: q = 1 or q = p; other
+ *                 values EINVAL); q = 0 disables the coarse level
  *                 (one-level method).
  * coarse_of_cell: [n_cells] nested coarse partition (coarse cell id of each
  *                 fine cell), or NULL when coarse_mesh is given.

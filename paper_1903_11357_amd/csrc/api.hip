@@ -891,6 +891,8 @@ asdg_status asdg_plan(asdg_problem* pb, asdg_precision precision, int32_t q, con
   if (precision != ASDG_FP64 && precision != ASDG_FP32_LOCAL) FAIL(pb, ASDG_EINVAL, "unknown precision");
   if (!bytes) FAIL(pb, ASDG_EINVAL, "bytes is null");
   if (q < 0 || q > pb->A.p) FAIL(pb, ASDG_EINVAL, "coarse degree q must satisfy 1 <= q <= p (or 0: no coarse level)");
+  if (pb->A.dim == 2 && pb->A.p >= 5 && q != 0 && q != 1 && q != pb->A.p)
+    FAIL(pb, ASDG_EINVAL, "for p >= 5 the coarse degree q must be 1 or p");
   pb->drop_graph();
   pb->stage = 1;
   pb->coarse_ready = false;

@@ -666,7 +666,7 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
                           const int32_t* subdomain,
                           void (*f)(int64_t, const double*, double*, void*), void* f_user,
                           Assembled& A) {
-  if (p < 1 || p > 4) return "p must be in 1..4";
+  if (p < 1 || p > kMaxDegree2D) return "p must be in 1.." + std::to_string(kMaxDegree2D);
   if (!(c_sigma > 0.0)) return "c_sigma must be positive";
   const int32_t N = mesh.n_cells;
   if (N < 1) return "empty mesh";
@@ -749,7 +749,12 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
           case 1: volume_range<1>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
           case 2: volume_range<2>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
           case 3: volume_range<3>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          default: volume_range<4>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 4: volume_range<4>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 5: volume_range<5>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 6: volume_range<6>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 7: volume_range<7>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 8: volume_range<8>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          default: volume_range<9>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
         }
       });
     }
@@ -767,7 +772,12 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
       case 1: face_range<1>(X, lo, hi); break;
       case 2: face_range<2>(X, lo, hi); break;
       case 3: face_range<3>(X, lo, hi); break;
-      default: face_range<4>(X, lo, hi); break;
+      case 4: face_range<4>(X, lo, hi); break;
+      case 5: face_range<5>(X, lo, hi); break;
+      case 6: face_range<6>(X, lo, hi); break;
+      case 7: face_range<7>(X, lo, hi); break;
+      case 8: face_range<8>(X, lo, hi); break;
+      default: face_range<9>(X, lo, hi); break;
     }
   });
 
@@ -897,7 +907,7 @@ void nested_exact_range(int p, int q, const CellGeom& G, const int32_t* coarse_o
   auto transfer = [&](double f0, double f1, double c0, double c1, double* T /* [q+1][p+1] */) {
     const double lf = f1 - f0, lc = c1 - c0, cf = 0.5 * (f0 + f1), cc = 0.5 * (c0 + c1);
     std::fill(T, T + (q + 1) * (p + 1), 0.0);
-    double vf[16], vc[16];
+    double vf[kMaxDegree2D + 1], vc[kMaxDegree2D + 1];
     for (int k = 0; k < m; ++k) {
       const double t = f0 + lf * gx[k], w = lf * gw[k];
       leg(t, cf, lf, p, vf);
@@ -949,7 +959,7 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
 
   // mass matrix of a fine cell (caller index c)
   auto mass = [&](int32_t c, std::vector<QuadPoint>& qp, std::vector<double>& M) {
-    double v[16];
+    double v[kMaxBasis2D];
     cell_points(fine, G, c, gq, wq, qp);
     M.assign(np * np, 0.0);
     BasisBox fbb;
@@ -998,7 +1008,7 @@ std::string build_coarse(const MeshView& fine, const Assembled& A, int q, const 
     parallel_for(N, [&](int64_t lo, int64_t hi) {
       std::vector<QuadPoint> qp, cq;
       std::vector<double> M, B(np * nq), P;
-      double v[16], psi[16];
+      double v[kMaxBasis2D], psi[kMaxBasis2D];
       for (int64_t c = lo; c < hi; ++c) {
         mass((int32_t)c, qp, M);
         cell_polygon(fine, (int32_t)c, P);

@@ -52,6 +52,10 @@ struct MeshView {
 // Gauss-Legendre rule with m points on [0, 1] (weights sum to one).
 void gauss_legendre01(int m, std::vector<double>& x, std::vector<double>& w);
 
+// Highest polynomial degree of the 2D assembly and its basis size.
+constexpr int kMaxDegree2D = 9;
+constexpr int kMaxBasis2D = (kMaxDegree2D + 1) * (kMaxDegree2D + 2) / 2;
+
 // Scaled Legendre basis of total degree p on box B: basis_prepare computes
 // the box's factors (centre, scalings, normalisations) once, basis_eval the
 // n_p values and gradients (either may be null) at a point.
@@ -59,7 +63,7 @@ int n_basis(int p);
 struct BasisBox {
   int p;
   double dx, dy, cx, cy, sx, sy;
-  double s[15];
+  double s[kMaxBasis2D];
 };
 void basis_prepare(int p, const Box& B, BasisBox& bb);
 void basis_eval(const BasisBox& bb, double x, double y, double* val, double* gx, double* gy);

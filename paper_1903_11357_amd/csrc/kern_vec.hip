@@ -488,6 +488,12 @@ hipError_t launch_spmv(int np, int32_t N, const int32_t* row_ptr, const int32_t*
     // tetrahedra: p = 1, 3 (p = 2 shares n_p = 10 with p = 3 in 2D)
     case 4: hipLaunchKernelGGL(k_spmv_even<4>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     case 20: hipLaunchKernelGGL(k_spmv_even<20>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    // 2D p = 5..9 (the condition-number studies of high degree): one thread per DoF
+    case 21: hipLaunchKernelGGL(k_spmv<21>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 28: hipLaunchKernelGGL(k_spmv<28>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 36: hipLaunchKernelGGL(k_spmv<36>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 45: hipLaunchKernelGGL(k_spmv<45>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
+    case 55: hipLaunchKernelGGL(k_spmv<55>, g, b, 0, s, N, row_ptr, col, blocks, p, q, red, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -553,6 +559,7 @@ hipError_t launch_restrict(int np, int nq, int32_t nc, int splits, const int32_t
 #define R_(A, B) ASDG_PQ_SWITCH(A, B, (restrict_t<A, B>(nc, splits, tptr, tcell, tblk, P, r, out, y0, z0, st, s)))
   R_(3, 3) R_(6, 3) R_(6, 6) R_(10, 3) R_(10, 6) R_(10, 10) R_(15, 3) R_(15, 6) R_(15, 10) R_(15, 15)
   R_(4, 4) R_(10, 4) R_(20, 4) R_(20, 10) R_(20, 20)
+  R_(21, 3) R_(21, 21) R_(28, 3) R_(28, 28) R_(36, 3) R_(36, 36) R_(45, 3) R_(45, 45) R_(55, 3) R_(55, 55)
 #undef R_
   return hipErrorInvalidValue;
 }
@@ -598,6 +605,7 @@ hipError_t launch_prolong(int np, int nq, int32_t N, const int32_t* pptr, const 
   ASDG_PQ_SWITCH(A, B, (prolong_t<A, B>(N, pptr, pcol, P, z0, zl, lp, f32, r, z, red, st, n_pq, n_rr, s)))
   P_(3, 3) P_(6, 3) P_(6, 6) P_(10, 3) P_(10, 6) P_(10, 10) P_(15, 3) P_(15, 6) P_(15, 10) P_(15, 15)
   P_(4, 4) P_(10, 4) P_(20, 4) P_(20, 10) P_(20, 20)
+  P_(21, 3) P_(21, 21) P_(28, 3) P_(28, 28) P_(36, 3) P_(36, 36) P_(45, 3) P_(45, 45) P_(55, 3) P_(55, 55)
 #undef P_
   return hipErrorInvalidValue;
 }

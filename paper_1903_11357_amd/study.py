@@ -20,6 +20,10 @@ nested coarse grids:
   Tables 5-6): K grows like (H/h)^2 along a row and stays roughly constant
   along diagonals; plain CG rows give K(A_h).
 - example4: independent (non-nested) coarse Voronoi grids (Example 4).
+- example5: K(P_ad) against the polynomial degree p = q = 1..9 on nested
+  square grids (Example 5, Fig. 6): n x n squares, coarse cells of
+  block x block squares, f = 1; this design is the paper's own, so its
+  printed values can be compared directly.
 - unpreconditioned CG on each fine grid: K(A_h) and its iteration count (the
   extra rows of Example 3's tables).
 
@@ -75,6 +79,18 @@ def per_element(mesh: I.Mesh, p: int, coarse_of_cell=None, coarse_mesh=None, rho
     return I.Problem(name=name, mesh=mesh, p=p, c_sigma=10.0, rho=np.ones(n) if rho is None else rho,
                      subdomain=np.arange(n, dtype=np.int32), q=p if q is None else q,
                      coarse_of_cell=coarse_of_cell, coarse_mesh=coarse_mesh, f=f)
+
+
+def example5(ps=range(1, 10), n: int = 32, block: int = 4, device: str = "cuda:0") -> dict:
+    """Example 5 (Fig. 6): one element per subdomain on n x n squares,
+    nested coarse agglomerates of block x block squares, q = p, rho = 1,
+    f = 1."""
+    out = {}
+    for p in ps:
+        P = I.squares_problem(n, p, 1, block, q=p, f=I.f_one)
+        out[p] = run(per_element(P.mesh, p, coarse_of_cell=P.coarse_of_cell, q=p, f=I.f_one, name="example5"),
+                     device=device)
+    return out
 
 
 def example1(p: int = 1, n_fine: int = 2000, bins: int = 4, rho_e=(1e1, 1e2, 1e3, 1e4, 1e5, 1e6), seed: int = 31,
@@ -179,7 +195,7 @@ def table_example2(p: int, table, plain, levels: int) -> str:
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--example", type=int, choices=(1, 2, 3, 4), default=2)
+    ap.add_argument("--example", type=int, choices=(1, 2, 3, 4, 5), default=2)
     ap.add_argument("--p", type=int, default=1)
     ap.add_argument("--n-finest", type=int, default=4096)
     ap.add_argument("--levels", type=int, default=4)
@@ -210,6 +226,14 @@ def main(argv=None):
                               "plain": {f"h=2^{k}": vars(v) for k, v in plain.items()}}))
         else:
             print(table_example2(a.p, table, plain, a.levels))
+    elif a.example == 5:
+        res = example5()
+        if a.json:
+            print(json.dumps({str(p): vars(v) for p, v in res.items()}))
+        else:
+            print("| p = q | " + " | ".join(str(p) for p in res) + " |")
+            print("|---" * (len(res) + 1) + "|")
+            print("| K(P_ad) (iterations) | " + " | ".join(_fmt(v) for v in res.values()) + " |")
     else:
         res = example4(a.p)
         if a.json:

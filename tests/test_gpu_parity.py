@@ -278,21 +278,60 @@ def test_indefinite_local_matrix_reports_enotspd():
     assert 0 <= pr.failed_subdomain() < 4
 
 
+def _fig6_rows():
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "example5_fig6.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            nx, cb, p, K = line.split()
+            rows.append((int(nx), int(cb), int(p), float(K)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _fig6_rows(), ids=lambda r: f"n{r[0]}_p{r[2]}")
+def test_example5_fig6_every_degree_on_gpu(row):
+    """Example 5 / Fig. 6 on the GPU through the study harness: one element
+    per subdomain (whole small inverses, n_p up to 55 at p = 9), nested
+    coarse cells of 4x4 squares with q = p, f = 1; the Lanczos estimate of
+    every printed case within FIG6_TOL of the printed K(P_ad)."""
+    from paper_1903_11357_amd import study
+
+    nx, cb, p, K = row
+    r = study.example5(ps=[p], n=nx, block=cb)[p]
+    print(f"Fig. 6 n={nx} p={p}: K = {r.K:.4f} (printed {K}), {r.iterations} iterations")
+    assert r.converged
+    assert abs(r.K / K - 1.0) < FIG6_TOL, (r.K, K)
+
+
+# The Lanczos estimate is read at the stopping iteration, while lambda_min is
+# still converging: one iteration more or less moves it by up to 0.2% here
+# (the oracle at p = 3: 193.92 / 194.22 / 194.62 after 120 / 121 / 122
+# iterations). The oracle stops at 121 with ||r|| / ||b|| = 9.88e-9, within
+# the rounding band of the tolerance where the GPU may stop one iteration
+# later (the FP64 parity rule above), and does: 194.62. The oracle itself
+# matches every printed value to 2.2e-4 (tests/test_oracle.py).
+FIG6_TOL = 5e-3
+
+
 @pytest.mark.parametrize("small", [True, False], ids=["small", "tiles"])
 def test_example5_printed_condition_number_on_gpu(small):
     """Massively parallel setting (one subdomain per element), 32x32 squares,
-    coarse 4x4-square agglomerates, p = q = 1, f = 1: the Lanczos estimate of
-    the GPU solve reproduces Fig. 6's printed 43.6818, with the whole small
-    inverses and with the tile path."""
+    coarse 4x4-square agglomerates, p = q = 1 and 9, f = 1: the Lanczos
+    estimate of the GPU solve reproduces Fig. 6's printed 43.6818 and
+    633.7908, with the whole small inverses and with the tile path (one
+    55-row tile per element at p = 9)."""
     from paper_1903_11357_amd import asdg
 
-    P = I.squares_problem(32, 1, 1, 4, q=1, f=I.f_one)
-    P.subdomain = np.arange(32 * 32, dtype=np.int32)
-    pr = asdg.setup_problem(P, asdg.FP64, device="cuda:0", small=small)
-    x, st = pr.solve(rtol=1e-8)
-    K = st["lambda_max"] / st["lambda_min"]
-    print("K =", K, "iterations", st["iterations"])
-    assert abs(K / 43.6818 - 1.0) < 1e-3
+    for p, Kp in ((1, 43.6818), (9, 633.7908)):
+        P = I.squares_problem(32, p, 1, 4, q=p, f=I.f_one)
+        P.subdomain = np.arange(32 * 32, dtype=np.int32)
+        pr = asdg.setup_problem(P, asdg.FP64, device="cuda:0", small=small)
+        x, st = pr.solve(rtol=1e-8)
+        K = st["lambda_max"] / st["lambda_min"]
+        print("p =", p, "K =", K, "iterations", st["iterations"])
+        assert abs(K / Kp - 1.0) < (1e-3 if p == 1 else FIG6_TOL)
 
 
 # ---------------------------------------------------------------- explicit local inverses

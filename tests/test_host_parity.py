@@ -103,6 +103,28 @@ def test_native_sine_series_load():
     assert _rel(bn.reshape(-1, P.n_p), b.reshape(-1, P.n_p)) < 1e-13
 
 
+@pytest.mark.parametrize("p", [5, 7, 9])
+def test_high_degree_assembly_matches_oracle(p):
+    """Degrees 5..9 (Sec. 7's Example 5 reaches p = 9): operator, load and
+    nested coarse operator with q = p against the oracle on a squares mesh
+    (one element per subdomain, 2x2 agglomerates), and with q = 1; other
+    coarse degrees are rejected for p >= 5."""
+    P = I.squares_problem(4, p, 1, 2, q=p, f=I.f_one)
+    P.subdomain = np.arange(16, dtype=np.int32)
+    A, b, geo, _ = assemble(P.mesh, p, P.rho, 10.0, P.f)
+    for q in (p, 1):
+        pr = asdg.Problem()
+        pr.assemble(P.mesh, p, 10.0, P.rho, P.subdomain, P.f)
+        pr.plan(asdg.FP64, q, coarse_of_cell=P.coarse_of_cell)
+        M = TwoLevelSchwarz(A, P.mesh, p, geo, P.subdomain, q=q, coarse_of_cell=P.coarse_of_cell, local=False)
+        assert _rel(pr.export_operator().toarray(), A.toarray()) < 1e-12
+        assert _rel(pr.export_rhs().reshape(-1, P.n_p), b.reshape(-1, P.n_p)) < 1e-13
+        assert _rel(pr.export_coarse(), M.A0) < 1e-11
+    with pytest.raises(asdg.AsdgError) as e:
+        pr.plan(asdg.FP64, 2, coarse_of_cell=P.coarse_of_cell)
+    assert e.value.status == asdg.EINVAL
+
+
 def test_plan_tile_edges():
     """Tile edge of the local factors (ASDG_TUNE_TILE): 32-row tiles of the
     sweeps store fewer words than 64-row ones on ragged subdomains, the
