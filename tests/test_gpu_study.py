@@ -119,3 +119,28 @@ def test_example3_trends():
     for a, b in zip(hs, hs[1:]):
         ratio = plain[b].K / plain[a].K
         assert 2.5 < ratio < 7.5, (a, b, ratio)
+
+
+def test_example5_degree_growth_nested_and_non_nested():
+    """Example 5 (Sec. 7.5) on 32x32 squares with 8x8 coarse cells, p = q =
+    1..9: with nested coarse cells K(P_ad) grows like p (least-squares slope
+    of log K against log p: 1.20 here, 1.21 for the printed series of
+    Fig. 6), within the O(p) bound of the condition-number remark of Sec. 6.
+    With an independent relaxed Voronoi coarse grid of 64 cells K is larger
+    at every p (the non-nested coarse space approximates less well) and grows
+    within the O(p^2) bound of the remark of Appendix B: slope 1.16 here,
+    2.1 on the paper's own polygonal grids, which are not available."""
+    from paper_1903_11357_amd import study
+
+    ps = list(range(1, 10))
+    K, slopes = {}, {}
+    for nonnested in (False, True):
+        res = study.example5(ps=ps, nonnested=nonnested)
+        assert all(r.converged for r in res.values())
+        K[nonnested] = np.array([res[p].K for p in ps])
+        slopes[nonnested] = float(np.polyfit(np.log(ps), np.log(K[nonnested]), 1)[0])
+        print(("non-nested" if nonnested else "nested"), [f"{k:.1f}" for k in K[nonnested]],
+              f"slope {slopes[nonnested]:.2f}")
+    assert 0.9 <= slopes[False] <= 1.5, slopes
+    assert np.all(K[True] > K[False]), K
+    assert slopes[True] <= 2.5, slopes

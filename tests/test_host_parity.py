@@ -123,6 +123,11 @@ def test_high_degree_assembly_matches_oracle(p):
     with pytest.raises(asdg.AsdgError) as e:
         pr.plan(asdg.FP64, 2, coarse_of_cell=P.coarse_of_cell)
     assert e.value.status == asdg.EINVAL
+    # an independent (non-nested) coarse Voronoi grid, q = p
+    cm = I.relaxed_voronoi_mesh(np.random.default_rng(5).random((5, 2)))
+    pr.plan(asdg.FP64, p, coarse_mesh=cm)
+    M = TwoLevelSchwarz(A, P.mesh, p, geo, P.subdomain, q=p, coarse_mesh=cm, local=False)
+    assert _rel(pr.export_coarse(), M.A0) < 1e-10
 
 
 def test_plan_tile_edges():
