@@ -1103,6 +1103,11 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   return ASDG_OK;
 }
 
+// Work-groups per compute unit of the Cholesky launch by default: the
+// kernel's occupancy (eight waves per CU: two work-groups of four waves for
+// 64-row tiles, eight of one wave for 32-row tiles).
+static int chol_occupancy(int tile) { return tile == 32 ? 8 : 2; }
+
 // Schedules of the local factorisation (1 tile tasks, 2 one work-group per
 // subdomain) and of the formation of X = L^{-1} (1 tile tasks, 2 one
 // work-group per block column). The schedules without waits run their
@@ -1113,11 +1118,6 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
 // Cholesky: subdomain tasks when the largest subdomain (about nb^3/6 tile
 // products) is at most 1.5 times that share (measured on 512 subdomains
 // whose largest is 1.65 times the mean: the tile tasks are 6% faster).
-// Work-groups per compute unit of the Cholesky launch by default: the
-// kernel's occupancy (eight waves per CU: two work-groups of four waves for
-// 64-row tiles, eight of one wave for 32-row tiles).
-static int chol_occupancy(int tile) { return tile == 32 ? 8 : 2; }
-
 static int factor_schedule(const asdg_problem* pb) {
   if (pb->factor_sched == 1 || pb->factor_sched == 2) return pb->factor_sched;
   double total = 0.0, largest = 0.0;
@@ -1627,10 +1627,13 @@ asdg_status relayout_local(asdg_problem* pb, int tile, hipStream_t s) {
 }
 }  // namespace
 
-// Launch-shape autotuner: every candidate is timed on this problem with
-// HIP events on the caller's stream (median of three runs; one run when it
-// takes more than 20 ms), the fastest is kept. The candidates change only which work-group does which task, never
-// the arithmetic, so results are the same for every choice.
+// Autotuner of the launch shapes and of the local factors' tile edge: every
+// candidate is timed on this problem with HIP events on the caller's stream
+// (the median of 3 to 15 runs filling about 20 ms; one run when it takes
+// more than 20 ms), the fastest is kept. The launch-shape candidates change
+// only which work-group does which task, never the arithmetic, so results
+// are the same for every choice; the tile edge changes the blocking of the
+// factorisation (results equal to rounding).
 asdg_status asdg_autotune(asdg_problem* pb, int32_t what, void* stream, asdg_tune_report* rep) {
   if (!pb) return ASDG_EINVAL;
   if ((what & ~(ASDG_AUTOTUNE_FACTOR | ASDG_AUTOTUNE_LOCAL | ASDG_AUTOTUNE_REUSE)) ||
