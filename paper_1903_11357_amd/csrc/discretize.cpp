@@ -719,8 +719,7 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   const double pp = (double)p * (double)p;
 
   // volume blocks and load vector, caller order (zeroed per cell by volume_range)
-  std::unique_ptr<double[]> vol(new double[(size_t)N * np * np]);
-  std::unique_ptr<double[]> rhs_c(new double[(size_t)N * np]);
+  std::vector<double, DefaultInit<double>> vol((size_t)N * np * np), rhs_c((size_t)N * np);
   {
     const int64_t chunk = 8192;
     for (int64_t c0 = 0; c0 < N; c0 += chunk) {
@@ -746,15 +745,15 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
       parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
         const int64_t* pp_ = pptr.data();
         switch (p) {
-          case 1: volume_range<1>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 2: volume_range<2>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 3: volume_range<3>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 4: volume_range<4>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 5: volume_range<5>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 6: volume_range<6>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 7: volume_range<7>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          case 8: volume_range<8>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
-          default: volume_range<9>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.get(), rhs_c.get()); break;
+          case 1: volume_range<1>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 2: volume_range<2>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 3: volume_range<3>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 4: volume_range<4>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 5: volume_range<5>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 6: volume_range<6>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 7: volume_range<7>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          case 8: volume_range<8>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
+          default: volume_range<9>(c0, lo, hi, pp_, pts.data(), wts.data(), fv.data(), G, rho, vol.data(), rhs_c.data()); break;
         }
       });
     }
@@ -765,8 +764,8 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   const int64_t NF = (int64_t)A.faces.size();
   // not value-initialised: face_range zeroes each face's blocks in its own
   // thread (a serial fill of this buffer cost as much as computing it)
-  std::unique_ptr<double[]> fblk(new double[(size_t)NF * 4 * np * np]);
-  const FaceCtx X{&mesh, &G, &A.faces, rho, c_sigma, pp, m, gq.data(), wq.data(), fblk.get()};
+  std::vector<double, DefaultInit<double>> fblk((size_t)NF * 4 * np * np);
+  const FaceCtx X{&mesh, &G, &A.faces, rho, c_sigma, pp, m, gq.data(), wq.data(), fblk.data()};
   parallel_for(NF, [&](int64_t lo, int64_t hi) {
     switch (p) {
       case 1: face_range<1>(X, lo, hi); break;
@@ -783,7 +782,7 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
 
   std::vector<std::pair<int32_t, int32_t>> pm(A.faces.size());
   for (size_t fi = 0; fi < A.faces.size(); ++fi) pm[fi] = {A.faces[fi].plus, A.faces[fi].minus};
-  return finish_assembly(A, subdomain, pm, vol.get(), rhs_c.get(), fblk.get());
+  return finish_assembly(A, subdomain, pm, vol.data(), rhs_c.data(), fblk.data());
 }
 
 // P_0 as CSR by internal fine cell from per-caller-cell block lists

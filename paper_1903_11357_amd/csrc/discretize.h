@@ -2,8 +2,12 @@
 // transfer (internal to libasdg). Plain C++17, no HIP dependency.
 #pragma once
 
+#include <sys/mman.h>
+
 #include <cstdint>
+#include <cstdlib>
 #include <memory>
+#include <new>
 #include <functional>
 #include <string>
 #include <utility>
@@ -13,8 +17,14 @@ namespace asdg {
 
 // Allocator whose resize leaves new elements uninitialised (each user
 // writes every element, in parallel, instead of a serial zero fill first).
+// Arrays of 4 MiB and more are placed on 2 MiB boundaries with transparent
+// huge pages requested: their first touch then faults once per 2 MiB
+// instead of once per 4 KiB page (about half the cost of first writing a
+// few hundred MB; the request is only advice and is ignored where huge
+// pages are off).
 template <class T>
 struct DefaultInit : std::allocator<T> {
+  static constexpr size_t kHuge = size_t(4) << 20, kAlign = size_t(2) << 20;
   template <class U>
   struct rebind {
     using other = DefaultInit<U>;
@@ -22,6 +32,20 @@ struct DefaultInit : std::allocator<T> {
   DefaultInit() = default;
   template <class U>
   DefaultInit(const DefaultInit<U>&) noexcept {}
+  T* allocate(size_t n) {
+    const size_t bytes = n * sizeof(T);
+    if (bytes < kHuge) return std::allocator<T>::allocate(n);
+    void* p = std::aligned_alloc(kAlign, (bytes + kAlign - 1) / kAlign * kAlign);
+    if (!p) throw std::bad_alloc();
+    (void)madvise(p, bytes, MADV_HUGEPAGE);
+    return static_cast<T*>(p);
+  }
+  void deallocate(T* p, size_t n) noexcept {
+    if (n * sizeof(T) < kHuge)
+      std::allocator<T>::deallocate(p, n);
+    else
+      std::free(p);
+  }
   template <class U>
   void construct(U* p) noexcept {
     ::new (static_cast<void*>(p)) U;
