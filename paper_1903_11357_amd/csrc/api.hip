@@ -150,7 +150,7 @@ struct asdg_problem {
   // coarse factor planning
   SubDesc csub{0, 0, 0, 0};
   std::vector<int4> cchol_tasks, ctrsv_tasks;
-  std::vector<double> ctiles_host;
+  std::vector<double, DefaultInit<double>> ctiles_host;  // every element written by plan_coarse_factor
   int64_t n_ctiles = 0;
   // buffer layout
   struct { size_t row_ptr, col, blocks, rhs, perm, cell_sub; } o0{};
@@ -495,7 +495,8 @@ void plan_coarse_factor(asdg_problem* pb) {
   const int nb = (n0 + TILE - 1) / TILE;
   pb->csub = SubDesc{0, n0, nb, 0};
   pb->n_ctiles = (int64_t)nb * (nb + 1) / 2;
-  pb->ctiles_host.assign((size_t)pb->n_ctiles * TILE * TILE, 0.0);
+  pb->ctiles_host.clear();
+  pb->ctiles_host.resize((size_t)pb->n_ctiles * TILE * TILE);
   for (int b = 0; b < nb; ++b)
     for (int j = 0; j <= b; ++j) {
       double* T = &pb->ctiles_host[(size_t)(b * (b + 1) / 2 + j) * TILE * TILE];

@@ -138,7 +138,7 @@ struct Coarse {
   std::vector<int32_t> tptr;    // [n_coarse + 1] transposed lists
   std::vector<int32_t> tcell;   // fine (internal) cell of each entry
   std::vector<int32_t> tblk;    // block index into col/val
-  std::vector<double> a0;       // dense n0 x n0 row-major
+  std::vector<double, DefaultInit<double>> a0;  // dense n0 x n0 row-major
 };
 
 std::string build_coarse(const MeshView& fine, const Assembled& A, int q,
