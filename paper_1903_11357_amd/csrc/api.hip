@@ -1054,21 +1054,7 @@ asdg_status asdg_bind(asdg_problem* pb, void* const d_buf[4], const size_t sizes
   };
   HIPCHK(pb, up(0, pb->o0.row_ptr, A.row_ptr.data(), 4 * A.row_ptr.size()));
   HIPCHK(pb, up(0, pb->o0.col, A.col_idx.data(), 4 * A.col_idx.size()));
-  {
-    // device blocks are row-major (host assembly keeps them column-major)
-    const int np = A.np;
-    std::vector<double, DefaultInit<double>> rm(A.blocks.size());
-    {
-      HostThreadCap cap(pb->host_threads);
-      parallel_for((int64_t)(A.blocks.size() / (np * np)), [&](int64_t lo, int64_t hi) {
-        for (int64_t k = lo; k < hi; ++k)
-          for (int r = 0; r < np; ++r)
-            for (int c = 0; c < np; ++c) rm[k * np * np + r * np + c] = A.blocks[k * np * np + c * np + r];
-      });
-    }
-    HIPCHK(pb, up(0, pb->o0.blocks, rm.data(), 8 * rm.size()));
-    HIPCHK(pb, hipStreamSynchronize(s));  // rm is released at the end of this scope
-  }
+  HIPCHK(pb, up(0, pb->o0.blocks, A.blocks.data(), 8 * A.blocks.size()));  // row-major blocks, as on the device
   HIPCHK(pb, up(0, pb->o0.rhs, pb->rhs_caller.data(), 8 * pb->rhs_caller.size()));
   HIPCHK(pb, up(0, pb->o0.perm, A.perm.data(), 4 * A.perm.size()));
   HIPCHK(pb, up(0, pb->o0.cell_sub, pb->cell_sub.data(), 4 * pb->cell_sub.size()));
@@ -1465,7 +1451,7 @@ asdg_status asdg_export_operator(const asdg_problem* pb, int64_t* rows, int64_t*
         for (int b = 0; b < np; ++b, ++o) {
           rows[o] = cr * np + a;
           cols[o] = cc * np + b;
-          vals[o] = B[b * np + a];
+          vals[o] = B[a * np + b];
         }
     }
   return ASDG_OK;

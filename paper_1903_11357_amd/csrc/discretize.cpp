@@ -460,24 +460,26 @@ std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::v
                               A.col_idx.begin());
         return &A.blocks[(size_t)k * np * np];
       };
+      // the per-cell and per-face blocks hold (a, b) at b*np + a; the
+      // operator keeps it at a*np + b (row-major, the device layout)
+      auto add_t = [np](double* dst, const double* src) {
+        for (int a = 0; a < np; ++a)
+          for (int b = 0; b < np; ++b) dst[a * np + b] += src[b * np + a];
+      };
       double* D = slot((int32_t)r);
-      const double* Vb = &vol[(size_t)c * np * np];
-      for (int e = 0; e < np * np; ++e) D[e] += Vb[e];
+      add_t(D, &vol[(size_t)c * np * np]);
       for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
         int32_t fi = cf[k] >> 1;
         int t = cf[k] & 1;
         const auto& F = pm[fi];
         const double* Bk = &fblk[(size_t)fi * 4 * np * np];
         if (F.second < 0) {
-          for (int e = 0; e < np * np; ++e) D[e] += Bk[e];
+          add_t(D, Bk);
           continue;
         }
-        const double* Btt = Bk + (t * 2 + t) * np * np;
-        for (int e = 0; e < np * np; ++e) D[e] += Btt[e];
+        add_t(D, Bk + (t * 2 + t) * np * np);
         int32_t other = t ? F.first : F.second;
-        double* O = slot(A.iperm[other]);
-        const double* Bts = Bk + (t * 2 + (1 - t)) * np * np;
-        for (int e = 0; e < np * np; ++e) O[e] += Bts[e];
+        add_t(slot(A.iperm[other]), Bk + (t * 2 + (1 - t)) * np * np);
       }
       for (int a = 0; a < np; ++a) A.rhs[(size_t)r * np + a] = rhs_c[(size_t)c * np + a];
     }
@@ -842,7 +844,7 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
           for (int a = 0; a < np; ++a)
             for (int d = 0; d < nq; ++d) {
               double acc = 0.0;
-              for (int b = 0; b < np; ++b) acc += Ab[b * np + a] * Pb[b * nq + d];
+              for (int b = 0; b < np; ++b) acc += Ab[a * np + b] * Pb[b * nq + d];
               W[a * nq + d] += acc;
             }
         }

@@ -112,7 +112,7 @@ struct Assembled {
   std::vector<int32_t> sub_ptr;  // [n_sub + 1] internal cell offsets
   std::vector<int32_t> row_ptr;  // BSR, internal order
   std::vector<int32_t> col_idx;
-  std::vector<double, DefaultInit<double>> blocks;  // per block np*np, element (a,b) at b*np + a
+  std::vector<double, DefaultInit<double>> blocks;  // per block np*np, element (a,b) at a*np + b (row-major)
   std::vector<double> rhs;       // internal order
   CellGeom geom;                 // caller order (2D)
   std::vector<Face> faces;       // caller cell ids (2D)
