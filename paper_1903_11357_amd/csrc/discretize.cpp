@@ -852,7 +852,11 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
     }
   });
   const int64_t n0 = (int64_t)nc * nq;
-  C.a0.assign((size_t)(n0 * n0), 0.0);
+  C.a0.clear();
+  C.a0.resize((size_t)(n0 * n0));  // uninitialised, zeroed in parallel (rows of n0)
+  parallel_for(n0, [&](int64_t lo, int64_t hi) {
+    std::fill(C.a0.begin() + lo * n0, C.a0.begin() + hi * n0, 0.0);
+  });
   parallel_for(nc, [&](int64_t lo, int64_t hi) {
     for (int64_t J = lo; J < hi; ++J) {
       for (int32_t k = C.tptr[J]; k < C.tptr[J + 1]; ++k) {
