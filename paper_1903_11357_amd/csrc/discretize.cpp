@@ -664,6 +664,83 @@ void face_range(const FaceCtx& X, int64_t lo, int64_t hi) {
 
 }  // namespace
 
+// Faces of a polygon mesh by edge matching: one face per edge of a cell,
+// shared by the two cells whose edges join the same two vertices (in
+// opposite directions). Faces are numbered in the order in which their
+// first edge appears (cells in order, edges in each cell's vertex order);
+// plus = that edge's cell, minus = the other one (-1 on the boundary).
+// Edges are bucketed by their smaller vertex id, so each edge finds its
+// partner among the few edges at that vertex.
+static std::string match_faces(const MeshView& mesh, std::vector<Face>& faces) {
+  const int32_t N = mesh.n_cells;
+  const int64_t E = mesh.ptr[N];
+  std::vector<int32_t> cell(E), other(E), lo(E), hi(E), partner(E, -1);
+  std::atomic<int32_t> bad_cell{INT32_MAX};
+  parallel_for(N, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      const int32_t a = mesh.ptr[c], b = mesh.ptr[c + 1];
+      for (int32_t k = a; k < b; ++k) {
+        const int32_t v0 = mesh.verts[k], v1 = mesh.verts[(k + 1 < b) ? k + 1 : a];
+        if (v0 == v1) {
+          int32_t cur = bad_cell.load();
+          while ((int32_t)c < cur && !bad_cell.compare_exchange_weak(cur, (int32_t)c)) {
+          }
+        }
+        cell[k] = (int32_t)c;
+        other[k] = v1;
+        lo[k] = std::min(v0, v1);
+        hi[k] = std::max(v0, v1);
+      }
+    }
+  });
+  if (bad_cell.load() != INT32_MAX) return "repeated vertex in cell " + std::to_string(bad_cell.load());
+  // edges bucketed by their smaller vertex, in edge order within a bucket
+  std::vector<int64_t> bptr((size_t)mesh.n_vertices + 1, 0);
+  for (int64_t k = 0; k < E; ++k) {
+    if (lo[k] < 0 || hi[k] >= mesh.n_vertices) return "vertex id out of range";
+    bptr[lo[k] + 1]++;
+  }
+  for (int32_t v = 0; v < mesh.n_vertices; ++v) bptr[v + 1] += bptr[v];
+  std::vector<int64_t> bucket(E);
+  {
+    std::vector<int64_t> fill(bptr.begin(), bptr.end() - 1);
+    for (int64_t k = 0; k < E; ++k) bucket[fill[lo[k]]++] = k;
+  }
+  std::atomic<int> shared3{0};
+  parallel_for(E, [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      int found = 0;
+      for (int64_t i = bptr[lo[k]]; i < bptr[lo[k] + 1]; ++i) {
+        const int64_t j = bucket[i];
+        if (j != k && hi[j] == hi[k]) {
+          partner[k] = (int32_t)j;
+          ++found;
+        }
+      }
+      if (found > 1) shared3 = 1;
+    }
+  });
+  if (shared3) return "edge shared by more than two cells";
+  // a face per edge without a partner or whose partner comes later
+  std::vector<int32_t> face_of(E, -1);
+  faces.clear();
+  for (int64_t k = 0; k < E; ++k) {
+    if (partner[k] < 0 || partner[k] > k) {
+      const int32_t v0 = mesh.verts[k];
+      face_of[k] = (int32_t)faces.size();
+      faces.push_back({cell[k], -1, v0, other[k]});
+    }
+  }
+  for (int64_t k = 0; k < E; ++k) {
+    if (partner[k] < 0 || partner[k] > k) continue;
+    Face& F = faces[face_of[partner[k]]];
+    const int32_t v0 = mesh.verts[k], v1 = other[k];
+    if (!(F.v0 == v1 && F.v1 == v0)) return "inconsistent orientation across an edge";
+    F.minus = cell[k];
+  }
+  return "";
+}
+
 std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const double* rho,
                           const int32_t* subdomain,
                           void (*f)(int64_t, const double*, double*, void*), void* f_user,
@@ -687,27 +764,9 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   const CellGeom& G = A.geom;
 
   // faces by edge matching
-  A.faces.clear();
-  std::unordered_map<uint64_t, int32_t> open;
-  open.reserve((size_t)N * 4);
-  for (int32_t c = 0; c < N; ++c) {
-    int32_t a = mesh.ptr[c], b = mesh.ptr[c + 1];
-    for (int32_t k = a; k < b; ++k) {
-      int32_t v0 = mesh.verts[k], v1 = mesh.verts[(k + 1 < b) ? k + 1 : a];
-      if (v0 == v1) return "repeated vertex in cell " + std::to_string(c);
-      uint64_t key = ((uint64_t)std::min(v0, v1) << 32) | (uint32_t)std::max(v0, v1);
-      auto it = open.find(key);
-      if (it == open.end()) {
-        open.emplace(key, (int32_t)A.faces.size());
-        A.faces.push_back({c, -1, v0, v1});
-      } else {
-        Face& F = A.faces[it->second];
-        if (F.minus >= 0) return "edge shared by more than two cells";
-        if (!(F.v0 == v1 && F.v1 == v0)) return "inconsistent orientation across an edge";
-        F.minus = c;
-        open.erase(it);
-      }
-    }
+  {
+    std::string e = match_faces(mesh, A.faces);
+    if (!e.empty()) return e;
   }
   for (const Face& F : A.faces) {
     if (F.minus < 0 &&

@@ -195,6 +195,32 @@ def test_validation_errors():
     assert e.value.status == asdg.ESTATE
 
 
+def test_mesh_topology_errors():
+    """Edge matching: two squares sharing an edge in opposite directions
+    assemble; the same directed edge in two cells, an edge of three cells and
+    a repeated vertex are rejected, each with its own message."""
+    xy = np.array([[0, 0], [.5, 0], [1, 0], [0, 1], [.5, 1], [1, 1], [.25, .5], [.75, .5]], dtype=np.float64)
+
+    def run(cells):
+        ptr = np.cumsum([0] + [len(c) for c in cells]).astype(np.int32)
+        mesh = I.Mesh(xy, ptr, np.concatenate(cells).astype(np.int32))
+        n = len(cells)
+        pr = asdg.Problem()
+        try:
+            pr.assemble(mesh, 1, 10.0, np.ones(n), np.zeros(n, np.int32), None)
+        except asdg.AsdgError as e:
+            assert e.status == asdg.EINVAL
+            return str(e)
+        A = pr.export_operator()
+        assert A.shape == (6, 6)
+        return "ok"
+
+    assert run([[0, 1, 4, 3], [1, 2, 5, 4]]) == "ok"
+    assert "inconsistent orientation" in run([[0, 1, 4, 3], [1, 4, 6]])
+    assert "more than two cells" in run([[0, 1, 4, 3], [1, 2, 5, 4], [4, 1, 7]])
+    assert "repeated vertex in cell 0" in run([[0, 1, 1, 4, 3], [1, 2, 5, 4]])
+
+
 class _NullStream:
     cuda_stream = 0
 
