@@ -783,13 +783,23 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   std::vector<double, DefaultInit<double>> vol((size_t)N * np * np), rhs_c((size_t)N * np);
   {
     const int64_t chunk = 8192;
+    // point buffers of one chunk, reused by every chunk and not
+    // value-initialised: each chunk writes every entry it reads (a zero fill
+    // of fresh buffers per chunk cost as much as the volume integrals)
+    int64_t max_pts = 0;
+    for (int64_t c0 = 0; c0 < N; c0 += chunk) {
+      const int64_t c1 = std::min<int64_t>(N, c0 + chunk);
+      max_pts = std::max<int64_t>(max_pts, (int64_t)(mesh.ptr[c1] - mesh.ptr[c0]) * m * m);
+    }
+    std::vector<double, DefaultInit<double>> pts(2 * max_pts), wts(max_pts), fv(max_pts);
+    if (!f)
+      parallel_for(max_pts, [&](int64_t lo, int64_t hi) { std::fill(fv.begin() + lo, fv.begin() + hi, 0.0); });
+    std::vector<int64_t> pptr(chunk + 1, 0);
     for (int64_t c0 = 0; c0 < N; c0 += chunk) {
       int64_t c1 = std::min<int64_t>(N, c0 + chunk);
       // points of this chunk, in cell order
-      std::vector<int64_t> pptr(c1 - c0 + 1, 0);
       for (int64_t c = c0; c < c1; ++c)
         pptr[c - c0 + 1] = pptr[c - c0] + (int64_t)(mesh.ptr[c + 1] - mesh.ptr[c]) * m * m;
-      std::vector<double> pts(2 * pptr.back()), wts(pptr.back()), fv(pptr.back(), 0.0);
       parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
         std::vector<QuadPoint> qp;
         for (int64_t cc = lo; cc < hi; ++cc) {
@@ -802,7 +812,7 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
           }
         }
       });
-      if (f) f(pptr.back(), pts.data(), fv.data(), f_user);
+      if (f) f(pptr[c1 - c0], pts.data(), fv.data(), f_user);
       parallel_for(c1 - c0, [&](int64_t lo, int64_t hi) {
         const int64_t* pp_ = pptr.data();
         switch (p) {
