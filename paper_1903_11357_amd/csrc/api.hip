@@ -497,15 +497,22 @@ void plan_coarse_factor(asdg_problem* pb) {
   pb->n_ctiles = (int64_t)nb * (nb + 1) / 2;
   pb->ctiles_host.clear();
   pb->ctiles_host.resize((size_t)pb->n_ctiles * TILE * TILE);
+  // packed lower tiles of A_0 (identity padding), one tile row per item
+  std::vector<int2> tile_bj(pb->n_ctiles);
   for (int b = 0; b < nb; ++b)
-    for (int j = 0; j <= b; ++j) {
-      double* T = &pb->ctiles_host[(size_t)(b * (b + 1) / 2 + j) * TILE * TILE];
-      for (int r = 0; r < TILE; ++r)
-        for (int c = 0; c < TILE; ++c) {
-          int gr = b * TILE + r, gc = j * TILE + c;
-          T[r * TILE + c] = (gr < n0 && gc < n0) ? pb->C.a0[(size_t)gr * n0 + gc] : (gr == gc ? 1.0 : 0.0);
-        }
+    for (int j = 0; j <= b; ++j) tile_bj[b * (b + 1) / 2 + j] = make_int2(b, j);
+  parallel_for(pb->n_ctiles * TILE, [&](int64_t lo, int64_t hi) {
+    for (int64_t it = lo; it < hi; ++it) {
+      const int64_t t = it / TILE;
+      const int r = (int)(it - t * TILE), b = tile_bj[t].x, j = tile_bj[t].y;
+      double* T = &pb->ctiles_host[(size_t)t * TILE * TILE + (size_t)r * TILE];
+      const int gr = b * TILE + r;
+      for (int c = 0; c < TILE; ++c) {
+        const int gc = j * TILE + c;
+        T[c] = (gr < n0 && gc < n0) ? pb->C.a0[(size_t)gr * n0 + gc] : (gr == gc ? 1.0 : 0.0);
+      }
     }
+  });
   pb->cchol_tasks.clear();
   for (int j = 0; j < nb; ++j)
     for (int b = j; b < nb; ++b) pb->cchol_tasks.push_back(make_int4(0, j, b, 0));

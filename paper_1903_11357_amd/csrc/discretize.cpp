@@ -868,11 +868,13 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
   for (int32_t r = 0; r < N; ++r) C.ptr[r + 1] = C.ptr[r] + (int32_t)bcol[A.perm[r]].size();
   C.col.resize(C.ptr[N]);
   C.val.resize((size_t)C.ptr[N] * np * nq);
-  for (int32_t r = 0; r < N; ++r) {
-    int32_t c = A.perm[r];
-    std::copy(bcol[c].begin(), bcol[c].end(), C.col.begin() + C.ptr[r]);
-    std::copy(bval[c].begin(), bval[c].end(), C.val.begin() + (size_t)C.ptr[r] * np * nq);
-  }
+  parallel_for(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      const int32_t c = A.perm[r];
+      std::copy(bcol[c].begin(), bcol[c].end(), C.col.begin() + C.ptr[r]);
+      std::copy(bval[c].begin(), bval[c].end(), C.val.begin() + (size_t)C.ptr[r] * np * nq);
+    }
+  });
   // transposed lists (coarse cell -> entries in increasing fine order)
   const int32_t nc = C.n_coarse;
   C.tptr.assign(nc + 1, 0);
@@ -898,6 +900,12 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
     for (int64_t r = lo; r < hi; ++r) {
       auto& wc = wcol[r];
       auto& wv = wval[r];
+      // room for every (block, coarse entry) pair of the row: no regrowth
+      int32_t bound = 0;
+      for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k)
+        bound += C.ptr[A.col_idx[k] + 1] - C.ptr[A.col_idx[k]];
+      wc.reserve(bound);
+      wv.reserve((size_t)bound * np * nq);
       for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
         int32_t s = A.col_idx[k];
         const double* Ab = &A.blocks[(size_t)k * np * np];
