@@ -900,12 +900,6 @@ void finish_coarse(const Assembled& A, const std::vector<std::vector<int32_t>>& 
     for (int64_t r = lo; r < hi; ++r) {
       auto& wc = wcol[r];
       auto& wv = wval[r];
-      // room for every (block, coarse entry) pair of the row: no regrowth
-      int32_t bound = 0;
-      for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k)
-        bound += C.ptr[A.col_idx[k] + 1] - C.ptr[A.col_idx[k]];
-      wc.reserve(bound);
-      wv.reserve((size_t)bound * np * nq);
       for (int32_t k = A.row_ptr[r]; k < A.row_ptr[r + 1]; ++k) {
         int32_t s = A.col_idx[k];
         const double* Ab = &A.blocks[(size_t)k * np * np];
