@@ -460,26 +460,26 @@ std::string finish_assembly(Assembled& A, const int32_t* subdomain, const std::v
                               A.col_idx.begin());
         return &A.blocks[(size_t)k * np * np];
       };
-      // the per-cell and per-face blocks hold (a, b) at b*np + a; the
-      // operator keeps it at a*np + b (row-major, the device layout)
-      auto add_t = [np](double* dst, const double* src) {
-        for (int a = 0; a < np; ++a)
-          for (int b = 0; b < np; ++b) dst[a * np + b] += src[b * np + a];
+      // the per-cell (symmetric) and per-face blocks are row-major, as the
+      // operator's blocks (the device layout)
+      const int nn = np * np;
+      auto add = [nn](double* dst, const double* src) {
+        for (int e = 0; e < nn; ++e) dst[e] += src[e];
       };
       double* D = slot((int32_t)r);
-      add_t(D, &vol[(size_t)c * np * np]);
+      add(D, &vol[(size_t)c * np * np]);
       for (int32_t k = cf_ptr[c]; k < cf_ptr[c + 1]; ++k) {
         int32_t fi = cf[k] >> 1;
         int t = cf[k] & 1;
         const auto& F = pm[fi];
         const double* Bk = &fblk[(size_t)fi * 4 * np * np];
         if (F.second < 0) {
-          add_t(D, Bk);
+          add(D, Bk);
           continue;
         }
-        add_t(D, Bk + (t * 2 + t) * np * np);
+        add(D, Bk + (t * 2 + t) * np * np);
         int32_t other = t ? F.first : F.second;
-        add_t(slot(A.iperm[other]), Bk + (t * 2 + (1 - t)) * np * np);
+        add(slot(A.iperm[other]), Bk + (t * 2 + (1 - t)) * np * np);
       }
       for (int a = 0; a < np; ++a) A.rhs[(size_t)r * np + a] = rhs_c[(size_t)c * np + a];
     }
@@ -593,7 +593,7 @@ struct FaceCtx {
 };
 
 // Face blocks of faces [lo, hi): interior faces the four blocks (++, +-, -+,
-// --), boundary faces block 0; block (t, s) element (a, b) at b*np + a.
+// --), boundary faces block 0; block (t, s) element (a, b) at a*np + b.
 template <int P>
 void face_range(const FaceCtx& X, int64_t lo, int64_t hi) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
@@ -639,10 +639,10 @@ void face_range(const FaceCtx& X, int64_t lo, int64_t hi) {
             const double* Gt = GN[t];
             const double* Gs = GN[s];
 #pragma GCC unroll 15
-            for (int b = 0; b < NP; ++b)
+            for (int a = 0; a < NP; ++a)
 #pragma GCC unroll 15
-              for (int a = 0; a < NP; ++a)
-                blk[b * NP + a] += c1 * Vt[a] * Gs[b] + c2 * Gt[a] * Vs[b] + c3 * Vt[a] * Vs[b];
+              for (int b = 0; b < NP; ++b)
+                blk[a * NP + b] += c1 * Vt[a] * Gs[b] + c2 * Gt[a] * Vs[b] + c3 * Vt[a] * Vs[b];
           }
       }
     } else {
@@ -653,10 +653,10 @@ void face_range(const FaceCtx& X, int64_t lo, int64_t hi) {
         basis_eval_p<P>(bp, x, y, vp, gxp, gyp);
         for (int a = 0; a < NP; ++a) gnp[a] = gxp[a] * nx + gyp[a] * ny;
 #pragma GCC unroll 15
-        for (int b = 0; b < NP; ++b)
+        for (int a = 0; a < NP; ++a)
 #pragma GCC unroll 15
-          for (int a = 0; a < NP; ++a)
-            Bk[b * NP + a] += w * (-r * vp[a] * gnp[b] - r * gnp[a] * vp[b] + sigma * vp[a] * vp[b]);
+          for (int b = 0; b < NP; ++b)
+            Bk[a * NP + b] += w * (-r * vp[a] * gnp[b] - r * gnp[a] * vp[b] + sigma * vp[a] * vp[b]);
       }
     }
   }
@@ -831,7 +831,8 @@ std::string assemble_sipg(const MeshView& mesh, int p, double c_sigma, const dou
   }
 
   // face blocks: interior faces 4 blocks (++, +-, -+, --), boundary 1 block;
-  // block (t, s) element (a, b) stored at b*np + a (a: test on t, b: trial on s)
+  // block (t, s) element (a, b) stored at a*np + b (a: test on t, b: trial on s;
+  // row-major, the operator's layout)
   const int64_t NF = (int64_t)A.faces.size();
   // not value-initialised: face_range zeroes each face's blocks in its own
   // thread (a serial fill of this buffer cost as much as computing it)

@@ -324,9 +324,9 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
               double* blk = Bk + (t * 2 + s) * np * np;
               const double c1 = -0.5 * g * eps[t] * q.w, c2 = -0.5 * g * eps[s] * q.w;
               const double c3 = sigma * eps[t] * eps[s] * q.w;
-              for (int bb = 0; bb < np; ++bb)
-                for (int aa = 0; aa < np; ++aa)
-                  blk[bb * np + aa] +=
+              for (int aa = 0; aa < np; ++aa)
+                for (int bb = 0; bb < np; ++bb)
+                  blk[aa * np + bb] +=
                       c1 * V[t][aa] * GN[s][bb] + c2 * GN[t][aa] * V[s][bb] + c3 * V[t][aa] * V[s][bb];
             }
         }
@@ -336,9 +336,9 @@ std::string assemble_sipg_tet(const TetView& mesh, int p, double c_sigma, const 
         for (const QP3& q : qp) {
           basis_eval3(bp, q.x, q.y, q.z, vp, gxp, gyp, gzp);
           for (int k = 0; k < np; ++k) gnp[k] = gxp[k] * n[0] + gyp[k] * n[1] + gzp[k] * n[2];
-          for (int bb = 0; bb < np; ++bb)
-            for (int aa = 0; aa < np; ++aa)
-              Bk[bb * np + aa] += q.w * (-r * vp[aa] * gnp[bb] - r * gnp[aa] * vp[bb] + sigma * vp[aa] * vp[bb]);
+          for (int aa = 0; aa < np; ++aa)
+            for (int bb = 0; bb < np; ++bb)
+              Bk[aa * np + bb] += q.w * (-r * vp[aa] * gnp[bb] - r * gnp[aa] * vp[bb] + sigma * vp[aa] * vp[bb]);
         }
       }
     }
