@@ -19,7 +19,7 @@ CASES = {
                                                   log10_rho_range=1.0),
     # larger subdomains (> 10 tile rows): 2x2 bins of 1200 cells at p=2 (~1800 DoFs)
     "vor_p2_big": lambda: I.voronoi_problem(1200, 12, p=2, bx=2, by=2, q=2),
-    # the highest degree the library takes: p=4 (15 DoFs per cell), 4 ragged subdomains, nested q=3
+    # p=4 (15 DoFs per cell, odd block size), 4 ragged subdomains, nested q=3
     "vor_p4_q3": lambda: I.voronoi_problem(150, 9, p=4, bx=2, by=2, q=3),
     # the regime of the 786k-DoF jump workload at reduced size: relaxed Voronoi of 4096 cells, p=2,
     # 16x8 bins (128 ragged subdomains of 132..264 DoFs), rho = 10^U[-4,4] per subdomain (contrast
