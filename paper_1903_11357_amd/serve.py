@@ -15,7 +15,11 @@ time. The server
     stream (captured graphs), so the iterations of different requests are
     in flight on the device together; new requests join as slots and memory
     free up, finished ones leave at once and release their buffers,
-  * records arrival-to-completion latency for every request.
+  * records arrival-to-completion latency for every request,
+  * completes a request that the library rejects (invalid input at
+    assembly or planning, an error at binding, factorisation or coarse
+    setup) or that can never fit the HBM budget with an error status and
+    message, and goes on serving the others.
 
 Each request's arithmetic is independent of the others' (own buffers,
 deterministic kernels), so a result is the same alone and in the mix.
@@ -43,7 +47,8 @@ class Request:
     t_admitted: float = -1.0
     t_done: float = -1.0
     iterations: int = 0
-    status: str = ""
+    status: str = ""               # "OK", a PCG status, or the error's status name
+    error: str = ""                # the library's message for a rejected request
     bytes: int = 0
     x: Optional[object] = None      # torch tensor when keep_solutions
 
@@ -148,6 +153,18 @@ class Server:
         active: List[_Active] = []
         used = 0
         done: List[Request] = []
+
+        def reject(r, status, msg):
+            r.status, r.error = status, msg
+            r.t_done = now()
+            if r.t_assembled < 0:
+                r.t_assembled = r.t_done
+            if r.t_admitted < 0:
+                r.t_admitted = r.t_done
+            done.append(r)
+            if on_done is not None:
+                on_done(len(done), len(reqs), r.t_done)
+
         try:
             while len(done) < len(reqs):
                 t = now()
@@ -160,19 +177,34 @@ class Server:
                 # admission in arrival order (no overtaking)
                 while preparing and preparing[0][1].done() and len(active) < self.max_active:
                     r, fut = preparing[0]
-                    pr, nbytes = fut.result()
+                    try:
+                        pr, nbytes = fut.result()
+                    except asdg.AsdgError as e:
+                        preparing.pop(0)
+                        reject(r, asdg.STATUS_NAMES.get(e.status, str(e.status)), str(e))
+                        continue
                     if r.t_assembled < 0:
                         r.t_assembled = now()
                     if nbytes > self.hbm_budget:
-                        raise RuntimeError(f"request {r.rid} needs {nbytes} B, more than the HBM budget")
+                        preparing.pop(0)
+                        del pr
+                        reject(r, "EBUDGET", f"request {r.rid} needs {nbytes} B, more than the HBM budget "
+                                             f"({self.hbm_budget} B)")
+                        continue
                     if used + nbytes > self.hbm_budget:
                         break
                     preparing.pop(0)
+                    try:
+                        stream = _device_setup(pr, self.device)
+                        pr.begin(rtol=self.rtol, max_iter=self.max_iter, check_every=self.check_every,
+                                 stream=stream)
+                    except asdg.AsdgError as e:
+                        del pr
+                        reject(r, asdg.STATUS_NAMES.get(e.status, str(e.status)), str(e))
+                        continue
                     r.bytes = nbytes
                     used += nbytes
                     self.peak_bytes = max(self.peak_bytes, used)
-                    stream = _device_setup(pr, self.device)
-                    pr.begin(rtol=self.rtol, max_iter=self.max_iter, check_every=self.check_every, stream=stream)
                     r.t_admitted = now()
                     active.append(_Active(r, pr, stream))
                     self.peak_active = max(self.peak_active, len(active))
@@ -211,6 +243,13 @@ class Server:
 
 
 def latency_stats(done: List[Request]) -> dict:
+    """Latency and throughput over the solved requests; rejected requests
+    (an error status from the library or the HBM budget) are counted
+    apart."""
+    failed = [r for r in done if r.error]
+    done = [r for r in done if not r.error]
+    if not done:
+        return {"n": 0, "failed": len(failed)}
     lat = np.array([r.latency for r in done])
     span = max(r.t_done for r in done) - min(r.arrival for r in done)
     # where the latency goes: host assembly (arrival -> assembled), waiting for
@@ -218,7 +257,7 @@ def latency_stats(done: List[Request]) -> dict:
     asm = np.array([r.t_assembled - r.arrival for r in done])
     adm = np.array([r.t_admitted - r.t_assembled for r in done])
     dev = np.array([r.t_done - r.t_admitted for r in done])
-    return {"n": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+    return {"n": len(done), "failed": len(failed), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
             "solves_per_s": len(done) / span if span > 0 else None,
             "iterations_mean": float(np.mean([r.iterations for r in done])),

@@ -1,5 +1,6 @@
 """Continuous-batching server: results are identical alone and in the mix,
-admission respects the HBM budget, served solutions match the oracle."""
+admission respects the HBM budget, served solutions match the oracle,
+rejected requests complete with their error while the others are served."""
 import numpy as np
 import pytest
 
@@ -82,3 +83,38 @@ def test_served_fp64_solution_matches_oracle():
         xk, info = orc.solve(fixed_iters=done[i].iterations)
         xg = done[i].x.cpu().numpy()
         assert np.linalg.norm(xg - xk) <= 1e-10 * np.linalg.norm(xk)
+
+
+def _bad_problems(P):
+    """A clockwise cell (rejected by the assembly) and a degree the library
+    does not take (rejected before any work)."""
+    import dataclasses
+
+    cw = P.mesh.cell_vertices.copy()
+    a, b = P.mesh.cell_ptr[0], P.mesh.cell_ptr[1]
+    cw[a:b] = cw[a:b][::-1]
+    mesh = dataclasses.replace(P.mesh, cell_vertices=cw)
+    return [dataclasses.replace(P, mesh=mesh), dataclasses.replace(P, p=0)]
+
+
+@pytest.mark.gpu
+def test_rejected_requests_complete_with_their_error_and_the_rest_are_served():
+    probs = _problems(4)
+    bad = _bad_problems(probs[0])
+    mix = [probs[0], bad[0], probs[1], bad[1], probs[2], probs[3]]
+    done, srv = _run(mix, [0.0] * len(mix), max_active=4)
+    assert len(done) == len(mix)
+    for i in (1, 3):
+        assert done[i].status == "EINVAL" and done[i].error and done[i].iterations == 0
+        assert done[i].x is None
+    ok = [i for i in range(len(mix)) if i not in (1, 3)]
+    assert all(done[i].status == "OK" and not done[i].error for i in ok)
+    # the served requests are the ones served without the rejected neighbours
+    alone, _ = _run([mix[i] for i in ok], [0.0] * len(ok), max_active=4)
+    for k, i in enumerate(ok):
+        assert done[i].iterations == alone[k].iterations
+        assert bool((done[i].x == alone[k].x).all())
+    from paper_1903_11357_amd.serve import latency_stats
+
+    st = latency_stats(list(done.values()))
+    assert st["n"] == 4 and st["failed"] == 2 and st["all_converged"]
